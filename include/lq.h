@@ -1,0 +1,243 @@
+/*
+ * lq.h -- C ABI of the MI355X (gfx950) library for CG inversion of the Wilson
+ * and 2-flavour staggered Wilson Dirac matrices through the normal equations
+ *
+ *     (D + m)^dag (D + m) psi = (D + m)^dag chi                 (paper eq. (2))
+ *
+ * and for the Lanczos estimate of the condition number of (D+m)^dag (D+m)
+ * (paper Sec. 3).  Reference: D.H. Adams, D. Nogradi, A. Petrashyk,
+ * C. Zielinski, "Computational efficiency of staggered Wilson fermions: A
+ * first look", PoS LATTICE2013; the staggered Wilson operator itself is the one
+ * of D.H. Adams, PLB 699 (2011) 394, which the paper cites in Sec. 2.
+ *
+ * Conventions (all functions):
+ *  - Lattice dims are (L1, L2, L3, L4) = (x, y, z, t), every L even and >= 4.
+ *    Canonical site index i = x1 + L1*(x2 + L2*(x3 + L3*x4)).
+ *  - Canonical fields are interleaved complex arrays, site-major:
+ *      gauge field  U[i][mu][a][b]  complex128   (mu = 0..3 for x, y, z, t;
+ *                                                 U_mu(x) links x -> x + mu)
+ *      Wilson field psi[i][spin][colour]         (4 x 3 complex per site)
+ *      staggered Wilson field psi[i][colour]     (3 complex per site)
+ *    complex128 = two doubles (re, im).
+ *  - Operators (r = Wilson parameter, m = bare mass):
+ *      Wilson:  (M psi)(x) = (m + 4r) psi(x) - 1/2 sum_mu [(r - g_mu) U_mu(x) psi(x+mu)
+ *                                   + (r + g_mu) U_mu(x-mu)^dag psi(x-mu)]
+ *               in the hermitian basis g_1 = [[0, i s1], [-i s1, 0]],
+ *               g_2 = [[0, -i s2], [i s2, 0]], g_3 = [[0, i s3], [-i s3, 0]],
+ *               g_4 = [[0, 1], [1, 0]]  (g_5 = diag(1, 1, -1, -1));
+ *      staggered Wilson:  M = D_st + r (1 - Gamma_55) + m, with
+ *               D_st = sum_mu eta_mu (V_mu - V_mu^dag)/2,
+ *               Gamma_55 = phi (1/24) sum_{orderings} C_1 C_2 C_3 C_4,
+ *               C_mu = (V_mu + V_mu^dag)/2, (V_mu psi)(x) = U_mu(x) psi(x+mu),
+ *               eta_mu = (-1)^(x_1+..+x_{mu-1}), phi = (-1)^(x2+x4);
+ *               M^dag = eps M eps, eps = (-1)^(x1+x2+x3+x4)   (paper Sec. 2).
+ *    A fermion hop that crosses the lattice boundary in direction mu is
+ *    multiplied by bc[mu] (+1 periodic, -1 antiperiodic).
+ *  - Memory: the library allocates no device memory.  Every device buffer
+ *    (gauge storage, solver workspace, inputs, outputs) is owned by the caller,
+ *    sized with the *_bytes queries, and must stay alive while a handle that
+ *    points into it is in use.  Handles hold host metadata only.
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *    enqueued on it; lq_apply and the *_create calls are asynchronous, the
+ *    solve, condition-number and timing calls return after their own
+ *    synchronisation with that stream.
+ *  - Errors: 0 = success; negative = error (nothing useful was produced);
+ *    positive = a solve finished without meeting its target (info is filled).
+ *    lq_last_error() returns a thread-local description of the last failure.
+ *    No C++ exception crosses this interface.
+ */
+#ifndef LQ_H
+#define LQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LQ_OK 0
+#define LQ_NOT_CONVERGED 1     /* maxiter reached; info filled                */
+#define LQ_ERR_ARG (-1)        /* bad dims, pointer, size, enum, non-finite    */
+#define LQ_ERR_WORKSPACE (-2)  /* caller buffer smaller than the query says    */
+#define LQ_ERR_DEVICE (-3)     /* a HIP runtime call failed                    */
+#define LQ_ERR_BREAKDOWN (-4)  /* CG/Lanczos breakdown: <p,Ap> <= 0 or NaN     */
+#define LQ_ERR_STATE (-5)      /* handle used in a state that does not allow it */
+
+/* formulations */
+#define LQ_WILSON 0
+#define LQ_STAGGERED_WILSON 1
+
+/* operator selector for lq_apply */
+#define LQ_OP_M 0      /* out = (D + m) in          */
+#define LQ_OP_MDAG 1   /* out = (D + m)^dag in      */
+#define LQ_OP_MDAGM 2  /* out = (D+m)^dag (D+m) in  */
+
+/* how the staggered Wilson Gamma_55 is applied */
+#define LQ_G55_CORNERS 0    /* from precomputed path-averaged corner matrices */
+#define LQ_G55_ONTHEFLY 1   /* from the links, every application               */
+
+/* arithmetic / storage precision of the stencil and Krylov vectors */
+#define LQ_PREC_F64 0
+#define LQ_PREC_F32 1
+#define LQ_PREC_F16 2
+
+/* link storage: 18 reals (full 3x3) or 12 reals (two rows, third row
+ * rebuilt in-kernel as conj(row0 x row1), valid for SU(3) links only) */
+#define LQ_LINKS_18 18
+#define LQ_LINKS_12 12
+
+/* gauge features: which device copies lq_gauge_create builds */
+#define LQ_FEAT_CORNERS 0x1u  /* corner matrices W_s(x) in every built precision */
+#define LQ_FEAT_F32 0x2u      /* FP32 links, 18-real and 12-real               */
+#define LQ_FEAT_F16 0x4u      /* FP16 links, 12-real                           */
+
+typedef struct lq_lattice_s lq_lattice;
+typedef struct lq_gauge_s lq_gauge;
+typedef struct lq_batch_s lq_batch;
+
+/* The Dirac matrix of eq. (2): formulation, bare mass, Wilson parameter r and
+ * the Gamma_55 mode (ignored for Wilson). */
+typedef struct {
+  int32_t formulation;
+  int32_t g55_mode;
+  double mass;
+  double r;
+} lq_dirac;
+
+/* Solver options (zero-initialised = plain FP64 CG, default polling). */
+typedef struct {
+  int32_t precision;          /* LQ_PREC_*: F64 = plain FP64 CG; F32/F16 = inner
+                                 CG in that precision with FP64 reliable updates */
+  int32_t links;              /* LQ_LINKS_18 or LQ_LINKS_12 (F16 requires 12)    */
+  int32_t reliable_interval;  /* iterations between FP64 reliable updates
+                                 (0 = default 64; unused for F64)                */
+  int32_t poll_interval;      /* iterations between host convergence polls
+                                 (0 = default 16; rounded up to even)            */
+  int32_t use_graph;          /* 1 = replay steady iteration chunks as hipGraphs */
+  int32_t max_restarts;       /* reliable updates allowed after the iterated
+                                 residual first meets tol (0 = default 50)       */
+} lq_solve_opts;
+
+/* Per-solve report.  The residuals are relative: ||b - A x|| / ||b|| with
+ * b = M^dag chi, A = M^dag M; `true_residual` is recomputed in FP64 on the GPU
+ * from the returned x. */
+typedef struct {
+  int32_t status;             /* LQ_OK, LQ_NOT_CONVERGED or LQ_ERR_BREAKDOWN      */
+  int32_t iterations;         /* CG iterations (A-applications in the loop)      */
+  int32_t reliable_updates;   /* FP64 true-residual recomputations              */
+  int32_t applications;       /* all applications of A, including b and updates */
+  double iterated_residual;
+  double true_residual;
+  double seconds;             /* wall time of the call                          */
+} lq_solve_info;
+
+/* ---------------------------------------------------------------- errors */
+const char* lq_last_error(void);
+const char* lq_version(void);
+
+/* --------------------------------------------------------------- lattice
+ * dims: 4 lattice extents, each even and >= 4, volume < 2^28.
+ * bc:   4 fermion boundary signs, each +1 or -1 (NULL = all +1).  */
+int lq_lattice_create(const int32_t dims[4], const int32_t bc[4], lq_lattice** out);
+void lq_lattice_destroy(lq_lattice* lat);
+int64_t lq_lattice_volume(const lq_lattice* lat);
+
+/* ----------------------------------------------------------------- gauge
+ * The gauge field of paper Sec. 3 (there: quenched beta = 6 configurations).
+ * lq_gauge_bytes: device bytes lq_gauge_create needs for `features`.
+ * lq_gauge_create: repacks the canonical complex128 field `U` (device
+ *   pointer, V*4*9 complex) into the library's structure-of-arrays layout in
+ *   `buf`, builds the FP32/FP16 copies and the staggered Wilson corner matrices
+ *   W_s(x) = (1/24) sum over the 24 orderings of the one-link-per-direction
+ *   path products from x to x + s, s in {+-1}^4 (8 are stored; the other 8 are
+ *   W_{-s}(x+s)^dag).  U is only read during the call's stream work.
+ *   Links must be SU(3) to use 12-real storage.  */
+size_t lq_gauge_bytes(const lq_lattice* lat, uint32_t features);
+int lq_gauge_create(const lq_lattice* lat, const void* U, uint32_t features,
+                    void* buf, size_t buf_bytes, void* stream, lq_gauge** out);
+void lq_gauge_destroy(lq_gauge* g);
+/* Mean plaquette (1/6V) sum_x sum_{mu<nu} (1/3) Re tr U_mu U_nu U_mu^dag U_nu^dag,
+ * computed in FP64 on the device; synchronises `stream`. */
+int lq_gauge_plaquette(const lq_gauge* g, double* plaquette, void* stream);
+
+/* ----------------------------------------------------------------- apply
+ * out = op(in) for the Dirac matrix `d` (paper eq. (2)).  in/out: device
+ * canonical fields, complex128 for LQ_PREC_F64 and complex64 for F32/F16
+ * (F16 rounds the repacked input to FP16 storage; arithmetic is FP32).
+ * `ws` is device scratch of lq_apply_workspace_bytes.  Asynchronous. */
+size_t lq_apply_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t precision);
+int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t op, int32_t precision,
+             int32_t links, const void* in, void* out, void* ws, size_t ws_bytes,
+             void* stream);
+
+/* Average device time (ms) of one stencil launch M or M^dag on fields already
+ * in the library layout, over `reps` back-to-back launches, measured with HIP
+ * events on `stream`.  Uses the same kernels as the solvers.  */
+int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger,
+                   int32_t precision, int32_t links, int32_t nrhs, int32_t reps,
+                   void* ws, size_t ws_bytes, double* avg_ms, void* stream);
+
+/* ----------------------------------------------------------------- solve
+ * CG on eq. (2) for one source chi (device canonical complex128); the
+ * solution x (device canonical complex128) is returned when the FP64 true
+ * residual ||b - A x||/||b|| <= tol, with x0 = 0.  Mixed precision (opts)
+ * iterates in FP32/FP16 and recomputes the true residual in FP64 at every
+ * reliable update; scalars alpha, beta and all reductions are FP64. */
+size_t lq_solve_workspace_bytes(const lq_gauge* g, int32_t formulation,
+                                const lq_solve_opts* opts, int32_t nrhs);
+int lq_cg_solve(const lq_gauge* g, const lq_dirac* d, const void* chi, void* x,
+                double tol, int32_t maxiter, const lq_solve_opts* opts, void* ws,
+                size_t ws_bytes, lq_solve_info* info, void* stream);
+
+/* Batched multi-RHS CG: nrhs independent systems on one gauge field, each with
+ * its own mass (masses[k], host), source (chi + k*field) and tolerance
+ * (tols[k], host).  chi and x hold nrhs canonical complex128 fields back to
+ * back.  Every stencil launch serves all active systems; links are shared.
+ * infos: nrhs entries.  Returns the worst status. */
+int lq_cg_solve_batch(const lq_gauge* g, int32_t formulation, int32_t g55_mode,
+                      double r, int32_t nrhs, const double* masses, const void* chi,
+                      void* x, const double* tols, int32_t maxiter,
+                      const lq_solve_opts* opts, void* ws, size_t ws_bytes,
+                      lq_solve_info* infos, void* stream);
+
+/* -------------------------------------------------- continuous batching
+ * A resident multi-RHS solver with `nslots` slots (serving).  Slots are loaded
+ * and harvested between steps while the other slots keep iterating.
+ *   lq_batch_create: ws of lq_solve_workspace_bytes(g, formulation, opts, nslots).
+ *   lq_batch_load:   start slot `slot` on source chi (device canonical) with
+ *                    mass, tol and an iteration limit; asynchronous.
+ *   lq_batch_step:   advance every running slot by about `iterations` CG
+ *                    iterations (reliable updates included); then report each
+ *                    slot's state in states[nslots] (0 empty, 1 running,
+ *                    2 converged, 3 failed); synchronises `stream`.
+ *   lq_batch_fetch:  copy a finished slot's solution to x (device canonical)
+ *                    and its report to info; frees the slot.                  */
+int lq_batch_create(const lq_gauge* g, int32_t formulation, int32_t g55_mode, double r,
+                    int32_t nslots, const lq_solve_opts* opts, void* ws,
+                    size_t ws_bytes, lq_batch** out);
+int lq_batch_load(lq_batch* b, int32_t slot, const void* chi, double mass, double tol,
+                  int32_t maxiter, void* stream);
+int lq_batch_step(lq_batch* b, int32_t iterations, int32_t* states, void* stream);
+int lq_batch_fetch(lq_batch* b, int32_t slot, void* x, lq_solve_info* info, void* stream);
+void lq_batch_destroy(lq_batch* b);
+
+/* ---------------------------------------------------- condition number
+ * Lanczos with full reorthogonalisation (classical Gram-Schmidt, twice) on
+ * A = M^dag M from the caller's start vector v0 (device canonical complex128),
+ * `steps` steps; the Ritz values of the tridiagonal matrix give
+ * lmin = theta_min, lmax = theta_max and kappa = lmax/lmin (paper Sec. 3,
+ * kappa = lambda_max/lambda_min).  alpha[steps] and beta[steps-1] (host,
+ * may be NULL) receive the tridiagonal.  Workspace holds steps+1 FP64 basis
+ * vectors: lq_lanczos_workspace_bytes.  Synchronises `stream`.  */
+size_t lq_lanczos_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t steps);
+int lq_condition_number(const lq_gauge* g, const lq_dirac* d, int32_t steps,
+                        const void* v0, void* ws, size_t ws_bytes, double* lmin,
+                        double* lmax, double* kappa, double* alpha, double* beta,
+                        int32_t* steps_done, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LQ_H */

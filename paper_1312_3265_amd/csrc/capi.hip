@@ -1,0 +1,398 @@
+// extern "C" entry points of include/lq.h: argument validation, error codes,
+// and thin calls into the engine.  No C++ exception crosses this file.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "engine.h"
+
+using namespace lq;
+
+static thread_local std::string g_last_error;
+
+template <class F>
+static int guard(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return LQ_ERR_ARG;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return LQ_ERR_ARG;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return LQ_ERR_ARG;
+  }
+}
+
+static void need(bool ok, const char* msg) {
+  if (!ok) throw Error(LQ_ERR_ARG, msg);
+}
+
+static hipStream_t S(void* s) { return (hipStream_t)s; }
+
+static void check_dirac(const lq_dirac* d) {
+  need(d != nullptr, "null lq_dirac");
+  need(d->formulation == LQ_WILSON || d->formulation == LQ_STAGGERED_WILSON, "bad formulation");
+  need(d->g55_mode == LQ_G55_CORNERS || d->g55_mode == LQ_G55_ONTHEFLY, "bad g55_mode");
+  need(std::isfinite(d->mass) && std::isfinite(d->r), "mass and r must be finite");
+}
+
+static void check_prec(int32_t prec, int32_t links) {
+  need(prec == LQ_PREC_F64 || prec == LQ_PREC_F32 || prec == LQ_PREC_F16, "bad precision");
+  need(links == 0 || links == LQ_LINKS_18 || links == LQ_LINKS_12, "links must be 18 or 12");
+  need(!(prec == LQ_PREC_F16 && links == LQ_LINKS_18), "FP16 stencils use 12-real links");
+}
+
+static int links_for(int32_t prec, int32_t links) {
+  if (prec == LQ_PREC_F64) return 18;
+  if (links) return links;
+  return prec == LQ_PREC_F16 ? 12 : 18;
+}
+
+extern "C" {
+
+const char* lq_last_error(void) { return g_last_error.c_str(); }
+
+const char* lq_version(void) { return "lq 0.1 gfx950"; }
+
+int lq_lattice_create(const int32_t dims[4], const int32_t bc[4], lq_lattice** out) {
+  return guard([&] {
+    need(dims && out, "null argument");
+    int64_t V = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+      need(dims[mu] >= 4 && dims[mu] % 2 == 0, "every lattice extent must be even and >= 4");
+      V *= dims[mu];
+    }
+    need(V < (1ll << 28), "volume must be below 2^28 sites");
+    auto* l = new lq_lattice_s;
+    std::memset(l, 0, sizeof(*l));
+    Geom& g = l->g;
+    int st = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+      g.L[mu] = dims[mu];
+      g.stride[mu] = st;
+      st *= dims[mu];
+      l->dims[mu] = dims[mu];
+      const int b = bc ? bc[mu] : 1;
+      if (b != 1 && b != -1) { delete l; throw Error(LQ_ERR_ARG, "bc entries must be +1 or -1"); }
+      g.bc[mu] = b;
+      l->bc[mu] = b;
+      if (b < 0) g.has_bc = 1;
+    }
+    g.V = (int)V;
+    // pad each plane by 64 elements past a 64-multiple: plane starts avoid
+    // falling on the same HBM channel for power-of-two volumes
+    g.Vp = (int)(((V + 63) / 64) * 64 + 64);
+    for (int k = 0; k < 3; ++k) g.dv[k].init((uint32_t)dims[k]);
+    *out = l;
+    return LQ_OK;
+  });
+}
+
+void lq_lattice_destroy(lq_lattice* lat) { delete lat; }
+
+int64_t lq_lattice_volume(const lq_lattice* lat) { return lat ? (int64_t)lat->g.V : -1; }
+
+size_t lq_gauge_bytes(const lq_lattice* lat, uint32_t features) {
+  if (!lat) return 0;
+  return gauge_layout(lat->g, features, nullptr, nullptr);
+}
+
+int lq_gauge_create(const lq_lattice* lat, const void* U, uint32_t features, void* buf,
+                    size_t buf_bytes, void* stream, lq_gauge** out) {
+  return guard([&] {
+    need(lat && U && buf && out, "null argument");
+    need((features & ~7u) == 0, "unknown feature bits");
+    const size_t nb = gauge_layout(lat->g, features, nullptr, nullptr);
+    if (buf_bytes < nb)
+      throw Error(LQ_ERR_WORKSPACE, "gauge buffer too small: need " + std::to_string(nb));
+    std::unique_ptr<lq_gauge_s> g(new lq_gauge_s);
+    gauge_layout(lat->g, features, buf, g.get());
+    hipStream_t s = S(stream);
+    launch_fill_zero(buf, nb, s);
+    launch_gauge_in(g->g, U, g->u64, s);
+    if (features & LQ_FEAT_F32) {
+      launch_links_convert(P32, 18, g->g, g->u64, g->u32_18, s);
+      launch_links_convert(P32, 12, g->g, g->u64, g->u32_12, s);
+    }
+    if (features & LQ_FEAT_F16) launch_links_convert(P16, 12, g->g, g->u64, g->u16_12, s);
+    if (features & LQ_FEAT_CORNERS) {
+      launch_corners(g->g, g->u64, g->c64, s);
+      if (features & LQ_FEAT_F32) launch_corners_convert(P32, g->g, g->c64, g->c32, s);
+      if (features & LQ_FEAT_F16) launch_corners_convert(P16, g->g, g->c64, g->c16, s);
+    }
+    check_launch();
+    *out = g.release();
+    return LQ_OK;
+  });
+}
+
+void lq_gauge_destroy(lq_gauge* g) { delete g; }
+
+int lq_gauge_plaquette(const lq_gauge* g, double* plaquette, void* stream) {
+  return guard([&] {
+    need(g && plaquette, "null argument");
+    hipStream_t s = S(stream);
+    launch_plaquette(g->g, g->u64, g->scratch, g->nbp, g->scratch + g->nbp, s);
+    check_launch();
+    LQ_HIP(hipMemcpyAsync(plaquette, g->scratch + g->nbp, sizeof(double), hipMemcpyDeviceToHost, s));
+    LQ_HIP(hipStreamSynchronize(s));
+    return LQ_OK;
+  });
+}
+
+// -------------------------------------------------------------- apply
+size_t lq_apply_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t precision) {
+  if (!g || (formulation != LQ_WILSON && formulation != LQ_STAGGERED_WILSON)) return 0;
+  if (precision < 0 || precision > 2) return 0;
+  const size_t v = (size_t)ncomp_of(formulation) * g->g.Vp * store_bytes(precision);
+  Carver c(nullptr);
+  c.take(v); c.take(v); c.take(v);
+  c.take((size_t)nbp_of(g->g.V) * 8);
+  return c.size();
+}
+
+static OpArgs make_op(const lq_gauge* g, const lq_dirac* d, int prec, int nl) {
+  OpArgs a;
+  a.g = g->g;
+  a.links = g->links(prec, nl);
+  const int op = opkind(d->formulation, d->g55_mode);
+  a.corners = op == OP_SW_CORNERS ? g->corners(prec) : nullptr;
+  a.r = d->r;
+  a.mass0 = d->mass;
+  a.mass = nullptr;
+  a.mass_stride = 0;
+  return a;
+}
+
+int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t opsel, int32_t precision,
+             int32_t links, const void* in, void* out, void* ws, size_t ws_bytes, void* stream) {
+  return guard([&] {
+    need(g && in && out && ws, "null argument");
+    check_dirac(d);
+    check_prec(precision, links);
+    need(opsel == LQ_OP_M || opsel == LQ_OP_MDAG || opsel == LQ_OP_MDAGM, "bad op");
+    const size_t nb = lq_apply_workspace_bytes(g, d->formulation, precision);
+    if (ws_bytes < nb) throw Error(LQ_ERR_WORKSPACE, "apply workspace too small: need " + std::to_string(nb));
+    const int nl = links_for(precision, links);
+    const int nc = ncomp_of(d->formulation);
+    const int op = opkind(d->formulation, d->g55_mode);
+    const OpArgs oa = make_op(g, d, precision, nl);
+    const size_t v = (size_t)nc * g->g.Vp * store_bytes(precision);
+    Carver c(ws);
+    void* a = c.take(v);
+    void* b = c.take(v);
+    void* tmp = c.take(v);
+    (void)c.take((size_t)nbp_of(g->g.V) * 8);
+    hipStream_t s = S(stream);
+    const int nbp = nbp_of(g->g.V);
+    const int f64 = precision == LQ_PREC_F64;
+    launch_field_in(precision, nc, g->g, in, f64, a, nbp, 0, 1, s);
+    EpiArgs e;
+    std::memset(&e, 0, sizeof(e));
+    e.nbp = nbp;
+    if (opsel == LQ_OP_MDAGM) {
+      e.out = tmp;
+      launch_stencil(op, precision, nl, false, EPI_STORE, oa, a, e, 1, s);
+      e.out = b;
+      launch_stencil(op, precision, nl, true, EPI_STORE, oa, tmp, e, 1, s);
+    } else {
+      e.out = b;
+      launch_stencil(op, precision, nl, opsel == LQ_OP_MDAG, EPI_STORE, oa, a, e, 1, s);
+    }
+    launch_field_out(precision, nc, g->g, b, out, f64, nbp, 0, 1, s);
+    check_launch();
+    return LQ_OK;
+  });
+}
+
+int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t precision,
+                   int32_t links, int32_t nrhs, int32_t reps, void* ws, size_t ws_bytes,
+                   double* avg_ms, void* stream) {
+  return guard([&] {
+    need(g && ws && avg_ms, "null argument");
+    check_dirac(d);
+    check_prec(precision, links);
+    need(nrhs >= 1 && reps >= 1, "nrhs and reps must be >= 1");
+    const int nl = links_for(precision, links);
+    const int nc = ncomp_of(d->formulation);
+    const int op = opkind(d->formulation, d->g55_mode);
+    const size_t v = (size_t)nrhs * nc * g->g.Vp * store_bytes(precision);
+    Carver c(ws);
+    void* a = c.take(v);
+    void* b = c.take(v);
+    if (ws_bytes < c.size())
+      throw Error(LQ_ERR_WORKSPACE, "timing workspace too small: need " + std::to_string(c.size()));
+    const OpArgs oa = make_op(g, d, precision, nl);
+    hipStream_t s = S(stream);
+    launch_fill_zero(ws, c.size(), s);
+    EpiArgs e;
+    std::memset(&e, 0, sizeof(e));
+    e.nbp = nbp_of(g->g.V);
+    e.out = b;
+    launch_stencil(op, precision, nl, dagger != 0, EPI_STORE, oa, a, e, nrhs, s);   // warm-up
+    hipEvent_t t0, t1;
+    LQ_HIP(hipEventCreate(&t0));
+    LQ_HIP(hipEventCreate(&t1));
+    LQ_HIP(hipEventRecord(t0, s));
+    for (int k = 0; k < reps; ++k)
+      launch_stencil(op, precision, nl, dagger != 0, EPI_STORE, oa, a, e, nrhs, s);
+    LQ_HIP(hipEventRecord(t1, s));
+    LQ_HIP(hipEventSynchronize(t1));
+    check_launch();
+    float ms = 0.0f;
+    LQ_HIP(hipEventElapsedTime(&ms, t0, t1));
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    *avg_ms = ms / reps;
+    return LQ_OK;
+  });
+}
+
+// -------------------------------------------------------------- solves
+size_t lq_solve_workspace_bytes(const lq_gauge* g, int32_t formulation, const lq_solve_opts* opts,
+                                int32_t nrhs) {
+  if (!g || nrhs < 1) return 0;
+  if (formulation != LQ_WILSON && formulation != LQ_STAGGERED_WILSON) return 0;
+  return Engine::workspace_bytes(g->g, formulation, opts, nrhs);
+}
+
+static void check_opts(const lq_solve_opts* o) {
+  if (!o) return;
+  check_prec(o->precision, o->links);
+  need(o->reliable_interval >= 0 && o->poll_interval >= 0 && o->max_restarts >= 0,
+       "negative option");
+}
+
+int lq_cg_solve(const lq_gauge* g, const lq_dirac* d, const void* chi, void* x, double tol,
+                int32_t maxiter, const lq_solve_opts* opts, void* ws, size_t ws_bytes,
+                lq_solve_info* info, void* stream) {
+  return lq_cg_solve_batch(g, d ? d->formulation : -1, d ? d->g55_mode : 0, d ? d->r : 0.0, 1,
+                           d ? &d->mass : nullptr, chi, x, &tol, maxiter, opts, ws, ws_bytes, info,
+                           stream);
+}
+
+int lq_cg_solve_batch(const lq_gauge* g, int32_t formulation, int32_t g55_mode, double r,
+                      int32_t nrhs, const double* masses, const void* chi, void* x,
+                      const double* tols, int32_t maxiter, const lq_solve_opts* opts, void* ws,
+                      size_t ws_bytes, lq_solve_info* infos, void* stream) {
+  return guard([&] {
+    const auto t0 = std::chrono::steady_clock::now();
+    need(g && masses && chi && x && tols && ws && infos, "null argument");
+    lq_dirac d{formulation, g55_mode, masses[0], r};
+    check_dirac(&d);
+    check_opts(opts);
+    need(nrhs >= 1 && maxiter >= 1, "nrhs and maxiter must be >= 1");
+    hipStream_t s = S(stream);
+    Engine e;
+    e.init(g, formulation, g55_mode, r, nrhs, opts, ws, ws_bytes, s);
+    const int nc = ncomp_of(formulation);
+    const size_t field = (size_t)g->g.V * nc * 16;
+    for (int k = 0; k < nrhs; ++k)
+      e.load(k, (const char*)chi + k * field, masses[k], tols[k], maxiter, s);
+    for (int k = 0; k < nrhs; ++k)
+      if (e.hst[k].status == SLOT_FAILED && (e.hst[k].flags & 1))
+        throw Error(LQ_ERR_ARG, "source " + std::to_string(k) + " gives a non-finite b = M^dag chi");
+    while (e.running()) e.step(1 << 20, s);
+    int worst = LQ_OK;
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int k = 0; k < nrhs; ++k) {
+      e.fetch(k, (char*)x + k * field, infos + k, s);
+      infos[k].seconds = secs;
+      const int st = infos[k].status;
+      if (st < 0 && (worst >= 0 || st < worst)) worst = st;
+      if (st > 0 && worst == LQ_OK) worst = st;
+    }
+    if (worst != LQ_OK) g_last_error = "at least one system did not converge";
+    return worst;
+  });
+}
+
+// -------------------------------------------------- continuous batching
+struct lq_batch_s {
+  Engine e;
+};
+
+int lq_batch_create(const lq_gauge* g, int32_t formulation, int32_t g55_mode, double r,
+                    int32_t nslots, const lq_solve_opts* opts, void* ws, size_t ws_bytes,
+                    lq_batch** out) {
+  return guard([&] {
+    need(g && ws && out, "null argument");
+    lq_dirac d{formulation, g55_mode, 0.0, r};
+    check_dirac(&d);
+    check_opts(opts);
+    need(nslots >= 1, "nslots must be >= 1");
+    std::unique_ptr<lq_batch_s> b(new lq_batch_s);
+    b->e.init(g, formulation, g55_mode, r, nslots, opts, ws, ws_bytes, nullptr);
+    *out = b.release();
+    return LQ_OK;
+  });
+}
+
+int lq_batch_load(lq_batch* b, int32_t slot, const void* chi, double mass, double tol,
+                  int32_t maxiter, void* stream) {
+  return guard([&] {
+    need(b != nullptr, "null batch");
+    b->e.load(slot, chi, mass, tol, maxiter, S(stream));
+    if (b->e.hst[slot].status == SLOT_FAILED && (b->e.hst[slot].flags & 1))
+      throw Error(LQ_ERR_ARG, "source gives a non-finite b = M^dag chi");
+    return LQ_OK;
+  });
+}
+
+int lq_batch_step(lq_batch* b, int32_t iterations, int32_t* states, void* stream) {
+  return guard([&] {
+    need(b != nullptr && iterations >= 0, "bad argument");
+    if (iterations > 0) b->e.step(iterations, S(stream));
+    if (states)
+      for (int k = 0; k < b->e.nslots; ++k) states[k] = b->e.hst[k].status;
+    return LQ_OK;
+  });
+}
+
+int lq_batch_fetch(lq_batch* b, int32_t slot, void* x, lq_solve_info* info, void* stream) {
+  return guard([&] {
+    need(b != nullptr, "null batch");
+    b->e.fetch(slot, x, info, S(stream));
+    return LQ_OK;
+  });
+}
+
+void lq_batch_destroy(lq_batch* b) { delete b; }
+
+// ---------------------------------------------------- condition number
+size_t lq_lanczos_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t steps) {
+  if (!g || steps < 1 || steps > 1000) return 0;
+  if (formulation != LQ_WILSON && formulation != LQ_STAGGERED_WILSON) return 0;
+  return lanczos_workspace_bytes(g->g, formulation, steps);
+}
+
+int lq_condition_number(const lq_gauge* g, const lq_dirac* d, int32_t steps, const void* v0,
+                        void* ws, size_t ws_bytes, double* lmin, double* lmax, double* kappa,
+                        double* alpha, double* beta, int32_t* steps_done, void* stream) {
+  return guard([&] {
+    need(g && v0 && ws && lmin && lmax && kappa, "null argument");
+    check_dirac(d);
+    std::vector<double> a, b;
+    const int n = lanczos_run(g, d, steps, v0, ws, ws_bytes, a, b, S(stream));
+    double lo, hi;
+    tridiag_extremes(a, b, lo, hi);
+    *lmin = lo;
+    *lmax = hi;
+    *kappa = hi / lo;
+    if (alpha) for (int j = 0; j < n; ++j) alpha[j] = a[j];
+    if (beta) for (int j = 0; j + 1 < n; ++j) beta[j] = b[j];
+    if (steps_done) *steps_done = n;
+    return LQ_OK;
+  });
+}
+
+}  // extern "C"

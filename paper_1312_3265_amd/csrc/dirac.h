@@ -1,0 +1,393 @@
+// Per-site Dirac operators of eq. (2): the Wilson matrix (K1), the staggered
+// Wilson matrix from precomputed corner matrices (K4) and with Gamma_55 built
+// on the fly from the links (K2).  Each computes the NC output components of
+// one site for one right-hand side into registers; the stencil kernels add
+// their epilogues (store, fused norms, CG updates) around them.
+#pragma once
+
+#include "common.h"
+#include "lq_types.h"
+
+namespace lq {
+
+// Operator arguments shared by every stencil kernel.
+struct OpArgs {
+  Geom g;
+  const void* links;     // SoA links in the kernel's precision
+  const void* corners;   // SoA corners (staggered Wilson, corner form)
+  double r;              // Wilson parameter
+  double mass0;          // mass when `mass` is null
+  const double* mass;    // per-RHS mass, mass[k * mass_stride]
+  int mass_stride;
+};
+
+__device__ __forceinline__ double rhs_mass(const OpArgs& a, int k) {
+  return a.mass ? a.mass[(size_t)k * a.mass_stride] : a.mass0;
+}
+
+// ------------------------------------------------------------------ Wilson
+// (M psi)(x) = (m + 4r) psi(x) - 1/2 sum_mu [(r - s g_mu) U_mu(x) psi(x+mu)
+//                                    + (r + s g_mu) U_mu(x-mu)^dag psi(x-mu)]
+// s = +1 for M, -1 for M^dag (gamma_5-hermiticity).  The gamma basis is
+// g_mu = [[0, B_mu], [B_mu^dag, 0]] with B_1 = i s1, B_2 = -i s2, B_3 = i s3,
+// B_4 = 1.  For r = 1 the hop uses spin projection: (1 + t g_mu) psi =
+// [h; t B^dag h] with h = psi_up + t B psi_lo, so only the two-spinor h is
+// multiplied by the link (the paper's "8 x 2" count, Sec. 3).
+template <typename C>
+__device__ __forceinline__ void bmul(int mu, const C lo0, const C lo1, C& o0, C& o1) {
+  // (o0, o1) = B_mu (lo0, lo1)
+  switch (mu) {
+    case 0: o0 = cmuli(lo1); o1 = cmuli(lo0); break;
+    case 1: o0 = cscale(lo1, -1.0f); o1 = lo0; break;
+    case 2: o0 = cmuli(lo0); o1 = cmulmi(lo1); break;
+    default: o0 = lo0; o1 = lo1; break;
+  }
+}
+template <typename C>
+__device__ __forceinline__ void bdmul(int mu, const C h0, const C h1, C& o0, C& o1) {
+  // (o0, o1) = B_mu^dag (h0, h1)
+  switch (mu) {
+    case 0: o0 = cmulmi(h1); o1 = cmulmi(h0); break;
+    case 1: o0 = h1; o1 = cscale(h0, -1.0f); break;
+    case 2: o0 = cmulmi(h0); o1 = cmuli(h1); break;
+    default: o0 = h0; o1 = h1; break;
+  }
+}
+
+template <class P, int NL, bool DAG, bool GENERAL_R = false>
+struct WilsonOp {
+  using Pol = P;
+  static constexpr int NC = 12;
+  static constexpr int kWaves = P::id == 0 ? 3 : 4;
+  using C = typename P::C;
+  using R = typename P::R;
+  using S = typename P::S;
+
+  // Accumulate (r + t g_mu) L psi_nb into acc, with L = link or link^dag.
+  __device__ __forceinline__ static void hop(const OpArgs& a, const S* __restrict__ in, int nb,
+                                             int lsite, int mu, bool dagger_link, R t, R sgn,
+                                             C acc[12]) {
+    const int Vp = a.g.Vp;
+    C lk[9];
+    load_link<P, NL>((const S*)a.links, Vp, mu, lsite, lk);
+    if constexpr (!GENERAL_R) {
+      C h[2][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        C u0 = ldq<P>(in, Vp, 0 * 3 + c, nb);
+        C u1 = ldq<P>(in, Vp, 1 * 3 + c, nb);
+        C l0 = ldq<P>(in, Vp, 2 * 3 + c, nb);
+        C l1 = ldq<P>(in, Vp, 3 * 3 + c, nb);
+        C b0, b1;
+        bmul(mu, l0, l1, b0, b1);
+        h[0][c] = cscale(cadd(u0, cscale(b0, t)), sgn);
+        h[1][c] = cscale(cadd(u1, cscale(b1, t)), sgn);
+      }
+      C uh[2][3];
+      if (dagger_link) { mvd(lk, h[0], uh[0]); mvd(lk, h[1], uh[1]); }
+      else { mv(lk, h[0], uh[0]); mv(lk, h[1], uh[1]); }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        C d0, d1;
+        bdmul(mu, uh[0][c], uh[1][c], d0, d1);
+        acc[0 * 3 + c] = cadd(acc[0 * 3 + c], uh[0][c]);
+        acc[1 * 3 + c] = cadd(acc[1 * 3 + c], uh[1][c]);
+        acc[2 * 3 + c] = cadd(acc[2 * 3 + c], cscale(d0, t));
+        acc[3 * 3 + c] = cadd(acc[3 * 3 + c], cscale(d1, t));
+      }
+    } else {
+      // general r: (r + t g) L psi = r L psi + t g (L psi), all four spins
+      C w[4][3];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        C v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = cscale(ldq<P>(in, Vp, s * 3 + c, nb), sgn);
+        if (dagger_link) mvd(lk, v, w[s]); else mv(lk, v, w[s]);
+      }
+      const R rr = (R)a.r;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        C gu0, gu1, gl0, gl1;
+        bmul(mu, w[2][c], w[3][c], gu0, gu1);    // upper = B lower
+        bdmul(mu, w[0][c], w[1][c], gl0, gl1);   // lower = B^dag upper
+        acc[0 * 3 + c] = cadd(acc[0 * 3 + c], cadd(cscale(w[0][c], rr), cscale(gu0, t)));
+        acc[1 * 3 + c] = cadd(acc[1 * 3 + c], cadd(cscale(w[1][c], rr), cscale(gu1, t)));
+        acc[2 * 3 + c] = cadd(acc[2 * 3 + c], cadd(cscale(w[2][c], rr), cscale(gl0, t)));
+        acc[3 * 3 + c] = cadd(acc[3 * 3 + c], cadd(cscale(w[3][c], rr), cscale(gl1, t)));
+      }
+    }
+  }
+
+  __device__ __forceinline__ static void site(const OpArgs& a, const S* __restrict__ in, int i,
+                                              int k, C out[12]) {
+    const Geom& g = a.g;
+    Coord c = site_coords(g, i);
+    // acc starts at -2 (m + 4r) psi(x) so that out = -acc/2 at the end and
+    // psi(x) is not kept live across the hops
+    const R diag = (R)(rhs_mass(a, k) + 4.0 * a.r);
+    C acc[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) acc[q] = cscale(ldq<P>(in, g.Vp, q, i), (R)-2 * diag);
+    const R s = DAG ? (R)-1 : (R)1;
+    // The direction loop stays rolled: mu is uniform across the wavefront, so
+    // the gamma structure is a scalar branch, and only one hop's operands are
+    // live at a time (unrolling lets the scheduler hoist all 8 hops' loads).
+#pragma unroll 1
+    for (int h = 0; h < 8; ++h) {
+      const int mu = h >> 1;
+      bool wrap;
+      if ((h & 1) == 0) {
+        const int j = nb_fwd(g, c, i, mu, wrap);
+        const R sg = (wrap && g.bc[mu] < 0) ? (R)-1 : (R)1;
+        hop(a, in, j, i, mu, false, -s, sg, acc);    // (r - s g) U_mu(x) psi(x+mu)
+      } else {
+        const int j = nb_bwd(g, c, i, mu, wrap);
+        const R sg = (wrap && g.bc[mu] < 0) ? (R)-1 : (R)1;
+        hop(a, in, j, j, mu, true, s, sg, acc);      // (r + s g) U_mu(x-mu)^dag psi(x-mu)
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) out[q] = cscale(acc[q], (R)-0.5);
+  }
+};
+
+// Wilson with r != 1 (no spin projection); only FP64 is instantiated.
+template <class P, int NL, bool DAG>
+struct WilsonOpR : WilsonOp<P, NL, DAG, true> {};
+template <class P, int NL, bool DAG>
+struct WilsonOpR1 : WilsonOp<P, NL, DAG, false> {};
+
+// ------------------------------------------------------- staggered Wilson
+// M = D_st + r (1 - Gamma_55) + m, M^dag = -D_st + r (1 - Gamma_55) + m.
+// D_st psi(x) = 1/2 sum_mu eta_mu(x) [U_mu(x) psi(x+mu) - U_mu(x-mu)^dag psi(x-mu)].
+template <class P, int NL>
+__device__ __forceinline__ void dst_site(const OpArgs& a, const typename P::S* __restrict__ in,
+                                         const Coord& c, int i, typename P::C acc[3]) {
+  using C = typename P::C;
+  using R = typename P::R;
+  using S = typename P::S;
+  const Geom& g = a.g;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) acc[q] = czero<C>();
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    const R eta = (R)eta_sign(c, mu);
+    bool wrap;
+    C lk[9], v[3], y[3];
+    int j = nb_fwd(g, c, i, mu, wrap);
+    R sg = ((wrap && g.bc[mu] < 0) ? (R)-1 : (R)1) * eta;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) v[q] = ldq<P>(in, g.Vp, q, j);
+    load_link<P, NL>((const S*)a.links, g.Vp, mu, i, lk);
+    mv(lk, v, y);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[q] = cadd(acc[q], cscale(y[q], sg));
+    j = nb_bwd(g, c, i, mu, wrap);
+    sg = ((wrap && g.bc[mu] < 0) ? (R)-1 : (R)1) * eta;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) v[q] = ldq<P>(in, g.Vp, q, j);
+    load_link<P, NL>((const S*)a.links, g.Vp, mu, j, lk);
+    mvd(lk, v, y);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[q] = csub(acc[q], cscale(y[q], sg));
+  }
+}
+
+// Site index and boundary sign of x + s for a diagonal offset s in {+-1}^4.
+__device__ __forceinline__ int diag_nb(const Geom& g, const Coord& c, const int s[4], int& sign) {
+  int j = 0;
+  sign = 1;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    int y = c.x[mu] + s[mu];
+    if (y < 0) { y += g.L[mu]; sign *= g.bc[mu]; }
+    else if (y >= g.L[mu]) { y -= g.L[mu]; sign *= g.bc[mu]; }
+    j += y * g.stride[mu];
+  }
+  return j;
+}
+
+// Corner form (K4): Gamma_55 psi(x) = phi(x) (1/16) sum_s W_s(x) psi(x+s).
+// Stored: W_s for s = (s1, s2, s3, +1), index cidx = bits (s1<0, s2<0, s3<0);
+// the s4 = -1 corners are W_{-s}(x) = W_s(x - s)^dag.
+template <class P, int NL, bool DAG>
+struct SWCornerOp {
+  using Pol = P;
+  static constexpr int NC = 3;
+  static constexpr int kWaves = 4;
+  using C = typename P::C;
+  using R = typename P::R;
+  using S = typename P::S;
+
+  __device__ __forceinline__ static void site(const OpArgs& a, const S* __restrict__ in, int i,
+                                              int k, C out[3]) {
+    const Geom& g = a.g;
+    Coord c = site_coords(g, i);
+    C d[3];
+    dst_site<P, NL>(a, in, c, i, d);
+    C acc[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[q] = czero<C>();
+    const S* W = (const S*)a.corners;
+#pragma unroll 1
+    for (int cidx = 0; cidx < 8; ++cidx) {
+      int s[4] = {(cidx & 1) ? -1 : 1, (cidx & 2) ? -1 : 1, (cidx & 4) ? -1 : 1, 1};
+      int sign;
+      C w[9], v[3], y[3];
+      // forward corner: W_s(x) psi(x + s)
+      int j = diag_nb(g, c, s, sign);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) v[q] = ldq<P>(in, g.Vp, q, j);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) w[q] = ldq<P>(W, g.Vp, cidx * 9 + q, i);
+      mv(w, v, y);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc[q] = cadd(acc[q], cscale(y[q], (R)sign));
+      // reflected corner: W_{-s}(x) psi(x - s) = W_s(x - s)^dag psi(x - s)
+      int ms[4] = {-s[0], -s[1], -s[2], -s[3]};
+      j = diag_nb(g, c, ms, sign);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) v[q] = ldq<P>(in, g.Vp, q, j);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) w[q] = ldq<P>(W, g.Vp, cidx * 9 + q, j);
+      mvd(w, v, y);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc[q] = cadd(acc[q], cscale(y[q], (R)sign));
+    }
+    const R mr = (R)(rhs_mass(a, k) + a.r);
+    const R gcoef = (R)(a.r * phi_sign(c) / 16.0);
+    const R dcoef = DAG ? (R)-0.5 : (R)0.5;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      C v = ldq<P>(in, g.Vp, q, i);
+      out[q] = csub(cadd(cscale(v, mr), cscale(d[q], dcoef)), cscale(acc[q], gcoef));
+    }
+  }
+};
+
+// On-the-fly form (K2): Gamma_55 psi(x) = phi(x)/24 F_{1234}(x) with
+// F_S(y) = sum_{mu in S} C_mu F_{S\mu}(y), evaluated depth-first inside the
+// 3^4 hypercube around x straight from the links.  C_mu = (V_mu + V_mu^dag)/2,
+// so each level carries a factor 1/2, collected once at the end (1/16).
+template <class P, int NL>
+__device__ __forceinline__ void apply_L(const OpArgs& a, int ysite, int mu, int sgn,
+                                        int nbsite, const typename P::C v[3],
+                                        typename P::C y[3]) {
+  // y = L(y, sgn*mu) v: U_mu(y) v (sgn > 0) or U_mu(y - mu)^dag v (sgn < 0)
+  using C = typename P::C;
+  C lk[9];
+  if (sgn > 0) {
+    load_link<P, NL>((const typename P::S*)a.links, a.g.Vp, mu, ysite, lk);
+    mv(lk, v, y);
+  } else {
+    load_link<P, NL>((const typename P::S*)a.links, a.g.Vp, mu, nbsite, lk);
+    mvd(lk, v, y);
+  }
+}
+
+__device__ __forceinline__ int step_site(const Geom& g, int y[4], int idx, int mu, int sgn,
+                                         int& sign) {
+  // move coordinates y by sgn*mu, return the new site index, update bc sign
+  int n = y[mu] + sgn;
+  if (n < 0) { n += g.L[mu]; idx += (g.L[mu] - 1) * g.stride[mu]; sign *= g.bc[mu]; }
+  else if (n >= g.L[mu]) { n -= g.L[mu]; idx -= (g.L[mu] - 1) * g.stride[mu]; sign *= g.bc[mu]; }
+  else idx += sgn * g.stride[mu];
+  y[mu] = n;
+  return idx;
+}
+
+template <class P, int NL>
+__device__ __noinline__ void gamma55_otf(const OpArgs& a, const typename P::S* __restrict__ in,
+                                         const Coord& c, int i, typename P::C out[3]) {
+  using C = typename P::C;
+  using R = typename P::R;
+  const Geom& g = a.g;
+  C acc4[3] = {czero<C>(), czero<C>(), czero<C>()};
+#pragma unroll 1
+  for (int d4 = 0; d4 < 8; ++d4) {
+    const int mu4 = d4 >> 1, s4 = (d4 & 1) ? -1 : 1;
+    int y3[4] = {c.x[0], c.x[1], c.x[2], c.x[3]};
+    int sg3 = 1;
+    const int i3 = step_site(g, y3, i, mu4, s4, sg3);
+    const int S3 = 15 ^ (1 << mu4);
+    C acc3[3] = {czero<C>(), czero<C>(), czero<C>()};
+#pragma unroll 1
+    for (int d3 = 0; d3 < 8; ++d3) {
+      const int mu3 = d3 >> 1, s3 = (d3 & 1) ? -1 : 1;
+      if (!((S3 >> mu3) & 1)) continue;
+      int y2[4] = {y3[0], y3[1], y3[2], y3[3]};
+      int sg2 = 1;
+      const int i2 = step_site(g, y2, i3, mu3, s3, sg2);
+      const int S2 = S3 ^ (1 << mu3);
+      C acc2[3] = {czero<C>(), czero<C>(), czero<C>()};
+#pragma unroll 1
+      for (int d2 = 0; d2 < 8; ++d2) {
+        const int mu2 = d2 >> 1, s2 = (d2 & 1) ? -1 : 1;
+        if (!((S2 >> mu2) & 1)) continue;
+        int y1[4] = {y2[0], y2[1], y2[2], y2[3]};
+        int sg1 = 1;
+        const int i1 = step_site(g, y1, i2, mu2, s2, sg1);
+        const int mu1 = __ffs(S2 ^ (1 << mu2)) - 1;
+        // level 1: C_mu1 psi at y1 (unnormalised: V + V^dag)
+        C acc1[3] = {czero<C>(), czero<C>(), czero<C>()};
+#pragma unroll
+        for (int s1 = 1; s1 >= -1; s1 -= 2) {
+          int y0[4] = {y1[0], y1[1], y1[2], y1[3]};
+          int sg0 = 1;
+          const int i0 = step_site(g, y0, i1, mu1, s1, sg0);
+          C v[3], y[3];
+#pragma unroll
+          for (int q = 0; q < 3; ++q) v[q] = ldq<P>(in, g.Vp, q, i0);
+          apply_L<P, NL>(a, i1, mu1, s1, i0, v, y);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) acc1[q] = cadd(acc1[q], cscale(y[q], (R)sg0));
+        }
+        C y[3];
+        apply_L<P, NL>(a, i2, mu2, s2, i1, acc1, y);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc2[q] = cadd(acc2[q], cscale(y[q], (R)sg1));
+      }
+      C y[3];
+      apply_L<P, NL>(a, i3, mu3, s3, i2, acc2, y);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc3[q] = cadd(acc3[q], cscale(y[q], (R)sg2));
+    }
+    C y[3];
+    apply_L<P, NL>(a, i, mu4, s4, i3, acc3, y);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc4[q] = cadd(acc4[q], cscale(y[q], (R)sg3));
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) out[q] = acc4[q];
+}
+
+template <class P, int NL, bool DAG>
+struct SWOtfOp {
+  using Pol = P;
+  static constexpr int NC = 3;
+  static constexpr int kWaves = P::id == 0 ? 3 : 4;
+  using C = typename P::C;
+  using R = typename P::R;
+  using S = typename P::S;
+
+  __device__ __forceinline__ static void site(const OpArgs& a, const S* __restrict__ in, int i,
+                                              int k, C out[3]) {
+    const Geom& g = a.g;
+    Coord c = site_coords(g, i);
+    C d[3], f[3];
+    dst_site<P, NL>(a, in, c, i, d);
+    gamma55_otf<P, NL>(a, in, c, i, f);
+    const R mr = (R)(rhs_mass(a, k) + a.r);
+    // phi/24 * (1/2)^4 from the four C_mu factors
+    const R gcoef = (R)(a.r * phi_sign(c) / (24.0 * 16.0));
+    const R dcoef = DAG ? (R)-0.5 : (R)0.5;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      C v = ldq<P>(in, g.Vp, q, i);
+      out[q] = csub(cadd(cscale(v, mr), cscale(d[q], dcoef)), cscale(f[q], gcoef));
+    }
+  }
+};
+
+}  // namespace lq

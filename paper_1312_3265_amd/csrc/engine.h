@@ -1,0 +1,143 @@
+// Host engine: lattice/gauge handles, workspace carving, the slot-based CG
+// engine and the Lanczos driver.  Everything here runs on the host and only
+// enqueues kernels; device memory always belongs to the caller.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/lq.h"
+#include "common.h"
+#include "dirac.h"
+#include "kernels.h"
+#include "lq_types.h"
+#include "stencil.h"
+
+namespace lq {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define LQ_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::lq::Error(LQ_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(LQ_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+// Bump allocator over a caller buffer (or a size-only dry run when base is null).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  void* take(size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+  size_t size() const { return (off + 255) & ~(size_t)255; }
+};
+
+inline size_t store_bytes(int prec) { return prec == P64 ? 16 : (prec == P32 ? 8 : 4); }
+inline int ncomp_of(int formulation) { return formulation == LQ_WILSON ? 12 : 3; }
+inline int opkind(int formulation, int g55) {
+  if (formulation == LQ_WILSON) return OP_WILSON;
+  return g55 == LQ_G55_ONTHEFLY ? OP_SW_OTF : OP_SW_CORNERS;
+}
+
+}  // namespace lq
+
+struct lq_lattice_s {
+  lq::Geom g;
+  int32_t dims[4];
+  int32_t bc[4];
+};
+
+struct lq_gauge_s {
+  lq::Geom g;
+  uint32_t features;
+  double2* u64 = nullptr;     // 18-real FP64 links
+  float2* u32_18 = nullptr;
+  float2* u32_12 = nullptr;
+  __half2* u16_12 = nullptr;
+  double2* c64 = nullptr;     // corners
+  float2* c32 = nullptr;
+  __half2* c16 = nullptr;
+  double* scratch = nullptr;  // plaquette partials + result
+  int nbp = 0;
+
+  const void* links(int prec, int nl) const;
+  const void* corners(int prec) const;
+};
+
+namespace lq {
+
+// Carves a gauge buffer; with base == nullptr only the size is computed.
+size_t gauge_layout(const Geom& g, uint32_t features, void* base, lq_gauge_s* out);
+
+// The slot-based CG engine (single solves, batched solves and serving).
+struct Engine {
+  const lq_gauge_s* gauge = nullptr;
+  int formulation = 0, op = 0, nc = 0;
+  double r = 1.0;
+  int nslots = 0;
+  int prec_lo = P64, nl_lo = 18;
+  int reliable_interval = 64, poll_every = 16, use_graph = 0, max_cand = 50;
+  int nbp = 0;
+  // device
+  double2 *b = nullptr, *xhi = nullptr, *rhi = nullptr, *t64 = nullptr;
+  void *xlo = nullptr, *rlo = nullptr, *p = nullptr, *t = nullptr;
+  double *part_t = nullptr, *part_r = nullptr, *part_u = nullptr;
+  SlotState* st = nullptr;
+  // host
+  SlotState* hst = nullptr;   // pinned mirror
+  int since_ru = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t gstream = nullptr;
+  int gchunk = 0;
+
+  static size_t workspace_bytes(const Geom& g, int formulation, const lq_solve_opts* opts,
+                                int nslots);
+  void init(const lq_gauge_s* g, int formulation, int g55, double r, int nslots,
+            const lq_solve_opts* opts, void* ws, size_t ws_bytes, hipStream_t s);
+  ~Engine();
+
+  void load(int slot, const void* chi, double mass, double tol, int maxiter, hipStream_t s);
+  // advance about `iters` iterations; returns after polling the slot states
+  void step(int iters, hipStream_t s);
+  void fetch(int slot, void* x, lq_solve_info* info, hipStream_t s);
+  int running() const;
+
+ private:
+  OpArgs op_args(int prec, int nl) const;
+  EpiArgs epi_base() const;
+  void enqueue_iterations(int n, hipStream_t s);
+  void enqueue_reliable_update(hipStream_t s);
+  void poll(hipStream_t s);
+  bool needs_update() const;
+};
+
+// Lanczos with full reorthogonalisation on A = M^dag M.
+size_t lanczos_workspace_bytes(const Geom& g, int formulation, int steps);
+int lanczos_run(const lq_gauge_s* g, const lq_dirac* d, int steps, const void* v0, void* ws,
+                size_t ws_bytes, std::vector<double>& alpha, std::vector<double>& beta,
+                hipStream_t s);
+// extreme eigenvalues of the symmetric tridiagonal (alpha, beta) by Sturm bisection
+void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b, double& lo,
+                      double& hi);
+
+}  // namespace lq

@@ -1,0 +1,466 @@
+// Host engine implementation: gauge layout, the slot-based CG engine and the
+// Lanczos driver (see engine.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "engine.h"
+
+const void* lq_gauge_s::links(int prec, int nl) const {
+  using namespace lq;
+  const void* p = nullptr;
+  if (prec == P64 && nl == 18) p = u64;
+  if (prec == P32 && nl == 18) p = u32_18;
+  if (prec == P32 && nl == 12) p = u32_12;
+  if (prec == P16 && nl == 12) p = u16_12;
+  if (!p)
+    throw Error(LQ_ERR_ARG, "gauge field was not built for precision " + std::to_string(prec) +
+                                " with " + std::to_string(nl) + "-real links (check features)");
+  return p;
+}
+
+const void* lq_gauge_s::corners(int prec) const {
+  using namespace lq;
+  const void* p = prec == P64 ? (const void*)c64 : prec == P32 ? (const void*)c32 : (const void*)c16;
+  if (!p)
+    throw Error(LQ_ERR_ARG, "gauge field has no corner matrices for precision " +
+                                std::to_string(prec) + " (LQ_FEAT_CORNERS)");
+  return p;
+}
+
+namespace lq {
+
+size_t gauge_layout(const Geom& g, uint32_t f, void* base, lq_gauge_s* out) {
+  Carver c(base);
+  const size_t Vp = g.Vp;
+  double2* u64 = (double2*)c.take(36 * Vp * 16);
+  float2 *u32_18 = nullptr, *u32_12 = nullptr, *c32 = nullptr;
+  __half2 *u16_12 = nullptr, *c16 = nullptr;
+  double2* c64 = nullptr;
+  if (f & LQ_FEAT_F32) {
+    u32_18 = (float2*)c.take(36 * Vp * 8);
+    u32_12 = (float2*)c.take(24 * Vp * 8);
+  }
+  if (f & LQ_FEAT_F16) u16_12 = (__half2*)c.take(24 * Vp * 4);
+  if (f & LQ_FEAT_CORNERS) {
+    c64 = (double2*)c.take(72 * Vp * 16);
+    if (f & LQ_FEAT_F32) c32 = (float2*)c.take(72 * Vp * 8);
+    if (f & LQ_FEAT_F16) c16 = (__half2*)c.take(72 * Vp * 4);
+  }
+  const int nbp = nbp_of(g.V);
+  double* scratch = (double*)c.take((nbp + 8) * sizeof(double));
+  if (out) {
+    out->g = g;
+    out->features = f;
+    out->u64 = u64; out->u32_18 = u32_18; out->u32_12 = u32_12; out->u16_12 = u16_12;
+    out->c64 = c64; out->c32 = c32; out->c16 = c16;
+    out->scratch = scratch;
+    out->nbp = nbp;
+  }
+  return c.size();
+}
+
+// ================================================================ Engine
+static int prec_of(const lq_solve_opts* o) { return o ? o->precision : LQ_PREC_F64; }
+
+size_t Engine::workspace_bytes(const Geom& g, int formulation, const lq_solve_opts* opts,
+                               int nslots) {
+  const int nc = ncomp_of(formulation);
+  const int prec = prec_of(opts);
+  const size_t vhi = (size_t)nslots * nc * g.Vp * 16;
+  const size_t vlo = (size_t)nslots * nc * g.Vp * store_bytes(prec);
+  const int nbp = nbp_of(g.V);
+  Carver c(nullptr);
+  c.take(vhi); c.take(vhi); c.take(vhi);      // b, x_hi, r_hi
+  if (prec != P64) c.take(vhi);               // t64 (shares t when FP64)
+  c.take(vlo); c.take(vlo); c.take(vlo); c.take(vlo);   // x_lo, r_lo, p, t
+  for (int k = 0; k < 3; ++k) c.take((size_t)nslots * nbp * sizeof(double));
+  c.take((size_t)nslots * sizeof(SlotState));
+  return c.size();
+}
+
+void Engine::init(const lq_gauge_s* g, int form, int g55, double rr, int ns,
+                  const lq_solve_opts* opts, void* ws, size_t ws_bytes, hipStream_t s) {
+  gauge = g;
+  formulation = form;
+  op = opkind(form, g55);
+  nc = ncomp_of(form);
+  r = rr;
+  nslots = ns;
+  prec_lo = prec_of(opts);
+  nl_lo = (opts && opts->links) ? opts->links : (prec_lo == P16 ? 12 : 18);
+  if (prec_lo == P64) nl_lo = 18;
+  if (opts) {
+    if (opts->reliable_interval > 0) reliable_interval = opts->reliable_interval;
+    if (opts->poll_interval > 0) poll_every = opts->poll_interval;
+    use_graph = opts->use_graph;
+    if (opts->max_restarts > 0) max_cand = opts->max_restarts;
+  }
+  poll_every = (poll_every + 1) & ~1;
+  if (poll_every < 2) poll_every = 2;
+  // validate the stencil storage now (throws for a missing feature)
+  (void)g->links(prec_lo, nl_lo);
+  (void)g->links(P64, 18);
+  if (op == OP_SW_CORNERS) { (void)g->corners(prec_lo); (void)g->corners(P64); }
+
+  const size_t need = workspace_bytes(g->g, form, opts, ns);
+  if (!ws || ws_bytes < need)
+    throw Error(LQ_ERR_WORKSPACE, "solver workspace too small: need " + std::to_string(need) +
+                                      " bytes, got " + std::to_string(ws_bytes));
+  nbp = nbp_of(g->g.V);
+  const size_t vhi = (size_t)ns * nc * g->g.Vp * 16;
+  const size_t vlo = (size_t)ns * nc * g->g.Vp * store_bytes(prec_lo);
+  Carver c(ws);
+  b = (double2*)c.take(vhi);
+  xhi = (double2*)c.take(vhi);
+  rhi = (double2*)c.take(vhi);
+  if (prec_lo != P64) t64 = (double2*)c.take(vhi);
+  xlo = c.take(vlo);
+  rlo = c.take(vlo);
+  p = c.take(vlo);
+  t = c.take(vlo);
+  if (prec_lo == P64) t64 = (double2*)t;
+  part_t = (double*)c.take((size_t)ns * nbp * sizeof(double));
+  part_r = (double*)c.take((size_t)ns * nbp * sizeof(double));
+  part_u = (double*)c.take((size_t)ns * nbp * sizeof(double));
+  st = (SlotState*)c.take((size_t)ns * sizeof(SlotState));
+  // zero the whole workspace once: plane padding stays zero afterwards
+  launch_fill_zero(ws, c.size(), s);
+  check_launch();
+  LQ_HIP(hipHostMalloc((void**)&hst, sizeof(SlotState) * ns, hipHostMallocDefault));
+  std::memset(hst, 0, sizeof(SlotState) * ns);
+  LQ_HIP(hipStreamSynchronize(s));
+}
+
+Engine::~Engine() {
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (hst) (void)hipHostFree(hst);
+}
+
+OpArgs Engine::op_args(int prec, int nl) const {
+  OpArgs a;
+  a.g = gauge->g;
+  a.links = gauge->links(prec, nl);
+  a.corners = op == OP_SW_CORNERS ? gauge->corners(prec) : nullptr;
+  a.r = r;
+  a.mass0 = 0.0;
+  a.mass = &st[0].mass;
+  a.mass_stride = sizeof(SlotState) / sizeof(double);
+  return a;
+}
+
+EpiArgs Engine::epi_base() const {
+  EpiArgs e;
+  std::memset(&e, 0, sizeof(e));
+  e.nbp = nbp;
+  e.st = st;
+  return e;
+}
+
+int Engine::running() const {
+  int n = 0;
+  for (int k = 0; k < nslots; ++k) n += hst[k].status == SLOT_RUNNING;
+  return n;
+}
+
+void Engine::load(int slot, const void* chi, double mass, double tol, int maxiter,
+                  hipStream_t s) {
+  if (slot < 0 || slot >= nslots) throw Error(LQ_ERR_ARG, "slot out of range");
+  if (!chi) throw Error(LQ_ERR_ARG, "null source");
+  if (!std::isfinite(mass) || !std::isfinite(tol) || tol <= 0.0 || maxiter <= 0)
+    throw Error(LQ_ERR_ARG, "mass and tol must be finite, tol > 0, maxiter > 0");
+  if (hst[slot].status == SLOT_RUNNING) throw Error(LQ_ERR_STATE, "slot is busy");
+  SlotState init;
+  std::memset(&init, 0, sizeof(init));
+  init.status = SLOT_RUNNING;
+  init.mass = mass;
+  init.tol = tol;
+  init.maxiter = maxiter;
+  init.scale = init.scale_prev = 1.0;
+  hst[slot] = init;
+  LQ_HIP(hipMemcpyAsync(st + slot, hst + slot, sizeof(SlotState), hipMemcpyHostToDevice, s));
+  const Geom& g = gauge->g;
+  // chi -> FP64 SoA (in t64), b = M^dag chi with ||b||^2
+  launch_field_in(P64, nc, g, chi, 1, t64, nbp, slot, 1, s);
+  EpiArgs e = epi_base();
+  e.out = b; e.part = part_u; e.k0 = slot; e.state_mode = 2;
+  launch_stencil(op, P64, 18, true, EPI_STORE_NORM, op_args(P64, 18), t64, e, 1, s);
+  launch_load_prepare(prec_lo, nc, g, (double*)xhi, xlo, (double*)rhi, (const double*)b, nbp, slot,
+                      1, s);
+  const double ncomp = (double)nc * g.V;
+  launch_ru_finish(st, part_u, nbp, slot, 1, ncomp, prec_lo != P64, max_cand, 1, 0, s);
+  launch_ru_convert(prec_lo, nc, g, st, (const double*)rhi, rlo, p, part_u, nbp, 1, slot, 1, s);
+  launch_ru_commit(st, part_u, nbp, slot, 1, s);
+  check_launch();
+  LQ_HIP(hipMemcpyAsync(hst + slot, st + slot, sizeof(SlotState), hipMemcpyDeviceToHost, s));
+  LQ_HIP(hipStreamSynchronize(s));
+}
+
+void Engine::enqueue_iterations(int n, hipStream_t s) {
+  const OpArgs oa = op_args(prec_lo, nl_lo);
+  for (int it = 0; it < n; ++it) {
+    const int par = it & 1;
+    EpiArgs e = epi_base();
+    e.par = par;
+    e.state_mode = 1;
+    e.out = t;
+    e.part = part_t;
+    launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
+    EpiArgs f = epi_base();
+    f.par = par;
+    f.state_mode = 1;
+    f.part = part_r;
+    f.part_in = part_t;
+    f.x = xlo; f.r = rlo; f.p = p;
+    launch_stencil(op, prec_lo, nl_lo, true, EPI_CG_UPDATE, oa, t, f, nslots, s);
+    launch_p_update(prec_lo, nc, gauge->g, st, par, part_r, nbp, p, rlo, 0, nslots, s);
+  }
+}
+
+void Engine::enqueue_reliable_update(hipStream_t s) {
+  const Geom& g = gauge->g;
+  const OpArgs oa = op_args(P64, 18);
+  launch_ru_accumulate(prec_lo, nc, g, st, (double*)xhi, xlo, nbp, 0, nslots, s);
+  EpiArgs e = epi_base();
+  e.state_mode = 2;
+  e.out = t64;
+  launch_stencil(op, P64, 18, false, EPI_STORE, oa, xhi, e, nslots, s);
+  EpiArgs f = epi_base();
+  f.state_mode = 2;
+  f.out = rhi;
+  f.b = b;
+  f.part = part_u;
+  launch_stencil(op, P64, 18, true, EPI_RESID, oa, t64, f, nslots, s);
+  launch_ru_finish(st, part_u, nbp, 0, nslots, (double)nc * g.V, prec_lo != P64, max_cand, 0, 0, s);
+  launch_ru_convert(prec_lo, nc, g, st, (const double*)rhi, rlo, p, part_u, nbp, 0, 0, nslots, s);
+  launch_ru_commit(st, part_u, nbp, 0, nslots, s);
+  check_launch();
+  since_ru = 0;
+}
+
+void Engine::poll(hipStream_t s) {
+  LQ_HIP(hipMemcpyAsync(hst, st, sizeof(SlotState) * nslots, hipMemcpyDeviceToHost, s));
+  LQ_HIP(hipStreamSynchronize(s));
+}
+
+bool Engine::needs_update() const {
+  for (int k = 0; k < nslots; ++k) {
+    const SlotState& h = hst[k];
+    if (h.status != SLOT_RUNNING) continue;
+    if (h.stop[0] || h.flags) return true;          // frozen: confirm or finalise
+    if (prec_lo != P64 && since_ru >= reliable_interval) return true;
+  }
+  return false;
+}
+
+void Engine::step(int iters, hipStream_t s) {
+  int done = 0;
+  while (done < iters) {
+    if (!running()) return;
+    if (needs_update()) {
+      enqueue_reliable_update(s);
+      poll(s);
+      if (!running()) return;
+    }
+    const int n = poll_every;
+    bool graphed = false;
+    if (use_graph && s != nullptr) {
+      if (!gexec || gchunk != n || gstream != s) {
+        if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
+        if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+        LQ_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+          enqueue_iterations(n, s);
+        } catch (...) {
+          hipGraph_t tmp;
+          (void)hipStreamEndCapture(s, &tmp);
+          if (tmp) (void)hipGraphDestroy(tmp);
+          throw;
+        }
+        LQ_HIP(hipStreamEndCapture(s, &graph));
+        LQ_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        gchunk = n;
+        gstream = s;
+      }
+      LQ_HIP(hipGraphLaunch(gexec, s));
+      graphed = true;
+    }
+    if (!graphed) enqueue_iterations(n, s);
+    check_launch();
+    since_ru += n;
+    done += n;
+    poll(s);
+  }
+  if (running() && needs_update()) {
+    enqueue_reliable_update(s);
+    poll(s);
+  }
+}
+
+void Engine::fetch(int slot, void* x, lq_solve_info* info, hipStream_t s) {
+  if (slot < 0 || slot >= nslots) throw Error(LQ_ERR_ARG, "slot out of range");
+  SlotState& h = hst[slot];
+  if (h.status == SLOT_EMPTY) throw Error(LQ_ERR_STATE, "slot is empty");
+  if (h.status == SLOT_RUNNING) throw Error(LQ_ERR_STATE, "slot is still running");
+  if (x) launch_field_out(P64, nc, gauge->g, xhi, x, 1, nbp, slot, 1, s);
+  check_launch();
+  if (info) {
+    const double bn = h.bnorm2 > 0 ? h.bnorm2 : 1.0;
+    info->status = h.status == SLOT_DONE ? LQ_OK
+                   : (h.flags & 1)       ? LQ_ERR_BREAKDOWN
+                                         : LQ_NOT_CONVERGED;
+    info->iterations = h.iter;
+    info->reliable_updates = h.ru;
+    info->applications = h.apps + 1;   // + b = M^dag chi
+    info->iterated_residual = std::sqrt(h.iter_res2 / bn);
+    info->true_residual = std::sqrt(h.true_res2 / bn);
+    info->seconds = 0.0;
+  }
+  h.status = SLOT_EMPTY;
+  LQ_HIP(hipMemcpyAsync(&st[slot].status, &h.status, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  LQ_HIP(hipStreamSynchronize(s));
+}
+
+// =============================================================== Lanczos
+static constexpr int kLzBlocks = 256;
+
+size_t lanczos_workspace_bytes(const Geom& g, int formulation, int steps) {
+  const int nc = ncomp_of(formulation);
+  const size_t vec = (size_t)nc * g.Vp * 16;
+  Carver c(nullptr);
+  c.take(vec * (steps + 1));                                // basis
+  c.take(vec);                                              // w
+  c.take(vec);                                              // t
+  c.take((size_t)(steps + 1) * 16);                         // h
+  c.take((size_t)(steps + 1) * kLzBlocks * 2 * 8);          // part_h
+  c.take((size_t)nbp_of(g.V) * 8);                          // alpha partials
+  c.take((size_t)kLzBlocks * 8);                            // norm partials
+  c.take((size_t)(steps + 2) * 8 * 2);                      // alpha, beta
+  return c.size();
+}
+
+int lanczos_run(const lq_gauge_s* gs, const lq_dirac* d, int steps, const void* v0, void* ws,
+                size_t ws_bytes, std::vector<double>& alpha, std::vector<double>& beta,
+                hipStream_t s) {
+  const Geom& g = gs->g;
+  const int nc = ncomp_of(d->formulation);
+  const int op = opkind(d->formulation, d->g55_mode);
+  if (steps < 1 || steps > 1000) throw Error(LQ_ERR_ARG, "steps must be in [1, 1000]");
+  const size_t need = lanczos_workspace_bytes(g, d->formulation, steps);
+  if (!ws || ws_bytes < need)
+    throw Error(LQ_ERR_WORKSPACE, "Lanczos workspace too small: need " + std::to_string(need));
+  const size_t n = (size_t)nc * g.Vp;
+  const size_t vec = n * 16;
+  Carver c(ws);
+  double2* V = (double2*)c.take(vec * (steps + 1));
+  double2* w = (double2*)c.take(vec);
+  double2* t = (double2*)c.take(vec);
+  double2* h = (double2*)c.take((size_t)(steps + 1) * 16);
+  double* part_h = (double*)c.take((size_t)(steps + 1) * kLzBlocks * 2 * 8);
+  const int nbp = nbp_of(g.V);
+  double* part_a = (double*)c.take((size_t)nbp * 8);
+  double* part_n = (double*)c.take((size_t)kLzBlocks * 8);
+  double* ad = (double*)c.take((size_t)(steps + 2) * 8 * 2);
+  double* bd = ad + steps + 2;
+  launch_fill_zero(ws, c.size(), s);
+
+  OpArgs oa;
+  oa.g = g;
+  oa.links = gs->links(P64, 18);
+  oa.corners = op == OP_SW_CORNERS ? gs->corners(P64) : nullptr;
+  oa.r = d->r;
+  oa.mass0 = d->mass;
+  oa.mass = nullptr;
+  oa.mass_stride = 0;
+
+  // v_1 = v0 / ||v0||
+  launch_field_in(P64, nc, g, v0, 1, w, nbp, 0, 1, s);
+  launch_lz_update(g, nc, V, 0, h, w, part_n, kLzBlocks, 1, s);
+  launch_lz_finish(part_n, kLzBlocks, bd + steps, s);
+  launch_lz_normalize(g, nc, w, bd + steps, V, s);
+  check_launch();
+  for (int j = 0; j < steps; ++j) {
+    double2* vj = V + (size_t)j * n;
+    EpiArgs e;
+    std::memset(&e, 0, sizeof(e));
+    e.nbp = nbp;
+    e.out = t;
+    launch_stencil(op, P64, 18, false, EPI_STORE, oa, vj, e, 1, s);
+    EpiArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.nbp = nbp;
+    f.out = w;
+    f.part = part_a;
+    f.v = (const double*)vj;
+    f.vprev = (const double*)(j > 0 ? vj - n : vj);
+    f.beta_prev = j > 0 ? bd + (j - 1) : nullptr;
+    launch_stencil(op, P64, 18, true, EPI_LANCZOS, oa, t, f, 1, s);
+    // w -= alpha v_j; two classical Gram-Schmidt passes against v_1..v_j
+    launch_lz_dots(g, nc, V, j + 1, w, part_a, nbp, ad + j, part_h, kLzBlocks, s);
+    launch_lz_reduce(part_h, j + 1, kLzBlocks, h, s);
+    launch_lz_update(g, nc, V, j + 1, h, w, part_n, kLzBlocks, 0, s);
+    launch_lz_dots(g, nc, V, j + 1, w, nullptr, 0, nullptr, part_h, kLzBlocks, s);
+    launch_lz_reduce(part_h, j + 1, kLzBlocks, h, s);
+    launch_lz_update(g, nc, V, j + 1, h, w, part_n, kLzBlocks, 1, s);
+    launch_lz_finish(part_n, kLzBlocks, bd + j, s);
+    if (j + 1 < steps) launch_lz_normalize(g, nc, w, bd + j, V + (size_t)(j + 1) * n, s);
+    check_launch();
+  }
+  std::vector<double> ha(steps), hb(steps);
+  LQ_HIP(hipMemcpyAsync(ha.data(), ad, steps * 8, hipMemcpyDeviceToHost, s));
+  LQ_HIP(hipMemcpyAsync(hb.data(), bd, steps * 8, hipMemcpyDeviceToHost, s));
+  LQ_HIP(hipStreamSynchronize(s));
+  // truncate at an invariant subspace (beta_j negligible), as the basis ends there
+  alpha.clear();
+  beta.clear();
+  for (int j = 0; j < steps; ++j) {
+    alpha.push_back(ha[j]);
+    if (j == steps - 1) break;
+    if (!(hb[j] > 1e-14 * std::fabs(ha[j]))) break;
+    beta.push_back(hb[j]);
+  }
+  for (double v : alpha)
+    if (!std::isfinite(v)) throw Error(LQ_ERR_BREAKDOWN, "Lanczos produced a non-finite alpha");
+  return (int)alpha.size();
+}
+
+// number of eigenvalues of tridiag(a, b) smaller than x (Sturm sequence)
+static int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double x) {
+  int cnt = 0;
+  double d = 1.0;
+  const double tiny = 1e-300;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+    d = a[i] - x - (i > 0 ? bb / d : 0.0);
+    if (d == 0.0) d = -tiny;
+    if (d < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+static double kth_eigenvalue(const std::vector<double>& a, const std::vector<double>& b, int k,
+                             double lo, double hi) {
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(a, b, mid) > k) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b, double& lo,
+                      double& hi) {
+  const size_t n = a.size();
+  double glo = a[0], ghi = a[0];
+  for (size_t i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(b[i]) : 0.0);
+    glo = std::min(glo, a[i] - r);
+    ghi = std::max(ghi, a[i] + r);
+  }
+  const double pad = 1e-12 * std::max(std::fabs(glo), std::fabs(ghi)) + 1e-300;
+  lo = kth_eigenvalue(a, b, 0, glo - pad, ghi + pad);
+  hi = kth_eigenvalue(a, b, (int)n - 1, glo - pad, ghi + pad);
+}
+
+}  // namespace lq

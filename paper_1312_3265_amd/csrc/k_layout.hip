@@ -1,0 +1,337 @@
+// Layout kernels: canonical <-> SoA repacking, link compression to 12 reals
+// (K6), the staggered Wilson corner matrices (K3) and the mean plaquette.
+#include <stdexcept>
+
+#include "kernels.h"
+#include "stencil.h"
+
+namespace lq {
+
+// ------------------------------------------------------------ fermions
+template <class P, int NC, bool F64SRC>
+__global__ void __launch_bounds__(256)
+field_in_kernel(const Geom g, const void* __restrict__ canon, typename P::S* __restrict__ soa,
+                int nbp, int k0, int nrhs) {
+  using C = typename P::C;
+  using R = typename P::R;
+  int sb, kl;
+  map_block(nbp, nrhs, sb, kl);
+  const int k = k0 + kl;
+  const int i = sb * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  const size_t cbase = ((size_t)kl * g.V + i) * NC;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    C v;
+    if constexpr (F64SRC) {
+      const double2 z = ((const double2*)canon)[cbase + q];
+      v.x = (R)z.x; v.y = (R)z.y;
+    } else {
+      const float2 z = ((const float2*)canon)[cbase + q];
+      v.x = (R)z.x; v.y = (R)z.y;
+    }
+    P::st(soa + ((size_t)k * NC + q) * g.Vp + i, v);
+  }
+}
+
+template <class P, int NC, bool F64DST>
+__global__ void __launch_bounds__(256)
+field_out_kernel(const Geom g, const typename P::S* __restrict__ soa, void* __restrict__ canon,
+                 int nbp, int k0, int nrhs) {
+  using C = typename P::C;
+  int sb, kl;
+  map_block(nbp, nrhs, sb, kl);
+  const int k = k0 + kl;
+  const int i = sb * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  const size_t cbase = ((size_t)kl * g.V + i) * NC;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const C v = P::ld(soa + ((size_t)k * NC + q) * g.Vp + i);
+    if constexpr (F64DST) ((double2*)canon)[cbase + q] = make_double2(v.x, v.y);
+    else ((float2*)canon)[cbase + q] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+#define LQ_PNC(prec, nc, CALL)                                                        \
+  do {                                                                                \
+    if (prec == P64 && nc == 12) { using PP = F64; constexpr int NCC = 12; CALL; }    \
+    else if (prec == P64 && nc == 3) { using PP = F64; constexpr int NCC = 3; CALL; }  \
+    else if (prec == P32 && nc == 12) { using PP = F32; constexpr int NCC = 12; CALL; } \
+    else if (prec == P32 && nc == 3) { using PP = F32; constexpr int NCC = 3; CALL; }  \
+    else if (prec == P16 && nc == 12) { using PP = F16; constexpr int NCC = 12; CALL; } \
+    else if (prec == P16 && nc == 3) { using PP = F16; constexpr int NCC = 3; CALL; }  \
+    else throw std::runtime_error("unsupported precision/components");                \
+  } while (0)
+
+void launch_field_in(int prec, int nc, const Geom& g, const void* canon, int canon_f64, void* soa,
+                     int nbp, int k0, int nrhs, hipStream_t s) {
+  if (nbp * nrhs == 0) return;
+  if (canon_f64)
+    LQ_PNC(prec, nc, hipLaunchKernelGGL((field_in_kernel<PP, NCC, true>), dim3(nbp * nrhs),
+                                        dim3(kBlock), 0, s, g, canon, (typename PP::S*)soa, nbp,
+                                        k0, nrhs));
+  else
+    LQ_PNC(prec, nc, hipLaunchKernelGGL((field_in_kernel<PP, NCC, false>), dim3(nbp * nrhs),
+                                        dim3(kBlock), 0, s, g, canon, (typename PP::S*)soa, nbp,
+                                        k0, nrhs));
+}
+
+void launch_field_out(int prec, int nc, const Geom& g, const void* soa, void* canon, int canon_f64,
+                      int nbp, int k0, int nrhs, hipStream_t s) {
+  if (nbp * nrhs == 0) return;
+  if (canon_f64)
+    LQ_PNC(prec, nc, hipLaunchKernelGGL((field_out_kernel<PP, NCC, true>), dim3(nbp * nrhs),
+                                        dim3(kBlock), 0, s, g, (const typename PP::S*)soa, canon,
+                                        nbp, k0, nrhs));
+  else
+    LQ_PNC(prec, nc, hipLaunchKernelGGL((field_out_kernel<PP, NCC, false>), dim3(nbp * nrhs),
+                                        dim3(kBlock), 0, s, g, (const typename PP::S*)soa, canon,
+                                        nbp, k0, nrhs));
+}
+
+// --------------------------------------------------------------- links
+__global__ void __launch_bounds__(256)
+gauge_in_kernel(const Geom g, const double2* __restrict__ canon, double2* __restrict__ u64) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+#pragma unroll 4
+  for (int q = 0; q < 36; ++q) u64[(size_t)q * g.Vp + i] = canon[(size_t)i * 36 + q];
+}
+
+void launch_gauge_in(const Geom& g, const void* canon, double2* u64, hipStream_t s) {
+  hipLaunchKernelGGL(gauge_in_kernel, dim3((g.V + 255) / 256), dim3(256), 0, s, g,
+                     (const double2*)canon, u64);
+}
+
+// FP64 18-real -> precision P with NL reals (12: rows 0 and 1 only)
+template <class P, int NL>
+__global__ void __launch_bounds__(256)
+links_convert_kernel(const Geom g, const double2* __restrict__ u64, typename P::S* __restrict__ dst) {
+  using C = typename P::C;
+  using R = typename P::R;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  constexpr int rows = NL / 6;
+  for (int mu = 0; mu < 4; ++mu)
+    for (int a = 0; a < rows; ++a)
+      for (int b = 0; b < 3; ++b) {
+        const double2 z = u64[(size_t)((mu * 3 + a) * 3 + b) * g.Vp + i];
+        C v; v.x = (R)z.x; v.y = (R)z.y;
+        P::st(dst + (size_t)((mu * rows + a) * 3 + b) * g.Vp + i, v);
+      }
+}
+
+void launch_links_convert(int prec, int nl, const Geom& g, const double2* u64, void* dst,
+                          hipStream_t s) {
+  dim3 grid((g.V + 255) / 256), blk(256);
+  if (prec == P32 && nl == 18)
+    hipLaunchKernelGGL((links_convert_kernel<F32, 18>), grid, blk, 0, s, g, u64, (float2*)dst);
+  else if (prec == P32 && nl == 12)
+    hipLaunchKernelGGL((links_convert_kernel<F32, 12>), grid, blk, 0, s, g, u64, (float2*)dst);
+  else if (prec == P16 && nl == 12)
+    hipLaunchKernelGGL((links_convert_kernel<F16, 12>), grid, blk, 0, s, g, u64, (__half2*)dst);
+  else
+    throw std::runtime_error("links_convert: unsupported precision/storage");
+}
+
+// ---------------------------------------------------------- corners (K3)
+// W_s(x) = (1/24) sum over the 24 orderings of the path products from x to
+// x + s taking one link per direction.  With pt(T) = x + sum_{nu in T} s_nu nu
+// and P(T) = sum of the products along all orderings of the directions in T,
+//   P(T) = sum_{mu in T} P(T \ mu) L(pt(T \ mu), s_mu mu),   P({}) = 1,
+// where L(y, +mu) = U_mu(y) and L(y, -mu) = U_mu(y - mu)^dag.  Level 2 is
+// rebuilt inside level 3 (40 matrix products per corner, no large live state).
+struct M3 { double2 e[9]; };
+
+__device__ __forceinline__ void m3_load(const double2* __restrict__ u, int Vp, int mu, int site,
+                                        bool dag, M3& m) {
+  if (!dag) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m.e[k] = u[(size_t)(mu * 9 + k) * Vp + site];
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) m.e[a * 3 + b] = cconj(u[(size_t)(mu * 9 + b * 3 + a) * Vp + site]);
+  }
+}
+
+__device__ __forceinline__ void m3_mul_acc(const M3& a, const M3& b, M3& acc) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double2 s = acc.e[i * 3 + j];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s = cfma(a.e[i * 3 + k], b.e[k * 3 + j], s);
+      acc.e[i * 3 + j] = s;
+    }
+}
+
+__device__ __forceinline__ void m3_zero(M3& m) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) m.e[k] = make_double2(0.0, 0.0);
+}
+
+// site index of x + offset (each offset component in {-1, 0, 1}), periodic
+__device__ __forceinline__ int offset_site(const Geom& g, const Coord& c, const int o[4]) {
+  int j = 0;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    int y = c.x[mu] + o[mu];
+    if (y < 0) y += g.L[mu];
+    else if (y >= g.L[mu]) y -= g.L[mu];
+    j += y * g.stride[mu];
+  }
+  return j;
+}
+
+// link L(pt, s_mu mu) for the point pt = x + sum_{nu in T} s_nu nu
+__device__ __forceinline__ void path_link(const Geom& g, const double2* __restrict__ u,
+                                          const Coord& c, const int s[4], int T, int mu, M3& m) {
+  int o[4];
+#pragma unroll
+  for (int nu = 0; nu < 4; ++nu) o[nu] = ((T >> nu) & 1) ? s[nu] : 0;
+  if (s[mu] > 0) {
+    m3_load(u, g.Vp, mu, offset_site(g, c, o), false, m);
+  } else {
+    o[mu] -= 1;
+    m3_load(u, g.Vp, mu, offset_site(g, c, o), true, m);
+  }
+}
+
+__global__ void __launch_bounds__(64)
+corners_kernel(const Geom g, const double2* __restrict__ u, double2* __restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cidx = blockIdx.y;
+  if (i >= g.V) return;
+  const Coord c = site_coords(g, i);
+  const int s[4] = {(cidx & 1) ? -1 : 1, (cidx & 2) ? -1 : 1, (cidx & 4) ? -1 : 1, 1};
+  M3 p4;
+  m3_zero(p4);
+#pragma unroll 1
+  for (int mu4 = 0; mu4 < 4; ++mu4) {
+    const int T3 = 15 ^ (1 << mu4);
+    M3 p3;
+    m3_zero(p3);
+#pragma unroll 1
+    for (int mu3 = 0; mu3 < 4; ++mu3) {
+      if (!((T3 >> mu3) & 1)) continue;
+      const int T2 = T3 ^ (1 << mu3);
+      // P(T2) for T2 = {a, b}: L(x, a) L(x + a, b) + L(x, b) L(x + b, a)
+      const int a = __ffs(T2) - 1;
+      const int b = __ffs(T2 ^ (1 << a)) - 1;
+      M3 p2, l1, l2;
+      m3_zero(p2);
+      path_link(g, u, c, s, 0, a, l1);
+      path_link(g, u, c, s, 1 << a, b, l2);
+      m3_mul_acc(l1, l2, p2);
+      path_link(g, u, c, s, 0, b, l1);
+      path_link(g, u, c, s, 1 << b, a, l2);
+      m3_mul_acc(l1, l2, p2);
+      path_link(g, u, c, s, T2, mu3, l1);
+      m3_mul_acc(p2, l1, p3);
+    }
+    M3 l;
+    path_link(g, u, c, s, T3, mu4, l);
+    m3_mul_acc(p3, l, p4);
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+    w[(size_t)(cidx * 9 + k) * g.Vp + i] = make_double2(p4.e[k].x / 24.0, p4.e[k].y / 24.0);
+}
+
+void launch_corners(const Geom& g, const double2* u64, double2* c64, hipStream_t s) {
+  hipLaunchKernelGGL(corners_kernel, dim3((g.V + 63) / 64, 8), dim3(64), 0, s, g, u64, c64);
+}
+
+template <class P>
+__global__ void __launch_bounds__(256)
+corners_convert_kernel(const Geom g, const double2* __restrict__ c64, typename P::S* __restrict__ dst) {
+  using C = typename P::C;
+  using R = typename P::R;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  for (int q = 0; q < 72; ++q) {
+    const double2 z = c64[(size_t)q * g.Vp + i];
+    C v; v.x = (R)z.x; v.y = (R)z.y;
+    P::st(dst + (size_t)q * g.Vp + i, v);
+  }
+}
+
+void launch_corners_convert(int prec, const Geom& g, const double2* c64, void* dst, hipStream_t s) {
+  dim3 grid((g.V + 255) / 256), blk(256);
+  if (prec == P32)
+    hipLaunchKernelGGL(corners_convert_kernel<F32>, grid, blk, 0, s, g, c64, (float2*)dst);
+  else if (prec == P16)
+    hipLaunchKernelGGL(corners_convert_kernel<F16>, grid, blk, 0, s, g, c64, (__half2*)dst);
+  else
+    throw std::runtime_error("corners_convert: unsupported precision");
+}
+
+// ------------------------------------------------------------ plaquette
+// (1/3) Re tr U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag summed over mu < nu.
+__global__ void __launch_bounds__(256)
+plaquette_kernel(const Geom g, const double2* __restrict__ u, double* __restrict__ part) {
+  __shared__ double red[16];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (i < g.V) {
+    const Coord c = site_coords(g, i);
+    for (int mu = 0; mu < 4; ++mu)
+      for (int nu = mu + 1; nu < 4; ++nu) {
+        bool w;
+        const int xm = nb_fwd(g, c, i, mu, w);
+        const int xn = nb_fwd(g, c, i, nu, w);
+        M3 a, b, cc, d, ab, abc;
+        m3_load(u, g.Vp, mu, i, false, a);
+        m3_load(u, g.Vp, nu, xm, false, b);
+        m3_load(u, g.Vp, mu, xn, true, cc);
+        m3_load(u, g.Vp, nu, i, true, d);
+        m3_zero(ab);
+        m3_mul_acc(a, b, ab);
+        m3_zero(abc);
+        m3_mul_acc(ab, cc, abc);
+        double tr = 0.0;
+        for (int p = 0; p < 3; ++p)
+          for (int k = 0; k < 3; ++k) tr += abc.e[p * 3 + k].x * d.e[k * 3 + p].x - abc.e[p * 3 + k].y * d.e[k * 3 + p].y;
+        acc += tr / 3.0;
+      }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void plaquette_finish_kernel(const double* __restrict__ part, int n, double V,
+                                        double* out) {
+  __shared__ double red[16];
+  const double s = sum_partials(part, n, red);
+  if (threadIdx.x == 0) *out = s / (6.0 * V);
+}
+
+void launch_plaquette(const Geom& g, const double2* u64, double* part, int nbp, double* out,
+                      hipStream_t s) {
+  const int nb = (g.V + 255) / 256;
+  (void)nbp;
+  hipLaunchKernelGGL(plaquette_kernel, dim3(nb), dim3(256), 0, s, g, u64, part);
+  hipLaunchKernelGGL(plaquette_finish_kernel, dim3(1), dim3(64), 0, s, part, nb, (double)g.V, out);
+}
+
+// ------------------------------------------------------------- filling
+__global__ void fill_zero_kernel(uint4* __restrict__ p, size_t n16) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n16;
+       e += (size_t)gridDim.x * blockDim.x)
+    p[e] = make_uint4(0, 0, 0, 0);
+}
+
+void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  // callers pass 16-byte aligned, 16-byte multiple regions
+  const size_t n16 = bytes / 16;
+  if (n16 == 0) return;
+  size_t blocks = (n16 + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (uint4*)p, n16);
+}
+
+}  // namespace lq

@@ -1,0 +1,9 @@
+// Stencil kernel instantiations for SWOtfOp.
+#include "stencil_dispatch.h"
+
+namespace lq {
+void launch_stencil_otf(int prec, int nl, bool dag, int epi, const OpArgs& oa, const void* in,
+          const EpiArgs& ea, int nrhs, hipStream_t s) {
+  dispatch_prec<SWOtfOp>(prec, nl, dag, epi, oa, in, ea, nrhs, s);
+}
+}  // namespace lq

@@ -1,0 +1,419 @@
+// CG vector kernels (p update, reliable updates, slot loading), the Lanczos
+// vector kernels, and the stencil launch dispatcher.
+//
+// CG on eq. (2) per system (x0 = 0), with the low-precision vectors held in
+// units of a per-system scale s (true value = s * stored value):
+//   t = M p;  alpha = rho / ||t||^2  (= rho / <p, A p>);  x_lo += alpha p;
+//   r_lo -= alpha M^dag t;  rho' = ||r_lo||^2;  p = r_lo + (rho'/rho) p.
+// A reliable update recomputes the residual in FP64:
+//   x_hi += s x_lo; x_lo = 0; r_hi = b - M^dag M x_hi; s' = ||r_hi|| / sqrt(N);
+//   r_lo = r_hi / s'; p *= s / s'; rho = ||r_lo||^2.
+// The system is converged when ||r_hi|| <= tol ||b||.  With FP64 storage the
+// scale stays 1 and reliable updates happen only to confirm convergence.
+#include <stdexcept>
+#include <string>
+
+#include "kernels.h"
+#include "stencil.h"
+
+namespace lq {
+
+void launch_stencil_wilson(int, int, bool, int, const OpArgs&, const void*, const EpiArgs&, int,
+                           hipStream_t);
+void launch_stencil_sw(int, int, bool, int, const OpArgs&, const void*, const EpiArgs&, int,
+                       hipStream_t);
+void launch_stencil_otf(int, int, bool, int, const OpArgs&, const void*, const EpiArgs&, int,
+                        hipStream_t);
+
+void launch_stencil(int op, int prec, int nl, bool dag, int epi, const OpArgs& oa, const void* in,
+                    const EpiArgs& ea, int nrhs, hipStream_t s) {
+  switch (op) {
+    case OP_WILSON: return launch_stencil_wilson(prec, nl, dag, epi, oa, in, ea, nrhs, s);
+    case OP_SW_CORNERS: return launch_stencil_sw(prec, nl, dag, epi, oa, in, ea, nrhs, s);
+    case OP_SW_OTF: return launch_stencil_otf(prec, nl, dag, epi, oa, in, ea, nrhs, s);
+    default: throw std::runtime_error("unknown operator " + std::to_string(op));
+  }
+}
+
+// ------------------------------------------------------------- p update
+template <class P, int NC>
+__global__ void __launch_bounds__(256)
+p_update_kernel(const Geom g, SlotState* st, int par, const double* __restrict__ part, int nbp,
+                typename P::S* __restrict__ p, const typename P::S* __restrict__ r, int k0,
+                int nrhs) {
+  using C = typename P::C;
+  using R = typename P::R;
+  __shared__ double red[16];
+  int sb, kl;
+  map_block(nbp, nrhs, sb, kl);
+  const int k = k0 + kl;
+  SlotState* s = st + k;
+  if (s->status != SLOT_RUNNING) return;
+  if (s->stop[par]) {
+    // frozen: carry the state into the next parity entry
+    if (sb == 0 && threadIdx.x == 0) {
+      s->stop[par ^ 1] = 1;
+      s->rho[par ^ 1] = s->rho[par];
+    }
+    return;
+  }
+  const double rr = sum_partials(part + (size_t)k * nbp, nbp, red);
+  const double rho = s->rho[par];
+  const double beta = (rho > 0.0 && isfinite(rr)) ? rr / rho : 0.0;
+  const int i = sb * blockDim.x + threadIdx.x;
+  if (i < g.V) {
+    const size_t off = (size_t)k * NC * g.Vp;
+    const R bt = (R)beta;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const size_t e = off + (size_t)q * g.Vp + i;
+      C pv = P::ld(p + e), rv = P::ld(r + e);
+      pv.x = rv.x + bt * pv.x;
+      pv.y = rv.y + bt * pv.y;
+      P::st(p + e, pv);
+    }
+  }
+  if (sb == 0 && threadIdx.x == 0) {
+    s->rho[par ^ 1] = rr;
+    s->iter += 1;
+    s->apps += 1;
+    s->iter_res2 = rr * s->scale * s->scale;
+    int stop = 0;
+    if (!isfinite(rr) || (s->flags & 1)) { s->flags |= 1; stop = 1; }
+    if (rr <= s->thr_lo2) stop = 1;
+    if (s->iter >= s->maxiter) { s->flags |= 2; stop = 1; }
+    s->stop[par ^ 1] = stop;
+  }
+}
+
+// ------------------------------------------------------- reliable updates
+template <class P, int NC>
+__global__ void __launch_bounds__(256)
+ru_accumulate_kernel(const Geom g, const SlotState* st, double2* __restrict__ xhi,
+                     typename P::S* __restrict__ xlo, int nbp, int k0, int nrhs) {
+  using C = typename P::C;
+  int sb, kl;
+  map_block(nbp, nrhs, sb, kl);
+  const int k = k0 + kl;
+  if (st[k].status != SLOT_RUNNING) return;
+  const double sc = st[k].scale;
+  const int i = sb * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  const size_t off = (size_t)k * NC * g.Vp;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const size_t e = off + (size_t)q * g.Vp + i;
+    C v = P::ld(xlo + e);
+    double2 h = xhi[e];
+    h.x += sc * (double)v.x;
+    h.y += sc * (double)v.y;
+    xhi[e] = h;
+    P::st(xlo + e, czero<C>());
+  }
+}
+
+__global__ void ru_finish_kernel(SlotState* st, const double* __restrict__ part, int nbp, int k0,
+                                 double ncomp, int rescale, int max_cand, int init, int par) {
+  __shared__ double red[16];
+  const int k = k0 + blockIdx.x;
+  SlotState* s = st + k;
+  if (s->status != SLOT_RUNNING) return;
+  const double rr = sum_partials(part + (size_t)k * nbp, nbp, red);
+  if (threadIdx.x != 0) return;
+  if (init) {
+    s->bnorm2 = rr;
+    s->thr2 = s->tol * s->tol * rr;
+  } else {
+    s->ru += 1;
+    s->apps += 1;
+  }
+  s->true_res2 = rr;
+  if (!isfinite(rr)) { s->flags |= 1; s->status = SLOT_FAILED; return; }
+  if (rr <= s->thr2) { s->status = SLOT_DONE; return; }
+  if (s->flags) { s->status = SLOT_FAILED; return; }
+  if (!init && s->stop[par]) {
+    // the iterated residual met tol but the true residual did not
+    s->cand += 1;
+    if (s->cand > max_cand) { s->flags |= 4; s->status = SLOT_FAILED; return; }
+  }
+  double sn = rescale ? sqrt(rr / ncomp) : 1.0;
+  if (!(sn > 0.0) || !isfinite(sn)) sn = 1.0;
+  s->scale_prev = init ? sn : s->scale;
+  s->scale = sn;
+  s->thr_lo2 = s->thr2 / (sn * sn);
+}
+
+template <class P, int NC>
+__global__ void __launch_bounds__(256)
+ru_convert_kernel(const Geom g, const SlotState* st, const double2* __restrict__ rhi,
+                  typename P::S* __restrict__ rlo, typename P::S* __restrict__ p,
+                  double* __restrict__ part, int nbp, int init, int k0, int nrhs) {
+  using C = typename P::C;
+  using R = typename P::R;
+  __shared__ double red[16];
+  int sb, kl;
+  map_block(nbp, nrhs, sb, kl);
+  const int k = k0 + kl;
+  if (st[k].status != SLOT_RUNNING) return;
+  const double inv = 1.0 / st[k].scale;
+  const R pr = (R)(st[k].scale_prev / st[k].scale);
+  const int i = sb * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (i < g.V) {
+    const size_t off = (size_t)k * NC * g.Vp;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const size_t e = off + (size_t)q * g.Vp + i;
+      const double2 h = rhi[e];
+      C v;
+      v.x = (R)(h.x * inv);
+      v.y = (R)(h.y * inv);
+      P::st(rlo + e, v);
+      const C vs = P::ld(rlo + e);
+      acc += cnorm2(vs);
+      if (init) {
+        P::st(p + e, vs);
+      } else {
+        C pv = P::ld(p + e);
+        pv.x *= pr;
+        pv.y *= pr;
+        P::st(p + e, pv);
+      }
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) part[(size_t)k * nbp + sb] = s;
+}
+
+__global__ void ru_commit_kernel(SlotState* st, const double* __restrict__ part, int nbp, int k0) {
+  __shared__ double red[16];
+  const int k = k0 + blockIdx.x;
+  SlotState* s = st + k;
+  if (s->status != SLOT_RUNNING) return;
+  const double rr = sum_partials(part + (size_t)k * nbp, nbp, red);
+  if (threadIdx.x != 0) return;
+  s->rho[0] = s->rho[1] = rr;
+  s->stop[0] = s->stop[1] = 0;
+  s->iter_res2 = rr * s->scale * s->scale;
+}
+
+template <class P, int NC>
+__global__ void __launch_bounds__(256)
+load_prepare_kernel(const Geom g, double2* __restrict__ xhi, typename P::S* __restrict__ xlo,
+                    double2* __restrict__ rhi, const double2* __restrict__ b, int nbp, int k0,
+                    int nrhs) {
+  using C = typename P::C;
+  int sb, kl;
+  map_block(nbp, nrhs, sb, kl);
+  const int k = k0 + kl;
+  const int i = sb * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  const size_t off = (size_t)k * NC * g.Vp;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const size_t e = off + (size_t)q * g.Vp + i;
+    xhi[e] = make_double2(0.0, 0.0);
+    P::st(xlo + e, czero<C>());
+    rhi[e] = b[e];
+  }
+}
+
+// ----------------------------------------------------------- dispatch
+#define LQ_PREC_NC_SWITCH(prec, nc, CALL)                                            \
+  do {                                                                               \
+    if (prec == P64 && nc == 12) { using PP = F64; constexpr int NCC = 12; CALL; }   \
+    else if (prec == P64 && nc == 3) { using PP = F64; constexpr int NCC = 3; CALL; } \
+    else if (prec == P32 && nc == 12) { using PP = F32; constexpr int NCC = 12; CALL; } \
+    else if (prec == P32 && nc == 3) { using PP = F32; constexpr int NCC = 3; CALL; }  \
+    else if (prec == P16 && nc == 12) { using PP = F16; constexpr int NCC = 12; CALL; } \
+    else if (prec == P16 && nc == 3) { using PP = F16; constexpr int NCC = 3; CALL; }  \
+    else throw std::runtime_error("unsupported precision/components");               \
+  } while (0)
+
+void launch_p_update(int prec, int nc, const Geom& g, SlotState* st, int par, const double* part,
+                     int nbp, void* p, const void* r, int k0, int nrhs, hipStream_t s) {
+  if (nbp * nrhs == 0) return;
+  LQ_PREC_NC_SWITCH(prec, nc,
+                    hipLaunchKernelGGL((p_update_kernel<PP, NCC>), dim3(nbp * nrhs), dim3(kBlock),
+                                       0, s, g, st, par, part, nbp, (typename PP::S*)p,
+                                       (const typename PP::S*)r, k0, nrhs));
+}
+
+void launch_ru_accumulate(int prec, int nc, const Geom& g, const SlotState* st, double* xhi,
+                          void* xlo, int nbp, int k0, int nrhs, hipStream_t s) {
+  if (nbp * nrhs == 0) return;
+  LQ_PREC_NC_SWITCH(prec, nc,
+                    hipLaunchKernelGGL((ru_accumulate_kernel<PP, NCC>), dim3(nbp * nrhs),
+                                       dim3(kBlock), 0, s, g, st, (double2*)xhi,
+                                       (typename PP::S*)xlo, nbp, k0, nrhs));
+}
+
+void launch_ru_finish(SlotState* st, const double* part, int nbp, int k0, int nrhs, double ncomp,
+                      int rescale, int max_cand, int init, int par, hipStream_t s) {
+  if (nrhs == 0) return;
+  hipLaunchKernelGGL(ru_finish_kernel, dim3(nrhs), dim3(64), 0, s, st, part, nbp, k0, ncomp,
+                     rescale, max_cand, init, par);
+}
+
+void launch_ru_convert(int prec, int nc, const Geom& g, const SlotState* st, const double* rhi,
+                       void* rlo, void* p, double* part, int nbp, int init, int k0, int nrhs,
+                       hipStream_t s) {
+  if (nbp * nrhs == 0) return;
+  LQ_PREC_NC_SWITCH(prec, nc,
+                    hipLaunchKernelGGL((ru_convert_kernel<PP, NCC>), dim3(nbp * nrhs),
+                                       dim3(kBlock), 0, s, g, st, (const double2*)rhi,
+                                       (typename PP::S*)rlo, (typename PP::S*)p, part, nbp, init,
+                                       k0, nrhs));
+}
+
+void launch_ru_commit(SlotState* st, const double* part, int nbp, int k0, int nrhs,
+                      hipStream_t s) {
+  if (nrhs == 0) return;
+  hipLaunchKernelGGL(ru_commit_kernel, dim3(nrhs), dim3(64), 0, s, st, part, nbp, k0);
+}
+
+void launch_load_prepare(int prec, int nc, const Geom& g, double* xhi, void* xlo, double* rhi,
+                         const double* b, int nbp, int k0, int nrhs, hipStream_t s) {
+  if (nbp * nrhs == 0) return;
+  LQ_PREC_NC_SWITCH(prec, nc,
+                    hipLaunchKernelGGL((load_prepare_kernel<PP, NCC>), dim3(nbp * nrhs),
+                                       dim3(kBlock), 0, s, g, (double2*)xhi, (typename PP::S*)xlo,
+                                       (double2*)rhi, (const double2*)b, nbp, k0, nrhs));
+}
+
+// ------------------------------------------------------------- Lanczos
+// Basis V (nvec vectors of nc*Vp complex), work vector w.  Classical
+// Gram-Schmidt: h = V^H w (lz_dots + lz_reduce), w -= V h (lz_update).
+constexpr int kDotChunk = 8;
+
+__global__ void __launch_bounds__(256)
+lz_dots_kernel(const Geom g, int nc, const double2* __restrict__ V, int nvec, double2* w,
+               const double* __restrict__ alpha_part, int nbp_alpha, double* alpha_out,
+               double* __restrict__ part_h, int nblk) {
+  __shared__ double red[16];
+  const size_t n = (size_t)nc * g.Vp;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  if (alpha_part) {
+    // w -= alpha v_j with alpha = Re<v_j, A v_j - beta v_{j-1}>, v_j = V[nvec-1]
+    const double a = sum_partials(alpha_part, nbp_alpha, red);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *alpha_out = a;
+    const double2* vj = V + (size_t)(nvec - 1) * n;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+      double2 x = w[e];
+      x.x -= a * vj[e].x;
+      x.y -= a * vj[e].y;
+      w[e] = x;
+    }
+    __syncthreads();
+  }
+  for (int k0 = 0; k0 < nvec; k0 += kDotChunk) {
+    double re[kDotChunk], im[kDotChunk];
+#pragma unroll
+    for (int c = 0; c < kDotChunk; ++c) re[c] = im[c] = 0.0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+      const double2 x = w[e];
+#pragma unroll
+      for (int c = 0; c < kDotChunk; ++c) {
+        if (k0 + c < nvec) {
+          const double2 v = V[(size_t)(k0 + c) * n + e];
+          re[c] += v.x * x.x + v.y * x.y;
+          im[c] += v.x * x.y - v.y * x.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kDotChunk; ++c) {
+      if (k0 + c < nvec) {
+        const double sr = block_sum(re[c], red);
+        const double si = block_sum(im[c], red);
+        if (threadIdx.x == 0) {
+          part_h[((size_t)(k0 + c) * nblk + blockIdx.x) * 2 + 0] = sr;
+          part_h[((size_t)(k0 + c) * nblk + blockIdx.x) * 2 + 1] = si;
+        }
+      }
+    }
+  }
+}
+
+__global__ void lz_reduce_kernel(const double* __restrict__ part_h, int nvec, int nblk,
+                                 double2* __restrict__ h) {
+  for (int k = threadIdx.x; k < nvec; k += blockDim.x) {
+    double sr = 0.0, si = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+      sr += part_h[((size_t)k * nblk + b) * 2 + 0];
+      si += part_h[((size_t)k * nblk + b) * 2 + 1];
+    }
+    h[k] = make_double2(sr, si);
+  }
+}
+
+__global__ void __launch_bounds__(256)
+lz_update_kernel(const Geom g, int nc, const double2* __restrict__ V, int nvec,
+                 const double2* __restrict__ h, double2* w, double* __restrict__ part_n,
+                 int with_norm) {
+  __shared__ double red[16];
+  __shared__ double2 hs[1024];
+  for (int k = threadIdx.x; k < nvec && k < 1024; k += blockDim.x) hs[k] = h[k];
+  __syncthreads();
+  const size_t n = (size_t)nc * g.Vp;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  double acc = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    double2 x = w[e];
+    for (int k = 0; k < nvec; ++k) {
+      const double2 v = V[(size_t)k * n + e];
+      const double2 c = hs[k];
+      x.x -= v.x * c.x - v.y * c.y;
+      x.y -= v.x * c.y + v.y * c.x;
+    }
+    w[e] = x;
+    acc += x.x * x.x + x.y * x.y;
+  }
+  if (with_norm) {
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) part_n[blockIdx.x] = s;
+  }
+}
+
+__global__ void lz_finish_kernel(const double* __restrict__ part_n, int nblk, double* beta_out) {
+  __shared__ double red[16];
+  const double s = sum_partials(part_n, nblk, red);
+  if (threadIdx.x == 0) *beta_out = sqrt(s);
+}
+
+__global__ void __launch_bounds__(256)
+lz_normalize_kernel(const Geom g, int nc, const double2* __restrict__ w,
+                    const double* __restrict__ beta, double2* __restrict__ vnext) {
+  const size_t n = (size_t)nc * g.Vp;
+  const double bt = *beta;
+  const double inv = (bt > 1e-300 && isfinite(bt)) ? 1.0 / bt : 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const double2 x = w[e];
+    vnext[e] = make_double2(x.x * inv, x.y * inv);
+  }
+}
+
+void launch_lz_dots(const Geom& g, int nc, const double2* V, int nvec, double2* w,
+                    const double* alpha_part, int nbp_alpha, double* alpha_out, double* part_h,
+                    int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(lz_dots_kernel, dim3(nblk), dim3(kBlock), 0, s, g, nc, V, nvec, w,
+                     alpha_part, nbp_alpha, alpha_out, part_h, nblk);
+}
+void launch_lz_reduce(const double* part_h, int nvec, int nblk, double2* h, hipStream_t s) {
+  hipLaunchKernelGGL(lz_reduce_kernel, dim3(1), dim3(256), 0, s, part_h, nvec, nblk, h);
+}
+void launch_lz_update(const Geom& g, int nc, const double2* V, int nvec, const double2* h,
+                      double2* w, double* part_n, int nblk, int with_norm, hipStream_t s) {
+  hipLaunchKernelGGL(lz_update_kernel, dim3(nblk), dim3(kBlock), 0, s, g, nc, V, nvec, h, w,
+                     part_n, with_norm);
+}
+void launch_lz_finish(const double* part_n, int nblk, double* beta_out, hipStream_t s) {
+  hipLaunchKernelGGL(lz_finish_kernel, dim3(1), dim3(64), 0, s, part_n, nblk, beta_out);
+}
+void launch_lz_normalize(const Geom& g, int nc, const double2* w, const double* beta,
+                         double2* vnext, hipStream_t s) {
+  hipLaunchKernelGGL(lz_normalize_kernel, dim3(1024), dim3(kBlock), 0, s, g, nc, w, beta, vnext);
+}
+
+}  // namespace lq

@@ -1,0 +1,63 @@
+// Host-side launch interface of the kernels (one translation unit per group).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "lq_types.h"
+
+namespace lq {
+
+struct OpArgs;
+struct EpiArgs;
+
+// Threads per block of every site-block kernel; partial-sum arrays hold
+// nbp(V) entries per right-hand side.
+constexpr int kBlock = 256;
+inline int nbp_of(int V, int block = kBlock) { return (((V + block - 1) / block) + 7) / 8 * 8; }
+
+// ---- stencils: op = OpKind, prec = Prec, nl = 18/12 link reals
+void launch_stencil(int op, int prec, int nl, bool dag, int epi, const OpArgs& oa,
+                    const void* in, const EpiArgs& ea, int nrhs, hipStream_t s);
+
+// ---- CG vector kernels (templated on precision and components)
+void launch_p_update(int prec, int nc, const Geom& g, SlotState* st, int par, const double* part,
+                     int nbp, void* p, const void* r, int k0, int nrhs, hipStream_t s);
+void launch_ru_accumulate(int prec, int nc, const Geom& g, const SlotState* st, double* xhi,
+                          void* xlo, int nbp, int k0, int nrhs, hipStream_t s);
+void launch_ru_finish(SlotState* st, const double* part, int nbp, int k0, int nrhs, double ncomp,
+                      int rescale, int max_cand, int init, int par, hipStream_t s);
+void launch_ru_convert(int prec, int nc, const Geom& g, const SlotState* st, const double* rhi,
+                       void* rlo, void* p, double* part, int nbp, int init, int k0, int nrhs,
+                       hipStream_t s);
+void launch_ru_commit(SlotState* st, const double* part, int nbp, int k0, int nrhs, hipStream_t s);
+void launch_load_prepare(int prec, int nc, const Geom& g, double* xhi, void* xlo, double* rhi,
+                         const double* b, int nbp, int k0, int nrhs, hipStream_t s);
+
+// ---- layout / conversion
+// canonical (V, nc) complex (c128 if src_f64 else c64) -> SoA field (prec) for rhs k0..
+void launch_field_in(int prec, int nc, const Geom& g, const void* canon, int canon_f64, void* soa,
+                     int nbp, int k0, int nrhs, hipStream_t s);
+void launch_field_out(int prec, int nc, const Geom& g, const void* soa, void* canon, int canon_f64,
+                      int nbp, int k0, int nrhs, hipStream_t s);
+void launch_gauge_in(const Geom& g, const void* canon, double2* u64, hipStream_t s);
+void launch_links_convert(int prec, int nl, const Geom& g, const double2* u64, void* dst,
+                          hipStream_t s);
+void launch_corners(const Geom& g, const double2* u64, double2* c64, hipStream_t s);
+void launch_corners_convert(int prec, const Geom& g, const double2* c64, void* dst, hipStream_t s);
+void launch_plaquette(const Geom& g, const double2* u64, double* part, int nbp, double* out,
+                      hipStream_t s);
+void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+// ---- Lanczos (FP64, one vector of nc planes)
+void launch_lz_dots(const Geom& g, int nc, const double2* V, int nvec, double2* w,
+                    const double* alpha_part, int nbp_alpha, double* alpha_out, double* part_h,
+                    int nblk, hipStream_t s);
+void launch_lz_reduce(const double* part_h, int nvec, int nblk, double2* h, hipStream_t s);
+void launch_lz_update(const Geom& g, int nc, const double2* V, int nvec, const double2* h,
+                      double2* w, double* part_n, int nblk, int with_norm, hipStream_t s);
+void launch_lz_finish(const double* part_n, int nblk, double* beta_out, hipStream_t s);
+void launch_lz_normalize(const Geom& g, int nc, const double2* w, const double* beta,
+                         double2* vnext, hipStream_t s);
+
+}  // namespace lq

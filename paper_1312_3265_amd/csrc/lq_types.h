@@ -1,0 +1,38 @@
+// Types shared by the host engine and the kernels.
+#pragma once
+
+#include <stdint.h>
+
+namespace lq {
+
+enum OpKind { OP_WILSON = 0, OP_SW_CORNERS = 1, OP_SW_OTF = 2, OP_WILSON_R = 3 };
+enum Prec { P64 = 0, P32 = 1, P16 = 2 };
+
+// Per-system solver state in device memory.  Written only by single-block
+// "finish" kernels, by block 0 of the p-update kernel (into the ring entry of
+// the next iteration parity), or by the host between steps; read by all.
+struct SlotState {
+  double rho[2];     // ||r_lo||^2 in storage units, ring indexed by iteration parity
+  double bnorm2;     // ||b||^2, b = M^dag chi (FP64)
+  double thr2;       // tol^2 * bnorm2
+  double thr_lo2;    // thr2 / scale^2: the same target in storage units
+  double scale;      // low-precision vectors hold (true value) / scale
+  double scale_prev; // scale before the latest reliable update
+  double mass;       // bare mass of this system
+  double tol;
+  double true_res2;  // ||b - A x_hi||^2 at the latest reliable update
+  double iter_res2;  // ||r_lo||^2 * scale^2 at the latest iteration
+  int32_t stop[2];   // ring: 1 = frozen until the next reliable update
+  int32_t status;    // 0 empty, 1 running, 2 converged, 3 failed
+  int32_t iter;      // CG iterations done
+  int32_t ru;        // reliable updates done
+  int32_t cand;      // reliable updates since the iterated residual met tol
+  int32_t maxiter;
+  int32_t flags;     // bit0 breakdown, bit1 maxiter reached
+  int32_t apps;      // applications of A (iterations + reliable updates + setup)
+  int32_t pad;
+};
+
+enum SlotStatus { SLOT_EMPTY = 0, SLOT_RUNNING = 1, SLOT_DONE = 2, SLOT_FAILED = 3 };
+
+}  // namespace lq

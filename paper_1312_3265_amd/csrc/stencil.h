@@ -1,0 +1,152 @@
+// Stencil kernels: one thread per (site, right-hand side), a Dirac operator's
+// site function, and a fused epilogue.  The epilogues implement the steps of
+// CG on eq. (2) around the two matvecs of an iteration:
+//   STORE       out = op(in)
+//   STORE_NORM  out = op(in), block partials of ||out||^2          (t = M p)
+//   CG_UPDATE   q = op(in) kept in registers; alpha = rho/||t||^2 from the
+//               partials of the previous launch; x += alpha p, r -= alpha q;
+//               block partials of ||r||^2                          (M^dag t)
+//   RESID       out = b - op(in), partials of ||out||^2   (FP64 true residual)
+//   LANCZOS     w = op(in) - beta_prev v_prev, partials of Re<v, w>
+// Partial sums are FP64, reduced in a fixed order (wavefront butterfly, then
+// waves in order), so results do not depend on scheduling.
+//
+// Grid: nbp site-blocks (a multiple of 8) x nrhs, flattened so that the blocks
+// of one site range and different right-hand sides go to the same XCD one
+// after another (blocks are dispatched round-robin over the 8 XCDs): the links
+// of that site range are then reused from that XCD's L2 by every RHS.
+#pragma once
+
+#include "common.h"
+#include "dirac.h"
+#include "lq_types.h"
+
+namespace lq {
+
+enum Epi { EPI_STORE = 0, EPI_STORE_NORM = 1, EPI_CG_UPDATE = 2, EPI_RESID = 3, EPI_LANCZOS = 4 };
+
+struct EpiArgs {
+  void* out;              // output fields (STORE, STORE_NORM, RESID, LANCZOS)
+  double* part;           // block partials out, [k * nbp + sb]
+  const double* part_in;  // CG_UPDATE: partials of ||t||^2 from the previous launch
+  int nbp;                // site blocks per RHS (multiple of 8)
+  int k0;                 // first RHS index handled by this launch
+  SlotState* st;          // per-RHS solver state (null: no state checks)
+  int par;                // iteration parity (ring index into SlotState)
+  int state_mode;         // 0: none, 1: running and not frozen, 2: running
+  void* x;                // CG_UPDATE: x_lo
+  void* r;                // CG_UPDATE: r_lo
+  const void* p;          // CG_UPDATE: p
+  const void* b;          // RESID: b (FP64)
+  const double* v;        // LANCZOS: v_j
+  const double* vprev;    // LANCZOS: v_{j-1}
+  const double* beta_prev;// LANCZOS: device scalar beta_{j-1} (null = 0)
+};
+
+// blockIdx.x -> (site block sb, rhs k), XCD-aware (see file comment).
+__device__ __forceinline__ void map_block(int nbp, int nrhs, int& sb, int& k) {
+  const int b = blockIdx.x;
+  const int xcd = b & 7, kk = b >> 3;
+  const int j = kk / nrhs;
+  k = kk - j * nrhs;
+  sb = 8 * j + xcd;
+}
+
+__device__ __forceinline__ bool slot_active(const SlotState* st, int mode, int par) {
+  if (mode == 0) return true;
+  if (st->status != SLOT_RUNNING) return false;
+  if (mode == 1 && st->stop[par]) return false;
+  return true;
+}
+
+// Register budget: FP64 kernels are held to 4 waves per SIMD (128 VGPRs) so
+// that enough waves are resident to cover HBM latency.
+template <class Op, int EPI>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Op::kWaves, 8)))
+stencil_kernel(const OpArgs oa, const typename Op::S* __restrict__ in, const EpiArgs ea, int nrhs) {
+  using P_C = typename Op::C;
+  using R = typename Op::R;
+  using S = typename Op::S;
+  constexpr int NC = Op::NC;
+  __shared__ double red[16];
+  int sb, kl;
+  map_block(ea.nbp, nrhs, sb, kl);
+  const int k = ea.k0 + kl;
+  if (ea.st && !slot_active(ea.st + k, ea.state_mode, ea.par)) return;
+
+  const int Vp = oa.g.Vp;
+  const int i = sb * blockDim.x + threadIdx.x;
+  const bool valid = i < oa.g.V;
+  const size_t off = (size_t)k * NC * Vp;
+
+  double alpha = 0.0;
+  if constexpr (EPI == EPI_CG_UPDATE) {
+    const double tt = sum_partials(ea.part_in + (size_t)k * ea.nbp, ea.nbp, red);
+    const double rho = ea.st[k].rho[ea.par];
+    alpha = (tt > 0.0 && isfinite(tt) && isfinite(rho)) ? rho / tt : 0.0;
+    if (!(tt > 0.0 && isfinite(tt)) && sb == 0 && threadIdx.x == 0) ea.st[k].flags |= 1;
+  }
+
+  P_C o[NC];
+  if (valid) Op::site(oa, in + off, i, k, o);
+
+  double acc = 0.0;
+  if (valid) {
+    if constexpr (EPI == EPI_STORE || EPI == EPI_STORE_NORM) {
+      S* out = (S*)ea.out + off;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        Op::Pol::st(out + (size_t)q * Vp + i, o[q]);
+        if constexpr (EPI == EPI_STORE_NORM) acc += cnorm2(Op::Pol::ld(out + (size_t)q * Vp + i));
+      }
+    } else if constexpr (EPI == EPI_CG_UPDATE) {
+      S* x = (S*)ea.x + off;
+      S* r = (S*)ea.r + off;
+      const S* p = (const S*)ea.p + off;
+      const R a = (R)alpha;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const size_t e = (size_t)q * Vp + i;
+        P_C xv = Op::Pol::ld(x + e), pv = Op::Pol::ld(p + e), rv = Op::Pol::ld(r + e);
+        xv.x += a * pv.x; xv.y += a * pv.y;
+        rv.x -= a * o[q].x; rv.y -= a * o[q].y;
+        Op::Pol::st(x + e, xv);
+        Op::Pol::st(r + e, rv);
+        acc += cnorm2(Op::Pol::ld(r + e));
+      }
+    } else if constexpr (EPI == EPI_RESID) {
+      double2* out = (double2*)ea.out + off;
+      const double2* b = (const double2*)ea.b + off;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const size_t e = (size_t)q * Vp + i;
+        double2 bv = b[e];
+        double2 w;
+        w.x = bv.x - (double)o[q].x;
+        w.y = bv.y - (double)o[q].y;
+        out[e] = w;
+        acc += w.x * w.x + w.y * w.y;
+      }
+    } else if constexpr (EPI == EPI_LANCZOS) {
+      double2* out = (double2*)ea.out + off;
+      const double2* v = (const double2*)ea.v + off;
+      const double2* vp = (const double2*)ea.vprev + off;
+      const double bp = ea.beta_prev ? *ea.beta_prev : 0.0;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const size_t e = (size_t)q * Vp + i;
+        double2 w;
+        w.x = (double)o[q].x - bp * vp[e].x;
+        w.y = (double)o[q].y - bp * vp[e].y;
+        out[e] = w;
+        acc += v[e].x * w.x + v[e].y * w.y;
+      }
+    }
+  }
+  if constexpr (EPI != EPI_STORE) {
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) ea.part[(size_t)k * ea.nbp + sb] = s;
+  }
+}
+
+}  // namespace lq

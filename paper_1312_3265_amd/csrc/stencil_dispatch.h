@@ -1,0 +1,69 @@
+// Instantiates the stencil kernels of one operator family for the supported
+// (precision, link storage, dagger, epilogue) combinations and launches them.
+//   FP64: 18-real links; every epilogue, both M and M^dag.
+//   FP32: 18- or 12-real links; STORE, STORE_NORM (M), CG_UPDATE (M^dag).
+//   FP16: 12-real links; same epilogues as FP32.
+#pragma once
+
+#include <stdexcept>
+#include <string>
+
+#include "kernels.h"
+#include "stencil.h"
+
+namespace lq {
+
+template <template <class, int, bool> class OpT, class P, int NL, bool DAG, int EPI>
+static void launch_one(const OpArgs& oa, const void* in, const EpiArgs& ea, int nrhs,
+                       hipStream_t s) {
+  using Op = OpT<P, NL, DAG>;
+  const int grid = ea.nbp * nrhs;
+  if (grid == 0) return;
+  hipLaunchKernelGGL((stencil_kernel<Op, EPI>), dim3(grid), dim3(kBlock), 0, s, oa,
+                     (const typename Op::S*)in, ea, nrhs);
+}
+
+template <template <class, int, bool> class OpT, class P, int NL>
+static void dispatch_epi(bool dag, int epi, const OpArgs& oa, const void* in, const EpiArgs& ea,
+                         int nrhs, hipStream_t s) {
+  constexpr bool full = (P::id == 0);
+  if (!dag) {
+    switch (epi) {
+      case EPI_STORE: return launch_one<OpT, P, NL, false, EPI_STORE>(oa, in, ea, nrhs, s);
+      case EPI_STORE_NORM: return launch_one<OpT, P, NL, false, EPI_STORE_NORM>(oa, in, ea, nrhs, s);
+      default: break;
+    }
+    if constexpr (full) {
+      if (epi == EPI_RESID) return launch_one<OpT, P, NL, false, EPI_RESID>(oa, in, ea, nrhs, s);
+    }
+  } else {
+    switch (epi) {
+      case EPI_STORE: return launch_one<OpT, P, NL, true, EPI_STORE>(oa, in, ea, nrhs, s);
+      case EPI_CG_UPDATE: return launch_one<OpT, P, NL, true, EPI_CG_UPDATE>(oa, in, ea, nrhs, s);
+      default: break;
+    }
+    if constexpr (full) {
+      switch (epi) {
+        case EPI_STORE_NORM: return launch_one<OpT, P, NL, true, EPI_STORE_NORM>(oa, in, ea, nrhs, s);
+        case EPI_RESID: return launch_one<OpT, P, NL, true, EPI_RESID>(oa, in, ea, nrhs, s);
+        case EPI_LANCZOS: return launch_one<OpT, P, NL, true, EPI_LANCZOS>(oa, in, ea, nrhs, s);
+        default: break;
+      }
+    }
+  }
+  throw std::runtime_error("stencil: unsupported epilogue " + std::to_string(epi) +
+                           " for precision " + std::to_string(P::id));
+}
+
+template <template <class, int, bool> class OpT>
+static void dispatch_prec(int prec, int nl, bool dag, int epi, const OpArgs& oa, const void* in,
+                          const EpiArgs& ea, int nrhs, hipStream_t s) {
+  if (prec == P64 && nl == 18) return dispatch_epi<OpT, F64, 18>(dag, epi, oa, in, ea, nrhs, s);
+  if (prec == P32 && nl == 18) return dispatch_epi<OpT, F32, 18>(dag, epi, oa, in, ea, nrhs, s);
+  if (prec == P32 && nl == 12) return dispatch_epi<OpT, F32, 12>(dag, epi, oa, in, ea, nrhs, s);
+  if (prec == P16 && nl == 12) return dispatch_epi<OpT, F16, 12>(dag, epi, oa, in, ea, nrhs, s);
+  throw std::runtime_error("stencil: unsupported precision/link storage " + std::to_string(prec) +
+                           "/" + std::to_string(nl));
+}
+
+}  // namespace lq

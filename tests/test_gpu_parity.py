@@ -1,0 +1,147 @@
+"""GPU parity of the HIP path against the FP64 oracle (needs an MI355X).
+
+Inputs are seeded synthetic fields from ``synth``; the oracle and the library
+share nothing else.  Bars: FP64 matvec relative error <= 1e-13 (max-norm over
+the field); FP32 and FP16 stencils within bounds derived from their unit
+roundoff times the operator's term count; solves judged by the FP64 true
+residual recomputed by the oracle, which must be <= the requested tolerance.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import gauge as ogauge
+from oracle import solvers
+from oracle import staggered_wilson as SW
+from oracle import wilson as W
+
+pytestmark = pytest.mark.gpu
+
+lq = pytest.importorskip("paper_1312_3265_amd")
+torch = pytest.importorskip("torch")
+
+FORMS = [synth.WILSON, synth.STAGGERED_WILSON]
+
+
+def _oracle_apply(formulation, U, psi, m, op, r=1.0, bc=(1, 1, 1, 1)):
+    mod = W if formulation == synth.WILSON else SW
+    if op == lq.OP_M:
+        return mod.apply(U, psi, m, r, bc)
+    if op == lq.OP_MDAG:
+        return mod.apply(U, psi, m, r, bc, dagger=True)
+    return mod.apply(U, mod.apply(U, psi, m, r, bc), m, r, bc, dagger=True)
+
+
+def _relerr(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+_GAUGE_CACHE = {}
+
+
+def _gauge(dims, kind, seed, bc=(1, 1, 1, 1), eps=None,
+           features=lq.FEAT_CORNERS | lq.FEAT_F32 | lq.FEAT_F16):
+    key = (dims, kind, seed, bc, eps, features)
+    if key not in _GAUGE_CACHE:
+        U = synth.gauge_field(dims, kind, seed, eps)
+        lat = lq.Lattice(dims, bc)
+        _GAUGE_CACHE[key] = (U, lat, lq.Gauge(lat, U, features))
+    return _GAUGE_CACHE[key]
+
+
+# ------------------------------------------------------------------ gauge
+@pytest.mark.parametrize("dims,kind,eps", [((4, 4, 4, 4), "haar", None),
+                                           ((8, 6, 4, 10), "near_identity", 0.436)])
+def test_plaquette_matches_oracle(dims, kind, eps):
+    U, lat, g = _gauge(dims, kind, 3, eps=eps)
+    assert abs(g.plaquette() - ogauge.plaquette(U)) < 1e-13
+
+
+# ---------------------------------------------------------------- matvecs
+CASES = [((4, 4, 4, 4), "haar", (1, 1, 1, 1)),
+         ((6, 4, 6, 8), "haar", (1, 1, 1, -1)),       # V = 1152: ragged last block
+         ((8, 8, 6, 4), "near_identity", (-1, 1, 1, -1))]
+
+
+@pytest.mark.parametrize("dims,kind,bc", CASES)
+@pytest.mark.parametrize("formulation,g55", [(synth.WILSON, 0),
+                                             (synth.STAGGERED_WILSON, lq.G55_CORNERS),
+                                             (synth.STAGGERED_WILSON, lq.G55_ONTHEFLY)])
+@pytest.mark.parametrize("op", [lq.OP_M, lq.OP_MDAG, lq.OP_MDAGM])
+def test_fp64_matvec_matches_oracle(dims, kind, bc, formulation, g55, op):
+    U, lat, g = _gauge(dims, kind, 11, bc=bc, eps=0.436 if kind != "haar" else None)
+    psi = synth.gaussian_field(dims, formulation, 5)
+    m = 0.137
+    out = lq.apply(g, formulation, m, psi, op=op, g55=g55).cpu().numpy()
+    ref = _oracle_apply(formulation, U, psi, m, op, 1.0, bc)
+    assert _relerr(out, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("r", [0.7, 1.3])
+def test_fp64_matvec_general_r(r):
+    dims = (4, 6, 4, 4)
+    U, lat, g = _gauge(dims, "haar", 12)
+    for formulation in FORMS:
+        psi = synth.gaussian_field(dims, formulation, 6)
+        out = lq.apply(g, formulation, -0.2, psi, op=lq.OP_M, r=r).cpu().numpy()
+        ref = _oracle_apply(formulation, U, psi, -0.2, lq.OP_M, r)
+        assert _relerr(out, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("formulation,g55", [(synth.WILSON, 0),
+                                             (synth.STAGGERED_WILSON, lq.G55_CORNERS),
+                                             (synth.STAGGERED_WILSON, lq.G55_ONTHEFLY)])
+@pytest.mark.parametrize("precision,links,bound", [(lq.F32, 18, 2e-6), (lq.F32, 12, 4e-6),
+                                                  (lq.F16, 12, 4e-3)])
+def test_low_precision_matvec_within_roundoff(formulation, g55, precision, links, bound):
+    """FP32: u = 6e-8 per operation over O(30) accumulated terms; FP16 storage:
+    u = 4.9e-4 on every stored input, link and corner entry."""
+    dims = (6, 4, 6, 8)
+    U, lat, g = _gauge(dims, "near_identity", 21, eps=0.436)
+    psi = synth.gaussian_field(dims, formulation, 7)
+    out = lq.apply(g, formulation, 0.1, psi, op=lq.OP_M, g55=g55, precision=precision,
+                   links=links).cpu().numpy()
+    ref = _oracle_apply(formulation, U, psi, 0.1, lq.OP_M)
+    assert _relerr(out, ref) <= bound
+
+
+def test_fp64_matvec_full_size_16x32():
+    """16^3 x 32 near-identity field: the whole field against the oracle."""
+    dims = (16, 16, 16, 32)
+    U, lat, g = _gauge(dims, "near_identity", 2000, eps=0.4359375,
+                       features=lq.FEAT_CORNERS)
+    for formulation, g55 in [(synth.WILSON, 0), (synth.STAGGERED_WILSON, lq.G55_CORNERS)]:
+        psi = synth.gaussian_field(dims, formulation, 8)
+        out = lq.apply(g, formulation, -0.4, psi, op=lq.OP_M, g55=g55).cpu().numpy()
+        ref = _oracle_apply(formulation, U, psi, -0.4, lq.OP_M)
+        assert _relerr(out, ref) <= 1e-13
+
+
+# ------------------------------------------------------------------ solves
+@pytest.mark.parametrize("formulation", FORMS)
+def test_fp64_cg_4x4_matches_oracle(formulation):
+    dims = (4, 4, 4, 4)
+    U, lat, g = _gauge(dims, "haar", 1000)
+    chi = synth.point_source(dims, formulation, 0)
+    m, tol = 0.5, 1e-10
+    x, info = lq.cg_solve(g, formulation, m, chi, tol)
+    assert info["status"] == lq.OK
+    xo, oinfo = solvers.cgnr(formulation, U, chi, m, tol, 10000)
+    rn, _ = solvers.true_residual(formulation, U, chi, x.cpu().numpy(), m)
+    assert rn <= tol
+    assert abs(info["iterations"] - oinfo["iterations"]) <= 2
+    assert info["true_residual"] <= tol
+    assert abs(info["true_residual"] - rn) <= 1e-3 * tol + 1e-15
+
+
+@pytest.mark.parametrize("formulation", FORMS)
+def test_lanczos_4x4_matches_oracle(formulation):
+    dims = (4, 4, 4, 4)
+    U, lat, g = _gauge(dims, "haar", 1000)
+    v0 = synth.gaussian_field(dims, formulation, 7)
+    res = lq.condition_number(g, formulation, 0.5, v0, steps=60)
+    lo, hi, kap, (a, b) = solvers.condition_number(formulation, U, 0.5, v0, 60)
+    np.testing.assert_allclose(res["alpha"][:30], a[:30], rtol=1e-10)
+    np.testing.assert_allclose(res["beta"][:30], b[:30], rtol=1e-9)
+    assert abs(res["lmin"] - lo) <= 1e-8 * hi
+    assert abs(res["lmax"] - hi) <= 1e-10 * hi

@@ -1,0 +1,351 @@
+"""Pins of the FP64 oracle against mathematics and the paper (CPU only).
+
+Each check is chosen so that a plausible slip in the oracle -- a dropped hop, a
+wrong sign, a link taken at the wrong site, a missing dagger, a wrong phase
+function -- fails at least one of them:
+
+* free-field plane waves against the closed-form symbols (Sec. 3 free-field
+  discussion), on lattices with L = 6 so that a wrong phi(x) is not hidden;
+* the closed-form spectra and the paper's 8/sqrt(5) limit (Sec. 3);
+* adjoint relations: D_st anti-hermitian, Gamma_55 hermitian, epsilon- and
+  gamma_5-hermiticity (Sec. 2);
+* gauge covariance M[U^g] = g M[U] g^dag on Haar-random links;
+* three independently written forms of Gamma_55;
+* CG against dense LU, CG's finite-termination property, Lanczos against dense
+  eigenvalues and on a matrix with known spectrum.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dense, freefield, gauge, lattice, solvers
+from oracle import staggered_wilson as SW
+from oracle import wilson as W
+
+RNG = np.random.default_rng(12345)
+_CACHE = {}
+
+
+def dense_sw_normal(kind, m):
+    """Dense A_SW on 4^4 (free field or the seed-1000 Haar field), cached."""
+    key = ("swA", kind, m)
+    if key not in _CACHE:
+        dims = (4, 4, 4, 4)
+        U = synth.gauge_field(dims, kind, 1000)
+        M = dense.dense_matrix(lambda v: SW.apply(U, v, m), synth.field_shape(dims, 1))
+        _CACHE[key] = (M, M.conj().T @ M)
+    return _CACHE[key]
+
+
+def _inner(a, b):
+    return np.vdot(a.ravel(), b.ravel())
+
+
+def _allowed_momentum(dims, bc, rng):
+    p = []
+    for mu in range(4):
+        th = 0.0 if bc[mu] == 1 else np.pi
+        n = rng.integers(0, dims[mu])
+        p.append((2 * np.pi * n + th) / dims[mu])
+    return np.array(p)
+
+
+# ---------------------------------------------------------------- gamma basis
+def test_gamma_basis_clifford_and_hermitian():
+    g = W.GAMMA
+    for mu in range(4):
+        assert np.allclose(g[mu], g[mu].conj().T)
+        for nu in range(4):
+            ac = g[mu] @ g[nu] + g[nu] @ g[mu]
+            assert np.allclose(ac, 2.0 * (mu == nu) * np.eye(4))
+    assert np.allclose(W.GAMMA5, np.diag([1, 1, -1, -1]))
+    for mu in range(4):
+        assert np.linalg.matrix_rank(np.eye(4) - g[mu]) == 2
+        assert np.linalg.matrix_rank(np.eye(4) + g[mu]) == 2
+
+
+# ------------------------------------------------------------- gauge fields
+def test_haar_su3_properties():
+    rng = np.random.Generator(np.random.PCG64(3))
+    u = synth.haar_su3(20000, rng)
+    eye = np.eye(3)
+    assert np.abs(u @ np.conj(np.swapaxes(u, -1, -2)) - eye).max() < 1e-13
+    assert np.abs(np.linalg.det(u) - 1.0).max() < 1e-13
+    tr = np.trace(u, axis1=-2, axis2=-1)
+    # Haar SU(3): E[tr U] = 0 and E|tr U|^2 = 1 (number of irreducible
+    # components of the fundamental representation).
+    assert abs(tr.mean()) < 5.0 / np.sqrt(len(tr))
+    assert abs(np.mean(np.abs(tr) ** 2) - 1.0) < 0.05
+
+
+def test_near_identity_is_su3_and_tunes_plaquette():
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, "near_identity", 5, eps=0.44)
+    m = U.reshape(-1, 3, 3)
+    assert np.abs(m @ np.conj(np.swapaxes(m, -1, -2)) - np.eye(3)).max() < 1e-13
+    assert np.abs(np.linalg.det(m) - 1.0).max() < 1e-13
+    P = gauge.plaquette(synth.gauge_field((8, 8, 8, 8), "near_identity", 5, eps=0.436))
+    assert abs(P - 0.594) < 0.01
+
+
+def test_plaquette_unit_and_abelian_closed_form():
+    dims = (4, 6, 4, 4)
+    U = synth.gauge_field(dims, "unit")
+    assert abs(gauge.plaquette(U) - 1.0) < 1e-15
+    # U_1(x) = exp(i a x2 T), T = diag(1,-1,0), a = 2 pi / L2: every 1-2
+    # plaquette equals exp(-i a T), the other five planes are 1.
+    a = 2 * np.pi / dims[1]
+    x1, x2, x3, x4 = lattice.coords(dims)
+    ph = np.exp(1j * a * x2)
+    U[..., 0, 0, 0] = ph
+    U[..., 0, 1, 1] = np.conj(ph)
+    expect = (5.0 + (1.0 + 2.0 * np.cos(a)) / 3.0) / 6.0
+    assert abs(gauge.plaquette(U) - expect) < 1e-14
+
+
+def test_plaquette_gauge_invariant():
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, "haar", 1)
+    g = synth.gauge_transform(dims, 2)
+    assert abs(gauge.plaquette(U) - gauge.plaquette(gauge.transform_links(U, g))) < 1e-13
+
+
+# -------------------------------------------------------------------- Wilson
+@pytest.mark.parametrize("dims,bc", [((4, 6, 4, 6), (1, 1, 1, 1)),
+                                     ((6, 4, 4, 8), (1, 1, 1, -1))])
+def test_wilson_free_plane_waves(dims, bc):
+    U = synth.gauge_field(dims, "unit")
+    for trial in range(6):
+        p = _allowed_momentum(dims, bc, RNG)
+        u = RNG.standard_normal((4, 3)) + 1j * RNG.standard_normal((4, 3))
+        psi = synth.plane_wave(dims, p, u)
+        for dagger in (False, True):
+            m, r = 0.3, 1.0 if trial % 2 == 0 else 0.7
+            Mp = W.momentum_matrix(p, m, r)
+            if dagger:
+                Mp = Mp.conj().T
+            got = W.apply(U, psi, m, r, bc, dagger=dagger)
+            want = synth.plane_wave(dims, p, Mp @ u)
+            assert np.abs(got - want).max() < 1e-12
+
+
+def test_wilson_free_all_momenta_give_closed_form_spectrum_and_8_over_sqrt5():
+    """Every plane wave on 4^4 is an eigenvector of A_W with the closed-form
+    eigenvalue; with the dense staggered Wilson spectrum this fixes both free
+    condition numbers, whose square-root ratio tends to 8/sqrt(5) (Sec. 3)."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, "unit")
+    m = 1e-3
+    lam = []
+    for p in freefield.momenta(dims):
+        u = np.zeros((4, 3), dtype=complex)
+        u[:, 0] = RNG.standard_normal(4) + 1j * RNG.standard_normal(4)
+        psi = synth.plane_wave(dims, p, u)
+        Apsi = W.apply_normal(U, psi, m)
+        ratio = _inner(psi, Apsi) / _inner(psi, psi)
+        assert np.abs(Apsi - ratio * psi).max() < 1e-12
+        lam.append(ratio.real)
+    lam = np.sort(np.array(lam))
+    closed = np.sort(freefield.wilson_spectrum(dims, m)[::12])
+    assert np.abs(lam - closed).max() < 1e-12
+    ev = np.linalg.eigvalsh(dense_sw_normal("unit", m)[1])
+    ratio = np.sqrt((lam[-1] / lam[0]) / (ev[-1] / ev[0]))
+    # lambda_min = m^2 = 1e-6 carries the dense solver's ~1e-14 absolute error
+    assert abs(ratio - (8.0 + m) / np.sqrt(4.0 + (1.0 + m) ** 2)) < 1e-6
+    assert abs(ratio - 8.0 / np.sqrt(5.0)) < 1e-3
+
+
+def test_wilson_adjoint_and_gamma5_hermiticity():
+    dims = (4, 4, 4, 6)
+    bc = (1, 1, 1, -1)
+    U = synth.gauge_field(dims, "haar", 11)
+    psi = synth.gaussian_field(dims, synth.WILSON, 1)
+    chi = synth.gaussian_field(dims, synth.WILSON, 2)
+    m = 0.37
+    Mpsi = W.apply(U, psi, m, 1.0, bc)
+    Mdchi = W.apply(U, chi, m, 1.0, bc, dagger=True)
+    assert abs(_inner(chi, Mpsi) - _inner(Mdchi, psi)) < 1e-11
+    g5 = W.gamma5(W.apply(U, W.gamma5(psi), m, 1.0, bc))
+    assert np.abs(g5 - W.apply(U, psi, m, 1.0, bc, dagger=True)).max() < 1e-13
+
+
+def test_wilson_gauge_covariance():
+    dims = (4, 4, 6, 4)
+    U = synth.gauge_field(dims, "haar", 21)
+    g = synth.gauge_transform(dims, 22)
+    psi = synth.gaussian_field(dims, synth.WILSON, 23)
+    Ug = gauge.transform_links(U, g)
+    lhs = W.apply(Ug, gauge.transform_fermion(g, psi, synth.WILSON), 0.1)
+    rhs = gauge.transform_fermion(g, W.apply(U, psi, 0.1), synth.WILSON)
+    assert np.abs(lhs - rhs).max() < 1e-13
+
+
+# --------------------------------------------------------- staggered Wilson
+def test_sw_hermiticity_relations():
+    dims = (4, 6, 4, 6)
+    bc = (1, 1, 1, -1)
+    U = synth.gauge_field(dims, "haar", 31)
+    psi = synth.gaussian_field(dims, synth.STAGGERED_WILSON, 1)
+    chi = synth.gaussian_field(dims, synth.STAGGERED_WILSON, 2)
+    d_psi, d_chi = SW.dst(U, psi, bc), SW.dst(U, chi, bc)
+    assert abs(_inner(chi, d_psi) + _inner(d_chi, psi)) < 1e-11
+    g_psi, g_chi = SW.gamma55_subsets(U, psi, bc), SW.gamma55_subsets(U, chi, bc)
+    assert abs(_inner(chi, g_psi) - _inner(g_chi, psi)) < 1e-11
+    m = 0.2
+    M = SW.apply(U, psi, m, 1.0, bc)
+    eMe = SW.epsilon_mul(SW.apply(U, SW.epsilon_mul(psi), m, 1.0, bc))
+    Md = SW.apply(U, psi, m, 1.0, bc, dagger=True)
+    assert np.abs(eMe - Md).max() < 1e-13
+    assert abs(_inner(chi, M) - _inner(SW.apply(U, chi, m, 1.0, bc, dagger=True), psi)) < 1e-11
+
+
+def test_sw_gauge_covariance():
+    dims = (4, 6, 4, 4)
+    U = synth.gauge_field(dims, "haar", 41)
+    g = synth.gauge_transform(dims, 42)
+    psi = synth.gaussian_field(dims, synth.STAGGERED_WILSON, 43)
+    Ug = gauge.transform_links(U, g)
+    lhs = SW.apply(Ug, gauge.transform_fermion(g, psi, synth.STAGGERED_WILSON), 0.1)
+    rhs = gauge.transform_fermion(g, SW.apply(U, psi, 0.1), synth.STAGGERED_WILSON)
+    assert np.abs(lhs - rhs).max() < 1e-13
+    # the corner matrices transform as W_s(x) -> g(x) W_s(x) g(x+s)^dag
+    Wc, Wg = SW.corners(U), SW.corners(Ug)
+    for si, s in enumerate(SW.SIGNS):
+        want = g @ Wc[si] @ np.conj(np.swapaxes(SW.gather_field(g, s), -1, -2))
+        assert np.abs(Wg[si] - want).max() < 1e-13
+
+
+@pytest.mark.parametrize("bc", [(1, 1, 1, 1), (1, 1, 1, -1), (-1, 1, -1, 1)])
+def test_gamma55_three_forms_agree(bc):
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, "haar", 1000)
+    psi = synth.gaussian_field(dims, synth.STAGGERED_WILSON, 3)
+    a = SW.gamma55_subsets(U, psi, bc)
+    b = SW.gamma55_paths(U, psi, bc)
+    c = SW.gamma55_corners(SW.corners(U), psi, bc)
+    assert np.abs(a - b).max() < 1e-14
+    assert np.abs(a - c).max() < 1e-14
+
+
+def test_corner_reflection_identity():
+    """W_{-s}(x + s)^dag = W_s(x): the reversed path set is the same set."""
+    dims = (4, 4, 6, 4)
+    U = synth.gauge_field(dims, "haar", 51)
+    Wc = SW.corners(U)
+    for si, s in enumerate(SW.SIGNS):
+        ms = tuple(-v for v in s)
+        other = SW.gather_field(Wc[SW.SIGNS.index(ms)], s)
+        assert np.abs(np.conj(np.swapaxes(other, -1, -2)) - Wc[si]).max() < 1e-14
+
+
+@pytest.mark.parametrize("dims,bc", [((6, 6, 6, 6), (1, 1, 1, 1)),
+                                     ((4, 6, 8, 6), (1, 1, 1, -1))])
+def test_sw_free_plane_waves(dims, bc):
+    U = synth.gauge_field(dims, "unit")
+    shift = np.array([0.0, np.pi, 0.0, np.pi])
+    for trial in range(4):
+        p = _allowed_momentum(dims, bc, RNG)
+        u = RNG.standard_normal(3) + 1j * RNG.standard_normal(3)
+        psi = synth.plane_wave(dims, p, u)
+        m, r = 0.25, 1.0 if trial % 2 == 0 else 0.6
+        a, b = freefield.sw_normal_on_plane_wave(p, m, r)
+        want = a * psi + b * synth.plane_wave(dims, p + shift, u)
+        assert np.abs(SW.apply_normal(U, psi, m, r, bc) - want).max() < 1e-12
+        # Gamma_55 alone moves p by pi(0,1,0,1) with weight prod cos p
+        c = np.prod(np.cos(p))
+        g = SW.gamma55_subsets(U, psi, bc)
+        assert np.abs(g - c * synth.plane_wave(dims, p + shift, u)).max() < 1e-12
+
+
+def test_sw_free_dense_spectrum_and_norm_bound():
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, "unit")
+    for m in (1e-3,):
+        ev = np.linalg.eigvalsh(dense_sw_normal("unit", m)[1])
+        assert np.abs(ev - freefield.sw_spectrum(dims, m)).max() < 1e-12
+        lo, hi = freefield.extreme_eigenvalues(False, m)
+        assert abs(ev[0] - lo) < 1e-12 and abs(ev[-1] - hi) < 1e-12
+    Uh = synth.gauge_field(dims, "haar", 61)
+    G = dense.dense_matrix(lambda v: SW.gamma55_subsets(Uh, v), synth.field_shape(dims, 1))
+    assert np.abs(G - G.conj().T).max() < 1e-15
+    assert np.abs(np.linalg.eigvalsh(G)).max() <= 1.0 + 1e-12
+
+
+def test_sw_free_dst_commutes_with_gamma55_only_with_right_phase():
+    """At U = 1 on 6^4, [D_st, Gamma_55] = 0 for phi = (-1)^(x2+x4); a wrong
+    phase such as (-1)^(x1+x3) does not commute there."""
+    dims = (6, 6, 6, 6)
+    U = synth.gauge_field(dims, "unit")
+    psi = synth.gaussian_field(dims, synth.STAGGERED_WILSON, 71)
+    lhs = SW.dst(U, SW.gamma55_subsets(U, psi))
+    rhs = SW.gamma55_subsets(U, SW.dst(U, psi))
+    assert np.abs(lhs - rhs).max() < 1e-13
+    x = lattice.coords(dims)
+    wrong = np.where((x[0] + x[2]) % 2 == 0, 1.0, -1.0) * SW.phi(dims)
+    g_wrong = lambda v: lattice.site_mul(wrong, SW.gamma55_subsets(U, v))
+    diff = SW.dst(U, g_wrong(psi)) - g_wrong(SW.dst(U, psi))
+    assert np.abs(diff).max() > 1e-2
+
+
+# ---------------------------------------------------------------- solvers
+def test_cg_terminates_in_number_of_distinct_eigenvalues():
+    """Textbook CG property: with k distinct eigenvalues CG converges in k steps."""
+    rng = np.random.default_rng(5)
+    n, k = 60, 5
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    d = np.repeat(np.array([1.0, 2.0, 3.5, 7.0, 11.0]), n // k)
+    A = (Q * d) @ Q.conj().T
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, info = solvers.cg(lambda v: A @ v, b, 1e-10, 100)
+    assert info["iterations"] == k
+    assert np.abs(x - np.linalg.solve(A, b)).max() < 1e-10
+
+
+@pytest.mark.parametrize("formulation", [synth.WILSON, synth.STAGGERED_WILSON])
+def test_cgnr_matches_dense_lu_4x4(formulation):
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, "haar", 1000)
+    chi = synth.point_source(dims, formulation, 0)
+    m = 0.5
+    x, info = solvers.cgnr(formulation, U, chi, m, 1e-10, 5000)
+    assert info["status"] == solvers.CONVERGED
+    assert info["true_residual"] <= 1e-10
+    if formulation == synth.WILSON:
+        M = dense.dense_matrix(lambda v: W.apply(U, v, m), synth.field_shape(dims, formulation))
+    else:
+        M = dense_sw_normal("haar", m)[0]
+    x_lu = np.linalg.solve(M, chi.ravel())
+    # kappa(A) on this field is O(10) (Lanczos below), so the error is ~1e-9
+    assert np.linalg.norm(x.ravel() - x_lu) / np.linalg.norm(x_lu) <= 1e-8
+
+
+def test_cg_detects_breakdown_and_maxiter():
+    A = lambda v: v * 2.0
+    b = np.ones(8, dtype=complex)
+    b[3] = np.nan
+    _, info = solvers.cg(A, b, 1e-10, 10)
+    assert info["status"] == solvers.BREAKDOWN
+    Aop = lambda v: np.arange(1, 9) * v
+    _, info = solvers.cg(Aop, np.ones(8, dtype=complex), 1e-14, 3)
+    assert info["status"] == solvers.NOT_CONVERGED and info["iterations"] == 3
+
+
+def test_lanczos_known_spectrum_and_dense_sw():
+    rng = np.random.default_rng(9)
+    n = 40
+    d = np.linspace(0.5, 9.0, n)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    A = (Q * d) @ Q.conj().T
+    a, b = solvers.lanczos(lambda v: A @ v, rng.standard_normal(n) + 0j, n)
+    assert np.abs(np.sort(solvers.ritz_values(a, b)) - d).max() < 1e-10
+
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, "haar", 1000)
+    m = 0.5
+    ev = np.linalg.eigvalsh(dense_sw_normal("haar", m)[1])
+    v0 = synth.gaussian_field(dims, synth.STAGGERED_WILSON, 7)
+    lmin, lmax, kappa, _ = solvers.condition_number(synth.STAGGERED_WILSON, U, m, v0, 200)
+    assert lmin >= ev[0] - 1e-10 and lmax <= ev[-1] + 1e-10   # Cauchy interlacing
+    assert abs(lmax - ev[-1]) / ev[-1] < 1e-8
+    assert abs(lmin - ev[0]) / ev[0] < 1e-6
+    assert kappa <= ev[-1] / ev[0] * (1 + 1e-10)
