@@ -118,6 +118,9 @@ typedef struct {
   int32_t use_graph;          /* 1 = replay steady iteration chunks as hipGraphs */
   int32_t max_restarts;       /* reliable updates allowed after the iterated
                                  residual first meets tol (0 = default 50)       */
+  double reliable_delta;      /* also update once the iterated residual has
+                                 dropped by this factor since the last update
+                                 (0 = default: 0.1 for F16, 1e-3 for F32)        */
 } lq_solve_opts;
 
 /* Per-solve report.  The residuals are relative: ||b - A x|| / ||b|| with
@@ -221,6 +224,12 @@ int lq_batch_load(lq_batch* b, int32_t slot, const void* chi, double mass, doubl
                   int32_t maxiter, void* stream);
 int lq_batch_step(lq_batch* b, int32_t iterations, int32_t* states, void* stream);
 int lq_batch_fetch(lq_batch* b, int32_t slot, void* x, lq_solve_info* info, void* stream);
+/* Progress of a slot as of the latest step (host copy, no device work): info
+ * gets the slot state (0..3) in `status`, the iteration and update counts,
+ * the iterated residual and the FP64 residual of the latest reliable update;
+ * `seconds` carries the slot's flag bits (1 breakdown, 2 maxiter, 4 restart
+ * limit); scale (may be NULL) the storage scale of its low-precision vectors. */
+int lq_batch_peek(lq_batch* b, int32_t slot, lq_solve_info* info, double* scale);
 void lq_batch_destroy(lq_batch* b);
 
 /* ---------------------------------------------------- condition number
@@ -236,6 +245,17 @@ int lq_condition_number(const lq_gauge* g, const lq_dirac* d, int32_t steps,
                         const void* v0, void* ws, size_t ws_bytes, double* lmin,
                         double* lmax, double* kappa, double* alpha, double* beta,
                         int32_t* steps_done, void* stream);
+
+/* Critical mass estimate for the synthetic workloads (the paper compares at
+ * equal pion mass, Sec. 3; the stand-in uses m = m_c + delta): m_c is the mass
+ * in [lo, hi] that minimises the lowest Ritz value theta_min of a `steps`-step
+ * Lanczos run on A(m) = (D+m)^dag (D+m) from v0 -- an ngrid-point scan, then
+ * ngolden golden-section steps on the bracket around the best grid point; the
+ * best evaluated point is returned.  ws as for lq_condition_number. */
+int lq_critical_mass(const lq_gauge* g, int32_t formulation, int32_t g55_mode, double r,
+                     double lo, double hi, int32_t ngrid, int32_t ngolden, int32_t steps,
+                     const void* v0, void* ws, size_t ws_bytes, double* m_c, double* theta_min,
+                     void* stream);
 
 #ifdef __cplusplus
 }

@@ -45,7 +45,8 @@ class Dirac(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("links", ctypes.c_int32),
                 ("reliable_interval", ctypes.c_int32), ("poll_interval", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("max_restarts", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
+                ("reliable_delta", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -76,6 +77,14 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_1312_3265_amd.build` (there is no fallback)")
+    # torch ships its own HIP runtime (soname libamdhip64.so.7).  Loading torch
+    # first makes the library bind to that same runtime, so device pointers and
+    # streams from torch are valid in the library; loading the library first
+    # would put a second runtime in the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     c = ctypes
     P, I32, I64, D, SZ = c.c_void_p, c.c_int32, c.c_int64, c.c_double, c.c_size_t
@@ -100,8 +109,10 @@ def lib():
         "lq_batch_step": ([P, I32, P, P], I32),
         "lq_batch_fetch": ([P, I32, P, P, P], I32),
         "lq_batch_destroy": ([P], None),
+        "lq_batch_peek": ([P, I32, P, P], I32),
         "lq_lanczos_workspace_bytes": ([P, I32, I32], SZ),
         "lq_condition_number": ([P, P, I32, P, P, SZ, P, P, P, P, P, P, P], I32),
+        "lq_critical_mass": ([P, I32, I32, D, D, D, I32, I32, I32, P, P, SZ, P, P, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -233,8 +244,9 @@ def time_dslash(gauge, formulation, mass, dagger=False, r=1.0, g55=G55_CORNERS, 
 
 
 def solve_opts(precision=F64, links=0, reliable_interval=0, poll_interval=0, use_graph=0,
-               max_restarts=0):
-    return SolveOpts(precision, links, reliable_interval, poll_interval, use_graph, max_restarts)
+               max_restarts=0, reliable_delta=0.0):
+    return SolveOpts(precision, links, reliable_interval, poll_interval, use_graph, max_restarts,
+                     reliable_delta)
 
 
 def cg_solve(gauge, formulation, mass, chi, tol, maxiter=100000, r=1.0, g55=G55_CORNERS,
@@ -299,6 +311,20 @@ def condition_number(gauge, formulation, mass, v0, steps=200, r=1.0, g55=G55_COR
                 beta=list(b[:max(n - 1, 0)]), steps=n)
 
 
+def critical_mass(gauge, formulation, v0, lo, hi, steps=200, ngrid=7, ngolden=8, r=1.0,
+                  g55=G55_CORNERS, stream=None):
+    """m_c = argmin_m of the Lanczos lowest Ritz value (scan + golden section)."""
+    torch = _torch()
+    v = _device_tensor(v0, torch.complex128)
+    nb = int(lib().lq_lanczos_workspace_bytes(gauge._h, formulation, steps))
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    mc, th = ctypes.c_double(), ctypes.c_double()
+    _check(lib().lq_critical_mass(gauge._h, formulation, g55, r, lo, hi, ngrid, ngolden, steps,
+                                  _ptr(v), _ptr(ws), nb, ctypes.byref(mc), ctypes.byref(th),
+                                  _stream(stream)))
+    return mc.value, th.value
+
+
 class Batch:
     """Resident multi-slot solver for continuous batching (serving)."""
 
@@ -337,6 +363,16 @@ class Batch:
         _check(lib().lq_batch_fetch(self._h, slot, _ptr(x), ctypes.byref(info), _stream(stream)))
         self._keep.pop(slot, None)
         return x, info.as_dict()
+
+    def peek(self, slot):
+        """Slot progress as of the latest step (no device work)."""
+        info = SolveInfo()
+        sc = ctypes.c_double()
+        _check(lib().lq_batch_peek(self._h, slot, ctypes.byref(info), ctypes.byref(sc)))
+        d = info.as_dict()
+        d["flags"] = int(d.pop("seconds"))
+        d["scale"] = sc.value
+        return d
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

@@ -269,6 +269,8 @@ static void check_opts(const lq_solve_opts* o) {
   check_prec(o->precision, o->links);
   need(o->reliable_interval >= 0 && o->poll_interval >= 0 && o->max_restarts >= 0,
        "negative option");
+  need(std::isfinite(o->reliable_delta) && o->reliable_delta >= 0.0 && o->reliable_delta < 1.0,
+       "reliable_delta must be in [0, 1)");
 }
 
 int lq_cg_solve(const lq_gauge* g, const lq_dirac* d, const void* chi, void* x, double tol,
@@ -366,6 +368,24 @@ int lq_batch_fetch(lq_batch* b, int32_t slot, void* x, lq_solve_info* info, void
   });
 }
 
+int lq_batch_peek(lq_batch* b, int32_t slot, lq_solve_info* info, double* scale) {
+  return guard([&] {
+    need(b != nullptr && info != nullptr, "null argument");
+    need(slot >= 0 && slot < b->e.nslots, "slot out of range");
+    const SlotState& h = b->e.hst[slot];
+    const double bn = h.bnorm2 > 0 ? h.bnorm2 : 1.0;
+    info->status = h.status;
+    info->iterations = h.iter;
+    info->reliable_updates = h.ru;
+    info->applications = h.apps + 1;
+    info->iterated_residual = std::sqrt(h.iter_res2 / bn);
+    info->true_residual = std::sqrt(h.true_res2 / bn);
+    info->seconds = (double)h.flags;
+    if (scale) *scale = h.scale;
+    return LQ_OK;
+  });
+}
+
 void lq_batch_destroy(lq_batch* b) { delete b; }
 
 // ---------------------------------------------------- condition number
@@ -391,6 +411,49 @@ int lq_condition_number(const lq_gauge* g, const lq_dirac* d, int32_t steps, con
     if (alpha) for (int j = 0; j < n; ++j) alpha[j] = a[j];
     if (beta) for (int j = 0; j + 1 < n; ++j) beta[j] = b[j];
     if (steps_done) *steps_done = n;
+    return LQ_OK;
+  });
+}
+
+int lq_critical_mass(const lq_gauge* g, int32_t formulation, int32_t g55_mode, double r, double lo,
+                     double hi, int32_t ngrid, int32_t ngolden, int32_t steps, const void* v0,
+                     void* ws, size_t ws_bytes, double* m_c, double* theta_min, void* stream) {
+  return guard([&] {
+    need(g && v0 && ws && m_c && theta_min, "null argument");
+    need(std::isfinite(lo) && std::isfinite(hi) && lo < hi, "need a finite bracket lo < hi");
+    need(ngrid >= 3 && ngolden >= 0, "ngrid >= 3, ngolden >= 0");
+    lq_dirac d{formulation, g55_mode, lo, r};
+    check_dirac(&d);
+    std::vector<std::pair<double, double>> trace;
+    auto f = [&](double m) {
+      d.mass = m;
+      std::vector<double> a, b;
+      lanczos_run(g, &d, steps, v0, ws, ws_bytes, a, b, S(stream));
+      double tl, th;
+      tridiag_extremes(a, b, tl, th);
+      trace.emplace_back(m, tl);
+      return tl;
+    };
+    // grid scan, then golden section on the bracket around the best grid point
+    std::vector<double> grid(ngrid), val(ngrid);
+    for (int k = 0; k < ngrid; ++k) {
+      grid[k] = lo + (hi - lo) * k / (ngrid - 1);
+      val[k] = f(grid[k]);
+    }
+    int kb = 0;
+    for (int k = 1; k < ngrid; ++k) if (val[k] < val[kb]) kb = k;
+    double a = grid[std::max(kb - 1, 0)], b = grid[std::min(kb + 1, ngrid - 1)];
+    const double gr = (std::sqrt(5.0) - 1.0) / 2.0;
+    double c = b - gr * (b - a), e = a + gr * (b - a);
+    double fc = f(c), fe = f(e);
+    for (int it = 0; it < ngolden; ++it) {
+      if (fc < fe) { b = e; e = c; fe = fc; c = b - gr * (b - a); fc = f(c); }
+      else { a = c; c = e; fc = fe; e = a + gr * (b - a); fe = f(e); }
+    }
+    size_t best = 0;
+    for (size_t k = 1; k < trace.size(); ++k) if (trace[k].second < trace[best].second) best = k;
+    *m_c = trace[best].first;
+    *theta_min = trace[best].second;
     return LQ_OK;
   });
 }

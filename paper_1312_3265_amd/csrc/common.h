@@ -75,6 +75,12 @@ struct F16 {
   __device__ __forceinline__ static void st(S* p, C v) { *p = __float22half2_rn(v); }
 };
 
+// Storage of the solution increment x_lo: FP32 when the Krylov vectors are
+// FP16.  x_lo is amplified by the operator (errors in it grow by up to kappa),
+// so FP16 rounding there would stall the outer iteration.
+template <class P> struct XPol { using type = P; };
+template <> struct XPol<F16> { using type = F32; };
+
 // --------------------------------------------------------------- geometry
 // Division by a runtime-invariant 32-bit divisor via multiply-high
 // (Granlund & Montgomery, PLDI 1994): q = (umulhi(n, m) + n) >> l for n < 2^31.

@@ -96,15 +96,17 @@ struct Engine {
   int nslots = 0;
   int prec_lo = P64, nl_lo = 18;
   int reliable_interval = 64, poll_every = 16, use_graph = 0, max_cand = 50;
+  double delta = 0.0;
   int nbp = 0;
   // device
   double2 *b = nullptr, *xhi = nullptr, *rhi = nullptr, *t64 = nullptr;
   void *xlo = nullptr, *rlo = nullptr, *p = nullptr, *t = nullptr;
   double *part_t = nullptr, *part_r = nullptr, *part_u = nullptr;
   SlotState* st = nullptr;
+  int* mask = nullptr;        // per-slot reliable-update selection
   // host
   SlotState* hst = nullptr;   // pinned mirror
-  int since_ru = 0;
+  int* hmask = nullptr;       // pinned
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   hipStream_t gstream = nullptr;
@@ -128,7 +130,7 @@ struct Engine {
   void enqueue_iterations(int n, hipStream_t s);
   void enqueue_reliable_update(hipStream_t s);
   void poll(hipStream_t s);
-  bool needs_update() const;
+  bool select_updates();
 };
 
 // Lanczos with full reorthogonalisation on A = M^dag M.

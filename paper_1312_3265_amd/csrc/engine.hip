@@ -73,9 +73,11 @@ size_t Engine::workspace_bytes(const Geom& g, int formulation, const lq_solve_op
   Carver c(nullptr);
   c.take(vhi); c.take(vhi); c.take(vhi);      // b, x_hi, r_hi
   if (prec != P64) c.take(vhi);               // t64 (shares t when FP64)
-  c.take(vlo); c.take(vlo); c.take(vlo); c.take(vlo);   // x_lo, r_lo, p, t
+  const size_t vx = (size_t)nslots * nc * g.Vp * store_bytes(prec == P16 ? P32 : prec);
+  c.take(vx); c.take(vlo); c.take(vlo); c.take(vlo);    // x_lo (FP32 under FP16), r_lo, p, t
   for (int k = 0; k < 3; ++k) c.take((size_t)nslots * nbp * sizeof(double));
   c.take((size_t)nslots * sizeof(SlotState));
+  c.take((size_t)nslots * sizeof(int));
   return c.size();
 }
 
@@ -96,6 +98,8 @@ void Engine::init(const lq_gauge_s* g, int form, int g55, double rr, int ns,
     use_graph = opts->use_graph;
     if (opts->max_restarts > 0) max_cand = opts->max_restarts;
   }
+  delta = prec_lo == P16 ? 0.1 : (prec_lo == P32 ? 1e-3 : 0.0);
+  if (opts && opts->reliable_delta > 0.0 && prec_lo != P64) delta = opts->reliable_delta;
   poll_every = (poll_every + 1) & ~1;
   if (poll_every < 2) poll_every = 2;
   // validate the stencil storage now (throws for a missing feature)
@@ -115,7 +119,7 @@ void Engine::init(const lq_gauge_s* g, int form, int g55, double rr, int ns,
   xhi = (double2*)c.take(vhi);
   rhi = (double2*)c.take(vhi);
   if (prec_lo != P64) t64 = (double2*)c.take(vhi);
-  xlo = c.take(vlo);
+  xlo = c.take((size_t)ns * nc * g->g.Vp * store_bytes(prec_lo == P16 ? P32 : prec_lo));
   rlo = c.take(vlo);
   p = c.take(vlo);
   t = c.take(vlo);
@@ -124,11 +128,14 @@ void Engine::init(const lq_gauge_s* g, int form, int g55, double rr, int ns,
   part_r = (double*)c.take((size_t)ns * nbp * sizeof(double));
   part_u = (double*)c.take((size_t)ns * nbp * sizeof(double));
   st = (SlotState*)c.take((size_t)ns * sizeof(SlotState));
+  mask = (int*)c.take((size_t)ns * sizeof(int));
   // zero the whole workspace once: plane padding stays zero afterwards
   launch_fill_zero(ws, c.size(), s);
   check_launch();
   LQ_HIP(hipHostMalloc((void**)&hst, sizeof(SlotState) * ns, hipHostMallocDefault));
   std::memset(hst, 0, sizeof(SlotState) * ns);
+  LQ_HIP(hipHostMalloc((void**)&hmask, sizeof(int) * ns, hipHostMallocDefault));
+  std::memset(hmask, 0, sizeof(int) * ns);
   LQ_HIP(hipStreamSynchronize(s));
 }
 
@@ -136,6 +143,7 @@ Engine::~Engine() {
   if (gexec) (void)hipGraphExecDestroy(gexec);
   if (graph) (void)hipGraphDestroy(graph);
   if (hst) (void)hipHostFree(hst);
+  if (hmask) (void)hipHostFree(hmask);
 }
 
 OpArgs Engine::op_args(int prec, int nl) const {
@@ -178,6 +186,7 @@ void Engine::load(int slot, const void* chi, double mass, double tol, int maxite
   init.tol = tol;
   init.maxiter = maxiter;
   init.scale = init.scale_prev = 1.0;
+  init.delta2 = delta * delta;
   hst[slot] = init;
   LQ_HIP(hipMemcpyAsync(st + slot, hst + slot, sizeof(SlotState), hipMemcpyHostToDevice, s));
   const Geom& g = gauge->g;
@@ -189,9 +198,10 @@ void Engine::load(int slot, const void* chi, double mass, double tol, int maxite
   launch_load_prepare(prec_lo, nc, g, (double*)xhi, xlo, (double*)rhi, (const double*)b, nbp, slot,
                       1, s);
   const double ncomp = (double)nc * g.V;
-  launch_ru_finish(st, part_u, nbp, slot, 1, ncomp, prec_lo != P64, max_cand, 1, 0, s);
-  launch_ru_convert(prec_lo, nc, g, st, (const double*)rhi, rlo, p, part_u, nbp, 1, slot, 1, s);
-  launch_ru_commit(st, part_u, nbp, slot, 1, s);
+  launch_ru_finish(st, nullptr, part_u, nbp, slot, 1, ncomp, prec_lo != P64, max_cand, 1, 0, s);
+  launch_ru_convert(prec_lo, nc, g, st, nullptr, (const double*)rhi, rlo, p, part_u, nbp, 1, slot,
+                    1, s);
+  launch_ru_commit(st, nullptr, part_u, nbp, slot, 1, s);
   check_launch();
   LQ_HIP(hipMemcpyAsync(hst + slot, st + slot, sizeof(SlotState), hipMemcpyDeviceToHost, s));
   LQ_HIP(hipStreamSynchronize(s));
@@ -221,22 +231,26 @@ void Engine::enqueue_iterations(int n, hipStream_t s) {
 void Engine::enqueue_reliable_update(hipStream_t s) {
   const Geom& g = gauge->g;
   const OpArgs oa = op_args(P64, 18);
-  launch_ru_accumulate(prec_lo, nc, g, st, (double*)xhi, xlo, nbp, 0, nslots, s);
+  LQ_HIP(hipMemcpyAsync(mask, hmask, sizeof(int) * nslots, hipMemcpyHostToDevice, s));
+  launch_ru_accumulate(prec_lo, nc, g, st, mask, (double*)xhi, xlo, nbp, 0, nslots, s);
   EpiArgs e = epi_base();
   e.state_mode = 2;
+  e.ru_mask = mask;
   e.out = t64;
   launch_stencil(op, P64, 18, false, EPI_STORE, oa, xhi, e, nslots, s);
   EpiArgs f = epi_base();
   f.state_mode = 2;
+  f.ru_mask = mask;
   f.out = rhi;
   f.b = b;
   f.part = part_u;
   launch_stencil(op, P64, 18, true, EPI_RESID, oa, t64, f, nslots, s);
-  launch_ru_finish(st, part_u, nbp, 0, nslots, (double)nc * g.V, prec_lo != P64, max_cand, 0, 0, s);
-  launch_ru_convert(prec_lo, nc, g, st, (const double*)rhi, rlo, p, part_u, nbp, 0, 0, nslots, s);
-  launch_ru_commit(st, part_u, nbp, 0, nslots, s);
+  launch_ru_finish(st, mask, part_u, nbp, 0, nslots, (double)nc * g.V, prec_lo != P64, max_cand, 0,
+                   0, s);
+  launch_ru_convert(prec_lo, nc, g, st, mask, (const double*)rhi, rlo, p, part_u, nbp, 0, 0, nslots,
+                    s);
+  launch_ru_commit(st, mask, part_u, nbp, 0, nslots, s);
   check_launch();
-  since_ru = 0;
 }
 
 void Engine::poll(hipStream_t s) {
@@ -244,21 +258,30 @@ void Engine::poll(hipStream_t s) {
   LQ_HIP(hipStreamSynchronize(s));
 }
 
-bool Engine::needs_update() const {
+// Choose, per slot and from that slot's state alone, whether the next chunk
+// boundary performs a reliable update: frozen slots (iterated residual met
+// tol, breakdown or maxiter) to confirm or finalise, and in mixed precision
+// every `reliable_interval` iterations.
+bool Engine::select_updates() {
+  bool any = false;
   for (int k = 0; k < nslots; ++k) {
     const SlotState& h = hst[k];
-    if (h.status != SLOT_RUNNING) continue;
-    if (h.stop[0] || h.flags) return true;          // frozen: confirm or finalise
-    if (prec_lo != P64 && since_ru >= reliable_interval) return true;
+    int sel = 0;
+    if (h.status == SLOT_RUNNING) {
+      if (h.stop[0] || h.flags) sel = 1;
+      if (prec_lo != P64 && h.iter - h.ru_iter >= reliable_interval) sel = 1;
+    }
+    hmask[k] = sel;
+    any = any || sel;
   }
-  return false;
+  return any;
 }
 
 void Engine::step(int iters, hipStream_t s) {
   int done = 0;
   while (done < iters) {
     if (!running()) return;
-    if (needs_update()) {
+    if (select_updates()) {
       enqueue_reliable_update(s);
       poll(s);
       if (!running()) return;
@@ -288,11 +311,10 @@ void Engine::step(int iters, hipStream_t s) {
     }
     if (!graphed) enqueue_iterations(n, s);
     check_launch();
-    since_ru += n;
     done += n;
     poll(s);
   }
-  if (running() && needs_update()) {
+  if (running() && select_updates()) {
     enqueue_reliable_update(s);
     poll(s);
   }

@@ -81,6 +81,7 @@ p_update_kernel(const Geom g, SlotState* st, int par, const double* __restrict__
     int stop = 0;
     if (!isfinite(rr) || (s->flags & 1)) { s->flags |= 1; stop = 1; }
     if (rr <= s->thr_lo2) stop = 1;
+    else if (s->delta2 > 0.0 && rr <= s->delta2 * s->rho_ru) { stop = 1; s->want_ru = 1; }
     if (s->iter >= s->maxiter) { s->flags |= 2; stop = 1; }
     s->stop[par ^ 1] = stop;
   }
@@ -89,13 +90,14 @@ p_update_kernel(const Geom g, SlotState* st, int par, const double* __restrict__
 // ------------------------------------------------------- reliable updates
 template <class P, int NC>
 __global__ void __launch_bounds__(256)
-ru_accumulate_kernel(const Geom g, const SlotState* st, double2* __restrict__ xhi,
-                     typename P::S* __restrict__ xlo, int nbp, int k0, int nrhs) {
-  using C = typename P::C;
+ru_accumulate_kernel(const Geom g, const SlotState* st, const int* mask, double2* __restrict__ xhi,
+                     typename XPol<P>::type::S* __restrict__ xlo, int nbp, int k0, int nrhs) {
+  using XP = typename XPol<P>::type;
+  using C = typename XP::C;
   int sb, kl;
   map_block(nbp, nrhs, sb, kl);
   const int k = k0 + kl;
-  if (st[k].status != SLOT_RUNNING) return;
+  if (!ru_selected(st, mask, k)) return;
   const double sc = st[k].scale;
   const int i = sb * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
@@ -103,21 +105,22 @@ ru_accumulate_kernel(const Geom g, const SlotState* st, double2* __restrict__ xh
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
     const size_t e = off + (size_t)q * g.Vp + i;
-    C v = P::ld(xlo + e);
+    C v = XP::ld(xlo + e);
     double2 h = xhi[e];
     h.x += sc * (double)v.x;
     h.y += sc * (double)v.y;
     xhi[e] = h;
-    P::st(xlo + e, czero<C>());
+    XP::st(xlo + e, czero<C>());
   }
 }
 
-__global__ void ru_finish_kernel(SlotState* st, const double* __restrict__ part, int nbp, int k0,
-                                 double ncomp, int rescale, int max_cand, int init, int par) {
+__global__ void ru_finish_kernel(SlotState* st, const int* mask, const double* __restrict__ part,
+                                 int nbp, int k0, double ncomp, int rescale, int max_cand,
+                                 int init, int par) {
   __shared__ double red[16];
   const int k = k0 + blockIdx.x;
   SlotState* s = st + k;
-  if (s->status != SLOT_RUNNING) return;
+  if (!ru_selected(st, mask, k)) return;
   const double rr = sum_partials(part + (size_t)k * nbp, nbp, red);
   if (threadIdx.x != 0) return;
   if (init) {
@@ -127,15 +130,17 @@ __global__ void ru_finish_kernel(SlotState* st, const double* __restrict__ part,
     s->ru += 1;
     s->apps += 1;
   }
+  s->ru_iter = s->iter;
   s->true_res2 = rr;
   if (!isfinite(rr)) { s->flags |= 1; s->status = SLOT_FAILED; return; }
   if (rr <= s->thr2) { s->status = SLOT_DONE; return; }
   if (s->flags) { s->status = SLOT_FAILED; return; }
-  if (!init && s->stop[par]) {
+  if (!init && s->stop[par] && !s->want_ru) {
     // the iterated residual met tol but the true residual did not
     s->cand += 1;
     if (s->cand > max_cand) { s->flags |= 4; s->status = SLOT_FAILED; return; }
   }
+  s->want_ru = 0;
   double sn = rescale ? sqrt(rr / ncomp) : 1.0;
   if (!(sn > 0.0) || !isfinite(sn)) sn = 1.0;
   s->scale_prev = init ? sn : s->scale;
@@ -145,16 +150,17 @@ __global__ void ru_finish_kernel(SlotState* st, const double* __restrict__ part,
 
 template <class P, int NC>
 __global__ void __launch_bounds__(256)
-ru_convert_kernel(const Geom g, const SlotState* st, const double2* __restrict__ rhi,
-                  typename P::S* __restrict__ rlo, typename P::S* __restrict__ p,
-                  double* __restrict__ part, int nbp, int init, int k0, int nrhs) {
+ru_convert_kernel(const Geom g, const SlotState* st, const int* mask,
+                  const double2* __restrict__ rhi, typename P::S* __restrict__ rlo,
+                  typename P::S* __restrict__ p, double* __restrict__ part, int nbp, int init,
+                  int k0, int nrhs) {
   using C = typename P::C;
   using R = typename P::R;
   __shared__ double red[16];
   int sb, kl;
   map_block(nbp, nrhs, sb, kl);
   const int k = k0 + kl;
-  if (st[k].status != SLOT_RUNNING) return;
+  if (!ru_selected(st, mask, k)) return;
   const double inv = 1.0 / st[k].scale;
   const R pr = (R)(st[k].scale_prev / st[k].scale);
   const int i = sb * blockDim.x + threadIdx.x;
@@ -185,24 +191,27 @@ ru_convert_kernel(const Geom g, const SlotState* st, const double2* __restrict__
   if (threadIdx.x == 0) part[(size_t)k * nbp + sb] = s;
 }
 
-__global__ void ru_commit_kernel(SlotState* st, const double* __restrict__ part, int nbp, int k0) {
+__global__ void ru_commit_kernel(SlotState* st, const int* mask, const double* __restrict__ part,
+                                 int nbp, int k0) {
   __shared__ double red[16];
   const int k = k0 + blockIdx.x;
   SlotState* s = st + k;
-  if (s->status != SLOT_RUNNING) return;
+  if (!ru_selected(st, mask, k)) return;
   const double rr = sum_partials(part + (size_t)k * nbp, nbp, red);
   if (threadIdx.x != 0) return;
   s->rho[0] = s->rho[1] = rr;
+  s->rho_ru = rr;
   s->stop[0] = s->stop[1] = 0;
   s->iter_res2 = rr * s->scale * s->scale;
 }
 
 template <class P, int NC>
 __global__ void __launch_bounds__(256)
-load_prepare_kernel(const Geom g, double2* __restrict__ xhi, typename P::S* __restrict__ xlo,
-                    double2* __restrict__ rhi, const double2* __restrict__ b, int nbp, int k0,
-                    int nrhs) {
-  using C = typename P::C;
+load_prepare_kernel(const Geom g, double2* __restrict__ xhi,
+                    typename XPol<P>::type::S* __restrict__ xlo, double2* __restrict__ rhi,
+                    const double2* __restrict__ b, int nbp, int k0, int nrhs) {
+  using XP = typename XPol<P>::type;
+  using C = typename XP::C;
   int sb, kl;
   map_block(nbp, nrhs, sb, kl);
   const int k = k0 + kl;
@@ -213,7 +222,7 @@ load_prepare_kernel(const Geom g, double2* __restrict__ xhi, typename P::S* __re
   for (int q = 0; q < NC; ++q) {
     const size_t e = off + (size_t)q * g.Vp + i;
     xhi[e] = make_double2(0.0, 0.0);
-    P::st(xlo + e, czero<C>());
+    XP::st(xlo + e, czero<C>());
     rhi[e] = b[e];
   }
 }
@@ -239,37 +248,38 @@ void launch_p_update(int prec, int nc, const Geom& g, SlotState* st, int par, co
                                        (const typename PP::S*)r, k0, nrhs));
 }
 
-void launch_ru_accumulate(int prec, int nc, const Geom& g, const SlotState* st, double* xhi,
-                          void* xlo, int nbp, int k0, int nrhs, hipStream_t s) {
+void launch_ru_accumulate(int prec, int nc, const Geom& g, const SlotState* st, const int* mask,
+                          double* xhi, void* xlo, int nbp, int k0, int nrhs, hipStream_t s) {
   if (nbp * nrhs == 0) return;
   LQ_PREC_NC_SWITCH(prec, nc,
                     hipLaunchKernelGGL((ru_accumulate_kernel<PP, NCC>), dim3(nbp * nrhs),
-                                       dim3(kBlock), 0, s, g, st, (double2*)xhi,
-                                       (typename PP::S*)xlo, nbp, k0, nrhs));
+                                       dim3(kBlock), 0, s, g, st, mask, (double2*)xhi,
+                                       (typename XPol<PP>::type::S*)xlo, nbp, k0, nrhs));
 }
 
-void launch_ru_finish(SlotState* st, const double* part, int nbp, int k0, int nrhs, double ncomp,
-                      int rescale, int max_cand, int init, int par, hipStream_t s) {
+void launch_ru_finish(SlotState* st, const int* mask, const double* part, int nbp, int k0,
+                      int nrhs, double ncomp, int rescale, int max_cand, int init, int par,
+                      hipStream_t s) {
   if (nrhs == 0) return;
-  hipLaunchKernelGGL(ru_finish_kernel, dim3(nrhs), dim3(64), 0, s, st, part, nbp, k0, ncomp,
+  hipLaunchKernelGGL(ru_finish_kernel, dim3(nrhs), dim3(64), 0, s, st, mask, part, nbp, k0, ncomp,
                      rescale, max_cand, init, par);
 }
 
-void launch_ru_convert(int prec, int nc, const Geom& g, const SlotState* st, const double* rhi,
-                       void* rlo, void* p, double* part, int nbp, int init, int k0, int nrhs,
-                       hipStream_t s) {
+void launch_ru_convert(int prec, int nc, const Geom& g, const SlotState* st, const int* mask,
+                       const double* rhi, void* rlo, void* p, double* part, int nbp, int init,
+                       int k0, int nrhs, hipStream_t s) {
   if (nbp * nrhs == 0) return;
   LQ_PREC_NC_SWITCH(prec, nc,
                     hipLaunchKernelGGL((ru_convert_kernel<PP, NCC>), dim3(nbp * nrhs),
-                                       dim3(kBlock), 0, s, g, st, (const double2*)rhi,
+                                       dim3(kBlock), 0, s, g, st, mask, (const double2*)rhi,
                                        (typename PP::S*)rlo, (typename PP::S*)p, part, nbp, init,
                                        k0, nrhs));
 }
 
-void launch_ru_commit(SlotState* st, const double* part, int nbp, int k0, int nrhs,
-                      hipStream_t s) {
+void launch_ru_commit(SlotState* st, const int* mask, const double* part, int nbp, int k0,
+                      int nrhs, hipStream_t s) {
   if (nrhs == 0) return;
-  hipLaunchKernelGGL(ru_commit_kernel, dim3(nrhs), dim3(64), 0, s, st, part, nbp, k0);
+  hipLaunchKernelGGL(ru_commit_kernel, dim3(nrhs), dim3(64), 0, s, st, mask, part, nbp, k0);
 }
 
 void launch_load_prepare(int prec, int nc, const Geom& g, double* xhi, void* xlo, double* rhi,
@@ -277,8 +287,9 @@ void launch_load_prepare(int prec, int nc, const Geom& g, double* xhi, void* xlo
   if (nbp * nrhs == 0) return;
   LQ_PREC_NC_SWITCH(prec, nc,
                     hipLaunchKernelGGL((load_prepare_kernel<PP, NCC>), dim3(nbp * nrhs),
-                                       dim3(kBlock), 0, s, g, (double2*)xhi, (typename PP::S*)xlo,
-                                       (double2*)rhi, (const double2*)b, nbp, k0, nrhs));
+                                       dim3(kBlock), 0, s, g, (double2*)xhi,
+                                       (typename XPol<PP>::type::S*)xlo, (double2*)rhi,
+                                       (const double2*)b, nbp, k0, nrhs));
 }
 
 // ------------------------------------------------------------- Lanczos

@@ -22,6 +22,8 @@ struct SlotState {
   double tol;
   double true_res2;  // ||b - A x_hi||^2 at the latest reliable update
   double iter_res2;  // ||r_lo||^2 * scale^2 at the latest iteration
+  double rho_ru;     // ||r_lo||^2 right after the latest reliable update
+  double delta2;     // request a reliable update once rho <= delta2 * rho_ru (0: never)
   int32_t stop[2];   // ring: 1 = frozen until the next reliable update
   int32_t status;    // 0 empty, 1 running, 2 converged, 3 failed
   int32_t iter;      // CG iterations done
@@ -30,9 +32,18 @@ struct SlotState {
   int32_t maxiter;
   int32_t flags;     // bit0 breakdown, bit1 maxiter reached
   int32_t apps;      // applications of A (iterations + reliable updates + setup)
+  int32_t ru_iter;   // iteration count at the latest reliable update
+  int32_t want_ru;   // frozen because the residual dropped by delta (not converged)
   int32_t pad;
 };
 
 enum SlotStatus { SLOT_EMPTY = 0, SLOT_RUNNING = 1, SLOT_DONE = 2, SLOT_FAILED = 3 };
+
+// A reliable update acts on slot k only when mask[k] != 0 (host-chosen per
+// slot from that slot's own state), so a system's trajectory does not depend
+// on which other systems share the batch.
+__host__ __device__ inline bool ru_selected(const SlotState* st, const int* mask, int k) {
+  return st[k].status == SLOT_RUNNING && (mask == nullptr || mask[k] != 0);
+}
 
 }  // namespace lq

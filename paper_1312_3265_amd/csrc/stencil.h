@@ -33,7 +33,8 @@ struct EpiArgs {
   int k0;                 // first RHS index handled by this launch
   SlotState* st;          // per-RHS solver state (null: no state checks)
   int par;                // iteration parity (ring index into SlotState)
-  int state_mode;         // 0: none, 1: running and not frozen, 2: running
+  int state_mode;         // 0: none, 1: running and not frozen, 2: running and in ru_mask
+  const int* ru_mask;     // per-RHS reliable-update selection (state_mode 2)
   void* x;                // CG_UPDATE: x_lo
   void* r;                // CG_UPDATE: r_lo
   const void* p;          // CG_UPDATE: p
@@ -52,11 +53,12 @@ __device__ __forceinline__ void map_block(int nbp, int nrhs, int& sb, int& k) {
   sb = 8 * j + xcd;
 }
 
-__device__ __forceinline__ bool slot_active(const SlotState* st, int mode, int par) {
+__device__ __forceinline__ bool slot_active(const SlotState* st, int k, int mode, int par,
+                                            const int* mask) {
   if (mode == 0) return true;
-  if (st->status != SLOT_RUNNING) return false;
-  if (mode == 1 && st->stop[par]) return false;
-  return true;
+  if (st[k].status != SLOT_RUNNING) return false;
+  if (mode == 1) return st[k].stop[par] == 0;
+  return mask == nullptr || mask[k] != 0;
 }
 
 // Register budget: FP64 kernels are held to 4 waves per SIMD (128 VGPRs) so
@@ -72,7 +74,7 @@ stencil_kernel(const OpArgs oa, const typename Op::S* __restrict__ in, const Epi
   int sb, kl;
   map_block(ea.nbp, nrhs, sb, kl);
   const int k = ea.k0 + kl;
-  if (ea.st && !slot_active(ea.st + k, ea.state_mode, ea.par)) return;
+  if (ea.st && !slot_active(ea.st, k, ea.state_mode, ea.par, ea.ru_mask)) return;
 
   const int Vp = oa.g.Vp;
   const int i = sb * blockDim.x + threadIdx.x;
@@ -100,17 +102,19 @@ stencil_kernel(const OpArgs oa, const typename Op::S* __restrict__ in, const Epi
         if constexpr (EPI == EPI_STORE_NORM) acc += cnorm2(Op::Pol::ld(out + (size_t)q * Vp + i));
       }
     } else if constexpr (EPI == EPI_CG_UPDATE) {
-      S* x = (S*)ea.x + off;
+      using XP = typename XPol<typename Op::Pol>::type;
+      typename XP::S* x = (typename XP::S*)ea.x + off;
       S* r = (S*)ea.r + off;
       const S* p = (const S*)ea.p + off;
       const R a = (R)alpha;
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
         const size_t e = (size_t)q * Vp + i;
-        P_C xv = Op::Pol::ld(x + e), pv = Op::Pol::ld(p + e), rv = Op::Pol::ld(r + e);
+        typename XP::C xv = XP::ld(x + e);
+        P_C pv = Op::Pol::ld(p + e), rv = Op::Pol::ld(r + e);
         xv.x += a * pv.x; xv.y += a * pv.y;
         rv.x -= a * o[q].x; rv.y -= a * o[q].y;
-        Op::Pol::st(x + e, xv);
+        XP::st(x + e, xv);
         Op::Pol::st(r + e, rv);
         acc += cnorm2(Op::Pol::ld(r + e));
       }

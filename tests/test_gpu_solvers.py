@@ -1,0 +1,162 @@
+"""GPU solver parity: mixed precision with FP64 reliable updates, batched
+multi-RHS solves, continuous batching (alone vs in the mix), failure
+statuses, and the m_c search.  Every solution is judged by the oracle's FP64
+true residual ||b - A x|| / ||b||, b = M^dag chi (several x are correct;
+the residual is unique)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import critical, solvers
+
+pytestmark = pytest.mark.gpu
+
+lq = pytest.importorskip("paper_1312_3265_amd")
+torch = pytest.importorskip("torch")
+
+DIMS = (8, 8, 6, 8)          # V = 3072: 12 site blocks of 256
+EPS = 0.436
+MASS = {synth.WILSON: -0.30, synth.STAGGERED_WILSON: -0.35}
+
+_G = {}
+
+
+def _field(dims=DIMS, seed=5):
+    key = (dims, seed)
+    if key not in _G:
+        U = synth.gauge_field(dims, "near_identity", seed, EPS)
+        lat = lq.Lattice(dims)
+        _G[key] = (U, lat, lq.Gauge(lat, U))
+    return _G[key]
+
+
+def _res(form, U, chi, x, m):
+    rn, _ = solvers.true_residual(form, U, chi, x.cpu().numpy(), m)
+    return rn
+
+
+@pytest.mark.parametrize("formulation", [synth.WILSON, synth.STAGGERED_WILSON])
+@pytest.mark.parametrize("precision,links", [(lq.F32, 18), (lq.F32, 12), (lq.F16, 12)])
+def test_mixed_precision_reaches_fp64_tolerance(formulation, precision, links):
+    U, lat, g = _field()
+    chi = synth.point_source(DIMS, formulation, 1)
+    m, tol = MASS[formulation], 1e-8
+    opts = lq.solve_opts(precision=precision, links=links, reliable_interval=50)
+    x, info = lq.cg_solve(g, formulation, m, chi, tol, opts=opts)
+    assert info["status"] == lq.OK, info
+    assert info["reliable_updates"] >= 1
+    rn = _res(formulation, U, chi, x, m)
+    assert rn <= tol, (rn, info)
+    x64, i64 = lq.cg_solve(g, formulation, m, chi, tol)
+    err = (torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64)).item()
+    print(f"prec={precision} links={links} iters={info['iterations']} "
+          f"(fp64 {i64['iterations']}) ru={info['reliable_updates']} err_vs_fp64={err:.2e}")
+
+
+def test_otf_gamma55_solve():
+    U, lat, g = _field()
+    chi = synth.point_source(DIMS, synth.STAGGERED_WILSON, 0)
+    m, tol = MASS[synth.STAGGERED_WILSON], 1e-9
+    xa, ia = lq.cg_solve(g, synth.STAGGERED_WILSON, m, chi, tol, g55=lq.G55_ONTHEFLY)
+    xb, ib = lq.cg_solve(g, synth.STAGGERED_WILSON, m, chi, tol, g55=lq.G55_CORNERS)
+    assert ia["status"] == lq.OK and ib["status"] == lq.OK
+    assert _res(synth.STAGGERED_WILSON, U, chi, xa, m) <= tol
+    assert abs(ia["iterations"] - ib["iterations"]) <= 2
+
+
+def test_batched_multi_rhs_all_sources_and_masses():
+    U, lat, g = _field()
+    form = synth.WILSON
+    chis, masses = [], []
+    for alpha in (0, 4, 11):
+        for dm in (0.0, 0.05):
+            chis.append(synth.point_source(DIMS, form, alpha))
+            masses.append(MASS[form] + dm)
+    tol = 1e-8
+    for opts in (lq.solve_opts(), lq.solve_opts(precision=lq.F16, links=12)):
+        x, infos = lq.cg_solve_batch(g, form, masses, np.stack(chis), [tol] * len(chis),
+                                     opts=opts)
+        for k in range(len(chis)):
+            assert infos[k]["status"] == lq.OK
+            assert _res(form, U, chis[k], x[k], masses[k]) <= tol
+
+
+def test_batch_result_is_bitwise_the_single_result():
+    """Each system's trajectory depends on its own state only (per-slot
+    reliable updates, fixed-order reductions), so batching changes nothing."""
+    U, lat, g = _field()
+    form = synth.STAGGERED_WILSON
+    chis = np.stack([synth.point_source(DIMS, form, a) for a in range(3)]
+                    + [synth.z2_source(DIMS, form, 9)])
+    masses = [MASS[form], MASS[form] + 0.1, MASS[form] + 0.02, MASS[form] + 0.05]
+    tols = [1e-8, 1e-9, 1e-7, 1e-8]
+    opts = lq.solve_opts(precision=lq.F32, links=12, reliable_interval=40)
+    xb, ib = lq.cg_solve_batch(g, form, masses, chis, tols, opts=opts)
+    for k in range(4):
+        xs, is_ = lq.cg_solve(g, form, masses[k], chis[k], tols[k], opts=opts)
+        assert is_["iterations"] == ib[k]["iterations"]
+        assert torch.equal(xs, xb[k])
+
+
+def test_continuous_batching_alone_vs_in_the_mix():
+    """Requests admitted while others iterate give the same result as alone."""
+    U, lat, g = _field()
+    form = synth.WILSON
+    opts = lq.solve_opts(precision=lq.F16, links=12, reliable_interval=48, poll_interval=8)
+    reqs = [(synth.point_source(DIMS, form, a), MASS[form] + d, t)
+            for a, d, t in ((0, 0.0, 1e-8), (5, 0.05, 1e-7), (7, 0.1, 1e-9), (2, 0.02, 1e-8),
+                            (9, 0.05, 1e-6))]
+    alone = [lq.cg_solve(g, form, m, c, t, opts=opts) for c, m, t in reqs]
+    b = lq.Batch(g, form, nslots=3, opts=opts)
+    pending = list(range(len(reqs)))
+    slot_of, results = {}, {}
+    free = [0, 1, 2]
+    guard = 0
+    while pending or slot_of:
+        while pending and free:
+            k = pending.pop(0)
+            s = free.pop(0)
+            c, m, t = reqs[k]
+            b.load(s, c, m, t)
+            slot_of[s] = k
+        states = b.step(16)
+        for s, st in enumerate(states):
+            if s in slot_of and st in (lq.SLOT_DONE, lq.SLOT_FAILED):
+                results[slot_of.pop(s)] = b.fetch(s)
+                free.append(s)
+        guard += 1
+        assert guard < 10000
+    for k, (c, m, t) in enumerate(reqs):
+        xm, im = results[k]
+        xa, ia = alone[k]
+        assert im["status"] == lq.OK
+        assert im["iterations"] == ia["iterations"]
+        assert torch.equal(xm, xa)
+        assert _res(form, U, c, xm, m) <= t
+
+
+def test_failure_statuses():
+    U, lat, g = _field()
+    form = synth.STAGGERED_WILSON
+    chi = synth.point_source(DIMS, form, 0)
+    x, info = lq.cg_solve(g, form, MASS[form], chi, 1e-12, maxiter=5)
+    assert info["status"] == lq.NOT_CONVERGED and info["iterations"] == 5
+    bad = chi.copy()
+    bad[0, 0, 0, 1, 1] = np.nan
+    with pytest.raises(lq.LQError) as e:
+        lq.cg_solve(g, form, MASS[form], bad, 1e-8)
+    assert e.value.code == lq.ERR_ARG
+
+
+@pytest.mark.parametrize("formulation", [synth.WILSON, synth.STAGGERED_WILSON])
+def test_critical_mass_matches_oracle_search(formulation):
+    dims = (6, 6, 6, 6)
+    U = synth.gauge_field(dims, "near_identity", 77, EPS)
+    lat = lq.Lattice(dims)
+    g = lq.Gauge(lat, U)
+    v0 = synth.gaussian_field(dims, formulation, 7)
+    mc, th = lq.critical_mass(g, formulation, v0, -0.8, -0.2, steps=80, ngrid=5, ngolden=4)
+    mco, tho, _ = critical.critical_mass(formulation, U, v0, -0.8, -0.2, steps=80, ngrid=5,
+                                         ngolden=4)
+    assert abs(mc - mco) <= 1e-9
+    assert abs(th - tho) <= 1e-6 * abs(tho) + 1e-12
