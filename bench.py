@@ -1,0 +1,285 @@
+"""Benchmark: CG solves/s on the 16^3 x 32 workload, mixed-precision batched vs FP64.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (synthetic stand-in for the paper's quenched beta = 6 ensemble on
+16^3 x 32, Sec. 3): 8 gauge fields of independent near-identity SU(3) links
+(seeds 2000..2007, spread tuned to mean plaquette 0.594), point sources at the
+origin -- 12 spin-colour sources for Wilson and 3 colour sources for staggered
+Wilson, as the paper averages over -- at bare masses m_c + delta, delta in
+{0.02, 0.05, 0.1}, with m_c frozen per formulation by the oracle
+(tests/golden/workloads.json).  Every system is solved to an FP64 true
+residual ||b - A x|| / ||b|| <= 1e-8 on eq. (2), unpreconditioned.
+
+One step = all 360 systems: per field, one batched launch sequence for the 36
+Wilson systems and one for the 9 staggered Wilson systems, FP32 stencil and
+Krylov vectors with FP64 reliable updates.  `value` is systems solved per
+second over the timed steps.  Alongside (outside the timed region): FP64
+single-RHS CG on the same mix (the baseline the speed-up is quoted against),
+the dominant kernel's roofline figures from HIP events, the Lanczos condition
+numbers and the oracle timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = os.path.join(ROOT, "tests", "golden", "workloads.json")
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+TOL = 1e-8
+DELTAS = (0.02, 0.05, 0.1)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def load_workload():
+    with open(WORKLOADS) as f:
+        w = json.load(f)
+    return w
+
+
+def bytes_per_site(formulation, precision, links, nrhs):
+    """Compulsory HBM bytes per site of one stencil launch over nrhs fields:
+    input and output vectors once per RHS, the links (and corners) once."""
+    nc = 12 if formulation == 0 else 3
+    per = {0: 16, 1: 8, 2: 4}[precision]
+    vec = 2 * nc * per
+    link = 4 * (links // 2) * per if precision != 0 else 4 * 9 * 16
+    corner = 0 if formulation == 0 else 8 * 9 * per
+    return nrhs * vec + link + corner
+
+
+def cpu_baseline(U, workload, iters_fp64):
+    """The oracle, timed on the host on a bounded sample: a few CG iterations
+    of each formulation at the delta = 0.1 mass, single-threaded BLAS."""
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import solvers
+
+    dims = tuple(workload["dims"])
+    out = {}
+    with threadpool_limits(limits=1):
+        for form, name in ((0, "wilson"), (1, "staggered_wilson")):
+            m = workload["m_c"][name] + 0.1
+            M, Md, A = solvers.operator(form, U, m)
+            b = Md(synth.point_source(dims, form, 0))
+            n = 3
+            t0 = time.time()
+            x, info = solvers.cg(A, b, 1e-30, n)
+            # n iterations plus the closing true-residual application of A
+            out[name] = (time.time() - t0) / (n + 1)
+    # projected solve time on the benchmark mix: GPU FP64 iteration counts x
+    # oracle seconds per iteration
+    tot = 0.0
+    nsys = 0
+    for name, per_sys in (("wilson", 12), ("staggered_wilson", 3)):
+        for d in DELTAS:
+            tot += 8 * per_sys * iters_fp64[name][str(d)] * out[name]
+            nsys += 8 * per_sys
+    return dict(value=nsys / tot, unit="solves/s", cores=1, kind="oracle",
+                sample=("3 oracle CG iterations per formulation at 16^3x32, delta=0.1, "
+                        "1 BLAS thread; projected to the 360-system mix with the GPU FP64 "
+                        f"iteration counts (s/iter: W {out['wilson']:.2f}, "
+                        f"SW {out['staggered_wilson']:.2f})"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f16"])
+    ap.add_argument("--fields", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the workload is a single-GPU batch of "
+              "independent solves (multi-GPU runs are not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1312_3265_amd as lq
+    import synth
+
+    w = load_workload()
+    dims = tuple(w["dims"])
+    eps = w["eps"]
+    mc = w["m_c"]
+    seeds = w["batch_seeds"][: a.fields]
+    prec = lq.F32 if a.precision == "f32" else lq.F16
+    links = 12
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+
+    # ---------------------------------------------------------------- setup
+    t0 = time.time()
+    lat = lq.Lattice(dims)
+    fields = []
+    U0 = None
+    for s in seeds:
+        U = synth.gauge_field(dims, "near_identity", s, eps)
+        if U0 is None:
+            U0 = U
+        fields.append(lq.Gauge(lat, U, lq.FEAT_CORNERS | lq.FEAT_F32 | lq.FEAT_F16,
+                               stream=stream))
+    plaq = fields[0].plaquette(stream=stream)
+    src = {}
+    masses = {}
+    for form, name, nsrc in ((0, "wilson", 12), (1, "staggered_wilson", 3)):
+        chis, ms = [], []
+        for d in DELTAS:
+            for alpha in range(nsrc):
+                chis.append(synth.point_source(dims, form, alpha))
+                ms.append(mc[name] + d)
+        src[form] = torch.from_numpy(np.stack(chis)).to("cuda")
+        masses[form] = ms
+    opts = lq.solve_opts(precision=prec, links=links, poll_interval=16, use_graph=1)
+    ws = {}
+    for form in (0, 1):
+        n = len(masses[form])
+        ws[form] = torch.empty(lq.solve_workspace_bytes(fields[0], form, opts, n),
+                               dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    log(f"setup {time.time() - t0:.1f}s plaquette {plaq:.4f} m_c {mc}")
+
+    def one_step(record=None):
+        n = 0
+        for gi, g in enumerate(fields):
+            for form in (0, 1):
+                x, infos = lq.cg_solve_batch(g, form, masses[form], src[form],
+                                             [TOL] * len(masses[form]), opts=opts,
+                                             stream=stream, workspace=ws[form])
+                for k, inf in enumerate(infos):
+                    if inf["status"] != lq.OK or inf["true_residual"] > TOL:
+                        raise RuntimeError(f"field {gi} formulation {form} system {k}: {inf}")
+                    if record is not None:
+                        record.append((gi, form, k, inf["iterations"], inf["reliable_updates"]))
+                n += len(infos)
+        return n
+
+    for i in range(a.warmup):
+        one_step()
+        log(f"warmup step {i} done")
+    rec = []
+    torch.cuda.synchronize()
+    t0 = time.time()
+    nsolved = 0
+    for i in range(a.steps):
+        nsolved += one_step(rec if i == 0 else None)
+        log(f"step {i} done")
+    torch.cuda.synchronize()
+    elapsed = time.time() - t0
+    value = nsolved / elapsed
+
+    # ------------------------------------------ FP64 single-RHS reference
+    g0 = fields[0]
+    iters64 = {"wilson": {}, "staggered_wilson": {}}
+    t64 = {"wilson": {}, "staggered_wilson": {}}
+    for form, name in ((0, "wilson"), (1, "staggered_wilson")):
+        for d in DELTAS:
+            chi = synth.point_source(dims, form, 0)
+            lq.cg_solve(g0, form, mc[name] + d, chi, TOL, stream=stream)   # warm
+            torch.cuda.synchronize()
+            ts = time.time()
+            x, inf = lq.cg_solve(g0, form, mc[name] + d, chi, TOL, stream=stream)
+            torch.cuda.synchronize()
+            t64[name][str(d)] = time.time() - ts
+            iters64[name][str(d)] = inf["iterations"]
+            assert inf["status"] == lq.OK and inf["true_residual"] <= TOL
+    per_field = sum(t64["wilson"][str(d)] * 12 + t64["staggered_wilson"][str(d)] * 3
+                    for d in DELTAS)
+    fp64_rate = 45.0 / per_field
+    mixed_iters = {"wilson": {}, "staggered_wilson": {}}
+    for gi, form, k, it, ru in rec:
+        if gi == 0:
+            name = "wilson" if form == 0 else "staggered_wilson"
+            d = str(DELTAS[k // (12 if form == 0 else 3)])
+            mixed_iters[name].setdefault(d, []).append(it)
+    mixed_iters = {n: {d: float(np.mean(v)) for d, v in dd.items()} for n, dd in mixed_iters.items()}
+
+    # --------------------------------------------- dominant kernel roofline
+    nrhs = 36
+    reps = 50
+    ms = lq.time_dslash(g0, 0, mc["wilson"] + 0.1, dagger=False, precision=prec, links=links,
+                        nrhs=nrhs, reps=reps, stream=stream)
+    V = lat.volume
+    algo = bytes_per_site(0, prec, links, nrhs) * V
+    achieved = algo / (ms * 1e-3) / 1e9
+    ms64 = lq.time_dslash(g0, 0, mc["wilson"] + 0.1, precision=lq.F64, reps=reps, stream=stream)
+    ms64_sw = lq.time_dslash(g0, 1, mc["staggered_wilson"] + 0.1, precision=lq.F64, reps=reps,
+                             stream=stream)
+    gbs64 = bytes_per_site(0, 0, 18, 1) * V / (ms64 * 1e-3) / 1e9
+    gbs64_sw = bytes_per_site(1, 0, 18, 1) * V / (ms64_sw * 1e-3) / 1e9
+
+    # ----------------------------------------------- condition numbers (context)
+    kap = {}
+    for form, name in ((0, "wilson"), (1, "staggered_wilson")):
+        v0 = synth.gaussian_field(dims, form, w["v0_seed"])
+        r = lq.condition_number(g0, form, mc[name] + 0.1, v0, steps=200, stream=stream)
+        kap[name] = r["kappa"]
+
+    cpu = None
+    if not a.no_cpu:
+        cpu = cpu_baseline(U0, w, iters64)
+
+    iter_ratio = {d: iters64["wilson"][str(d)] / iters64["staggered_wilson"][str(d)]
+                  for d in DELTAS}
+    line = {
+        "metric": "CG solves/s + Dslash HBM GB/s vs peak, 16^3x32, mixed-prec batched vs FP64",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(elapsed / a.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == lq.F32 else "f16",
+        "data": "synthetic",
+        "config": {
+            "workload": ("16^3x32, 8 near-identity SU(3) fields (plaquette 0.594), "
+                         "W 12 + SW 3 point sources x 3 masses m_c+{0.02,0.05,0.1}, "
+                         "tol 1e-8, batched CG with FP64 reliable updates"),
+            "systems_per_step": nsolved // a.steps,
+            "precision": a.precision, "links": links,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": f"Wilson M p + ||t||^2, {a.precision} 12-real links, {nrhs} RHS",
+            "avg_launch_us": round(ms * 1e3, 2),
+            "algorithmic_bytes_per_launch": int(algo),
+        },
+        "cpu_baseline": cpu,
+        "fp64_single_rhs": {
+            "solves_per_s_same_mix": round(fp64_rate, 3),
+            "speedup_mixed_batched_vs_fp64": round(value / fp64_rate, 2),
+            "iterations": iters64,
+            "seconds": {n: {d: round(v, 4) for d, v in dd.items()} for n, dd in t64.items()},
+            "dslash_fp64_gbs": {"wilson": round(gbs64, 1), "staggered_wilson_corners": round(gbs64_sw, 1)},
+            "dslash_fp64_us": {"wilson": round(ms64 * 1e3, 1), "staggered_wilson_corners": round(ms64_sw * 1e3, 1)},
+        },
+        "mixed_iterations_field0": mixed_iters,
+        "paper_context": {
+            "cg_iteration_ratio_W_over_SW": {str(d): round(v, 2) for d, v in iter_ratio.items()},
+            "sqrt_kappa_ratio_W_over_SW_delta0.1": round((kap["wilson"] / kap["staggered_wilson"]) ** 0.5, 2),
+            "kappa_lanczos200_delta0.1": {k: round(v, 1) for k, v in kap.items()},
+        },
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -175,9 +175,14 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t op, int32_t precision
              int32_t links, const void* in, void* out, void* ws, size_t ws_bytes,
              void* stream);
 
-/* Average device time (ms) of one stencil launch M or M^dag on fields already
- * in the library layout, over `reps` back-to-back launches, measured with HIP
- * events on `stream`.  Uses the same kernels as the solvers.  */
+/* Average device time (ms) of one stencil launch on `nrhs` fields already in
+ * the library layout, over `reps` back-to-back launches, measured with HIP
+ * events on `stream`.  dagger = 0 times the kernel of the first matvec of a
+ * CG iteration (t = M p fused with ||t||^2), dagger = 1 the plain M^dag
+ * stencil -- the same kernels the solvers launch.  ws: device scratch of
+ * lq_time_dslash_workspace_bytes (contents overwritten).  */
+size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t precision,
+                                      int32_t nrhs);
 int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger,
                    int32_t precision, int32_t links, int32_t nrhs, int32_t reps,
                    void* ws, size_t ws_bytes, double* avg_ms, void* stream);

@@ -101,6 +101,7 @@ def lib():
         "lq_apply_workspace_bytes": ([P, I32, I32], SZ),
         "lq_apply": ([P, P, I32, I32, I32, P, P, P, SZ, P], I32),
         "lq_time_dslash": ([P, P, I32, I32, I32, I32, I32, P, SZ, P, P], I32),
+        "lq_time_dslash_workspace_bytes": ([P, I32, I32, I32], SZ),
         "lq_solve_workspace_bytes": ([P, I32, P, I32], SZ),
         "lq_cg_solve": ([P, P, P, P, D, I32, P, P, SZ, P, P], I32),
         "lq_cg_solve_batch": ([P, I32, I32, D, I32, P, P, P, P, I32, P, P, SZ, P, P], I32),
@@ -231,10 +232,7 @@ def time_dslash(gauge, formulation, mass, dagger=False, r=1.0, g55=G55_CORNERS, 
                 links=0, nrhs=1, reps=50, stream=None):
     """Average milliseconds per stencil launch (HIP events on the launch stream)."""
     torch = _torch()
-    nc = 12 if formulation == WILSON else 3
-    per = {F64: 16, F32: 8, F16: 4}[precision]
-    Vp = ((gauge.lattice.volume + 63) // 64) * 64 + 64
-    nb = 2 * nrhs * nc * Vp * per + 4096
+    nb = int(lib().lq_time_dslash_workspace_bytes(gauge._h, formulation, precision, nrhs))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     d = Dirac(formulation, g55, mass, r)
     ms = ctypes.c_double()
@@ -247,6 +245,11 @@ def solve_opts(precision=F64, links=0, reliable_interval=0, poll_interval=0, use
                max_restarts=0, reliable_delta=0.0):
     return SolveOpts(precision, links, reliable_interval, poll_interval, use_graph, max_restarts,
                      reliable_delta)
+
+
+def solve_workspace_bytes(gauge, formulation, opts, nrhs):
+    """Device bytes the solver needs for nrhs systems with these options."""
+    return int(lib().lq_solve_workspace_bytes(gauge._h, formulation, ctypes.byref(opts), nrhs))
 
 
 def cg_solve(gauge, formulation, mass, chi, tol, maxiter=100000, r=1.0, g55=G55_CORNERS,

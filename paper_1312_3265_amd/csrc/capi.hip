@@ -213,6 +213,18 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t opsel, int32_t precis
   });
 }
 
+size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t precision,
+                                      int32_t nrhs) {
+  if (!g || nrhs < 1 || precision < 0 || precision > 2) return 0;
+  if (formulation != LQ_WILSON && formulation != LQ_STAGGERED_WILSON) return 0;
+  const size_t v = (size_t)nrhs * ncomp_of(formulation) * g->g.Vp * store_bytes(precision);
+  Carver c(nullptr);
+  c.take(v);
+  c.take(v);
+  c.take((size_t)nrhs * nbp_of(g->g.V) * sizeof(double));
+  return c.size();
+}
+
 int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t precision,
                    int32_t links, int32_t nrhs, int32_t reps, void* ws, size_t ws_bytes,
                    double* avg_ms, void* stream) {
@@ -228,6 +240,7 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t
     Carver c(ws);
     void* a = c.take(v);
     void* b = c.take(v);
+    double* part = (double*)c.take((size_t)nrhs * nbp_of(g->g.V) * sizeof(double));
     if (ws_bytes < c.size())
       throw Error(LQ_ERR_WORKSPACE, "timing workspace too small: need " + std::to_string(c.size()));
     const OpArgs oa = make_op(g, d, precision, nl);
@@ -237,13 +250,17 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t
     std::memset(&e, 0, sizeof(e));
     e.nbp = nbp_of(g->g.V);
     e.out = b;
-    launch_stencil(op, precision, nl, dagger != 0, EPI_STORE, oa, a, e, nrhs, s);   // warm-up
+    e.part = part;
+    // the stencil of the first matvec of a CG iteration (t = M p with ||t||^2),
+    // or the plain M^dag stencil
+    const int epi = dagger ? EPI_STORE : EPI_STORE_NORM;
+    launch_stencil(op, precision, nl, dagger != 0, epi, oa, a, e, nrhs, s);   // warm-up
     hipEvent_t t0, t1;
     LQ_HIP(hipEventCreate(&t0));
     LQ_HIP(hipEventCreate(&t1));
     LQ_HIP(hipEventRecord(t0, s));
     for (int k = 0; k < reps; ++k)
-      launch_stencil(op, precision, nl, dagger != 0, EPI_STORE, oa, a, e, nrhs, s);
+      launch_stencil(op, precision, nl, dagger != 0, epi, oa, a, e, nrhs, s);
     LQ_HIP(hipEventRecord(t1, s));
     LQ_HIP(hipEventSynchronize(t1));
     check_launch();
