@@ -1,0 +1,193 @@
+"""Continuous-batching solve server over the resident multi-slot CG solver.
+
+Requests (lattice size, formulation, mass, source, tolerance) arrive over
+time.  Gauge fields stay resident in HBM, one per lattice size.  Requests that
+share a gauge field and formulation share one multi-slot solver (``Batch``):
+every stencil launch serves all of its running systems.  A request is admitted
+into a free slot as soon as one frees up, while the other slots keep iterating;
+finished systems are harvested between chunks of iterations.  Each group runs
+in its own host thread on its own HIP stream, so the groups' kernels overlap
+on the device (the library calls release the GIL).
+
+HBM admission: every group's solver workspace is allocated when the group is
+created, with as many slots as fit into its share of the memory budget; a
+request waits in its group's queue until a slot is free.  A request whose
+group cannot hold even one system is rejected.
+
+The arithmetic all happens in the library; this module only schedules.
+"""
+from __future__ import annotations
+
+import queue
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import Batch, Gauge, Lattice, SLOT_DONE, SLOT_FAILED, _torch, solve_opts, \
+    solve_workspace_bytes
+
+
+@dataclass
+class Request:
+    id: int
+    dims: tuple
+    formulation: int
+    mass: float
+    source: object            # canonical complex128 field (numpy or torch)
+    tol: float
+    arrival: float = 0.0      # seconds after the server's start
+    maxiter: int = 100000
+
+
+@dataclass
+class Result:
+    id: int
+    x: object
+    info: dict
+    arrival: float
+    admitted: float
+    finished: float
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+@dataclass
+class _Group:
+    key: tuple
+    batch: Batch
+    stream: object
+    pending: "queue.Queue" = field(default_factory=queue.Queue)
+    slot_req: dict = field(default_factory=dict)
+    thread: threading.Thread = None
+
+
+class SolveServer:
+    """Serve solve requests on resident gauge fields with continuous batching.
+
+    fields: {dims: canonical gauge field (numpy or torch)}; opts: solver
+    options (default FP32 Krylov vectors, 12-real links, FP64 reliable
+    updates); mem_budget: bytes of HBM for solver workspaces (all groups);
+    slots: upper bound on slots per group; chunk: iterations per step.
+    """
+
+    def __init__(self, fields, opts=None, mem_budget=8 << 30, slots=16, chunk=16, r=1.0,
+                 g55=0):
+        self.torch = _torch()
+        self.opts = opts or solve_opts(precision=1, links=12, poll_interval=chunk)
+        self.chunk = chunk
+        self.r = r
+        self.g55 = g55
+        self.max_slots = slots
+        self.mem_budget = int(mem_budget)
+        self.lattices = {}
+        self.gauges = {}
+        for dims, U in fields.items():
+            dims = tuple(dims)
+            lat = Lattice(dims)
+            self.lattices[dims] = lat
+            self.gauges[dims] = Gauge(lat, U)
+        self.groups = {}
+        self.results = []
+        self.rejected = []
+        self._lock = threading.Lock()
+        self._t0 = None
+        self._stop = threading.Event()
+        self.allocated = 0
+
+    # ----------------------------------------------------------- admission
+    def per_system_bytes(self, dims, formulation):
+        return solve_workspace_bytes(self.gauges[dims], formulation, self.opts, 2) - \
+            solve_workspace_bytes(self.gauges[dims], formulation, self.opts, 1)
+
+    def _group(self, dims, formulation):
+        key = (dims, formulation)
+        if key in self.groups:
+            return self.groups[key]
+        # each (dims, formulation) pair gets an equal share of the budget
+        share = self.mem_budget // (2 * len(self.gauges))
+        per = self.per_system_bytes(dims, formulation)
+        nslots = int(min(self.max_slots, max(0, share // max(per, 1))))
+        while nslots > 0 and solve_workspace_bytes(self.gauges[dims], formulation, self.opts,
+                                                   nslots) > share:
+            nslots -= 1
+        if nslots == 0:
+            self.groups[key] = None
+            return None
+        stream = self.torch.cuda.Stream()
+        with self.torch.cuda.stream(stream):
+            b = Batch(self.gauges[dims], formulation, nslots, r=self.r, g55=self.g55,
+                      opts=self.opts)
+        self.allocated += b.nbytes
+        g = _Group(key=key, batch=b, stream=stream)
+        g.thread = threading.Thread(target=self._worker, args=(g,), daemon=True)
+        self.groups[key] = g
+        g.thread.start()
+        return g
+
+    def _now(self):
+        return time.perf_counter() - self._t0
+
+    # -------------------------------------------------------------- worker
+    def _worker(self, g):
+        b = g.batch
+        free = list(range(b.nslots))
+        torch = self.torch
+        while True:
+            # admit waiting requests into free slots
+            while free:
+                try:
+                    req = g.pending.get_nowait()
+                except queue.Empty:
+                    break
+                s = free.pop(0)
+                b.load(s, req.source, req.mass, req.tol, req.maxiter, stream=g.stream)
+                g.slot_req[s] = (req, self._now())
+            if not g.slot_req:
+                if self._stop.is_set() and g.pending.empty():
+                    return
+                time.sleep(0.0005)
+                continue
+            states = b.step(self.chunk, stream=g.stream)
+            for s, st in enumerate(states):
+                if s in g.slot_req and st in (SLOT_DONE, SLOT_FAILED):
+                    req, adm = g.slot_req.pop(s)
+                    x, info = b.fetch(s, stream=g.stream)
+                    with self._lock:
+                        self.results.append(Result(req.id, x, info, req.arrival, adm, self._now()))
+                    free.append(s)
+
+    # ----------------------------------------------------------------- API
+    def run(self, requests):
+        """Feed requests at their arrival times (seconds from now) and wait
+        for all of them.  Returns the results in completion order."""
+        self._t0 = time.perf_counter()
+        for req in sorted(requests, key=lambda r: r.arrival):
+            delay = req.arrival - self._now()
+            if delay > 0:
+                time.sleep(delay)
+            g = self._group(tuple(req.dims), req.formulation)
+            if g is None:
+                self.rejected.append(req.id)
+                continue
+            g.pending.put(req)
+        self._stop.set()
+        for g in list(self.groups.values()):
+            if g is not None:
+                g.thread.join()
+        return self.results
+
+    def report(self):
+        lat = np.array([r.latency for r in self.results]) if self.results else np.zeros(1)
+        span = max((r.finished for r in self.results), default=0.0)
+        ok = sum(1 for r in self.results if r.info["status"] == 0)
+        return dict(completed=len(self.results), converged=ok, rejected=len(self.rejected),
+                    solves_per_s=len(self.results) / span if span > 0 else 0.0,
+                    p50_latency_s=float(np.percentile(lat, 50)),
+                    p99_latency_s=float(np.percentile(lat, 99)),
+                    workspace_bytes=self.allocated, budget_bytes=self.mem_budget,
+                    groups={f"{k[0]}:{k[1]}": (g.batch.nslots if g else 0)
+                            for k, g in self.groups.items()})

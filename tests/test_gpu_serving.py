@@ -1,0 +1,61 @@
+"""Continuous-batching server: Poisson arrivals over two lattice sizes and both
+formulations; every result must match the same request solved alone
+(bitwise: per-system trajectories do not depend on the batch) and pass the
+oracle's FP64 residual check; admission respects the HBM budget."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import solvers
+
+pytestmark = pytest.mark.gpu
+
+lq = pytest.importorskip("paper_1312_3265_amd")
+torch = pytest.importorskip("torch")
+serve = pytest.importorskip("paper_1312_3265_amd.serve")
+
+
+def test_server_poisson_stream_matches_alone_solves():
+    dims_choices = [(4, 4, 4, 4), (6, 4, 4, 6)]
+    fields = {d: synth.gauge_field(d, "near_identity", 31 + i, 0.436)
+              for i, d in enumerate(dims_choices)}
+    descs = synth.serving_requests(24, seed=42, dims_choices=dims_choices,
+                                   tol_range=(1e-10, 1e-6))
+    arrivals = synth.poisson_arrivals(rate=400.0, n=len(descs), seed=43)
+    base_mass = {synth.WILSON: -0.1, synth.STAGGERED_WILSON: -0.15}
+    reqs = []
+    for d, t in zip(descs, arrivals):
+        f = d["formulation"]
+        if d["source"] == "point":
+            chi = synth.point_source(d["dims"], f, d["alpha"])
+        else:
+            chi = synth.z2_source(d["dims"], f, d["source_seed"])
+        reqs.append(serve.Request(d["id"], d["dims"], f, base_mass[f] + d["delta"], chi,
+                                  d["tol"], arrival=float(t)))
+    opts = lq.solve_opts(precision=lq.F32, links=12, poll_interval=8)
+    budget = 64 << 20
+    srv = serve.SolveServer(fields, opts=opts, mem_budget=budget, slots=4, chunk=8)
+    results = srv.run(reqs)
+    rep = srv.report()
+    assert rep["completed"] == len(reqs) and rep["converged"] == len(reqs)
+    assert rep["workspace_bytes"] <= budget
+    assert rep["p99_latency_s"] >= rep["p50_latency_s"] > 0
+    by_id = {r.id: r for r in results}
+    for req in reqs:
+        r = by_id[req.id]
+        g = srv.gauges[tuple(req.dims)]
+        xa, ia = lq.cg_solve(g, req.formulation, req.mass, req.source, req.tol, opts=opts)
+        assert ia["iterations"] == r.info["iterations"]
+        assert torch.equal(xa, r.x)
+        rn, _ = solvers.true_residual(req.formulation, fields[tuple(req.dims)], req.source,
+                                      r.x.cpu().numpy(), req.mass)
+        assert rn <= req.tol
+
+
+def test_server_rejects_what_cannot_fit():
+    dims = (4, 4, 4, 4)
+    fields = {dims: synth.gauge_field(dims, "haar", 5)}
+    chi = synth.point_source(dims, synth.WILSON, 0)
+    srv = serve.SolveServer(fields, mem_budget=1 << 10, slots=4)
+    srv.run([serve.Request(0, dims, synth.WILSON, 0.5, chi, 1e-8)])
+    assert srv.rejected == [0] and srv.report()["completed"] == 0
