@@ -179,13 +179,15 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t op, int32_t precision
  * the library layout, over `reps` back-to-back launches, measured with HIP
  * events on `stream`.  dagger = 0 times the kernel of the first matvec of a
  * CG iteration (t = M p fused with ||t||^2), dagger = 1 the plain M^dag
- * stencil -- the same kernels the solvers launch.  ws: device scratch of
+ * stencil -- the same kernels the solvers launch.  rhs_per_thread (1, 2, 4;
+ * FP32/FP16 only) is the number of systems each thread serves, the choice the
+ * solvers' autotuner makes per batch.  ws: device scratch of
  * lq_time_dslash_workspace_bytes (contents overwritten).  */
 size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t precision,
                                       int32_t nrhs);
 int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger,
-                   int32_t precision, int32_t links, int32_t nrhs, int32_t reps,
-                   void* ws, size_t ws_bytes, double* avg_ms, void* stream);
+                   int32_t precision, int32_t links, int32_t nrhs, int32_t rhs_per_thread,
+                   int32_t reps, void* ws, size_t ws_bytes, double* avg_ms, void* stream);
 
 /* ----------------------------------------------------------------- solve
  * CG on eq. (2) for one source chi (device canonical complex128); the

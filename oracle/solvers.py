@@ -160,7 +160,8 @@ def lanczos(A, v0, steps, reorth=True):
         w = w - a * v
         if reorth:
             for _ in range(2):
-                h = Vb[: j + 1].conj() @ w
+                # h_k = <v_k, w> = conj(v_k . conj(w)), without copying the basis
+                h = np.conj(Vb[: j + 1] @ np.conj(w))
                 w = w - Vb[: j + 1].T @ h
         alpha.append(a)
         bj = np.sqrt(_norm2(w))

@@ -226,13 +226,16 @@ size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, in
 }
 
 int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t precision,
-                   int32_t links, int32_t nrhs, int32_t reps, void* ws, size_t ws_bytes,
-                   double* avg_ms, void* stream) {
+                   int32_t links, int32_t nrhs, int32_t rhs_per_thread, int32_t reps, void* ws,
+                   size_t ws_bytes, double* avg_ms, void* stream) {
   return guard([&] {
     need(g && ws && avg_ms, "null argument");
     check_dirac(d);
     check_prec(precision, links);
     need(nrhs >= 1 && reps >= 1, "nrhs and reps must be >= 1");
+    need(rhs_per_thread == 1 || rhs_per_thread == 2 || rhs_per_thread == 4,
+         "rhs_per_thread must be 1, 2 or 4");
+    need(rhs_per_thread == 1 || precision != LQ_PREC_F64, "FP64 stencils take one system per thread");
     const int nl = links_for(precision, links);
     const int nc = ncomp_of(d->formulation);
     const int op = opkind(d->formulation, d->g55_mode);
@@ -251,6 +254,7 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t
     e.nbp = nbp_of(g->g.V);
     e.out = b;
     e.part = part;
+    e.rhs_per_thread = rhs_per_thread;
     // the stencil of the first matvec of a CG iteration (t = M p with ||t||^2),
     // or the plain M^dag stencil
     const int epi = dagger ? EPI_STORE : EPI_STORE_NORM;

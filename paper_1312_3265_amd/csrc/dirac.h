@@ -63,13 +63,11 @@ struct WilsonOp {
   using R = typename P::R;
   using S = typename P::S;
 
-  // Accumulate (r + t g_mu) L psi_nb into acc, with L = link or link^dag.
+  // acc += (r + t g_mu) L psi_nb, L = the pre-loaded link lk or its adjoint.
   __device__ __forceinline__ static void hop(const OpArgs& a, const S* __restrict__ in, int nb,
-                                             int lsite, int mu, bool dagger_link, R t, R sgn,
+                                             int mu, bool dagger_link, R t, R sgn, const C lk[9],
                                              C acc[12]) {
     const int Vp = a.g.Vp;
-    C lk[9];
-    load_link<P, NL>((const S*)a.links, Vp, mu, lsite, lk);
     if constexpr (!GENERAL_R) {
       C h[2][3];
 #pragma unroll
@@ -119,16 +117,26 @@ struct WilsonOp {
     }
   }
 
-  __device__ __forceinline__ static void site(const OpArgs& a, const S* __restrict__ in, int i,
-                                              int k, C out[12]) {
+  // K right-hand sides of one site: input k at in0 + k * rstride, mass of
+  // system k0 + k, bit k of `act` set for the systems to compute.  Each link
+  // is loaded (and, for 12-real storage, completed) once for all K.
+  template <int K>
+  __device__ __forceinline__ static void site_multi(const OpArgs& a, const S* __restrict__ in0,
+                                                    size_t rstride, int i, int k0, unsigned act,
+                                                    C out[K][12]) {
     const Geom& g = a.g;
     Coord c = site_coords(g, i);
     // acc starts at -2 (m + 4r) psi(x) so that out = -acc/2 at the end and
     // psi(x) is not kept live across the hops
-    const R diag = (R)(rhs_mass(a, k) + 4.0 * a.r);
-    C acc[12];
+    C acc[K][12];
 #pragma unroll
-    for (int q = 0; q < 12; ++q) acc[q] = cscale(ldq<P>(in, g.Vp, q, i), (R)-2 * diag);
+    for (int k = 0; k < K; ++k) {
+      const R diag = (R)(rhs_mass(a, k0 + k) + 4.0 * a.r);
+#pragma unroll
+      for (int q = 0; q < 12; ++q)
+        acc[k][q] = ((act >> k) & 1) ? cscale(ldq<P>(in0 + k * rstride, g.Vp, q, i), (R)-2 * diag)
+                                     : czero<C>();
+    }
     const R s = DAG ? (R)-1 : (R)1;
     // The direction loop stays rolled: mu is uniform across the wavefront, so
     // the gamma structure is a scalar branch, and only one hop's operands are
@@ -136,19 +144,21 @@ struct WilsonOp {
 #pragma unroll 1
     for (int h = 0; h < 8; ++h) {
       const int mu = h >> 1;
+      const bool back = h & 1;
       bool wrap;
-      if ((h & 1) == 0) {
-        const int j = nb_fwd(g, c, i, mu, wrap);
-        const R sg = (wrap && g.bc[mu] < 0) ? (R)-1 : (R)1;
-        hop(a, in, j, i, mu, false, -s, sg, acc);    // (r - s g) U_mu(x) psi(x+mu)
-      } else {
-        const int j = nb_bwd(g, c, i, mu, wrap);
-        const R sg = (wrap && g.bc[mu] < 0) ? (R)-1 : (R)1;
-        hop(a, in, j, j, mu, true, s, sg, acc);      // (r + s g) U_mu(x-mu)^dag psi(x-mu)
-      }
+      const int j = back ? nb_bwd(g, c, i, mu, wrap) : nb_fwd(g, c, i, mu, wrap);
+      const R sg = (wrap && g.bc[mu] < 0) ? (R)-1 : (R)1;
+      C lk[9];
+      // forward: (r - s g) U_mu(x) psi(x+mu); backward: (r + s g) U_mu(x-mu)^dag psi(x-mu)
+      load_link<P, NL>((const S*)a.links, g.Vp, mu, back ? j : i, lk);
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if ((act >> k) & 1) hop(a, in0 + k * rstride, j, mu, back, back ? s : -s, sg, lk, acc[k]);
     }
 #pragma unroll
-    for (int q = 0; q < 12; ++q) out[q] = cscale(acc[q], (R)-0.5);
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int q = 0; q < 12; ++q) out[k][q] = cscale(acc[k][q], (R)-0.5);
   }
 };
 
@@ -161,36 +171,41 @@ struct WilsonOpR1 : WilsonOp<P, NL, DAG, false> {};
 // ------------------------------------------------------- staggered Wilson
 // M = D_st + r (1 - Gamma_55) + m, M^dag = -D_st + r (1 - Gamma_55) + m.
 // D_st psi(x) = 1/2 sum_mu eta_mu(x) [U_mu(x) psi(x+mu) - U_mu(x-mu)^dag psi(x-mu)].
-template <class P, int NL>
-__device__ __forceinline__ void dst_site(const OpArgs& a, const typename P::S* __restrict__ in,
-                                         const Coord& c, int i, typename P::C acc[3]) {
+// acc[k] = sum_mu eta_mu [U_mu(x) psi_k(x+mu) - U_mu(x-mu)^dag psi_k(x-mu)] for the
+// K inputs psi_k = in0 + k*rstride selected by `act`; each link loaded once.
+template <class P, int NL, int K>
+__device__ __forceinline__ void dst_site(const OpArgs& a, const typename P::S* __restrict__ in0,
+                                         size_t rstride, const Coord& c, int i, unsigned act,
+                                         typename P::C acc[K][3]) {
   using C = typename P::C;
   using R = typename P::R;
   using S = typename P::S;
   const Geom& g = a.g;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) acc[q] = czero<C>();
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[k][q] = czero<C>();
 #pragma unroll 1
-  for (int mu = 0; mu < 4; ++mu) {
+  for (int h = 0; h < 8; ++h) {
+    const int mu = h >> 1;
+    const bool back = h & 1;
     const R eta = (R)eta_sign(c, mu);
     bool wrap;
-    C lk[9], v[3], y[3];
-    int j = nb_fwd(g, c, i, mu, wrap);
-    R sg = ((wrap && g.bc[mu] < 0) ? (R)-1 : (R)1) * eta;
+    const int j = back ? nb_bwd(g, c, i, mu, wrap) : nb_fwd(g, c, i, mu, wrap);
+    // forward hops enter with +eta, backward hops with -eta
+    const R sg = ((wrap && g.bc[mu] < 0) ? (R)-1 : (R)1) * (back ? -eta : eta);
+    C lk[9];
+    load_link<P, NL>((const S*)a.links, g.Vp, mu, back ? j : i, lk);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) v[q] = ldq<P>(in, g.Vp, q, j);
-    load_link<P, NL>((const S*)a.links, g.Vp, mu, i, lk);
-    mv(lk, v, y);
+    for (int k = 0; k < K; ++k) {
+      if (!((act >> k) & 1)) continue;
+      C v[3], y[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) acc[q] = cadd(acc[q], cscale(y[q], sg));
-    j = nb_bwd(g, c, i, mu, wrap);
-    sg = ((wrap && g.bc[mu] < 0) ? (R)-1 : (R)1) * eta;
+      for (int q = 0; q < 3; ++q) v[q] = ldq<P>(in0 + k * rstride, g.Vp, q, j);
+      if (back) mvd(lk, v, y); else mv(lk, v, y);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) v[q] = ldq<P>(in, g.Vp, q, j);
-    load_link<P, NL>((const S*)a.links, g.Vp, mu, j, lk);
-    mvd(lk, v, y);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) acc[q] = csub(acc[q], cscale(y[q], sg));
+      for (int q = 0; q < 3; ++q) acc[k][q] = cadd(acc[k][q], cscale(y[q], sg));
+    }
   }
 }
 
@@ -220,48 +235,54 @@ struct SWCornerOp {
   using R = typename P::R;
   using S = typename P::S;
 
-  __device__ __forceinline__ static void site(const OpArgs& a, const S* __restrict__ in, int i,
-                                              int k, C out[3]) {
+  template <int K>
+  __device__ __forceinline__ static void site_multi(const OpArgs& a, const S* __restrict__ in0,
+                                                    size_t rstride, int i, int k0, unsigned act,
+                                                    C out[K][3]) {
     const Geom& g = a.g;
     Coord c = site_coords(g, i);
-    C d[3];
-    dst_site<P, NL>(a, in, c, i, d);
-    C acc[3];
+    C d[K][3];
+    dst_site<P, NL, K>(a, in0, rstride, c, i, act, d);
+    C acc[K][3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) acc[q] = czero<C>();
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc[k][q] = czero<C>();
     const S* W = (const S*)a.corners;
 #pragma unroll 1
-    for (int cidx = 0; cidx < 8; ++cidx) {
-      int s[4] = {(cidx & 1) ? -1 : 1, (cidx & 2) ? -1 : 1, (cidx & 4) ? -1 : 1, 1};
+    for (int h = 0; h < 16; ++h) {
+      // h = 2*cidx + reflected: forward corner W_s(x) psi(x + s), or the
+      // reflected one W_{-s}(x) psi(x - s) = W_s(x - s)^dag psi(x - s)
+      const int cidx = h >> 1;
+      const bool refl = h & 1;
+      const int sg4 = refl ? -1 : 1;
+      int s[4] = {(cidx & 1) ? -sg4 : sg4, (cidx & 2) ? -sg4 : sg4, (cidx & 4) ? -sg4 : sg4, sg4};
       int sign;
-      C w[9], v[3], y[3];
-      // forward corner: W_s(x) psi(x + s)
-      int j = diag_nb(g, c, s, sign);
+      const int j = diag_nb(g, c, s, sign);
+      C w[9];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) v[q] = ldq<P>(in, g.Vp, q, j);
+      for (int q = 0; q < 9; ++q) w[q] = ldq<P>(W, g.Vp, cidx * 9 + q, refl ? j : i);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) w[q] = ldq<P>(W, g.Vp, cidx * 9 + q, i);
-      mv(w, v, y);
+      for (int k = 0; k < K; ++k) {
+        if (!((act >> k) & 1)) continue;
+        C v[3], y[3];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) acc[q] = cadd(acc[q], cscale(y[q], (R)sign));
-      // reflected corner: W_{-s}(x) psi(x - s) = W_s(x - s)^dag psi(x - s)
-      int ms[4] = {-s[0], -s[1], -s[2], -s[3]};
-      j = diag_nb(g, c, ms, sign);
+        for (int q = 0; q < 3; ++q) v[q] = ldq<P>(in0 + k * rstride, g.Vp, q, j);
+        if (refl) mvd(w, v, y); else mv(w, v, y);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) v[q] = ldq<P>(in, g.Vp, q, j);
-#pragma unroll
-      for (int q = 0; q < 9; ++q) w[q] = ldq<P>(W, g.Vp, cidx * 9 + q, j);
-      mvd(w, v, y);
-#pragma unroll
-      for (int q = 0; q < 3; ++q) acc[q] = cadd(acc[q], cscale(y[q], (R)sign));
+        for (int q = 0; q < 3; ++q) acc[k][q] = cadd(acc[k][q], cscale(y[q], (R)sign));
+      }
     }
-    const R mr = (R)(rhs_mass(a, k) + a.r);
     const R gcoef = (R)(a.r * phi_sign(c) / 16.0);
     const R dcoef = DAG ? (R)-0.5 : (R)0.5;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      C v = ldq<P>(in, g.Vp, q, i);
-      out[q] = csub(cadd(cscale(v, mr), cscale(d[q], dcoef)), cscale(acc[q], gcoef));
+    for (int k = 0; k < K; ++k) {
+      const R mr = (R)(rhs_mass(a, k0 + k) + a.r);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        C v = ((act >> k) & 1) ? ldq<P>(in0 + k * rstride, g.Vp, q, i) : czero<C>();
+        out[k][q] = csub(cadd(cscale(v, mr), cscale(d[k][q], dcoef)), cscale(acc[k][q], gcoef));
+      }
     }
   }
 };
@@ -371,12 +392,22 @@ struct SWOtfOp {
   using R = typename P::R;
   using S = typename P::S;
 
+  template <int K>
+  __device__ __forceinline__ static void site_multi(const OpArgs& a, const S* __restrict__ in0,
+                                                    size_t rstride, int i, int k0, unsigned act,
+                                                    C out[K][3]) {
+#pragma unroll 1
+    for (int k = 0; k < K; ++k)
+      if ((act >> k) & 1) site(a, in0 + k * rstride, i, k0 + k, out[k]);
+  }
+
   __device__ __forceinline__ static void site(const OpArgs& a, const S* __restrict__ in, int i,
                                               int k, C out[3]) {
     const Geom& g = a.g;
     Coord c = site_coords(g, i);
-    C d[3], f[3];
-    dst_site<P, NL>(a, in, c, i, d);
+    C d1[1][3], f[3];
+    dst_site<P, NL, 1>(a, in, 0, c, i, 1u, d1);
+    C* d = d1[0];
     gamma55_otf<P, NL>(a, in, c, i, f);
     const R mr = (R)(rhs_mass(a, k) + a.r);
     // phi/24 * (1/2)^4 from the four C_mu factors

@@ -98,6 +98,7 @@ struct Engine {
   int reliable_interval = 64, poll_every = 16, use_graph = 0, max_cand = 50;
   double delta = 0.0;
   int nbp = 0;
+  int rhs_per_thread = 1;     // systems per thread of the CG stencils (autotuned)
   // device
   double2 *b = nullptr, *xhi = nullptr, *rhi = nullptr, *t64 = nullptr;
   void *xlo = nullptr, *rlo = nullptr, *p = nullptr, *t = nullptr;
@@ -131,7 +132,15 @@ struct Engine {
   void enqueue_reliable_update(hipStream_t s);
   void poll(hipStream_t s);
   bool select_updates();
+  void tune(hipStream_t s);
 };
+
+// Systems-per-thread choice for a batched low-precision stencil: timed on the
+// device once per (GPU, lattice, operator, precision, links, batch size) and
+// remembered in memory and in a small text cache file (LQ_TUNE_CACHE, default
+// $HOME/.cache/lq_tune.txt).
+int tuned_rhs_per_thread(const std::string& key);
+void remember_rhs_per_thread(const std::string& key, int k);
 
 // Lanczos with full reorthogonalisation on A = M^dag M.
 size_t lanczos_workspace_bytes(const Geom& g, int formulation, int steps);

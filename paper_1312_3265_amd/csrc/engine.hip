@@ -2,7 +2,12 @@
 // Lanczos driver (see engine.h).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 
 #include "engine.h"
 
@@ -58,6 +63,87 @@ size_t gauge_layout(const Geom& g, uint32_t f, void* base, lq_gauge_s* out) {
     out->nbp = nbp;
   }
   return c.size();
+}
+
+// =============================================================== autotune
+static std::mutex g_tune_mu;
+static std::map<std::string, int>* g_tune = nullptr;
+
+static std::string tune_path() {
+  const char* e = std::getenv("LQ_TUNE_CACHE");
+  if (e && *e) return e;
+  const char* h = std::getenv("HOME");
+  return std::string(h ? h : "/tmp") + "/.cache/lq_tune.txt";
+}
+
+static void tune_load_locked() {
+  if (g_tune) return;
+  g_tune = new std::map<std::string, int>();
+  std::ifstream f(tune_path());
+  std::string k;
+  int v;
+  while (f >> k >> v) (*g_tune)[k] = v;
+}
+
+int tuned_rhs_per_thread(const std::string& key) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tune->find(key);
+  return it == g_tune->end() ? 0 : it->second;
+}
+
+void remember_rhs_per_thread(const std::string& key, int k) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  (*g_tune)[key] = k;
+  std::ofstream f(tune_path(), std::ios::app);   // best effort
+  if (f) f << key << " " << k << "\n";
+}
+
+// Time the CG stencil t = M p (+||t||^2) over all slots for K = 1, 2, 4 on the
+// (zeroed) solver buffers and keep the fastest.
+void Engine::tune(hipStream_t s) {
+  rhs_per_thread = 1;
+  if (prec_lo == P64 || nslots < 2) return;
+  hipDeviceProp_t prop;
+  int dev = 0;
+  LQ_HIP(hipGetDevice(&dev));
+  LQ_HIP(hipGetDeviceProperties(&prop, dev));
+  std::ostringstream key;
+  const Geom& g = gauge->g;
+  key << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
+      << ":op" << op << ":p" << prec_lo << ":l" << nl_lo << ":n" << nslots;
+  std::string k = key.str();
+  for (auto& ch : k) if (ch == ' ') ch = '_';
+  const int cached = tuned_rhs_per_thread(k);
+  if (cached) { rhs_per_thread = cached; return; }
+  OpArgs oa = op_args(prec_lo, nl_lo);
+  EpiArgs e = epi_base();
+  e.st = nullptr;
+  e.out = t;
+  e.part = part_t;
+  hipEvent_t t0, t1;
+  LQ_HIP(hipEventCreate(&t0));
+  LQ_HIP(hipEventCreate(&t1));
+  float best = 1e30f;
+  int bestk = 1;
+  for (int kk : {1, 2, 4}) {
+    if (kk > nslots) break;
+    e.rhs_per_thread = kk;
+    launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
+    LQ_HIP(hipEventRecord(t0, s));
+    for (int r = 0; r < 5; ++r) launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
+    LQ_HIP(hipEventRecord(t1, s));
+    LQ_HIP(hipEventSynchronize(t1));
+    check_launch();
+    float ms = 0.0f;
+    LQ_HIP(hipEventElapsedTime(&ms, t0, t1));
+    if (ms < best) { best = ms; bestk = kk; }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  rhs_per_thread = bestk;
+  remember_rhs_per_thread(k, bestk);
 }
 
 // ================================================================ Engine
@@ -136,6 +222,7 @@ void Engine::init(const lq_gauge_s* g, int form, int g55, double rr, int ns,
   std::memset(hst, 0, sizeof(SlotState) * ns);
   LQ_HIP(hipHostMalloc((void**)&hmask, sizeof(int) * ns, hipHostMallocDefault));
   std::memset(hmask, 0, sizeof(int) * ns);
+  tune(s);
   LQ_HIP(hipStreamSynchronize(s));
 }
 
@@ -216,8 +303,10 @@ void Engine::enqueue_iterations(int n, hipStream_t s) {
     e.state_mode = 1;
     e.out = t;
     e.part = part_t;
+    e.rhs_per_thread = rhs_per_thread;
     launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
     EpiArgs f = epi_base();
+    f.rhs_per_thread = rhs_per_thread;
     f.par = par;
     f.state_mode = 1;
     f.part = part_r;

@@ -42,6 +42,7 @@ struct EpiArgs {
   const double* v;        // LANCZOS: v_j
   const double* vprev;    // LANCZOS: v_{j-1}
   const double* beta_prev;// LANCZOS: device scalar beta_{j-1} (null = 0)
+  int rhs_per_thread;     // systems per thread (1, 2 or 4; FP32/FP16 CG kernels)
 };
 
 // blockIdx.x -> (site block sb, rhs k), XCD-aware (see file comment).
@@ -61,95 +62,125 @@ __device__ __forceinline__ bool slot_active(const SlotState* st, int k, int mode
   return mask == nullptr || mask[k] != 0;
 }
 
-// Register budget: FP64 kernels are held to 4 waves per SIMD (128 VGPRs) so
-// that enough waves are resident to cover HBM latency.
-template <class Op, int EPI>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Op::kWaves, 8)))
-stencil_kernel(const OpArgs oa, const typename Op::S* __restrict__ in, const EpiArgs ea, int nrhs) {
+// Register budget: FP64 kernels are held to 3-4 waves per SIMD so that enough
+// waves are resident to cover HBM latency.
+//
+// K systems per thread: the block covers kBlock sites of the K systems
+// k0 .. k0+K-1 (k0 = ea.k0 + K * group); links and corner matrices are loaded
+// once per site for all K.  Each system keeps its own alpha, state and
+// partial sums, so the result of a system does not depend on K or on the
+// other systems.
+template <class Op, int K>
+constexpr int stencil_waves() { return (Op::NC == 12 && K >= 4) ? 3 : Op::kWaves; }
+
+template <class Op, int EPI, int K>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(stencil_waves<Op, K>(), 8)))
+stencil_kernel(const OpArgs oa, const typename Op::S* __restrict__ in, const EpiArgs ea,
+               int ngroups, int nrhs) {
   using P_C = typename Op::C;
   using R = typename Op::R;
   using S = typename Op::S;
   constexpr int NC = Op::NC;
   __shared__ double red[16];
-  int sb, kl;
-  map_block(ea.nbp, nrhs, sb, kl);
-  const int k = ea.k0 + kl;
-  if (ea.st && !slot_active(ea.st, k, ea.state_mode, ea.par, ea.ru_mask)) return;
+  int sb, kg;
+  map_block(ea.nbp, ngroups, sb, kg);
+  const int k0 = ea.k0 + kg * K;
+  unsigned act = 0;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int k = k0 + kk;
+    if (k < ea.k0 + nrhs && (!ea.st || slot_active(ea.st, k, ea.state_mode, ea.par, ea.ru_mask)))
+      act |= 1u << kk;
+  }
+  if (act == 0) return;   // uniform over the block
 
   const int Vp = oa.g.Vp;
   const int i = sb * blockDim.x + threadIdx.x;
   const bool valid = i < oa.g.V;
-  const size_t off = (size_t)k * NC * Vp;
+  const size_t rstride = (size_t)NC * Vp;
 
-  double alpha = 0.0;
+  double alpha[K];
   if constexpr (EPI == EPI_CG_UPDATE) {
-    const double tt = sum_partials(ea.part_in + (size_t)k * ea.nbp, ea.nbp, red);
-    const double rho = ea.st[k].rho[ea.par];
-    alpha = (tt > 0.0 && isfinite(tt) && isfinite(rho)) ? rho / tt : 0.0;
-    if (!(tt > 0.0 && isfinite(tt)) && sb == 0 && threadIdx.x == 0) ea.st[k].flags |= 1;
-  }
-
-  P_C o[NC];
-  if (valid) Op::site(oa, in + off, i, k, o);
-
-  double acc = 0.0;
-  if (valid) {
-    if constexpr (EPI == EPI_STORE || EPI == EPI_STORE_NORM) {
-      S* out = (S*)ea.out + off;
 #pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        Op::Pol::st(out + (size_t)q * Vp + i, o[q]);
-        if constexpr (EPI == EPI_STORE_NORM) acc += cnorm2(Op::Pol::ld(out + (size_t)q * Vp + i));
-      }
-    } else if constexpr (EPI == EPI_CG_UPDATE) {
-      using XP = typename XPol<typename Op::Pol>::type;
-      typename XP::S* x = (typename XP::S*)ea.x + off;
-      S* r = (S*)ea.r + off;
-      const S* p = (const S*)ea.p + off;
-      const R a = (R)alpha;
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const size_t e = (size_t)q * Vp + i;
-        typename XP::C xv = XP::ld(x + e);
-        P_C pv = Op::Pol::ld(p + e), rv = Op::Pol::ld(r + e);
-        xv.x += a * pv.x; xv.y += a * pv.y;
-        rv.x -= a * o[q].x; rv.y -= a * o[q].y;
-        XP::st(x + e, xv);
-        Op::Pol::st(r + e, rv);
-        acc += cnorm2(Op::Pol::ld(r + e));
-      }
-    } else if constexpr (EPI == EPI_RESID) {
-      double2* out = (double2*)ea.out + off;
-      const double2* b = (const double2*)ea.b + off;
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const size_t e = (size_t)q * Vp + i;
-        double2 bv = b[e];
-        double2 w;
-        w.x = bv.x - (double)o[q].x;
-        w.y = bv.y - (double)o[q].y;
-        out[e] = w;
-        acc += w.x * w.x + w.y * w.y;
-      }
-    } else if constexpr (EPI == EPI_LANCZOS) {
-      double2* out = (double2*)ea.out + off;
-      const double2* v = (const double2*)ea.v + off;
-      const double2* vp = (const double2*)ea.vprev + off;
-      const double bp = ea.beta_prev ? *ea.beta_prev : 0.0;
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const size_t e = (size_t)q * Vp + i;
-        double2 w;
-        w.x = (double)o[q].x - bp * vp[e].x;
-        w.y = (double)o[q].y - bp * vp[e].y;
-        out[e] = w;
-        acc += v[e].x * w.x + v[e].y * w.y;
-      }
+    for (int kk = 0; kk < K; ++kk) {
+      alpha[kk] = 0.0;
+      if (!((act >> kk) & 1)) continue;
+      const int k = k0 + kk;
+      const double tt = sum_partials(ea.part_in + (size_t)k * ea.nbp, ea.nbp, red);
+      const double rho = ea.st[k].rho[ea.par];
+      alpha[kk] = (tt > 0.0 && isfinite(tt) && isfinite(rho)) ? rho / tt : 0.0;
+      if (!(tt > 0.0 && isfinite(tt)) && sb == 0 && threadIdx.x == 0) ea.st[k].flags |= 1;
     }
   }
-  if constexpr (EPI != EPI_STORE) {
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) ea.part[(size_t)k * ea.nbp + sb] = s;
+
+  P_C o[K][NC];
+  if (valid) Op::template site_multi<K>(oa, in + (size_t)k0 * rstride, rstride, i, k0, act, o);
+
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    if (!((act >> kk) & 1)) continue;   // uniform over the block
+    const int k = k0 + kk;
+    const size_t off = (size_t)k * rstride;
+    double acc = 0.0;
+    if (valid) {
+      if constexpr (EPI == EPI_STORE || EPI == EPI_STORE_NORM) {
+        S* out = (S*)ea.out + off;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          Op::Pol::st(out + (size_t)q * Vp + i, o[kk][q]);
+          if constexpr (EPI == EPI_STORE_NORM) acc += cnorm2(Op::Pol::ld(out + (size_t)q * Vp + i));
+        }
+      } else if constexpr (EPI == EPI_CG_UPDATE) {
+        using XP = typename XPol<typename Op::Pol>::type;
+        typename XP::S* x = (typename XP::S*)ea.x + off;
+        S* r = (S*)ea.r + off;
+        const S* p = (const S*)ea.p + off;
+        const R a = (R)alpha[kk];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          const size_t e = (size_t)q * Vp + i;
+          typename XP::C xv = XP::ld(x + e);
+          P_C pv = Op::Pol::ld(p + e), rv = Op::Pol::ld(r + e);
+          xv.x += a * pv.x; xv.y += a * pv.y;
+          rv.x -= a * o[kk][q].x; rv.y -= a * o[kk][q].y;
+          XP::st(x + e, xv);
+          Op::Pol::st(r + e, rv);
+          acc += cnorm2(Op::Pol::ld(r + e));
+        }
+      } else if constexpr (EPI == EPI_RESID) {
+        double2* out = (double2*)ea.out + off;
+        const double2* b = (const double2*)ea.b + off;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          const size_t e = (size_t)q * Vp + i;
+          double2 bv = b[e];
+          double2 w;
+          w.x = bv.x - (double)o[kk][q].x;
+          w.y = bv.y - (double)o[kk][q].y;
+          out[e] = w;
+          acc += w.x * w.x + w.y * w.y;
+        }
+      } else if constexpr (EPI == EPI_LANCZOS) {
+        double2* out = (double2*)ea.out + off;
+        const double2* v = (const double2*)ea.v + off;
+        const double2* vp = (const double2*)ea.vprev + off;
+        const double bp = ea.beta_prev ? *ea.beta_prev : 0.0;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          const size_t e = (size_t)q * Vp + i;
+          double2 w;
+          w.x = (double)o[kk][q].x - bp * vp[e].x;
+          w.y = (double)o[kk][q].y - bp * vp[e].y;
+          out[e] = w;
+          acc += v[e].x * w.x + v[e].y * w.y;
+        }
+      }
+    }
+    if constexpr (EPI != EPI_STORE) {
+      const double bs = block_sum(acc, red);
+      if (threadIdx.x == 0) ea.part[(size_t)k * ea.nbp + sb] = bs;
+    }
   }
 }
 

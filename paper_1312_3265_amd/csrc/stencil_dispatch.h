@@ -13,14 +13,31 @@
 
 namespace lq {
 
+// Systems per thread (K) for the low-precision CG kernels; 1 elsewhere.
+template <template <class, int, bool> class OpT, class P, int NL, bool DAG, int EPI, int K>
+static void launch_k(const OpArgs& oa, const void* in, const EpiArgs& ea, int nrhs,
+                     hipStream_t s) {
+  using Op = OpT<P, NL, DAG>;
+  const int ngroups = (nrhs + K - 1) / K;
+  const int grid = ea.nbp * ngroups;
+  if (grid == 0) return;
+  hipLaunchKernelGGL((stencil_kernel<Op, EPI, K>), dim3(grid), dim3(kBlock), 0, s, oa,
+                     (const typename Op::S*)in, ea, ngroups, nrhs);
+}
+
 template <template <class, int, bool> class OpT, class P, int NL, bool DAG, int EPI>
 static void launch_one(const OpArgs& oa, const void* in, const EpiArgs& ea, int nrhs,
                        hipStream_t s) {
-  using Op = OpT<P, NL, DAG>;
-  const int grid = ea.nbp * nrhs;
-  if (grid == 0) return;
-  hipLaunchKernelGGL((stencil_kernel<Op, EPI>), dim3(grid), dim3(kBlock), 0, s, oa,
-                     (const typename Op::S*)in, ea, nrhs);
+  constexpr bool multi = (P::id != 0) && (EPI == EPI_STORE_NORM || EPI == EPI_CG_UPDATE ||
+                                          EPI == EPI_STORE);
+  const int K = multi ? ea.rhs_per_thread : 1;
+  if constexpr (multi) {
+    if (K == 2) return launch_k<OpT, P, NL, DAG, EPI, 2>(oa, in, ea, nrhs, s);
+    if (K == 4) return launch_k<OpT, P, NL, DAG, EPI, 4>(oa, in, ea, nrhs, s);
+  }
+  if (K != 1 && K != 0)
+    throw std::runtime_error("stencil: unsupported systems per thread " + std::to_string(K));
+  launch_k<OpT, P, NL, DAG, EPI, 1>(oa, in, ea, nrhs, s);
 }
 
 template <template <class, int, bool> class OpT, class P, int NL>

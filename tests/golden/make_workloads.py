@@ -6,7 +6,9 @@ paper's ensemble of Sec. 3), then finds m_c for each formulation as the
 minimiser of the 200-step Lanczos lowest Ritz value of (D+m)^dag (D+m).  The
 bare masses of the workload are m_c + delta, delta in {0.02, 0.05, 0.1}.
 
-Run:  python tests/golden/make_workloads.py      (about an hour on 8 cores)
+Run:  python tests/golden/make_workloads.py      (about an hour on 8 cores), or
+      python tests/golden/make_workloads.py --only W   and   --only SW   in parallel,
+      then  python tests/golden/make_workloads.py --merge
 """
 from __future__ import annotations
 
@@ -45,10 +47,30 @@ def _mc(args):
 
 
 def main():
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--only", choices=["W", "SW"], help="compute one formulation's m_c into "
+                    "workload_<W|SW>.json (run both, then --merge)")
+    ap.add_argument("--merge", action="store_true", help="combine the two partial files")
+    args = ap.parse_args()
     eps, plaq = gauge.tune_epsilon(DIMS, SEED, TARGET_PLAQ)
     print(f"epsilon={eps} plaquette={plaq}", flush=True)
-    with mp.Pool(2) as pool:
-        res = dict(pool.map(_mc, [(synth.WILSON, eps), (synth.STAGGERED_WILSON, eps)]))
+    if args.only:
+        form = synth.WILSON if args.only == "W" else synth.STAGGERED_WILSON
+        tag, r = _mc((form, eps))
+        with open(os.path.join(HERE, f"workload_{tag}.json"), "w") as f:
+            json.dump(dict(eps=eps, plaquette=plaq, result=r), f, indent=1)
+        return
+    if args.merge:
+        res = {}
+        for tag in ("W", "SW"):
+            with open(os.path.join(HERE, f"workload_{tag}.json")) as f:
+                part = json.load(f)
+            assert part["eps"] == eps
+            res[tag] = part["result"]
+    else:
+        with mp.Pool(2) as pool:
+            res = dict(pool.map(_mc, [(synth.WILSON, eps), (synth.STAGGERED_WILSON, eps)]))
     out = dict(
         description="Synthetic 16^3x32 stand-in for the paper's quenched beta=6 ensemble "
                     "(Sec. 3): independent near-identity SU(3) links exp(i eps H), eps tuned "
