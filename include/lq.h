@@ -181,13 +181,16 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t op, int32_t precision
  * CG iteration (t = M p fused with ||t||^2), dagger = 1 the plain M^dag
  * stencil -- the same kernels the solvers launch.  rhs_per_thread (1, 2, 4;
  * FP32/FP16 only) is the number of systems each thread serves, the choice the
- * solvers' autotuner makes per batch.  ws: device scratch of
+ * solvers' autotuner makes per batch; window (>= 0; 0 = all) is the number of
+ * site blocks each XCD sweeps for one system before the next system, the
+ * autotuner's other choice.  ws: device scratch of
  * lq_time_dslash_workspace_bytes (contents overwritten).  */
 size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t precision,
                                       int32_t nrhs);
 int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger,
                    int32_t precision, int32_t links, int32_t nrhs, int32_t rhs_per_thread,
-                   int32_t reps, void* ws, size_t ws_bytes, double* avg_ms, void* stream);
+                   int32_t window, int32_t reps, void* ws, size_t ws_bytes, double* avg_ms,
+                   void* stream);
 
 /* ----------------------------------------------------------------- solve
  * CG on eq. (2) for one source chi (device canonical complex128); the

@@ -100,7 +100,7 @@ def lib():
         "lq_gauge_plaquette": ([P, P, P], I32),
         "lq_apply_workspace_bytes": ([P, I32, I32], SZ),
         "lq_apply": ([P, P, I32, I32, I32, P, P, P, SZ, P], I32),
-        "lq_time_dslash": ([P, P, I32, I32, I32, I32, I32, I32, P, SZ, P, P], I32),
+        "lq_time_dslash": ([P, P, I32, I32, I32, I32, I32, I32, I32, P, SZ, P, P], I32),
         "lq_time_dslash_workspace_bytes": ([P, I32, I32, I32], SZ),
         "lq_solve_workspace_bytes": ([P, I32, P, I32], SZ),
         "lq_cg_solve": ([P, P, P, P, D, I32, P, P, SZ, P, P], I32),
@@ -229,7 +229,7 @@ def apply(gauge, formulation, mass, psi, op=OP_M, r=1.0, g55=G55_CORNERS, precis
 
 
 def time_dslash(gauge, formulation, mass, dagger=False, r=1.0, g55=G55_CORNERS, precision=F64,
-                links=0, nrhs=1, reps=50, rhs_per_thread=1, stream=None):
+                links=0, nrhs=1, reps=50, rhs_per_thread=1, window=0, stream=None):
     """Average milliseconds per stencil launch (HIP events on the launch stream)."""
     torch = _torch()
     nb = int(lib().lq_time_dslash_workspace_bytes(gauge._h, formulation, precision, nrhs))
@@ -237,7 +237,7 @@ def time_dslash(gauge, formulation, mass, dagger=False, r=1.0, g55=G55_CORNERS, 
     d = Dirac(formulation, g55, mass, r)
     ms = ctypes.c_double()
     _check(lib().lq_time_dslash(gauge._h, ctypes.byref(d), int(dagger), precision, links, nrhs,
-                                rhs_per_thread, reps, _ptr(ws), nb, ctypes.byref(ms),
+                                rhs_per_thread, window, reps, _ptr(ws), nb, ctypes.byref(ms),
                                 _stream(stream)))
     return ms.value
 

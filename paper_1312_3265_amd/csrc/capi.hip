@@ -226,8 +226,8 @@ size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, in
 }
 
 int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t precision,
-                   int32_t links, int32_t nrhs, int32_t rhs_per_thread, int32_t reps, void* ws,
-                   size_t ws_bytes, double* avg_ms, void* stream) {
+                   int32_t links, int32_t nrhs, int32_t rhs_per_thread, int32_t window,
+                   int32_t reps, void* ws, size_t ws_bytes, double* avg_ms, void* stream) {
   return guard([&] {
     need(g && ws && avg_ms, "null argument");
     check_dirac(d);
@@ -255,6 +255,7 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t
     e.out = b;
     e.part = part;
     e.rhs_per_thread = rhs_per_thread;
+    e.window = window;
     // the stencil of the first matvec of a CG iteration (t = M p with ||t||^2),
     // or the plain M^dag stencil
     const int epi = dagger ? EPI_STORE : EPI_STORE_NORM;

@@ -59,18 +59,21 @@ template <typename C> __device__ __forceinline__ double cnorm2(C a) { return (do
 struct F64 {
   using S = double2; using C = double2; using R = double;
   static constexpr int id = 0;
+  __device__ __forceinline__ static C cvt(S v) { return v; }
   __device__ __forceinline__ static C ld(const S* p) { return *p; }
   __device__ __forceinline__ static void st(S* p, C v) { *p = v; }
 };
 struct F32 {
   using S = float2; using C = float2; using R = float;
   static constexpr int id = 1;
+  __device__ __forceinline__ static C cvt(S v) { return v; }
   __device__ __forceinline__ static C ld(const S* p) { return *p; }
   __device__ __forceinline__ static void st(S* p, C v) { *p = v; }
 };
 struct F16 {
   using S = __half2; using C = float2; using R = float;
   static constexpr int id = 2;
+  __device__ __forceinline__ static C cvt(S v) { return __half22float2(v); }
   __device__ __forceinline__ static C ld(const S* p) { return __half22float2(*p); }
   __device__ __forceinline__ static void st(S* p, C v) { *p = __float22half2_rn(v); }
 };
@@ -133,13 +136,28 @@ __device__ __forceinline__ int nb_bwd(const Geom& g, const Coord& c, int i, int 
   return i + d;
 }
 
-// Element `site` of plane q of a SoA array: the plane base is uniform across
-// the wavefront (scalar registers), the per-lane part is a 32-bit offset.
+// Element `site` of plane q of a SoA array, as a raw buffer load: the array
+// base is wavefront-uniform (a buffer descriptor in scalar registers), the
+// plane offset q * Vp is a scalar offset and the per-lane part a 32-bit vector
+// offset, so no per-load 64-bit address arithmetic is spent.  Every SoA array
+// a kernel reads this way is smaller than 4 GiB (checked at lattice creation).
+constexpr int kBufferDword3 = 0x00020000;   // raw (untyped) buffer access on CDNA
+
 template <class P>
 __device__ __forceinline__ typename P::C ldq(const typename P::S* __restrict__ base, int Vp, int q,
                                              int site) {
-  const typename P::S* plane = base + (size_t)q * (size_t)Vp;
-  return P::ld(plane + (uint32_t)site);
+  using S = typename P::S;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, -1, kBufferDword3);
+  const uint32_t vo = (uint32_t)site * (uint32_t)sizeof(S);
+  const uint32_t so = (uint32_t)q * (uint32_t)Vp * (uint32_t)sizeof(S);
+  if constexpr (sizeof(S) == 16) {
+    return P::cvt(__builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, so, 0)));
+  } else if constexpr (sizeof(S) == 8) {
+    return P::cvt(__builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0)));
+  } else {
+    return P::cvt(__builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0)));
+  }
 }
 
 // Staggered phases as +-1: eta_mu = (-1)^(x_1+..+x_{mu-1}), phi = (-1)^(x2+x4).

@@ -99,6 +99,7 @@ struct Engine {
   double delta = 0.0;
   int nbp = 0;
   int rhs_per_thread = 1;     // systems per thread of the CG stencils (autotuned)
+  int window = 0;             // XCD window of the CG stencils' block order (autotuned)
   // device
   double2 *b = nullptr, *xhi = nullptr, *rhi = nullptr, *t64 = nullptr;
   void *xlo = nullptr, *rlo = nullptr, *p = nullptr, *t = nullptr;

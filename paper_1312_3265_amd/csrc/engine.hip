@@ -104,6 +104,7 @@ void remember_rhs_per_thread(const std::string& key, int k) {
 // (zeroed) solver buffers and keep the fastest.
 void Engine::tune(hipStream_t s) {
   rhs_per_thread = 1;
+  window = 0;
   if (prec_lo == P64 || nslots < 2) return;
   hipDeviceProp_t prop;
   int dev = 0;
@@ -111,12 +112,12 @@ void Engine::tune(hipStream_t s) {
   LQ_HIP(hipGetDeviceProperties(&prop, dev));
   std::ostringstream key;
   const Geom& g = gauge->g;
-  key << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
+  key << "v3:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
       << ":op" << op << ":p" << prec_lo << ":l" << nl_lo << ":n" << nslots;
   std::string k = key.str();
   for (auto& ch : k) if (ch == ' ') ch = '_';
-  const int cached = tuned_rhs_per_thread(k);
-  if (cached) { rhs_per_thread = cached; return; }
+  const int cached = tuned_rhs_per_thread(k);   // encoded as K + 8 * (window + 1)
+  if (cached) { rhs_per_thread = cached & 7; window = (cached >> 3) - 1; return; }
   OpArgs oa = op_args(prec_lo, nl_lo);
   EpiArgs e = epi_base();
   e.st = nullptr;
@@ -126,24 +127,29 @@ void Engine::tune(hipStream_t s) {
   LQ_HIP(hipEventCreate(&t0));
   LQ_HIP(hipEventCreate(&t1));
   float best = 1e30f;
-  int bestk = 1;
+  int bestk = 1, bestw = 0;
   for (int kk : {1, 2, 4}) {
     if (kk > nslots) break;
-    e.rhs_per_thread = kk;
-    launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
-    LQ_HIP(hipEventRecord(t0, s));
-    for (int r = 0; r < 5; ++r) launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
-    LQ_HIP(hipEventRecord(t1, s));
-    LQ_HIP(hipEventSynchronize(t1));
-    check_launch();
-    float ms = 0.0f;
-    LQ_HIP(hipEventElapsedTime(&ms, t0, t1));
-    if (ms < best) { best = ms; bestk = kk; }
+    for (int w : {1, 2, 4, 0}) {
+      e.rhs_per_thread = kk;
+      e.window = w;
+      launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
+      LQ_HIP(hipEventRecord(t0, s));
+      for (int r = 0; r < 5; ++r)
+        launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
+      LQ_HIP(hipEventRecord(t1, s));
+      LQ_HIP(hipEventSynchronize(t1));
+      check_launch();
+      float ms = 0.0f;
+      LQ_HIP(hipEventElapsedTime(&ms, t0, t1));
+      if (ms < best) { best = ms; bestk = kk; bestw = w; }
+    }
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   rhs_per_thread = bestk;
-  remember_rhs_per_thread(k, bestk);
+  window = bestw;
+  remember_rhs_per_thread(k, bestk + 8 * (bestw + 1));
 }
 
 // ================================================================ Engine
@@ -304,9 +310,11 @@ void Engine::enqueue_iterations(int n, hipStream_t s) {
     e.out = t;
     e.part = part_t;
     e.rhs_per_thread = rhs_per_thread;
+    e.window = window;
     launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
     EpiArgs f = epi_base();
     f.rhs_per_thread = rhs_per_thread;
+    f.window = window;
     f.par = par;
     f.state_mode = 1;
     f.part = part_r;

@@ -15,7 +15,7 @@ field_in_kernel(const Geom g, const void* __restrict__ canon, typename P::S* __r
   using C = typename P::C;
   using R = typename P::R;
   int sb, kl;
-  map_block(nbp, nrhs, sb, kl);
+  map_block(nbp, nrhs, 1, sb, kl);
   const int k = k0 + kl;
   const int i = sb * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
@@ -40,7 +40,7 @@ field_out_kernel(const Geom g, const typename P::S* __restrict__ soa, void* __re
                  int nbp, int k0, int nrhs) {
   using C = typename P::C;
   int sb, kl;
-  map_block(nbp, nrhs, sb, kl);
+  map_block(nbp, nrhs, 1, sb, kl);
   const int k = k0 + kl;
   const int i = sb * blockDim.x + threadIdx.x;
   if (i >= g.V) return;

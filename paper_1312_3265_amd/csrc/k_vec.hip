@@ -45,7 +45,7 @@ p_update_kernel(const Geom g, SlotState* st, int par, const double* __restrict__
   using R = typename P::R;
   __shared__ double red[16];
   int sb, kl;
-  map_block(nbp, nrhs, sb, kl);
+  map_block(nbp, nrhs, 1, sb, kl);
   const int k = k0 + kl;
   SlotState* s = st + k;
   if (s->status != SLOT_RUNNING) return;
@@ -95,7 +95,7 @@ ru_accumulate_kernel(const Geom g, const SlotState* st, const int* mask, double2
   using XP = typename XPol<P>::type;
   using C = typename XP::C;
   int sb, kl;
-  map_block(nbp, nrhs, sb, kl);
+  map_block(nbp, nrhs, 1, sb, kl);
   const int k = k0 + kl;
   if (!ru_selected(st, mask, k)) return;
   const double sc = st[k].scale;
@@ -158,7 +158,7 @@ ru_convert_kernel(const Geom g, const SlotState* st, const int* mask,
   using R = typename P::R;
   __shared__ double red[16];
   int sb, kl;
-  map_block(nbp, nrhs, sb, kl);
+  map_block(nbp, nrhs, 1, sb, kl);
   const int k = k0 + kl;
   if (!ru_selected(st, mask, k)) return;
   const double inv = 1.0 / st[k].scale;
@@ -213,7 +213,7 @@ load_prepare_kernel(const Geom g, double2* __restrict__ xhi,
   using XP = typename XPol<P>::type;
   using C = typename XP::C;
   int sb, kl;
-  map_block(nbp, nrhs, sb, kl);
+  map_block(nbp, nrhs, 1, sb, kl);
   const int k = k0 + kl;
   const int i = sb * blockDim.x + threadIdx.x;
   if (i >= g.V) return;

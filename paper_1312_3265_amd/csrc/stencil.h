@@ -11,10 +11,10 @@
 // Partial sums are FP64, reduced in a fixed order (wavefront butterfly, then
 // waves in order), so results do not depend on scheduling.
 //
-// Grid: nbp site-blocks (a multiple of 8) x nrhs, flattened so that the blocks
-// of one site range and different right-hand sides go to the same XCD one
-// after another (blocks are dispatched round-robin over the 8 XCDs): the links
-// of that site range are then reused from that XCD's L2 by every RHS.
+// Grid: nbp site-blocks (a multiple of 8) x nrhs, flattened so that each XCD
+// works through one contiguous range of site blocks, all right-hand sides of a
+// site block one after another (see map_block): stencil neighbours and the
+// links shared by the right-hand sides are then served from that XCD's L2.
 #pragma once
 
 #include "common.h"
@@ -43,15 +43,31 @@ struct EpiArgs {
   const double* vprev;    // LANCZOS: v_{j-1}
   const double* beta_prev;// LANCZOS: device scalar beta_{j-1} (null = 0)
   int rhs_per_thread;     // systems per thread (1, 2 or 4; FP32/FP16 CG kernels)
+  int window;             // site blocks per XCD window (map_block; <= 0: whole range)
 };
 
-// blockIdx.x -> (site block sb, rhs k), XCD-aware (see file comment).
-__device__ __forceinline__ void map_block(int nbp, int nrhs, int& sb, int& k) {
+// blockIdx.x -> (site block sb, rhs k), XCD-aware.  Block b runs on XCD b % 8,
+// as that XCD's (b / 8)-th block.  The site blocks are swept in windows of
+// 8*win consecutive blocks; in a window, XCD x owns the win blocks
+// [8*win*w + win*x, ... + win) and visits them for system 0, then system 1, ...
+// So the whole GPU works on one compact window at a time (its data stays in
+// the shared Infinity Cache), each XCD re-reads a window's links from its own
+// L2 for every system, and a block's t neighbours -- one t-slice away, which is
+// one window when 8*win*256 sites make a slice -- are visited by the same XCD
+// one window earlier or later.  win = 1 gives XCD-interleaved blocks with the
+// systems innermost; win = nbp/8 gives each XCD one contiguous range.
+__device__ __forceinline__ void map_block(int nbp, int nrhs, int win, int& sb, int& k) {
   const int b = blockIdx.x;
   const int xcd = b & 7, kk = b >> 3;
-  const int j = kk / nrhs;
-  k = kk - j * nrhs;
-  sb = 8 * j + xcd;
+  const int range = nbp >> 3;                // blocks per XCD in total
+  if (win <= 0 || win > range) win = range;
+  const int per_win = win * nrhs;
+  const int w = kk / per_win;
+  const int w0 = w * win;                    // blocks per XCD before this window
+  const int width = min(win, range - w0);    // the last window may be narrower
+  const int rem = kk - w * per_win;
+  k = rem / width;
+  sb = 8 * w0 + xcd * width + (rem - k * width);
 }
 
 __device__ __forceinline__ bool slot_active(const SlotState* st, int k, int mode, int par,
@@ -84,7 +100,7 @@ stencil_kernel(const OpArgs oa, const typename Op::S* __restrict__ in, const Epi
   constexpr int NC = Op::NC;
   __shared__ double red[16];
   int sb, kg;
-  map_block(ea.nbp, ngroups, sb, kg);
+  map_block(ea.nbp, ngroups, ea.window, sb, kg);
   const int k0 = ea.k0 + kg * K;
   unsigned act = 0;
 #pragma unroll
