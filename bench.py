@@ -51,7 +51,7 @@ def bytes_per_site(formulation, precision, links, nrhs):
     input and output vectors once per RHS, the links (and corners) once."""
     nc = 12 if formulation == 0 else 3
     per = {0: 16, 1: 8, 2: 4}[precision]
-    vec = 2 * nc * per
+    vec = 2 * nc * per + (2 * 4 if precision == 2 else 0)   # Q16: per-site float scale
     link = 4 * (links // 2) * per if precision != 0 else 4 * 9 * 16
     corner = 0 if formulation == 0 else 8 * 9 * per
     return nrhs * vec + link + corner
@@ -97,7 +97,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="f32", choices=["f32", "f16"])
+    ap.add_argument("--precision", default="f32", choices=["f32", "q16"])
     ap.add_argument("--fields", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     a = ap.parse_args()
@@ -117,7 +117,7 @@ def main():
     eps = w["eps"]
     mc = w["m_c"]
     seeds = w["batch_seeds"][: a.fields]
-    prec = lq.F32 if a.precision == "f32" else lq.F16
+    prec = lq.F32 if a.precision == "f32" else lq.Q16
     links = 12
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
@@ -131,7 +131,7 @@ def main():
         U = synth.gauge_field(dims, "near_identity", s, eps)
         if U0 is None:
             U0 = U
-        fields.append(lq.Gauge(lat, U, lq.FEAT_CORNERS | lq.FEAT_F32 | lq.FEAT_F16,
+        fields.append(lq.Gauge(lat, U, lq.FEAT_CORNERS | lq.FEAT_F32 | lq.FEAT_Q16,
                                stream=stream))
     plaq = fields[0].plaquette(stream=stream)
     src = {}

@@ -81,7 +81,9 @@ extern "C" {
 /* arithmetic / storage precision of the stencil and Krylov vectors */
 #define LQ_PREC_F64 0
 #define LQ_PREC_F32 1
-#define LQ_PREC_F16 2
+#define LQ_PREC_Q16 2   /* 16-bit fixed point: int16 components; vectors carry a
+                           per-site float scale (largest |re|, |im| of the site),
+                           links and corners a fixed scale of 1; FP32 arithmetic */
 
 /* link storage: 18 reals (full 3x3) or 12 reals (two rows, third row
  * rebuilt in-kernel as conj(row0 x row1), valid for SU(3) links only) */
@@ -91,7 +93,7 @@ extern "C" {
 /* gauge features: which device copies lq_gauge_create builds */
 #define LQ_FEAT_CORNERS 0x1u  /* corner matrices W_s(x) in every built precision */
 #define LQ_FEAT_F32 0x2u      /* FP32 links, 18-real and 12-real               */
-#define LQ_FEAT_F16 0x4u      /* FP16 links, 12-real                           */
+#define LQ_FEAT_Q16 0x4u      /* 16-bit fixed-point links (12-real) and corners  */
 
 typedef struct lq_lattice_s lq_lattice;
 typedef struct lq_gauge_s lq_gauge;
@@ -108,9 +110,9 @@ typedef struct {
 
 /* Solver options (zero-initialised = plain FP64 CG, default polling). */
 typedef struct {
-  int32_t precision;          /* LQ_PREC_*: F64 = plain FP64 CG; F32/F16 = inner
-                                 CG in that precision with FP64 reliable updates */
-  int32_t links;              /* LQ_LINKS_18 or LQ_LINKS_12 (F16 requires 12)    */
+  int32_t precision;          /* LQ_PREC_*: F64 = plain FP64 CG; F32/Q16 = inner
+                                 CG in that storage with FP64 reliable updates   */
+  int32_t links;              /* LQ_LINKS_18 or LQ_LINKS_12 (Q16 requires 12)    */
   int32_t reliable_interval;  /* iterations between FP64 reliable updates
                                  (0 = default 64; unused for F64)                */
   int32_t poll_interval;      /* iterations between host convergence polls
@@ -120,7 +122,7 @@ typedef struct {
                                  residual first meets tol (0 = default 50)       */
   double reliable_delta;      /* also update once the iterated residual has
                                  dropped by this factor since the last update
-                                 (0 = default: 0.1 for F16, 1e-3 for F32)        */
+                                 (0 = default: 0.1 for Q16, 1e-3 for F32)        */
 } lq_solve_opts;
 
 /* Per-solve report.  The residuals are relative: ||b - A x|| / ||b|| with
@@ -152,7 +154,7 @@ int64_t lq_lattice_volume(const lq_lattice* lat);
  * lq_gauge_bytes: device bytes lq_gauge_create needs for `features`.
  * lq_gauge_create: repacks the canonical complex128 field `U` (device
  *   pointer, V*4*9 complex) into the library's structure-of-arrays layout in
- *   `buf`, builds the FP32/FP16 copies and the staggered Wilson corner matrices
+ *   `buf`, builds the FP32/16-bit copies and the staggered Wilson corner matrices
  *   W_s(x) = (1/24) sum over the 24 orderings of the one-link-per-direction
  *   path products from x to x + s, s in {+-1}^4 (8 are stored; the other 8 are
  *   W_{-s}(x+s)^dag).  U is only read during the call's stream work.
@@ -167,8 +169,8 @@ int lq_gauge_plaquette(const lq_gauge* g, double* plaquette, void* stream);
 
 /* ----------------------------------------------------------------- apply
  * out = op(in) for the Dirac matrix `d` (paper eq. (2)).  in/out: device
- * canonical fields, complex128 for LQ_PREC_F64 and complex64 for F32/F16
- * (F16 rounds the repacked input to FP16 storage; arithmetic is FP32).
+ * canonical fields, complex128 for LQ_PREC_F64 and complex64 for F32/Q16
+ * (Q16 rounds the repacked input to 16-bit storage; arithmetic is FP32).
  * `ws` is device scratch of lq_apply_workspace_bytes.  Asynchronous. */
 size_t lq_apply_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t precision);
 int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t op, int32_t precision,
@@ -180,7 +182,7 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t op, int32_t precision
  * events on `stream`.  dagger = 0 times the kernel of the first matvec of a
  * CG iteration (t = M p fused with ||t||^2), dagger = 1 the plain M^dag
  * stencil -- the same kernels the solvers launch.  rhs_per_thread (1, 2, 4;
- * FP32/FP16 only) is the number of systems each thread serves, the choice the
+ * FP32/Q16 only) is the number of systems each thread serves, the choice the
  * solvers' autotuner makes per batch; window (>= 0; 0 = all) is the number of
  * site blocks each XCD sweeps for one system before the next system, the
  * autotuner's other choice.  ws: device scratch of
@@ -196,7 +198,7 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger,
  * CG on eq. (2) for one source chi (device canonical complex128); the
  * solution x (device canonical complex128) is returned when the FP64 true
  * residual ||b - A x||/||b|| <= tol, with x0 = 0.  Mixed precision (opts)
- * iterates in FP32/FP16 and recomputes the true residual in FP64 at every
+ * iterates in FP32/Q16 and recomputes the true residual in FP64 at every
  * reliable update; scalars alpha, beta and all reductions are FP64. */
 size_t lq_solve_workspace_bytes(const lq_gauge* g, int32_t formulation,
                                 const lq_solve_opts* opts, int32_t nrhs);

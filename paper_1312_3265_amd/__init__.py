@@ -8,7 +8,7 @@ calling into the library does, and raises if the built library is missing.
 
 Fields cross the boundary in the canonical layout (see ``synth``): torch tensors
 of shape (L4, L3, L2, L1, 4, 3) (Wilson) or (L4, L3, L2, L1, 3) (staggered
-Wilson), complex128 (complex64 for the FP32/FP16 ``apply``).
+Wilson), complex128 (complex64 for the FP32/Q16 ``apply``).
 """
 from __future__ import annotations
 
@@ -24,8 +24,8 @@ WILSON = 0
 STAGGERED_WILSON = 1
 OP_M, OP_MDAG, OP_MDAGM = 0, 1, 2
 G55_CORNERS, G55_ONTHEFLY = 0, 1
-F64, F32, F16 = 0, 1, 2
-FEAT_CORNERS, FEAT_F32, FEAT_F16 = 1, 2, 4
+F64, F32, Q16 = 0, 1, 2
+FEAT_CORNERS, FEAT_F32, FEAT_Q16 = 1, 2, 4
 OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_WORKSPACE, ERR_DEVICE, ERR_BREAKDOWN, ERR_STATE = -1, -2, -3, -4, -5
 SLOT_EMPTY, SLOT_RUNNING, SLOT_DONE, SLOT_FAILED = 0, 1, 2, 3
@@ -177,7 +177,7 @@ class Lattice:
 class Gauge:
     """Gauge field resident in HBM (library layout, FP64 plus requested copies)."""
 
-    def __init__(self, lattice, U, features=FEAT_CORNERS | FEAT_F32 | FEAT_F16, stream=None):
+    def __init__(self, lattice, U, features=FEAT_CORNERS | FEAT_F32 | FEAT_Q16, stream=None):
         torch = _torch()
         self.lattice = lattice
         self.features = features

@@ -45,15 +45,15 @@ static void check_dirac(const lq_dirac* d) {
 }
 
 static void check_prec(int32_t prec, int32_t links) {
-  need(prec == LQ_PREC_F64 || prec == LQ_PREC_F32 || prec == LQ_PREC_F16, "bad precision");
+  need(prec == LQ_PREC_F64 || prec == LQ_PREC_F32 || prec == LQ_PREC_Q16, "bad precision");
   need(links == 0 || links == LQ_LINKS_18 || links == LQ_LINKS_12, "links must be 18 or 12");
-  need(!(prec == LQ_PREC_F16 && links == LQ_LINKS_18), "FP16 stencils use 12-real links");
+  need(!(prec == LQ_PREC_Q16 && links == LQ_LINKS_18), "16-bit stencils use 12-real links");
 }
 
 static int links_for(int32_t prec, int32_t links) {
   if (prec == LQ_PREC_F64) return 18;
   if (links) return links;
-  return prec == LQ_PREC_F16 ? 12 : 18;
+  return prec == LQ_PREC_Q16 ? 12 : 18;
 }
 
 extern "C" {
@@ -122,11 +122,11 @@ int lq_gauge_create(const lq_lattice* lat, const void* U, uint32_t features, voi
       launch_links_convert(P32, 18, g->g, g->u64, g->u32_18, s);
       launch_links_convert(P32, 12, g->g, g->u64, g->u32_12, s);
     }
-    if (features & LQ_FEAT_F16) launch_links_convert(P16, 12, g->g, g->u64, g->u16_12, s);
+    if (features & LQ_FEAT_Q16) launch_links_convert(P16, 12, g->g, g->u64, g->u16_12, s);
     if (features & LQ_FEAT_CORNERS) {
       launch_corners(g->g, g->u64, g->c64, s);
       if (features & LQ_FEAT_F32) launch_corners_convert(P32, g->g, g->c64, g->c32, s);
-      if (features & LQ_FEAT_F16) launch_corners_convert(P16, g->g, g->c64, g->c16, s);
+      if (features & LQ_FEAT_Q16) launch_corners_convert(P16, g->g, g->c64, g->c16, s);
     }
     check_launch();
     *out = g.release();
@@ -152,7 +152,7 @@ int lq_gauge_plaquette(const lq_gauge* g, double* plaquette, void* stream) {
 size_t lq_apply_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t precision) {
   if (!g || (formulation != LQ_WILSON && formulation != LQ_STAGGERED_WILSON)) return 0;
   if (precision < 0 || precision > 2) return 0;
-  const size_t v = (size_t)ncomp_of(formulation) * g->g.Vp * store_bytes(precision);
+  const size_t v = field_bytes(g->g, precision, ncomp_of(formulation));
   Carver c(nullptr);
   c.take(v); c.take(v); c.take(v);
   c.take((size_t)nbp_of(g->g.V) * 8);
@@ -185,7 +185,7 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t opsel, int32_t precis
     const int nc = ncomp_of(d->formulation);
     const int op = opkind(d->formulation, d->g55_mode);
     const OpArgs oa = make_op(g, d, precision, nl);
-    const size_t v = (size_t)nc * g->g.Vp * store_bytes(precision);
+    const size_t v = field_bytes(g->g, precision, nc);
     Carver c(ws);
     void* a = c.take(v);
     void* b = c.take(v);
@@ -217,7 +217,7 @@ size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, in
                                       int32_t nrhs) {
   if (!g || nrhs < 1 || precision < 0 || precision > 2) return 0;
   if (formulation != LQ_WILSON && formulation != LQ_STAGGERED_WILSON) return 0;
-  const size_t v = (size_t)nrhs * ncomp_of(formulation) * g->g.Vp * store_bytes(precision);
+  const size_t v = (size_t)nrhs * field_bytes(g->g, precision, ncomp_of(formulation));
   Carver c(nullptr);
   c.take(v);
   c.take(v);
@@ -239,7 +239,7 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t
     const int nl = links_for(precision, links);
     const int nc = ncomp_of(d->formulation);
     const int op = opkind(d->formulation, d->g55_mode);
-    const size_t v = (size_t)nrhs * nc * g->g.Vp * store_bytes(precision);
+    const size_t v = (size_t)nrhs * field_bytes(g->g, precision, nc);
     Carver c(ws);
     void* a = c.take(v);
     void* b = c.take(v);

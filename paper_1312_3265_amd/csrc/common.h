@@ -15,7 +15,6 @@
 // plane element is a coalesced 64-lane access.
 #pragma once
 
-#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -55,34 +54,73 @@ template <typename C> __device__ __forceinline__ C cmul(C a, C b) { return cfma(
 template <typename C> __device__ __forceinline__ double cnorm2(C a) { return (double)a.x * a.x + (double)a.y * a.y; }
 
 // ---------------------------------------------------------- precision policy
-// Storage type S of a complex number and compute type C.
+// Storage type S of a complex number and compute type C.  Fields of the
+// vector policies are read and written a whole site at a time (ld_site /
+// st_site below); links and corner matrices element by element (cvt / enc).
 struct F64 {
   using S = double2; using C = double2; using R = double;
   static constexpr int id = 0;
+  static constexpr bool kSiteScale = false;
   __device__ __forceinline__ static C cvt(S v) { return v; }
+  __device__ __forceinline__ static S enc(C v) { return v; }
   __device__ __forceinline__ static C ld(const S* p) { return *p; }
   __device__ __forceinline__ static void st(S* p, C v) { *p = v; }
 };
 struct F32 {
   using S = float2; using C = float2; using R = float;
   static constexpr int id = 1;
+  static constexpr bool kSiteScale = false;
   __device__ __forceinline__ static C cvt(S v) { return v; }
+  __device__ __forceinline__ static S enc(C v) { return v; }
   __device__ __forceinline__ static C ld(const S* p) { return *p; }
   __device__ __forceinline__ static void st(S* p, C v) { *p = v; }
 };
-struct F16 {
-  using S = __half2; using C = float2; using R = float;
+
+// 16-bit fixed point.  A complex number is a pair of int16, value = q * s / 32767.
+// Vectors (Q16): s is a per-site scale, the largest |re| or |im| over the
+// site's components, kept in one extra float plane after the component planes;
+// the rounding error is at most 1.5e-5 of the site's largest component.
+// Links and corner matrices (Q16L): s = 1, since every entry of an SU(3)
+// matrix and of an average of products of SU(3) matrices is at most 1 in
+// modulus.  Arithmetic is FP32.
+constexpr float kQ16 = 32767.0f;
+__device__ __forceinline__ short q16_round(float v) {
+  return (short)max(-32767, min(32767, __float2int_rn(v)));
+}
+struct Q16 {
+  using S = short2; using C = float2; using R = float;
   static constexpr int id = 2;
-  __device__ __forceinline__ static C cvt(S v) { return __half22float2(v); }
-  __device__ __forceinline__ static C ld(const S* p) { return __half22float2(*p); }
-  __device__ __forceinline__ static void st(S* p, C v) { *p = __float22half2_rn(v); }
+  static constexpr bool kSiteScale = true;
+};
+struct Q16L {
+  using S = short2; using C = float2; using R = float;
+  static constexpr int id = 2;
+  static constexpr bool kSiteScale = false;
+  __device__ __forceinline__ static C cvt(S v) {
+    return make_float2((float)v.x * (1.0f / kQ16), (float)v.y * (1.0f / kQ16));
+  }
+  __device__ __forceinline__ static S enc(C v) {
+    short2 q;
+    q.x = q16_round(v.x * kQ16);
+    q.y = q16_round(v.y * kQ16);
+    return q;
+  }
 };
 
+// Policy of the links and corner matrices used with vectors of policy P.
+template <class P> struct LinkPol { using type = P; };
+template <> struct LinkPol<Q16> { using type = Q16L; };
+
 // Storage of the solution increment x_lo: FP32 when the Krylov vectors are
-// FP16.  x_lo is amplified by the operator (errors in it grow by up to kappa),
-// so FP16 rounding there would stall the outer iteration.
+// 16-bit.  x_lo is amplified by the operator (errors in it grow by up to
+// kappa), so 16-bit rounding there would stall the outer iteration.
 template <class P> struct XPol { using type = P; };
-template <> struct XPol<F16> { using type = F32; };
+template <> struct XPol<Q16> { using type = F32; };
+
+// Planes of one field of NC components (plus the scale plane of Q16).
+template <class P> __host__ __device__ constexpr int field_planes(int nc) {
+  return nc + (P::kSiteScale ? 1 : 0);
+}
 
 // --------------------------------------------------------------- geometry
 // Division by a runtime-invariant 32-bit divisor via multiply-high
@@ -158,6 +196,61 @@ __device__ __forceinline__ typename P::C ldq(const typename P::S* __restrict__ b
   } else {
     return P::cvt(__builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0)));
   }
+}
+
+// One raw 32-bit word of plane q (the Q16 component and scale planes).
+__device__ __forceinline__ uint32_t ld_word(const void* __restrict__ base, int Vp, int q, int site) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, -1, kBufferDword3);
+  return __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)site * 4u, (uint32_t)q * (uint32_t)Vp * 4u, 0);
+}
+
+// All NC components of site i of a vector field f (planes of Vp elements).
+template <class P, int NC>
+__device__ __forceinline__ void ld_site(const typename P::S* __restrict__ f, int Vp, int i,
+                                        typename P::C v[NC]) {
+  if constexpr (P::kSiteScale) {
+    const float s = __uint_as_float(ld_word(f, Vp, NC, i)) * (1.0f / kQ16);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const short2 w = __builtin_bit_cast(short2, ld_word(f, Vp, q, i));
+      v[q] = make_float2((float)w.x * s, (float)w.y * s);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) v[q] = ldq<P>(f, Vp, q, i);
+  }
+}
+
+// Store site i; returns ||stored value||^2 (the rounded value actually kept).
+template <class P, int NC>
+__device__ __forceinline__ double st_site(typename P::S* __restrict__ f, int Vp, int i,
+                                          const typename P::C v[NC]) {
+  double n2 = 0.0;
+  if constexpr (P::kSiteScale) {
+    float m = 0.0f;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) m = fmaxf(m, fmaxf(fabsf(v[q].x), fabsf(v[q].y)));
+    const float inv = m > 0.0f ? kQ16 / m : 0.0f;
+    const float s = m * (1.0f / kQ16);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      short2 w;
+      w.x = q16_round(v[q].x * inv);
+      w.y = q16_round(v[q].y * inv);
+      f[(size_t)q * Vp + i] = w;
+      const float a = (float)w.x * s, b = (float)w.y * s;
+      n2 += (double)a * a + (double)b * b;
+    }
+    ((float*)f)[(size_t)NC * Vp + i] = m;
+  } else {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      P::st(f + (size_t)q * Vp + i, v[q]);
+      n2 += cnorm2(v[q]);
+    }
+  }
+  return n2;
 }
 
 // Staggered phases as +-1: eta_mu = (-1)^(x_1+..+x_{mu-1}), phi = (-1)^(x2+x4).

@@ -68,14 +68,16 @@ struct WilsonOp {
                                              int mu, bool dagger_link, R t, R sgn, const C lk[9],
                                              C acc[12]) {
     const int Vp = a.g.Vp;
+    C psi[12];
+    ld_site<P, 12>(in, Vp, nb, psi);
     if constexpr (!GENERAL_R) {
       C h[2][3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        C u0 = ldq<P>(in, Vp, 0 * 3 + c, nb);
-        C u1 = ldq<P>(in, Vp, 1 * 3 + c, nb);
-        C l0 = ldq<P>(in, Vp, 2 * 3 + c, nb);
-        C l1 = ldq<P>(in, Vp, 3 * 3 + c, nb);
+        C u0 = psi[0 * 3 + c];
+        C u1 = psi[1 * 3 + c];
+        C l0 = psi[2 * 3 + c];
+        C l1 = psi[3 * 3 + c];
         C b0, b1;
         bmul(mu, l0, l1, b0, b1);
         h[0][c] = cscale(cadd(u0, cscale(b0, t)), sgn);
@@ -100,7 +102,7 @@ struct WilsonOp {
       for (int s = 0; s < 4; ++s) {
         C v[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) v[c] = cscale(ldq<P>(in, Vp, s * 3 + c, nb), sgn);
+        for (int c = 0; c < 3; ++c) v[c] = cscale(psi[s * 3 + c], sgn);
         if (dagger_link) mvd(lk, v, w[s]); else mv(lk, v, w[s]);
       }
       const R rr = (R)a.r;
@@ -132,10 +134,11 @@ struct WilsonOp {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const R diag = (R)(rhs_mass(a, k0 + k) + 4.0 * a.r);
+      C v[12];
+      if ((act >> k) & 1) ld_site<P, 12>(in0 + k * rstride, g.Vp, i, v);
 #pragma unroll
       for (int q = 0; q < 12; ++q)
-        acc[k][q] = ((act >> k) & 1) ? cscale(ldq<P>(in0 + k * rstride, g.Vp, q, i), (R)-2 * diag)
-                                     : czero<C>();
+        acc[k][q] = ((act >> k) & 1) ? cscale(v[q], (R)-2 * diag) : czero<C>();
     }
     const R s = DAG ? (R)-1 : (R)1;
     // The direction loop stays rolled: mu is uniform across the wavefront, so
@@ -150,7 +153,8 @@ struct WilsonOp {
       const R sg = (wrap && g.bc[mu] < 0) ? (R)-1 : (R)1;
       C lk[9];
       // forward: (r - s g) U_mu(x) psi(x+mu); backward: (r + s g) U_mu(x-mu)^dag psi(x-mu)
-      load_link<P, NL>((const S*)a.links, g.Vp, mu, back ? j : i, lk);
+      using LP = typename LinkPol<P>::type;
+      load_link<LP, NL>((const typename LP::S*)a.links, g.Vp, mu, back ? j : i, lk);
 #pragma unroll
       for (int k = 0; k < K; ++k)
         if ((act >> k) & 1) hop(a, in0 + k * rstride, j, mu, back, back ? s : -s, sg, lk, acc[k]);
@@ -195,13 +199,13 @@ __device__ __forceinline__ void dst_site(const OpArgs& a, const typename P::S* _
     // forward hops enter with +eta, backward hops with -eta
     const R sg = ((wrap && g.bc[mu] < 0) ? (R)-1 : (R)1) * (back ? -eta : eta);
     C lk[9];
-    load_link<P, NL>((const S*)a.links, g.Vp, mu, back ? j : i, lk);
+    using LP = typename LinkPol<P>::type;
+    load_link<LP, NL>((const typename LP::S*)a.links, g.Vp, mu, back ? j : i, lk);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (!((act >> k) & 1)) continue;
       C v[3], y[3];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) v[q] = ldq<P>(in0 + k * rstride, g.Vp, q, j);
+      ld_site<P, 3>(in0 + k * rstride, g.Vp, j, v);
       if (back) mvd(lk, v, y); else mv(lk, v, y);
 #pragma unroll
       for (int q = 0; q < 3; ++q) acc[k][q] = cadd(acc[k][q], cscale(y[q], sg));
@@ -248,7 +252,8 @@ struct SWCornerOp {
     for (int k = 0; k < K; ++k)
 #pragma unroll
       for (int q = 0; q < 3; ++q) acc[k][q] = czero<C>();
-    const S* W = (const S*)a.corners;
+    using LP = typename LinkPol<P>::type;
+    const typename LP::S* W = (const typename LP::S*)a.corners;
 #pragma unroll 1
     for (int h = 0; h < 16; ++h) {
       // h = 2*cidx + reflected: forward corner W_s(x) psi(x + s), or the
@@ -261,13 +266,12 @@ struct SWCornerOp {
       const int j = diag_nb(g, c, s, sign);
       C w[9];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) w[q] = ldq<P>(W, g.Vp, cidx * 9 + q, refl ? j : i);
+      for (int q = 0; q < 9; ++q) w[q] = ldq<LP>(W, g.Vp, cidx * 9 + q, refl ? j : i);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (!((act >> k) & 1)) continue;
         C v[3], y[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) v[q] = ldq<P>(in0 + k * rstride, g.Vp, q, j);
+        ld_site<P, 3>(in0 + k * rstride, g.Vp, j, v);
         if (refl) mvd(w, v, y); else mv(w, v, y);
 #pragma unroll
         for (int q = 0; q < 3; ++q) acc[k][q] = cadd(acc[k][q], cscale(y[q], (R)sign));
@@ -278,11 +282,11 @@ struct SWCornerOp {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const R mr = (R)(rhs_mass(a, k0 + k) + a.r);
+      C v[3] = {czero<C>(), czero<C>(), czero<C>()};
+      if ((act >> k) & 1) ld_site<P, 3>(in0 + k * rstride, g.Vp, i, v);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        C v = ((act >> k) & 1) ? ldq<P>(in0 + k * rstride, g.Vp, q, i) : czero<C>();
-        out[k][q] = csub(cadd(cscale(v, mr), cscale(d[k][q], dcoef)), cscale(acc[k][q], gcoef));
-      }
+      for (int q = 0; q < 3; ++q)
+        out[k][q] = csub(cadd(cscale(v[q], mr), cscale(d[k][q], dcoef)), cscale(acc[k][q], gcoef));
     }
   }
 };
@@ -297,12 +301,13 @@ __device__ __forceinline__ void apply_L(const OpArgs& a, int ysite, int mu, int 
                                         typename P::C y[3]) {
   // y = L(y, sgn*mu) v: U_mu(y) v (sgn > 0) or U_mu(y - mu)^dag v (sgn < 0)
   using C = typename P::C;
+  using LP = typename LinkPol<P>::type;
   C lk[9];
   if (sgn > 0) {
-    load_link<P, NL>((const typename P::S*)a.links, a.g.Vp, mu, ysite, lk);
+    load_link<LP, NL>((const typename LP::S*)a.links, a.g.Vp, mu, ysite, lk);
     mv(lk, v, y);
   } else {
-    load_link<P, NL>((const typename P::S*)a.links, a.g.Vp, mu, nbsite, lk);
+    load_link<LP, NL>((const typename LP::S*)a.links, a.g.Vp, mu, nbsite, lk);
     mvd(lk, v, y);
   }
 }
@@ -358,8 +363,7 @@ __device__ __noinline__ void gamma55_otf(const OpArgs& a, const typename P::S* _
           int sg0 = 1;
           const int i0 = step_site(g, y0, i1, mu1, s1, sg0);
           C v[3], y[3];
-#pragma unroll
-          for (int q = 0; q < 3; ++q) v[q] = ldq<P>(in, g.Vp, q, i0);
+          ld_site<P, 3>(in, g.Vp, i0, v);
           apply_L<P, NL>(a, i1, mu1, s1, i0, v, y);
 #pragma unroll
           for (int q = 0; q < 3; ++q) acc1[q] = cadd(acc1[q], cscale(y[q], (R)sg0));
@@ -413,11 +417,11 @@ struct SWOtfOp {
     // phi/24 * (1/2)^4 from the four C_mu factors
     const R gcoef = (R)(a.r * phi_sign(c) / (24.0 * 16.0));
     const R dcoef = DAG ? (R)-0.5 : (R)0.5;
+    C v[3];
+    ld_site<P, 3>(in, g.Vp, i, v);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      C v = ldq<P>(in, g.Vp, q, i);
-      out[q] = csub(cadd(cscale(v, mr), cscale(d[q], dcoef)), cscale(f[q], gcoef));
-    }
+    for (int q = 0; q < 3; ++q)
+      out[q] = csub(cadd(cscale(v[q], mr), cscale(d[q], dcoef)), cscale(f[q], gcoef));
   }
 };
 

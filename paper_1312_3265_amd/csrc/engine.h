@@ -52,6 +52,11 @@ struct Carver {
 };
 
 inline size_t store_bytes(int prec) { return prec == P64 ? 16 : (prec == P32 ? 8 : 4); }
+// planes of one vector field: the 16-bit format adds a per-site scale plane
+inline int field_planes_host(int prec, int nc) { return nc + (prec == P16 ? 1 : 0); }
+inline size_t field_bytes(const Geom& g, int prec, int nc) {
+  return (size_t)field_planes_host(prec, nc) * g.Vp * store_bytes(prec);
+}
 inline int ncomp_of(int formulation) { return formulation == LQ_WILSON ? 12 : 3; }
 inline int opkind(int formulation, int g55) {
   if (formulation == LQ_WILSON) return OP_WILSON;
@@ -72,10 +77,10 @@ struct lq_gauge_s {
   double2* u64 = nullptr;     // 18-real FP64 links
   float2* u32_18 = nullptr;
   float2* u32_12 = nullptr;
-  __half2* u16_12 = nullptr;
+  short2* u16_12 = nullptr;     // 16-bit fixed point, 12-real
   double2* c64 = nullptr;     // corners
   float2* c32 = nullptr;
-  __half2* c16 = nullptr;
+  short2* c16 = nullptr;
   double* scratch = nullptr;  // plaquette partials + result
   int nbp = 0;
 

@@ -40,17 +40,17 @@ size_t gauge_layout(const Geom& g, uint32_t f, void* base, lq_gauge_s* out) {
   const size_t Vp = g.Vp;
   double2* u64 = (double2*)c.take(36 * Vp * 16);
   float2 *u32_18 = nullptr, *u32_12 = nullptr, *c32 = nullptr;
-  __half2 *u16_12 = nullptr, *c16 = nullptr;
+  short2 *u16_12 = nullptr, *c16 = nullptr;
   double2* c64 = nullptr;
   if (f & LQ_FEAT_F32) {
     u32_18 = (float2*)c.take(36 * Vp * 8);
     u32_12 = (float2*)c.take(24 * Vp * 8);
   }
-  if (f & LQ_FEAT_F16) u16_12 = (__half2*)c.take(24 * Vp * 4);
+  if (f & LQ_FEAT_Q16) u16_12 = (short2*)c.take(24 * Vp * 4);
   if (f & LQ_FEAT_CORNERS) {
     c64 = (double2*)c.take(72 * Vp * 16);
     if (f & LQ_FEAT_F32) c32 = (float2*)c.take(72 * Vp * 8);
-    if (f & LQ_FEAT_F16) c16 = (__half2*)c.take(72 * Vp * 4);
+    if (f & LQ_FEAT_Q16) c16 = (short2*)c.take(72 * Vp * 4);
   }
   const int nbp = nbp_of(g.V);
   double* scratch = (double*)c.take((nbp + 8) * sizeof(double));
@@ -160,13 +160,13 @@ size_t Engine::workspace_bytes(const Geom& g, int formulation, const lq_solve_op
   const int nc = ncomp_of(formulation);
   const int prec = prec_of(opts);
   const size_t vhi = (size_t)nslots * nc * g.Vp * 16;
-  const size_t vlo = (size_t)nslots * nc * g.Vp * store_bytes(prec);
+  const size_t vlo = (size_t)nslots * field_bytes(g, prec, nc);
   const int nbp = nbp_of(g.V);
   Carver c(nullptr);
   c.take(vhi); c.take(vhi); c.take(vhi);      // b, x_hi, r_hi
   if (prec != P64) c.take(vhi);               // t64 (shares t when FP64)
   const size_t vx = (size_t)nslots * nc * g.Vp * store_bytes(prec == P16 ? P32 : prec);
-  c.take(vx); c.take(vlo); c.take(vlo); c.take(vlo);    // x_lo (FP32 under FP16), r_lo, p, t
+  c.take(vx); c.take(vlo); c.take(vlo); c.take(vlo);    // x_lo (FP32 under Q16), r_lo, p, t
   for (int k = 0; k < 3; ++k) c.take((size_t)nslots * nbp * sizeof(double));
   c.take((size_t)nslots * sizeof(SlotState));
   c.take((size_t)nslots * sizeof(int));
@@ -205,7 +205,7 @@ void Engine::init(const lq_gauge_s* g, int form, int g55, double rr, int ns,
                                       " bytes, got " + std::to_string(ws_bytes));
   nbp = nbp_of(g->g.V);
   const size_t vhi = (size_t)ns * nc * g->g.Vp * 16;
-  const size_t vlo = (size_t)ns * nc * g->g.Vp * store_bytes(prec_lo);
+  const size_t vlo = (size_t)ns * field_bytes(g->g, prec_lo, nc);
   Carver c(ws);
   b = (double2*)c.take(vhi);
   xhi = (double2*)c.take(vhi);

@@ -20,18 +20,18 @@ field_in_kernel(const Geom g, const void* __restrict__ canon, typename P::S* __r
   const int i = sb * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
   const size_t cbase = ((size_t)kl * g.V + i) * NC;
+  C v[NC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
-    C v;
     if constexpr (F64SRC) {
       const double2 z = ((const double2*)canon)[cbase + q];
-      v.x = (R)z.x; v.y = (R)z.y;
+      v[q].x = (R)z.x; v[q].y = (R)z.y;
     } else {
       const float2 z = ((const float2*)canon)[cbase + q];
-      v.x = (R)z.x; v.y = (R)z.y;
+      v[q].x = (R)z.x; v[q].y = (R)z.y;
     }
-    P::st(soa + ((size_t)k * NC + q) * g.Vp + i, v);
   }
+  st_site<P, NC>(soa + (size_t)k * field_planes<P>(NC) * g.Vp, g.Vp, i, v);
 }
 
 template <class P, int NC, bool F64DST>
@@ -45,11 +45,12 @@ field_out_kernel(const Geom g, const typename P::S* __restrict__ soa, void* __re
   const int i = sb * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
   const size_t cbase = ((size_t)kl * g.V + i) * NC;
+  C v[NC];
+  ld_site<P, NC>(soa + (size_t)k * field_planes<P>(NC) * g.Vp, g.Vp, i, v);
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
-    const C v = P::ld(soa + ((size_t)k * NC + q) * g.Vp + i);
-    if constexpr (F64DST) ((double2*)canon)[cbase + q] = make_double2(v.x, v.y);
-    else ((float2*)canon)[cbase + q] = make_float2((float)v.x, (float)v.y);
+    if constexpr (F64DST) ((double2*)canon)[cbase + q] = make_double2(v[q].x, v[q].y);
+    else ((float2*)canon)[cbase + q] = make_float2((float)v[q].x, (float)v[q].y);
   }
 }
 
@@ -59,8 +60,8 @@ field_out_kernel(const Geom g, const typename P::S* __restrict__ soa, void* __re
     else if (prec == P64 && nc == 3) { using PP = F64; constexpr int NCC = 3; CALL; }  \
     else if (prec == P32 && nc == 12) { using PP = F32; constexpr int NCC = 12; CALL; } \
     else if (prec == P32 && nc == 3) { using PP = F32; constexpr int NCC = 3; CALL; }  \
-    else if (prec == P16 && nc == 12) { using PP = F16; constexpr int NCC = 12; CALL; } \
-    else if (prec == P16 && nc == 3) { using PP = F16; constexpr int NCC = 3; CALL; }  \
+    else if (prec == P16 && nc == 12) { using PP = Q16; constexpr int NCC = 12; CALL; } \
+    else if (prec == P16 && nc == 3) { using PP = Q16; constexpr int NCC = 3; CALL; }  \
     else throw std::runtime_error("unsupported precision/components");                \
   } while (0)
 
@@ -118,7 +119,7 @@ links_convert_kernel(const Geom g, const double2* __restrict__ u64, typename P::
       for (int b = 0; b < 3; ++b) {
         const double2 z = u64[(size_t)((mu * 3 + a) * 3 + b) * g.Vp + i];
         C v; v.x = (R)z.x; v.y = (R)z.y;
-        P::st(dst + (size_t)((mu * rows + a) * 3 + b) * g.Vp + i, v);
+        dst[(size_t)((mu * rows + a) * 3 + b) * g.Vp + i] = P::enc(v);
       }
 }
 
@@ -130,7 +131,7 @@ void launch_links_convert(int prec, int nl, const Geom& g, const double2* u64, v
   else if (prec == P32 && nl == 12)
     hipLaunchKernelGGL((links_convert_kernel<F32, 12>), grid, blk, 0, s, g, u64, (float2*)dst);
   else if (prec == P16 && nl == 12)
-    hipLaunchKernelGGL((links_convert_kernel<F16, 12>), grid, blk, 0, s, g, u64, (__half2*)dst);
+    hipLaunchKernelGGL((links_convert_kernel<Q16L, 12>), grid, blk, 0, s, g, u64, (short2*)dst);
   else
     throw std::runtime_error("links_convert: unsupported precision/storage");
 }
@@ -256,7 +257,7 @@ corners_convert_kernel(const Geom g, const double2* __restrict__ c64, typename P
   for (int q = 0; q < 72; ++q) {
     const double2 z = c64[(size_t)q * g.Vp + i];
     C v; v.x = (R)z.x; v.y = (R)z.y;
-    P::st(dst + (size_t)q * g.Vp + i, v);
+    dst[(size_t)q * g.Vp + i] = P::enc(v);
   }
 }
 
@@ -265,7 +266,7 @@ void launch_corners_convert(int prec, const Geom& g, const double2* c64, void* d
   if (prec == P32)
     hipLaunchKernelGGL(corners_convert_kernel<F32>, grid, blk, 0, s, g, c64, (float2*)dst);
   else if (prec == P16)
-    hipLaunchKernelGGL(corners_convert_kernel<F16>, grid, blk, 0, s, g, c64, (__half2*)dst);
+    hipLaunchKernelGGL(corners_convert_kernel<Q16L>, grid, blk, 0, s, g, c64, (short2*)dst);
   else
     throw std::runtime_error("corners_convert: unsupported precision");
 }

@@ -62,16 +62,17 @@ p_update_kernel(const Geom g, SlotState* st, int par, const double* __restrict__
   const double beta = (rho > 0.0 && isfinite(rr)) ? rr / rho : 0.0;
   const int i = sb * blockDim.x + threadIdx.x;
   if (i < g.V) {
-    const size_t off = (size_t)k * NC * g.Vp;
+    const size_t off = (size_t)k * field_planes<P>(NC) * g.Vp;
     const R bt = (R)beta;
+    C pv[NC], rv[NC];
+    ld_site<P, NC>(p + off, g.Vp, i, pv);
+    ld_site<P, NC>(r + off, g.Vp, i, rv);
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      const size_t e = off + (size_t)q * g.Vp + i;
-      C pv = P::ld(p + e), rv = P::ld(r + e);
-      pv.x = rv.x + bt * pv.x;
-      pv.y = rv.y + bt * pv.y;
-      P::st(p + e, pv);
+      pv[q].x = rv[q].x + bt * pv[q].x;
+      pv[q].y = rv[q].y + bt * pv[q].y;
     }
+    st_site<P, NC>(p + off, g.Vp, i, pv);
   }
   if (sb == 0 && threadIdx.x == 0) {
     s->rho[par ^ 1] = rr;
@@ -102,16 +103,18 @@ ru_accumulate_kernel(const Geom g, const SlotState* st, const int* mask, double2
   const int i = sb * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
   const size_t off = (size_t)k * NC * g.Vp;
+  C v[NC], z[NC];
+  ld_site<XP, NC>(xlo + off, g.Vp, i, v);
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
     const size_t e = off + (size_t)q * g.Vp + i;
-    C v = XP::ld(xlo + e);
     double2 h = xhi[e];
-    h.x += sc * (double)v.x;
-    h.y += sc * (double)v.y;
+    h.x += sc * (double)v[q].x;
+    h.y += sc * (double)v[q].y;
     xhi[e] = h;
-    XP::st(xlo + e, czero<C>());
+    z[q] = czero<C>();
   }
+  st_site<XP, NC>(xlo + off, g.Vp, i, z);
 }
 
 __global__ void ru_finish_kernel(SlotState* st, const int* mask, const double* __restrict__ part,
@@ -166,25 +169,26 @@ ru_convert_kernel(const Geom g, const SlotState* st, const int* mask,
   const int i = sb * blockDim.x + threadIdx.x;
   double acc = 0.0;
   if (i < g.V) {
-    const size_t off = (size_t)k * NC * g.Vp;
+    const size_t off = (size_t)k * field_planes<P>(NC) * g.Vp;
+    const size_t off64 = (size_t)k * NC * g.Vp;
+    C v[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      const size_t e = off + (size_t)q * g.Vp + i;
-      const double2 h = rhi[e];
-      C v;
-      v.x = (R)(h.x * inv);
-      v.y = (R)(h.y * inv);
-      P::st(rlo + e, v);
-      const C vs = P::ld(rlo + e);
-      acc += cnorm2(vs);
-      if (init) {
-        P::st(p + e, vs);
-      } else {
-        C pv = P::ld(p + e);
-        pv.x *= pr;
-        pv.y *= pr;
-        P::st(p + e, pv);
-      }
+      const double2 h = rhi[off64 + (size_t)q * g.Vp + i];
+      v[q].x = (R)(h.x * inv);
+      v[q].y = (R)(h.y * inv);
+    }
+    acc = st_site<P, NC>(rlo + off, g.Vp, i, v);
+    if (init) {
+      C vs[NC];
+      ld_site<P, NC>(rlo + off, g.Vp, i, vs);   // p starts as the stored r
+      st_site<P, NC>(p + off, g.Vp, i, vs);
+    } else {
+      C pv[NC];
+      ld_site<P, NC>(p + off, g.Vp, i, pv);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) { pv[q].x *= pr; pv[q].y *= pr; }
+      st_site<P, NC>(p + off, g.Vp, i, pv);
     }
   }
   const double s = block_sum(acc, red);
@@ -218,13 +222,15 @@ load_prepare_kernel(const Geom g, double2* __restrict__ xhi,
   const int i = sb * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
   const size_t off = (size_t)k * NC * g.Vp;
+  C z[NC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
     const size_t e = off + (size_t)q * g.Vp + i;
     xhi[e] = make_double2(0.0, 0.0);
-    XP::st(xlo + e, czero<C>());
+    z[q] = czero<C>();
     rhi[e] = b[e];
   }
+  st_site<XP, NC>(xlo + off, g.Vp, i, z);
 }
 
 // ----------------------------------------------------------- dispatch
@@ -234,8 +240,8 @@ load_prepare_kernel(const Geom g, double2* __restrict__ xhi,
     else if (prec == P64 && nc == 3) { using PP = F64; constexpr int NCC = 3; CALL; } \
     else if (prec == P32 && nc == 12) { using PP = F32; constexpr int NCC = 12; CALL; } \
     else if (prec == P32 && nc == 3) { using PP = F32; constexpr int NCC = 3; CALL; }  \
-    else if (prec == P16 && nc == 12) { using PP = F16; constexpr int NCC = 12; CALL; } \
-    else if (prec == P16 && nc == 3) { using PP = F16; constexpr int NCC = 3; CALL; }  \
+    else if (prec == P16 && nc == 12) { using PP = Q16; constexpr int NCC = 12; CALL; } \
+    else if (prec == P16 && nc == 3) { using PP = Q16; constexpr int NCC = 3; CALL; }  \
     else throw std::runtime_error("unsupported precision/components");               \
   } while (0)
 

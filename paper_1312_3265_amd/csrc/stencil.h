@@ -42,7 +42,7 @@ struct EpiArgs {
   const double* v;        // LANCZOS: v_j
   const double* vprev;    // LANCZOS: v_{j-1}
   const double* beta_prev;// LANCZOS: device scalar beta_{j-1} (null = 0)
-  int rhs_per_thread;     // systems per thread (1, 2 or 4; FP32/FP16 CG kernels)
+  int rhs_per_thread;     // systems per thread (1, 2 or 4; FP32/Q16 CG kernels)
   int window;             // site blocks per XCD window (map_block; <= 0: whole range)
 };
 
@@ -114,7 +114,7 @@ stencil_kernel(const OpArgs oa, const typename Op::S* __restrict__ in, const Epi
   const int Vp = oa.g.Vp;
   const int i = sb * blockDim.x + threadIdx.x;
   const bool valid = i < oa.g.V;
-  const size_t rstride = (size_t)NC * Vp;
+  const size_t rstride = (size_t)field_planes<typename Op::Pol>(NC) * Vp;
 
   double alpha[K];
   if constexpr (EPI == EPI_CG_UPDATE) {
@@ -141,29 +141,26 @@ stencil_kernel(const OpArgs oa, const typename Op::S* __restrict__ in, const Epi
     double acc = 0.0;
     if (valid) {
       if constexpr (EPI == EPI_STORE || EPI == EPI_STORE_NORM) {
-        S* out = (S*)ea.out + off;
-#pragma unroll
-        for (int q = 0; q < NC; ++q) {
-          Op::Pol::st(out + (size_t)q * Vp + i, o[kk][q]);
-          if constexpr (EPI == EPI_STORE_NORM) acc += cnorm2(Op::Pol::ld(out + (size_t)q * Vp + i));
-        }
+        const double n2 = st_site<typename Op::Pol, NC>((S*)ea.out + off, Vp, i, o[kk]);
+        if constexpr (EPI == EPI_STORE_NORM) acc = n2;
       } else if constexpr (EPI == EPI_CG_UPDATE) {
         using XP = typename XPol<typename Op::Pol>::type;
-        typename XP::S* x = (typename XP::S*)ea.x + off;
+        typename XP::S* x = (typename XP::S*)ea.x + (size_t)k * NC * Vp;
         S* r = (S*)ea.r + off;
         const S* p = (const S*)ea.p + off;
         const R a = (R)alpha[kk];
+        P_C pv[NC], rv[NC];
+        typename XP::C xv[NC];
+        ld_site<typename Op::Pol, NC>(p, Vp, i, pv);
+        ld_site<typename Op::Pol, NC>(r, Vp, i, rv);
+        ld_site<XP, NC>(x, Vp, i, xv);
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
-          const size_t e = (size_t)q * Vp + i;
-          typename XP::C xv = XP::ld(x + e);
-          P_C pv = Op::Pol::ld(p + e), rv = Op::Pol::ld(r + e);
-          xv.x += a * pv.x; xv.y += a * pv.y;
-          rv.x -= a * o[kk][q].x; rv.y -= a * o[kk][q].y;
-          XP::st(x + e, xv);
-          Op::Pol::st(r + e, rv);
-          acc += cnorm2(Op::Pol::ld(r + e));
+          xv[q].x += a * pv[q].x; xv[q].y += a * pv[q].y;
+          rv[q].x -= a * o[kk][q].x; rv[q].y -= a * o[kk][q].y;
         }
+        st_site<XP, NC>(x, Vp, i, xv);
+        acc = st_site<typename Op::Pol, NC>(r, Vp, i, rv);
       } else if constexpr (EPI == EPI_RESID) {
         double2* out = (double2*)ea.out + off;
         const double2* b = (const double2*)ea.b + off;

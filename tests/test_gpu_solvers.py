@@ -36,7 +36,7 @@ def _res(form, U, chi, x, m):
 
 
 @pytest.mark.parametrize("formulation", [synth.WILSON, synth.STAGGERED_WILSON])
-@pytest.mark.parametrize("precision,links", [(lq.F32, 18), (lq.F32, 12), (lq.F16, 12)])
+@pytest.mark.parametrize("precision,links", [(lq.F32, 18), (lq.F32, 12), (lq.Q16, 12)])
 def test_mixed_precision_reaches_fp64_tolerance(formulation, precision, links):
     U, lat, g = _field()
     chi = synth.point_source(DIMS, formulation, 1)
@@ -73,7 +73,7 @@ def test_batched_multi_rhs_all_sources_and_masses():
             chis.append(synth.point_source(DIMS, form, alpha))
             masses.append(MASS[form] + dm)
     tol = 1e-8
-    for opts in (lq.solve_opts(), lq.solve_opts(precision=lq.F16, links=12)):
+    for opts in (lq.solve_opts(), lq.solve_opts(precision=lq.Q16, links=12)):
         x, infos = lq.cg_solve_batch(g, form, masses, np.stack(chis), [tol] * len(chis),
                                      opts=opts)
         for k in range(len(chis)):
@@ -102,7 +102,7 @@ def test_continuous_batching_alone_vs_in_the_mix():
     """Requests admitted while others iterate give the same result as alone."""
     U, lat, g = _field()
     form = synth.WILSON
-    opts = lq.solve_opts(precision=lq.F16, links=12, reliable_interval=48, poll_interval=8)
+    opts = lq.solve_opts(precision=lq.Q16, links=12, reliable_interval=48, poll_interval=8)
     reqs = [(synth.point_source(DIMS, form, a), MASS[form] + d, t)
             for a, d, t in ((0, 0.0, 1e-8), (5, 0.05, 1e-7), (7, 0.1, 1e-9), (2, 0.02, 1e-8),
                             (9, 0.05, 1e-6))]
