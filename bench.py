@@ -1,6 +1,6 @@
 """Benchmark: CG solves/s on the 16^3 x 32 workload, mixed-precision batched vs FP64.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision q16|f32]
 
 Workload (synthetic stand-in for the paper's quenched beta = 6 ensemble on
 16^3 x 32, Sec. 3): 8 gauge fields of independent near-identity SU(3) links
@@ -12,12 +12,20 @@ Wilson, as the paper averages over -- at bare masses m_c + delta, delta in
 residual ||b - A x|| / ||b|| <= 1e-8 on eq. (2), unpreconditioned.
 
 One step = all 360 systems: per field, one batched launch sequence for the 36
-Wilson systems and one for the 9 staggered Wilson systems, FP32 stencil and
-Krylov vectors with FP64 reliable updates.  `value` is systems solved per
-second over the timed steps.  Alongside (outside the timed region): FP64
-single-RHS CG on the same mix (the baseline the speed-up is quoted against),
-the dominant kernel's roofline figures from HIP events, the Lanczos condition
-numbers and the oracle timed on the host.
+Wilson systems and one for the 9 staggered Wilson systems; stencil and Krylov
+vectors stored in 16-bit fixed point (or FP32), FP32 arithmetic, FP64
+reductions and reliable updates.  `value` is systems solved per second over
+the timed steps.  Alongside (outside the timed region): FP64 single-RHS CG on
+the same mix (the baseline the speed-up is quoted against), the dominant
+kernel's roofline figures from HIP events, the Lanczos condition numbers and
+the oracle timed on the host.
+
+Profiling modes (each runs only what a profiler should see):
+    --roofline-only --rhs-per-thread K --window W   the dominant stencil alone
+    --copy-calibration                              a 256 MiB device copy x5
+    --summarize-profile TRACE FETCH WRITE CFETCH CWRITE
+        reads rocprofv3 output of the two modes above and writes the
+        counter-based traffic figures the roofline line reports
 """
 from __future__ import annotations
 
@@ -55,6 +63,105 @@ def bytes_per_site(formulation, precision, links, nrhs):
     link = 4 * (links // 2) * per if precision != 0 else 4 * 9 * 16
     corner = 0 if formulation == 0 else 8 * 9 * per
     return nrhs * vec + link + corner
+
+
+NRHS_W = 36                      # Wilson systems per field: 12 sources x 3 masses
+PROFILE_JSON = os.path.join(ROOT, "profiles", "stencil_wilson_batched_16x32_traffic.json")
+# sources whose change invalidates the stored counter readings of the stencil
+STENCIL_SOURCES = ["common.h", "dirac.h", "stencil.h", "stencil_dispatch.h", "k_stencil_wilson.hip"]
+
+
+def stencil_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in STENCIL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1312_3265_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(storage, cfg):
+    """HBM bytes per launch from the committed counter readings, if they were
+    taken on the current stencil sources with this configuration."""
+    try:
+        with open(PROFILE_JSON) as f:
+            p = json.load(f)
+    except OSError:
+        return None
+    if (p.get("source_sha256") != stencil_source_hash() or p.get("storage") != storage
+            or p.get("rhs_per_thread") != cfg[0] or p.get("window") != cfg[1]
+            or p.get("nrhs") != NRHS_W):
+        return None
+    return p["fetch_bytes_per_launch"] + p["write_bytes_per_launch"]
+
+
+def roofline(lq, g0, lat, mc, prec, links, storage, cfg, stream, reps=50):
+    """Average launch time (HIP events on `stream`) of the batched CG's
+    dominant kernel -- the Wilson stencil t = M p with ||t||^2 over the 36
+    systems of one field, in the launch configuration the autotuner chose --
+    against the algorithmic bytes of one launch."""
+    K, win = cfg
+    ms = lq.time_dslash(g0, 0, mc["wilson"] + 0.1, dagger=False, precision=prec, links=links,
+                        nrhs=NRHS_W, reps=reps, rhs_per_thread=K, window=win, stream=stream)
+    per_site = bytes_per_site(0, prec, links, NRHS_W)
+    algo = per_site * lat.volume
+    achieved = algo / (ms * 1e-3) / 1e9
+    return {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(storage, cfg),
+        "kernel": (f"stencil_kernel<WilsonOpR1<{'Q16' if prec == lq.Q16 else 'F32'}, 12>, "
+                   f"STORE_NORM, K={K}>: Wilson t = M p + ||t||^2, {NRHS_W} systems"),
+        "rhs_per_thread": K, "window": win,
+        "avg_launch_us": round(ms * 1e3, 2),
+        "algorithmic_bytes_per_site": per_site,
+        "algorithmic_bytes_per_launch": int(algo),
+    }
+
+
+def summarize_profile(a, trace, fetch, write, cfetch, cwrite):
+    """Profile summary of the dominant stencil: rocprofv3 kernel-trace stats and
+    the FETCH_SIZE / WRITE_SIZE counters per dispatch, scaled by what the same
+    counters read for a device copy of known size."""
+    import csv
+    import glob
+
+    def rows(d, pat):
+        f = glob.glob(os.path.join(d, "**", pat), recursive=True)
+        if not f:
+            raise SystemExit(f"no {pat} under {d}")
+        with open(f[0]) as fh:
+            return list(csv.DictReader(fh))
+
+    def per_dispatch(d, counter, match):
+        tot, ids = 0.0, set()
+        for r in rows(d, "*counter_collection.csv"):
+            if match(r["Kernel_Name"]) and r["Counter_Name"] == counter:
+                tot += float(r["Counter_Value"])
+                ids.add(r["Dispatch_Id"])
+        return tot / len(ids), len(ids)
+
+    stats = [r for r in rows(trace, "*kernel_stats.csv") if "stencil_kernel" in r["Name"]]
+    copy_f, _ = per_dispatch(cfetch, "FETCH_SIZE", lambda n: "copyBuffer" in n)
+    copy_w, _ = per_dispatch(cwrite, "WRITE_SIZE", lambda n: "copyBuffer" in n)
+    fs, wsz = 256 << 20, 256 << 20
+    fscale = fs / (copy_f * 1024.0)
+    wscale = wsz / (copy_w * 1024.0)
+    f_kib, nf = per_dispatch(fetch, "FETCH_SIZE", lambda n: "stencil_kernel" in n)
+    w_kib, nw = per_dispatch(write, "WRITE_SIZE", lambda n: "stencil_kernel" in n)
+    out = {
+        "storage": a.precision, "rhs_per_thread": a.rhs_per_thread, "window": a.window,
+        "nrhs": NRHS_W, "source_sha256": stencil_source_hash(),
+        "kernel_stats": stats,
+        "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib,
+        "copy_fetch_kib_per_256MiB": copy_f, "copy_write_kib_per_256MiB": copy_w,
+        "fetch_scale": fscale, "write_scale": wscale,
+        "fetch_bytes_per_launch": int(f_kib * 1024 * fscale),
+        "write_bytes_per_launch": int(w_kib * 1024 * wscale),
+        "dispatches_counted": [nf, nw],
+    }
+    with open(PROFILE_JSON, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
 
 
 def cpu_baseline(U, workload, iters_fp64):
@@ -97,10 +204,25 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="f32", choices=["f32", "q16"])
+    ap.add_argument("--precision", default="q16", choices=["f32", "q16"],
+                    help="storage of the batched CG's stencil and Krylov vectors "
+                         "(arithmetic is FP32, reductions and reliable updates FP64)")
     ap.add_argument("--fields", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only time the dominant stencil (the launches a profiler should see)")
+    ap.add_argument("--rhs-per-thread", type=int, default=1, help="with --roofline-only")
+    ap.add_argument("--window", type=int, default=2, help="with --roofline-only")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 256 MiB device copy five times (counter calibration)")
+    ap.add_argument("--summarize-profile", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "CFETCH", "CWRITE"),
+                    help="write the profile summary of the dominant stencil from rocprofv3 output "
+                         "directories (kernel trace, FETCH_SIZE, WRITE_SIZE of --roofline-only; "
+                         "FETCH_SIZE, WRITE_SIZE of --copy-calibration)")
     a = ap.parse_args()
+    if a.summarize_profile:
+        summarize_profile(a, *a.summarize_profile)
+        return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the workload is a single-GPU batch of "
               "independent solves (multi-GPU runs are not part of this build)", file=sys.stderr)
@@ -112,6 +234,15 @@ def main():
     import paper_1312_3265_amd as lq
     import synth
 
+    if a.copy_calibration:
+        x = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 256 << 20, "copies": 5}), flush=True)
+        return
+
     w = load_workload()
     dims = tuple(w["dims"])
     eps = w["eps"]
@@ -121,6 +252,14 @@ def main():
     links = 12
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+
+    if a.roofline_only:
+        lat = lq.Lattice(dims)
+        U = synth.gauge_field(dims, "near_identity", seeds[0], eps)
+        g0 = lq.Gauge(lat, U, lq.FEAT_CORNERS | lq.FEAT_F32 | lq.FEAT_Q16, stream=stream)
+        print(json.dumps({"roofline": roofline(lq, g0, lat, mc, prec, links, a.precision,
+                                               (a.rhs_per_thread, a.window), stream)}), flush=True)
+        return
 
     # ---------------------------------------------------------------- setup
     t0 = time.time()
@@ -209,20 +348,10 @@ def main():
     mixed_iters = {n: {d: float(np.mean(v)) for d, v in dd.items()} for n, dd in mixed_iters.items()}
 
     # --------------------------------------------- dominant kernel roofline
-    nrhs = 36
     reps = 50
-    # the solver's autotuner picks systems-per-thread K per batch; time every K
-    # and report the fastest, which is the one the solver runs
-    kt = {}
-    for K in (1, 2, 4):
-        kt[K] = lq.time_dslash(g0, 0, mc["wilson"] + 0.1, dagger=False, precision=prec,
-                               links=links, nrhs=nrhs, reps=reps, rhs_per_thread=K,
-                               stream=stream)
-    kbest = min(kt, key=kt.get)
-    ms = kt[kbest]
+    cfg = lq.tuned_launch(g0, 0, prec, links, NRHS_W)
+    roof = roofline(lq, g0, lat, mc, prec, links, a.precision, cfg or (1, 2), stream)
     V = lat.volume
-    algo = bytes_per_site(0, prec, links, nrhs) * V
-    achieved = algo / (ms * 1e-3) / 1e9
     ms64 = lq.time_dslash(g0, 0, mc["wilson"] + 0.1, precision=lq.F64, reps=reps, stream=stream)
     ms64_sw = lq.time_dslash(g0, 1, mc["staggered_wilson"] + 0.1, precision=lq.F64, reps=reps,
                              stream=stream)
@@ -253,24 +382,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == lq.F32 else "f16",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {
             "workload": ("16^3x32, 8 near-identity SU(3) fields (plaquette 0.594), "
                          "W 12 + SW 3 point sources x 3 masses m_c+{0.02,0.05,0.1}, "
                          "tol 1e-8, batched CG with FP64 reliable updates"),
             "systems_per_step": nsolved // a.steps,
-            "precision": a.precision, "links": links,
+            "storage": a.precision, "links": links,
         },
-        "roofline": {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": (f"Wilson M p + ||t||^2, {a.precision} 12-real links, {nrhs} RHS, "
-                       f"{kbest} per thread"),
-            "avg_launch_us_by_rhs_per_thread": {str(k): round(v * 1e3, 1) for k, v in kt.items()},
-            "avg_launch_us": round(ms * 1e3, 2),
-            "algorithmic_bytes_per_launch": int(algo),
-        },
+        "roofline": roof,
         "cpu_baseline": cpu,
         "fp64_single_rhs": {
             "solves_per_s_same_mix": round(fp64_rate, 3),

@@ -183,9 +183,11 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t op, int32_t precision
  * CG iteration (t = M p fused with ||t||^2), dagger = 1 the plain M^dag
  * stencil -- the same kernels the solvers launch.  rhs_per_thread (1, 2, 4;
  * FP32/Q16 only) is the number of systems each thread serves, the choice the
- * solvers' autotuner makes per batch; window (>= 0; 0 = all) is the number of
- * site blocks each XCD sweeps for one system before the next system, the
- * autotuner's other choice.  ws: device scratch of
+ * solvers' autotuner makes per batch; window, the autotuner's other choice,
+ * is the block order: w > 0 sweeps windows of w site blocks per XCD over all
+ * systems before moving on, 0 gives each XCD one contiguous site range, -1
+ * gives each XCD a contiguous eighth of the system-major (system, site)
+ * order, -2 the same with every other system swept backwards.  ws: device scratch of
  * lq_time_dslash_workspace_bytes (contents overwritten).  */
 size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t precision,
                                       int32_t nrhs);
@@ -243,6 +245,14 @@ int lq_batch_fetch(lq_batch* b, int32_t slot, void* x, lq_solve_info* info, void
  * limit); scale (may be NULL) the storage scale of its low-precision vectors. */
 int lq_batch_peek(lq_batch* b, int32_t slot, lq_solve_info* info, double* scale);
 void lq_batch_destroy(lq_batch* b);
+
+/* The launch configuration the solvers' autotuner chose for batches of
+ * `nrhs` systems of this operator and storage on this lattice (in this
+ * process or read back from the tuning cache): systems per thread and block
+ * order, as lq_time_dslash takes them.  LQ_ERR_STATE if no batch of that
+ * shape has been tuned yet; FP64 and single systems are never tuned (1, 0). */
+int lq_tuned_launch(const lq_gauge* g, const lq_dirac* d, int32_t precision, int32_t links,
+                    int32_t nrhs, int32_t* rhs_per_thread, int32_t* window);
 
 /* ---------------------------------------------------- condition number
  * Lanczos with full reorthogonalisation (classical Gram-Schmidt, twice) on

@@ -102,6 +102,7 @@ def lib():
         "lq_apply": ([P, P, I32, I32, I32, P, P, P, SZ, P], I32),
         "lq_time_dslash": ([P, P, I32, I32, I32, I32, I32, I32, I32, P, SZ, P, P], I32),
         "lq_time_dslash_workspace_bytes": ([P, I32, I32, I32], SZ),
+        "lq_tuned_launch": ([P, P, I32, I32, I32, P, P], I32),
         "lq_solve_workspace_bytes": ([P, I32, P, I32], SZ),
         "lq_cg_solve": ([P, P, P, P, D, I32, P, P, SZ, P, P], I32),
         "lq_cg_solve_batch": ([P, I32, I32, D, I32, P, P, P, P, I32, P, P, SZ, P, P], I32),
@@ -240,6 +241,19 @@ def time_dslash(gauge, formulation, mass, dagger=False, r=1.0, g55=G55_CORNERS, 
                                 rhs_per_thread, window, reps, _ptr(ws), nb, ctypes.byref(ms),
                                 _stream(stream)))
     return ms.value
+
+
+def tuned_launch(gauge, formulation, precision, links, nrhs, g55=G55_CORNERS):
+    """(rhs_per_thread, window) the solvers' autotuner chose for batches of
+    nrhs systems of this shape, or None if none has been tuned yet."""
+    d = Dirac(formulation, g55, 0.0, 1.0)
+    k, w = ctypes.c_int32(), ctypes.c_int32()
+    rc = lib().lq_tuned_launch(gauge._h, ctypes.byref(d), precision, links, nrhs,
+                               ctypes.byref(k), ctypes.byref(w))
+    if rc == ERR_STATE:
+        return None
+    _check(rc)
+    return k.value, w.value
 
 
 def solve_opts(precision=F64, links=0, reliable_interval=0, poll_interval=0, use_graph=0,

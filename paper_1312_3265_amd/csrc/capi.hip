@@ -236,6 +236,7 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t
     need(rhs_per_thread == 1 || rhs_per_thread == 2 || rhs_per_thread == 4,
          "rhs_per_thread must be 1, 2 or 4");
     need(rhs_per_thread == 1 || precision != LQ_PREC_F64, "FP64 stencils take one system per thread");
+    need(window >= -2, "window must be >= -2");
     const int nl = links_for(precision, links);
     const int nc = ncomp_of(d->formulation);
     const int op = opkind(d->formulation, d->g55_mode);
@@ -386,6 +387,26 @@ int lq_batch_fetch(lq_batch* b, int32_t slot, void* x, lq_solve_info* info, void
   return guard([&] {
     need(b != nullptr, "null batch");
     b->e.fetch(slot, x, info, S(stream));
+    return LQ_OK;
+  });
+}
+
+int lq_tuned_launch(const lq_gauge* g, const lq_dirac* d, int32_t precision, int32_t links,
+                    int32_t nrhs, int32_t* rhs_per_thread, int32_t* window) {
+  return guard([&] {
+    need(g && rhs_per_thread && window, "null argument");
+    check_dirac(d);
+    check_prec(precision, links);
+    need(nrhs >= 1, "nrhs must be >= 1");
+    *rhs_per_thread = 1;
+    *window = 0;
+    if (precision == LQ_PREC_F64 || nrhs < 2) return LQ_OK;
+    const int nl = links_for(precision, links);
+    const int v = tuned_rhs_per_thread(
+        tune_key(g->g, opkind(d->formulation, d->g55_mode), precision, nl, nrhs));
+    if (v == 0) throw Error(LQ_ERR_STATE, "no batch of this shape has been tuned");
+    *rhs_per_thread = v & 7;
+    *window = (v >> 3) - 3;
     return LQ_OK;
   });
 }

@@ -1,18 +1,19 @@
 // Shared device-side definitions: complex arithmetic, precision policies,
 // lattice geometry and the structure-of-arrays (SoA) field layout.
 //
-// Layout in HBM.  A field is a set of "planes"; plane c holds component c of
-// every site, sites in canonical order, with a padded plane stride Vp >= V so
-// that the many planes of one kernel do not start on the same HBM channel.
-//   fermion field (one RHS):  plane = spin*3 + colour (Wilson, 12 planes) or
-//                             colour (staggered Wilson, 3 planes)
-//   multi-RHS field:          RHS k occupies planes [k*nplanes, (k+1)*nplanes)
-//   links, 18 reals:          plane = (mu*3 + a)*3 + b      (36 planes)
-//   links, 12 reals:          plane = (mu*2 + a)*3 + b      (24 planes, rows 0,1)
-//   corners (8 stored):       plane = (c*3 + a)*3 + b       (72 planes),
-//                             c = bits (s1<0, s2<0, s3<0) of s = (s1,s2,s3,+1)
-// Consecutive lanes of a wavefront take consecutive sites, so every load of a
-// plane element is a coalesced 64-lane access.
+// Layout in HBM.  Each array holds per-site records (see "site records"
+// below) in slabs of 16-byte elements, sites in canonical order, with a padded
+// slab stride Vp >= V elements.  Record contents:
+//   fermion field (one RHS):  component spin*3 + colour (Wilson, 12) or colour
+//                             (staggered Wilson, 3), then the Q16 site scale
+//   multi-RHS field:          RHS k is the field at offset k * field_planes * Vp
+//   links:                    one record per direction mu, entries (a*3 + b),
+//                             a < 3 (18 reals) or a < 2 (12 reals)
+//   corners (8 stored):       record c = bits (s1<0, s2<0, s3<0) of
+//                             s = (s1,s2,s3,+1), entries (a*3 + b)
+// In FP64 a complex number is one 16-byte element, so a record's slab j is
+// simply its component j.  Consecutive lanes of a wavefront take consecutive
+// sites, so every load is a coalesced 64-lane access.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -117,7 +118,8 @@ template <> struct LinkPol<Q16> { using type = Q16L; };
 template <class P> struct XPol { using type = P; };
 template <> struct XPol<Q16> { using type = F32; };
 
-// Planes of one field of NC components (plus the scale plane of Q16).
+// Size of one field of NC components in storage elements per site (the Q16
+// scale adds one element); a field spans field_planes * Vp elements.
 template <class P> __host__ __device__ constexpr int field_planes(int nc) {
   return nc + (P::kSiteScale ? 1 : 0);
 }
@@ -174,51 +176,140 @@ __device__ __forceinline__ int nb_bwd(const Geom& g, const Coord& c, int i, int 
   return i + d;
 }
 
-// Element `site` of plane q of a SoA array, as a raw buffer load: the array
-// base is wavefront-uniform (a buffer descriptor in scalar registers), the
-// plane offset q * Vp is a scalar offset and the per-lane part a 32-bit vector
-// offset, so no per-load 64-bit address arithmetic is spent.  Every SoA array
-// a kernel reads this way is smaller than 4 GiB (checked at lattice creation).
+// ------------------------------------------------------------ site records
+// Everything a site holds in one array -- the components of a vector field
+// (and the Q16 scale), one direction's link, one corner matrix -- is a record
+// of BYTES bytes.  A field of records keeps them in slabs of 16-byte elements
+// (record bytes [16j, 16j+16) of every site in slab j), then, for what is
+// left, one plane of 8-byte and/or one plane of 4-byte elements; each slab or
+// plane has Vp elements, so a field occupies exactly Vp * BYTES bytes.  A lane
+// loads its record with BYTES/16 128-bit loads (plus a 64- and/or a 32-bit
+// one), each a coalesced access of 64 consecutive sites: four times fewer
+// load instructions than one complex component at a time in FP32, up to
+// sixteen times fewer in the 16-bit format.
+//
+// Loads and stores are raw buffer accesses: the array base is wavefront-
+// uniform (a buffer descriptor in scalar registers), the slab offset a scalar
+// offset and the per-lane part a 32-bit vector offset.  Every array a kernel
+// reads this way is smaller than 4 GiB (checked at lattice creation).
 constexpr int kBufferDword3 = 0x00020000;   // raw (untyped) buffer access on CDNA
 
-template <class P>
-__device__ __forceinline__ typename P::C ldq(const typename P::S* __restrict__ base, int Vp, int q,
-                                             int site) {
-  using S = typename P::S;
-  const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, -1, kBufferDword3);
-  const uint32_t vo = (uint32_t)site * (uint32_t)sizeof(S);
-  const uint32_t so = (uint32_t)q * (uint32_t)Vp * (uint32_t)sizeof(S);
-  if constexpr (sizeof(S) == 16) {
-    return P::cvt(__builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, so, 0)));
-  } else if constexpr (sizeof(S) == 8) {
-    return P::cvt(__builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0)));
-  } else {
-    return P::cvt(__builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0)));
+template <int BYTES>
+struct Rec {
+  static_assert(BYTES % 4 == 0, "records are whole 32-bit words");
+  static constexpr int A = BYTES / 16;          // 16-byte slabs
+  static constexpr int B = (BYTES % 16) / 8;    // one 8-byte plane?
+  static constexpr int C = (BYTES % 8) / 4;     // one 4-byte plane?
+  static constexpr int W = BYTES / 4;           // 32-bit words
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, -1, kBufferDword3);
+}
+
+template <int BYTES>
+__device__ __forceinline__ void ld_rec(const void* __restrict__ base, int Vp, int i,
+                                       uint32_t w[Rec<BYTES>::W]) {
+  using R = Rec<BYTES>;
+  const __amdgpu_buffer_rsrc_t rs = rsrc(base);
+  const uint32_t vp = (uint32_t)Vp, ui = (uint32_t)i;
+#pragma unroll
+  for (int j = 0; j < R::A; ++j) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, ui * 16u, (uint32_t)j * vp * 16u, 0);
+    w[4 * j] = v[0]; w[4 * j + 1] = v[1]; w[4 * j + 2] = v[2]; w[4 * j + 3] = v[3];
+  }
+  if constexpr (R::B) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, ui * 8u, (uint32_t)R::A * vp * 16u, 0);
+    w[4 * R::A] = v[0]; w[4 * R::A + 1] = v[1];
+  }
+  if constexpr (R::C) {
+    w[R::W - 1] = __builtin_amdgcn_raw_buffer_load_b32(
+        rs, ui * 4u, (uint32_t)R::A * vp * 16u + (uint32_t)R::B * vp * 8u, 0);
   }
 }
 
-// One raw 32-bit word of plane q (the Q16 component and scale planes).
-__device__ __forceinline__ uint32_t ld_word(const void* __restrict__ base, int Vp, int q, int site) {
-  const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, -1, kBufferDword3);
-  return __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)site * 4u, (uint32_t)q * (uint32_t)Vp * 4u, 0);
+template <int BYTES>
+__device__ __forceinline__ void st_rec(void* __restrict__ base, int Vp, int i,
+                                       const uint32_t w[Rec<BYTES>::W]) {
+  using R = Rec<BYTES>;
+  const __amdgpu_buffer_rsrc_t rs = rsrc(base);
+  const uint32_t vp = (uint32_t)Vp, ui = (uint32_t)i;
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int j = 0; j < R::A; ++j) {
+    u4 v = {w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]};
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, ui * 16u, (uint32_t)j * vp * 16u, 0);
+  }
+  if constexpr (R::B) {
+    u2 v = {w[4 * R::A], w[4 * R::A + 1]};
+    __builtin_amdgcn_raw_buffer_store_b64(v, rs, ui * 8u, (uint32_t)R::A * vp * 16u, 0);
+  }
+  if constexpr (R::C) {
+    __builtin_amdgcn_raw_buffer_store_b32(w[R::W - 1], rs, ui * 4u,
+                                          (uint32_t)R::A * vp * 16u + (uint32_t)R::B * vp * 8u, 0);
+  }
 }
 
-// All NC components of site i of a vector field f (planes of Vp elements).
+// Storage words <-> complex values of a policy
+template <class P>
+__device__ __forceinline__ typename P::C dec(const uint32_t* w) {
+  using S = typename P::S;
+  S v;
+  __builtin_memcpy(&v, w, sizeof(S));
+  return P::cvt(v);
+}
+template <class P>
+__device__ __forceinline__ void enc_to(uint32_t* w, typename P::C c) {
+  const typename P::S v = P::enc(c);
+  __builtin_memcpy(w, &v, sizeof(v));
+}
+
+// Bytes of the record of an NC-component vector site under policy P.
+template <class P> __host__ __device__ constexpr int vec_rec_bytes(int nc) {
+  return nc * (int)sizeof(typename P::S) + (P::kSiteScale ? 4 : 0);
+}
+
+// All NC components of site i of a vector field f.
 template <class P, int NC>
 __device__ __forceinline__ void ld_site(const typename P::S* __restrict__ f, int Vp, int i,
                                         typename P::C v[NC]) {
+  constexpr int BY = vec_rec_bytes<P>(NC);
+  uint32_t w[BY / 4];
+  ld_rec<BY>(f, Vp, i, w);
   if constexpr (P::kSiteScale) {
-    const float s = __uint_as_float(ld_word(f, Vp, NC, i)) * (1.0f / kQ16);
+    const float s = __uint_as_float(w[NC]) * (1.0f / kQ16);
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      const short2 w = __builtin_bit_cast(short2, ld_word(f, Vp, q, i));
-      v[q] = make_float2((float)w.x * s, (float)w.y * s);
+      const short2 z = __builtin_bit_cast(short2, w[q]);
+      v[q] = make_float2((float)z.x * s, (float)z.y * s);
     }
   } else {
+    constexpr int WPC = sizeof(typename P::S) / 4;
 #pragma unroll
-    for (int q = 0; q < NC; ++q) v[q] = ldq<P>(f, Vp, q, i);
+    for (int q = 0; q < NC; ++q) v[q] = dec<P>(w + q * WPC);
+  }
+}
+
+// Site i without applying the Q16 site scale: v = stored integers (as float)
+// and `scale` = the factor that turns them into values (1 for F32 and F64), so
+// that a caller can apply it after a linear step on fewer numbers.
+template <class P, int NC>
+__device__ __forceinline__ void ld_site_raw(const typename P::S* __restrict__ f, int Vp, int i,
+                                            typename P::C v[NC], typename P::R& scale) {
+  if constexpr (P::kSiteScale) {
+    constexpr int BY = vec_rec_bytes<P>(NC);
+    uint32_t w[BY / 4];
+    ld_rec<BY>(f, Vp, i, w);
+    scale = __uint_as_float(w[NC]) * (1.0f / kQ16);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const short2 z = __builtin_bit_cast(short2, w[q]);
+      v[q] = make_float2((float)z.x, (float)z.y);
+    }
+  } else {
+    scale = (typename P::R)1;
+    ld_site<P, NC>(f, Vp, i, v);
   }
 }
 
@@ -226,6 +317,8 @@ __device__ __forceinline__ void ld_site(const typename P::S* __restrict__ f, int
 template <class P, int NC>
 __device__ __forceinline__ double st_site(typename P::S* __restrict__ f, int Vp, int i,
                                           const typename P::C v[NC]) {
+  constexpr int BY = vec_rec_bytes<P>(NC);
+  uint32_t w[BY / 4];
   double n2 = 0.0;
   if constexpr (P::kSiteScale) {
     float m = 0.0f;
@@ -235,21 +328,23 @@ __device__ __forceinline__ double st_site(typename P::S* __restrict__ f, int Vp,
     const float s = m * (1.0f / kQ16);
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      short2 w;
-      w.x = q16_round(v[q].x * inv);
-      w.y = q16_round(v[q].y * inv);
-      f[(size_t)q * Vp + i] = w;
-      const float a = (float)w.x * s, b = (float)w.y * s;
+      short2 z;
+      z.x = q16_round(v[q].x * inv);
+      z.y = q16_round(v[q].y * inv);
+      w[q] = __builtin_bit_cast(uint32_t, z);
+      const float a = (float)z.x * s, b = (float)z.y * s;
       n2 += (double)a * a + (double)b * b;
     }
-    ((float*)f)[(size_t)NC * Vp + i] = m;
+    w[NC] = __float_as_uint(m);
   } else {
+    constexpr int WPC = sizeof(typename P::S) / 4;
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      P::st(f + (size_t)q * Vp + i, v[q]);
+      enc_to<P>(w + q * WPC, v[q]);
       n2 += cnorm2(v[q]);
     }
   }
+  st_rec<BY>(f, Vp, i, w);
   return n2;
 }
 
@@ -262,24 +357,58 @@ __device__ __forceinline__ int eta_sign(const Coord& c, int mu) {
 __device__ __forceinline__ int phi_sign(const Coord& c) { return ((c.x[1] + c.x[3]) & 1) ? -1 : 1; }
 
 // ----------------------------------------------------------------- links
-// Load a 3x3 link (row-major) from the SoA link arrays; 12-real storage keeps
-// rows 0 and 1 and rebuilds row 2 = conj(row0 x row1), exact for SU(3).
+// Links: four records per site, one per direction mu (the record field of mu
+// starts at u + mu * Vp * NREAL/2 storage elements), each the row-major 3x3
+// matrix (18 reals) or its rows 0 and 1 (12 reals; row 2 = conj(row0 x row1),
+// exact for SU(3)).  Corner matrices: eight records of 9 complex numbers.
 template <class P, int NREAL>
 __device__ __forceinline__ void load_link(const typename P::S* __restrict__ u, int Vp, int mu,
                                           int site, typename P::C m[9]) {
   using C = typename P::C;
-  if constexpr (NREAL == 18) {
+  constexpr int NCX = NREAL / 2;
+  constexpr int BY = NCX * (int)sizeof(typename P::S);
+  constexpr int WPC = sizeof(typename P::S) / 4;
+  uint32_t w[BY / 4];
+  ld_rec<BY>(u + (size_t)mu * NCX * Vp, Vp, site, w);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) m[k] = ldq<P>(u, Vp, mu * 9 + k, site);
-  } else {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) m[k] = ldq<P>(u, Vp, mu * 6 + k, site);
-    // row2 = conj(row0 x row1)
+  for (int k = 0; k < NCX; ++k) m[k] = dec<P>(w + k * WPC);
+  if constexpr (NREAL == 12) {
     C a0 = m[0], a1 = m[1], a2 = m[2], b0 = m[3], b1 = m[4], b2 = m[5];
     m[6] = cconj(csub(cmul(a1, b2), cmul(a2, b1)));
     m[7] = cconj(csub(cmul(a2, b0), cmul(a0, b2)));
     m[8] = cconj(csub(cmul(a0, b1), cmul(a1, b0)));
   }
+}
+template <class P, int NREAL>
+__device__ __forceinline__ void store_link(typename P::S* __restrict__ u, int Vp, int mu, int site,
+                                           const typename P::C m[9]) {
+  constexpr int NCX = NREAL / 2;
+  constexpr int BY = NCX * (int)sizeof(typename P::S);
+  constexpr int WPC = sizeof(typename P::S) / 4;
+  uint32_t w[BY / 4];
+#pragma unroll
+  for (int k = 0; k < NCX; ++k) enc_to<P>(w + k * WPC, m[k]);
+  st_rec<BY>(u + (size_t)mu * NCX * Vp, Vp, site, w);
+}
+template <class P>
+__device__ __forceinline__ void load_corner(const typename P::S* __restrict__ c, int Vp, int cidx,
+                                            int site, typename P::C m[9]) {
+  constexpr int BY = 9 * (int)sizeof(typename P::S);
+  constexpr int WPC = sizeof(typename P::S) / 4;
+  uint32_t w[BY / 4];
+  ld_rec<BY>(c + (size_t)cidx * 9 * Vp, Vp, site, w);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) m[k] = dec<P>(w + k * WPC);
+}
+template <class P>
+__device__ __forceinline__ void store_corner(typename P::S* __restrict__ c, int Vp, int cidx,
+                                             int site, const typename P::C m[9]) {
+  constexpr int BY = 9 * (int)sizeof(typename P::S);
+  constexpr int WPC = sizeof(typename P::S) / 4;
+  uint32_t w[BY / 4];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) enc_to<P>(w + k * WPC, m[k]);
+  st_rec<BY>(c + (size_t)cidx * 9 * Vp, Vp, site, w);
 }
 
 // y = M v and y = M^dag v for a 3x3 matrix and a colour vector

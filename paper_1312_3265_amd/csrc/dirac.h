@@ -63,39 +63,15 @@ struct WilsonOp {
   using R = typename P::R;
   using S = typename P::S;
 
-  // acc += (r + t g_mu) L psi_nb, L = the pre-loaded link lk or its adjoint.
+  // General r: acc += (r + t g_mu) L psi_nb, L = the pre-loaded link lk or
+  // its adjoint (no spin projection).
   __device__ __forceinline__ static void hop(const OpArgs& a, const S* __restrict__ in, int nb,
                                              int mu, bool dagger_link, R t, R sgn, const C lk[9],
                                              C acc[12]) {
     const int Vp = a.g.Vp;
     C psi[12];
     ld_site<P, 12>(in, Vp, nb, psi);
-    if constexpr (!GENERAL_R) {
-      C h[2][3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        C u0 = psi[0 * 3 + c];
-        C u1 = psi[1 * 3 + c];
-        C l0 = psi[2 * 3 + c];
-        C l1 = psi[3 * 3 + c];
-        C b0, b1;
-        bmul(mu, l0, l1, b0, b1);
-        h[0][c] = cscale(cadd(u0, cscale(b0, t)), sgn);
-        h[1][c] = cscale(cadd(u1, cscale(b1, t)), sgn);
-      }
-      C uh[2][3];
-      if (dagger_link) { mvd(lk, h[0], uh[0]); mvd(lk, h[1], uh[1]); }
-      else { mv(lk, h[0], uh[0]); mv(lk, h[1], uh[1]); }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        C d0, d1;
-        bdmul(mu, uh[0][c], uh[1][c], d0, d1);
-        acc[0 * 3 + c] = cadd(acc[0 * 3 + c], uh[0][c]);
-        acc[1 * 3 + c] = cadd(acc[1 * 3 + c], uh[1][c]);
-        acc[2 * 3 + c] = cadd(acc[2 * 3 + c], cscale(d0, t));
-        acc[3 * 3 + c] = cadd(acc[3 * 3 + c], cscale(d1, t));
-      }
-    } else {
+    {
       // general r: (r + t g) L psi = r L psi + t g (L psi), all four spins
       C w[4][3];
 #pragma unroll
@@ -115,6 +91,64 @@ struct WilsonOp {
         acc[1 * 3 + c] = cadd(acc[1 * 3 + c], cadd(cscale(w[1][c], rr), cscale(gu1, t)));
         acc[2 * 3 + c] = cadd(acc[2 * 3 + c], cadd(cscale(w[2][c], rr), cscale(gl0, t)));
         acc[3 * 3 + c] = cadd(acc[3 * 3 + c], cadd(cscale(w[3][c], rr), cscale(gl1, t)));
+      }
+    }
+  }
+
+  template <int K>
+  static constexpr bool kHopPairs() { return P::id != 0 && K == 1; }
+
+  // r = 1 hop along +-MU with the gamma structure fixed at compile time:
+  // h = sgn * scale * (psi_up + TT B psi_lo) (TT = -s forward, +s backward),
+  // uh = L h, then acc += [uh; TT B^dag uh].  Only the link load is shared by
+  // the K systems.
+  template <int MU, bool BACK, int K>
+  __device__ __forceinline__ static void hop_r1(const OpArgs& a, const S* __restrict__ in0,
+                                                size_t rstride, const Coord& c, int i,
+                                                unsigned act, C acc[K][12]) {
+    constexpr int s = DAG ? -1 : 1;
+    constexpr int TT = BACK ? s : -s;
+    const Geom& g = a.g;
+    bool wrap;
+    const int j = BACK ? nb_bwd(g, c, i, MU, wrap) : nb_fwd(g, c, i, MU, wrap);
+    const bool flip = wrap && g.bc[MU] < 0;
+    C lk[9];
+    using LP = typename LinkPol<P>::type;
+    load_link<LP, NL>((const typename LP::S*)a.links, g.Vp, MU, BACK ? j : i, lk);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!((act >> k) & 1)) continue;
+      C psi[12];
+      R sc;
+      ld_site_raw<P, 12>(in0 + k * rstride, g.Vp, j, psi, sc);
+      C h[2][3];
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        C b0, b1;
+        bmul(MU, psi[6 + cc], psi[9 + cc], b0, b1);
+        h[0][cc] = TT > 0 ? cadd(psi[cc], b0) : csub(psi[cc], b0);
+        h[1][cc] = TT > 0 ? cadd(psi[3 + cc], b1) : csub(psi[3 + cc], b1);
+      }
+      if constexpr (P::kSiteScale) {
+        const R f = flip ? -sc : sc;
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) { h[0][cc] = cscale(h[0][cc], f); h[1][cc] = cscale(h[1][cc], f); }
+      } else if (g.bc[MU] < 0) {   // wavefront-uniform
+        const R f = flip ? (R)-1 : (R)1;
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) { h[0][cc] = cscale(h[0][cc], f); h[1][cc] = cscale(h[1][cc], f); }
+      }
+      C uh[2][3];
+      if (BACK) { mvd(lk, h[0], uh[0]); mvd(lk, h[1], uh[1]); }
+      else { mv(lk, h[0], uh[0]); mv(lk, h[1], uh[1]); }
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        C d0, d1;
+        bdmul(MU, uh[0][cc], uh[1][cc], d0, d1);
+        acc[k][cc] = cadd(acc[k][cc], uh[0][cc]);
+        acc[k][3 + cc] = cadd(acc[k][3 + cc], uh[1][cc]);
+        acc[k][6 + cc] = TT > 0 ? cadd(acc[k][6 + cc], d0) : csub(acc[k][6 + cc], d0);
+        acc[k][9 + cc] = TT > 0 ? cadd(acc[k][9 + cc], d1) : csub(acc[k][9 + cc], d1);
       }
     }
   }
@@ -140,24 +174,62 @@ struct WilsonOp {
       for (int q = 0; q < 12; ++q)
         acc[k][q] = ((act >> k) & 1) ? cscale(v[q], (R)-2 * diag) : czero<C>();
     }
-    const R s = DAG ? (R)-1 : (R)1;
-    // The direction loop stays rolled: mu is uniform across the wavefront, so
-    // the gamma structure is a scalar branch, and only one hop's operands are
-    // live at a time (unrolling lets the scheduler hoist all 8 hops' loads).
+    if constexpr (!GENERAL_R) {
+      // Each hop's code has its gamma structure and coordinates built in.
+      // The loop stays rolled (its index made opaque to the compiler, which
+      // would otherwise unroll it and hoist every hop's loads into spills);
+      // an iteration covers one hop, or both hops of a direction where the
+      // registers allow (single-system FP32/Q16).
+      if constexpr (kHopPairs<K>()) {
 #pragma unroll 1
-    for (int h = 0; h < 8; ++h) {
-      const int mu = h >> 1;
-      const bool back = h & 1;
-      bool wrap;
-      const int j = back ? nb_bwd(g, c, i, mu, wrap) : nb_fwd(g, c, i, mu, wrap);
-      const R sg = (wrap && g.bc[mu] < 0) ? (R)-1 : (R)1;
-      C lk[9];
-      // forward: (r - s g) U_mu(x) psi(x+mu); backward: (r + s g) U_mu(x-mu)^dag psi(x-mu)
-      using LP = typename LinkPol<P>::type;
-      load_link<LP, NL>((const typename LP::S*)a.links, g.Vp, mu, back ? j : i, lk);
+        for (int m0 = 0; m0 < 4; ++m0) {
+          int mu = m0;
+          asm volatile("" : "+s"(mu));
+          switch (mu) {
+            case 0: hop_r1<0, false, K>(a, in0, rstride, c, i, act, acc);
+                    hop_r1<0, true, K>(a, in0, rstride, c, i, act, acc); break;
+            case 1: hop_r1<1, false, K>(a, in0, rstride, c, i, act, acc);
+                    hop_r1<1, true, K>(a, in0, rstride, c, i, act, acc); break;
+            case 2: hop_r1<2, false, K>(a, in0, rstride, c, i, act, acc);
+                    hop_r1<2, true, K>(a, in0, rstride, c, i, act, acc); break;
+            default: hop_r1<3, false, K>(a, in0, rstride, c, i, act, acc);
+                     hop_r1<3, true, K>(a, in0, rstride, c, i, act, acc); break;
+          }
+        }
+      } else {
+#pragma unroll 1
+        for (int h0 = 0; h0 < 8; ++h0) {
+          int h = h0;
+          asm volatile("" : "+s"(h));
+          switch (h) {
+            case 0: hop_r1<0, false, K>(a, in0, rstride, c, i, act, acc); break;
+            case 1: hop_r1<0, true, K>(a, in0, rstride, c, i, act, acc); break;
+            case 2: hop_r1<1, false, K>(a, in0, rstride, c, i, act, acc); break;
+            case 3: hop_r1<1, true, K>(a, in0, rstride, c, i, act, acc); break;
+            case 4: hop_r1<2, false, K>(a, in0, rstride, c, i, act, acc); break;
+            case 5: hop_r1<2, true, K>(a, in0, rstride, c, i, act, acc); break;
+            case 6: hop_r1<3, false, K>(a, in0, rstride, c, i, act, acc); break;
+            default: hop_r1<3, true, K>(a, in0, rstride, c, i, act, acc); break;
+          }
+        }
+      }
+    } else {
+      const R s = DAG ? (R)-1 : (R)1;
+#pragma unroll 1
+      for (int h = 0; h < 8; ++h) {
+        const int mu = h >> 1;
+        const bool back = h & 1;
+        bool wrap;
+        const int j = back ? nb_bwd(g, c, i, mu, wrap) : nb_fwd(g, c, i, mu, wrap);
+        const R sg = (wrap && g.bc[mu] < 0) ? (R)-1 : (R)1;
+        C lk[9];
+        // forward: (r - s g) U_mu(x) psi(x+mu); backward: (r + s g) U_mu(x-mu)^dag psi(x-mu)
+        using LP = typename LinkPol<P>::type;
+        load_link<LP, NL>((const typename LP::S*)a.links, g.Vp, mu, back ? j : i, lk);
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        if ((act >> k) & 1) hop(a, in0 + k * rstride, j, mu, back, back ? s : -s, sg, lk, acc[k]);
+        for (int k = 0; k < K; ++k)
+          if ((act >> k) & 1) hop(a, in0 + k * rstride, j, mu, back, back ? s : -s, sg, lk, acc[k]);
+      }
     }
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -265,8 +337,7 @@ struct SWCornerOp {
       int sign;
       const int j = diag_nb(g, c, s, sign);
       C w[9];
-#pragma unroll
-      for (int q = 0; q < 9; ++q) w[q] = ldq<LP>(W, g.Vp, cidx * 9 + q, refl ? j : i);
+      load_corner<LP>(W, g.Vp, cidx, refl ? j : i, w);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (!((act >> k) & 1)) continue;

@@ -145,7 +145,8 @@ struct Engine {
 // device once per (GPU, lattice, operator, precision, links, batch size) and
 // remembered in memory and in a small text cache file (LQ_TUNE_CACHE, default
 // $HOME/.cache/lq_tune.txt).
-int tuned_rhs_per_thread(const std::string& key);
+int tuned_rhs_per_thread(const std::string& key);   // 0: not tuned; else K + 8 * (window + 3)
+std::string tune_key(const Geom& g, int op, int prec, int nl, int nslots);
 void remember_rhs_per_thread(const std::string& key, int k);
 
 // Lanczos with full reorthogonalisation on A = M^dag M.

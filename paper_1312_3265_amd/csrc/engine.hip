@@ -100,24 +100,28 @@ void remember_rhs_per_thread(const std::string& key, int k) {
   if (f) f << key << " " << k << "\n";
 }
 
+std::string tune_key(const Geom& g, int op, int prec, int nl, int nslots) {
+  hipDeviceProp_t prop;
+  int dev = 0;
+  LQ_HIP(hipGetDevice(&dev));
+  LQ_HIP(hipGetDeviceProperties(&prop, dev));
+  std::ostringstream key;
+  key << "v4:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
+      << ":op" << op << ":p" << prec << ":l" << nl << ":n" << nslots;
+  std::string k = key.str();
+  for (auto& ch : k) if (ch == ' ') ch = '_';
+  return k;
+}
+
 // Time the CG stencil t = M p (+||t||^2) over all slots for K = 1, 2, 4 on the
 // (zeroed) solver buffers and keep the fastest.
 void Engine::tune(hipStream_t s) {
   rhs_per_thread = 1;
   window = 0;
   if (prec_lo == P64 || nslots < 2) return;
-  hipDeviceProp_t prop;
-  int dev = 0;
-  LQ_HIP(hipGetDevice(&dev));
-  LQ_HIP(hipGetDeviceProperties(&prop, dev));
-  std::ostringstream key;
-  const Geom& g = gauge->g;
-  key << "v3:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
-      << ":op" << op << ":p" << prec_lo << ":l" << nl_lo << ":n" << nslots;
-  std::string k = key.str();
-  for (auto& ch : k) if (ch == ' ') ch = '_';
-  const int cached = tuned_rhs_per_thread(k);   // encoded as K + 8 * (window + 1)
-  if (cached) { rhs_per_thread = cached & 7; window = (cached >> 3) - 1; return; }
+  const std::string k = tune_key(gauge->g, op, prec_lo, nl_lo, nslots);
+  const int cached = tuned_rhs_per_thread(k);   // encoded as K + 8 * (window + 3)
+  if (cached) { rhs_per_thread = cached & 7; window = (cached >> 3) - 3; return; }
   OpArgs oa = op_args(prec_lo, nl_lo);
   EpiArgs e = epi_base();
   e.st = nullptr;
@@ -130,7 +134,7 @@ void Engine::tune(hipStream_t s) {
   int bestk = 1, bestw = 0;
   for (int kk : {1, 2, 4}) {
     if (kk > nslots) break;
-    for (int w : {1, 2, 4, 0}) {
+    for (int w : {1, 2, 4, 0, -1, -2}) {
       e.rhs_per_thread = kk;
       e.window = w;
       launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
@@ -149,7 +153,7 @@ void Engine::tune(hipStream_t s) {
   (void)hipEventDestroy(t1);
   rhs_per_thread = bestk;
   window = bestw;
-  remember_rhs_per_thread(k, bestk + 8 * (bestw + 1));
+  remember_rhs_per_thread(k, bestk + 8 * (bestw + 3));
 }
 
 // ================================================================ Engine

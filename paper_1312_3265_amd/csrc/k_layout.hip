@@ -113,14 +113,15 @@ links_convert_kernel(const Geom g, const double2* __restrict__ u64, typename P::
   using R = typename P::R;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
-  constexpr int rows = NL / 6;
-  for (int mu = 0; mu < 4; ++mu)
-    for (int a = 0; a < rows; ++a)
-      for (int b = 0; b < 3; ++b) {
-        const double2 z = u64[(size_t)((mu * 3 + a) * 3 + b) * g.Vp + i];
-        C v; v.x = (R)z.x; v.y = (R)z.y;
-        dst[(size_t)((mu * rows + a) * 3 + b) * g.Vp + i] = P::enc(v);
-      }
+  for (int mu = 0; mu < 4; ++mu) {
+    C m[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double2 z = u64[(size_t)(mu * 9 + k) * g.Vp + i];
+      m[k].x = (R)z.x; m[k].y = (R)z.y;
+    }
+    store_link<P, NL>(dst, g.Vp, mu, i, m);
+  }
 }
 
 void launch_links_convert(int prec, int nl, const Geom& g, const double2* u64, void* dst,
@@ -254,10 +255,14 @@ corners_convert_kernel(const Geom g, const double2* __restrict__ c64, typename P
   using R = typename P::R;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
-  for (int q = 0; q < 72; ++q) {
-    const double2 z = c64[(size_t)q * g.Vp + i];
-    C v; v.x = (R)z.x; v.y = (R)z.y;
-    dst[(size_t)q * g.Vp + i] = P::enc(v);
+  for (int c = 0; c < 8; ++c) {
+    C m[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double2 z = c64[(size_t)(c * 9 + k) * g.Vp + i];
+      m[k].x = (R)z.x; m[k].y = (R)z.y;
+    }
+    store_corner<P>(dst, g.Vp, c, i, m);
   }
 }
 

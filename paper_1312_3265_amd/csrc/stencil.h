@@ -43,7 +43,7 @@ struct EpiArgs {
   const double* vprev;    // LANCZOS: v_{j-1}
   const double* beta_prev;// LANCZOS: device scalar beta_{j-1} (null = 0)
   int rhs_per_thread;     // systems per thread (1, 2 or 4; FP32/Q16 CG kernels)
-  int window;             // site blocks per XCD window (map_block; <= 0: whole range)
+  int window;             // block order (map_block): > 0 window width, 0 whole range, < 0 system-major
 };
 
 // blockIdx.x -> (site block sb, rhs k), XCD-aware.  Block b runs on XCD b % 8,
@@ -56,9 +56,23 @@ struct EpiArgs {
 // one window when 8*win*256 sites make a slice -- are visited by the same XCD
 // one window earlier or later.  win = 1 gives XCD-interleaved blocks with the
 // systems innermost; win = nbp/8 gives each XCD one contiguous range.
+//
+// win < 0: the (system, site block) pairs in system-major order, XCD x taking
+// the x-th contiguous eighth.  Each XCD then sweeps whole systems t-slice by
+// t-slice, so every neighbour plane is reused from its own L2 within one
+// system, and the links come from the shared Infinity Cache once per system.
+// win = -2 reverses the sweep of every other system, so that consecutive
+// systems meet on the same site blocks.
 __device__ __forceinline__ void map_block(int nbp, int nrhs, int win, int& sb, int& k) {
   const int b = blockIdx.x;
   const int xcd = b & 7, kk = b >> 3;
+  if (win < 0) {
+    const int p = xcd * ((nbp >> 3) * nrhs) + kk;
+    k = p / nbp;
+    sb = p - k * nbp;
+    if (win == -2 && (k & 1)) sb = nbp - 1 - sb;
+    return;
+  }
   const int range = nbp >> 3;                // blocks per XCD in total
   if (win <= 0 || win > range) win = range;
   const int per_win = win * nrhs;
