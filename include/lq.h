@@ -112,7 +112,9 @@ typedef struct {
 typedef struct {
   int32_t precision;          /* LQ_PREC_*: F64 = plain FP64 CG; F32/Q16 = inner
                                  CG in that storage with FP64 reliable updates   */
-  int32_t links;              /* LQ_LINKS_18 or LQ_LINKS_12 (Q16 requires 12)    */
+  int32_t links;              /* LQ_LINKS_18 or LQ_LINKS_12; with Q16, 12 = 16-bit
+                                 12-real links, 18 = FP32 18-real links (needs
+                                 LQ_FEAT_F32 on the gauge field)                 */
   int32_t reliable_interval;  /* iterations between FP64 reliable updates
                                  (0 = default 64; unused for F64)                */
   int32_t poll_interval;      /* iterations between host convergence polls

@@ -47,7 +47,6 @@ static void check_dirac(const lq_dirac* d) {
 static void check_prec(int32_t prec, int32_t links) {
   need(prec == LQ_PREC_F64 || prec == LQ_PREC_F32 || prec == LQ_PREC_Q16, "bad precision");
   need(links == 0 || links == LQ_LINKS_18 || links == LQ_LINKS_12, "links must be 18 or 12");
-  need(!(prec == LQ_PREC_Q16 && links == LQ_LINKS_18), "16-bit stencils use 12-real links");
 }
 
 static int links_for(int32_t prec, int32_t links) {

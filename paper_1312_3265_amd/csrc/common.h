@@ -108,9 +108,16 @@ struct Q16L {
   }
 };
 
-// Policy of the links and corner matrices used with vectors of policy P.
-template <class P> struct LinkPol { using type = P; };
-template <> struct LinkPol<Q16> { using type = Q16L; };
+// Storage of the links (NL reals) and of the corner matrices used with
+// vectors of policy P.  16-bit vectors take 16-bit 12-real links, or FP32
+// 18-real links: in a batch the links are read once for many systems, so
+// their bytes hardly count, while their conversion and row-2 rebuild are paid
+// per system and hop.
+template <class P, int NL> struct LinkPol { using type = P; };
+template <> struct LinkPol<Q16, 12> { using type = Q16L; };
+template <> struct LinkPol<Q16, 18> { using type = F32; };
+template <class P> struct CornerPol { using type = P; };
+template <> struct CornerPol<Q16> { using type = Q16L; };
 
 // Storage of the solution increment x_lo: FP32 when the Krylov vectors are
 // 16-bit.  x_lo is amplified by the operator (errors in it grow by up to

@@ -113,7 +113,7 @@ struct WilsonOp {
     const int j = BACK ? nb_bwd(g, c, i, MU, wrap) : nb_fwd(g, c, i, MU, wrap);
     const bool flip = wrap && g.bc[MU] < 0;
     C lk[9];
-    using LP = typename LinkPol<P>::type;
+    using LP = typename LinkPol<P, NL>::type;
     load_link<LP, NL>((const typename LP::S*)a.links, g.Vp, MU, BACK ? j : i, lk);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -224,7 +224,7 @@ struct WilsonOp {
         const R sg = (wrap && g.bc[mu] < 0) ? (R)-1 : (R)1;
         C lk[9];
         // forward: (r - s g) U_mu(x) psi(x+mu); backward: (r + s g) U_mu(x-mu)^dag psi(x-mu)
-        using LP = typename LinkPol<P>::type;
+        using LP = typename LinkPol<P, NL>::type;
         load_link<LP, NL>((const typename LP::S*)a.links, g.Vp, mu, back ? j : i, lk);
 #pragma unroll
         for (int k = 0; k < K; ++k)
@@ -271,7 +271,7 @@ __device__ __forceinline__ void dst_site(const OpArgs& a, const typename P::S* _
     // forward hops enter with +eta, backward hops with -eta
     const R sg = ((wrap && g.bc[mu] < 0) ? (R)-1 : (R)1) * (back ? -eta : eta);
     C lk[9];
-    using LP = typename LinkPol<P>::type;
+    using LP = typename LinkPol<P, NL>::type;
     load_link<LP, NL>((const typename LP::S*)a.links, g.Vp, mu, back ? j : i, lk);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -324,8 +324,8 @@ struct SWCornerOp {
     for (int k = 0; k < K; ++k)
 #pragma unroll
       for (int q = 0; q < 3; ++q) acc[k][q] = czero<C>();
-    using LP = typename LinkPol<P>::type;
-    const typename LP::S* W = (const typename LP::S*)a.corners;
+    using CP = typename CornerPol<P>::type;
+    const typename CP::S* W = (const typename CP::S*)a.corners;
 #pragma unroll 1
     for (int h = 0; h < 16; ++h) {
       // h = 2*cidx + reflected: forward corner W_s(x) psi(x + s), or the
@@ -337,7 +337,7 @@ struct SWCornerOp {
       int sign;
       const int j = diag_nb(g, c, s, sign);
       C w[9];
-      load_corner<LP>(W, g.Vp, cidx, refl ? j : i, w);
+      load_corner<CP>(W, g.Vp, cidx, refl ? j : i, w);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (!((act >> k) & 1)) continue;
@@ -372,7 +372,7 @@ __device__ __forceinline__ void apply_L(const OpArgs& a, int ysite, int mu, int 
                                         typename P::C y[3]) {
   // y = L(y, sgn*mu) v: U_mu(y) v (sgn > 0) or U_mu(y - mu)^dag v (sgn < 0)
   using C = typename P::C;
-  using LP = typename LinkPol<P>::type;
+  using LP = typename LinkPol<P, NL>::type;
   C lk[9];
   if (sgn > 0) {
     load_link<LP, NL>((const typename LP::S*)a.links, a.g.Vp, mu, ysite, lk);

@@ -18,6 +18,7 @@ const void* lq_gauge_s::links(int prec, int nl) const {
   if (prec == P32 && nl == 18) p = u32_18;
   if (prec == P32 && nl == 12) p = u32_12;
   if (prec == P16 && nl == 12) p = u16_12;
+  if (prec == P16 && nl == 18) p = u32_18;   // FP32 18-real links with 16-bit vectors
   if (!p)
     throw Error(LQ_ERR_ARG, "gauge field was not built for precision " + std::to_string(prec) +
                                 " with " + std::to_string(nl) + "-real links (check features)");

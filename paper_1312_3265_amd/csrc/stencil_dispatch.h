@@ -2,7 +2,8 @@
 // (precision, link storage, dagger, epilogue) combinations and launches them.
 //   FP64: 18-real links; every epilogue, both M and M^dag.
 //   FP32: 18- or 12-real links; STORE, STORE_NORM (M), CG_UPDATE (M^dag).
-//   Q16 (16-bit fixed point): 12-real links; same epilogues as FP32.
+//   Q16 (16-bit fixed point): 16-bit 12-real or FP32 18-real links; same
+//   epilogues as FP32.
 #pragma once
 
 #include <stdexcept>
@@ -79,6 +80,7 @@ static void dispatch_prec(int prec, int nl, bool dag, int epi, const OpArgs& oa,
   if (prec == P32 && nl == 18) return dispatch_epi<OpT, F32, 18>(dag, epi, oa, in, ea, nrhs, s);
   if (prec == P32 && nl == 12) return dispatch_epi<OpT, F32, 12>(dag, epi, oa, in, ea, nrhs, s);
   if (prec == P16 && nl == 12) return dispatch_epi<OpT, Q16, 12>(dag, epi, oa, in, ea, nrhs, s);
+  if (prec == P16 && nl == 18) return dispatch_epi<OpT, Q16, 18>(dag, epi, oa, in, ea, nrhs, s);
   throw std::runtime_error("stencil: unsupported precision/link storage " + std::to_string(prec) +
                            "/" + std::to_string(nl));
 }
