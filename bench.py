@@ -54,15 +54,21 @@ def load_workload():
     return w
 
 
-def bytes_per_site(formulation, precision, links, nrhs):
+def bytes_per_site(formulation, precision, links, nrhs, kernel=0):
     """Compulsory HBM bytes per site of one stencil launch over nrhs fields:
-    input and output vectors once per RHS, the links (and corners) once."""
+    the links (and corners) once, and per RHS: kernel 0 (t = M p + ||t||^2)
+    reads p and writes t; kernel 2 (q = M^dag t, x += alpha p, r -= alpha q,
+    ||r||^2) reads t and p, reads and writes r and x (x is FP32 under 16-bit
+    storage)."""
     nc = 12 if formulation == 0 else 3
     per = {0: 16, 1: 8, 2: 4}[precision]
-    vec = 2 * nc * per + (2 * 4 if precision == 2 else 0)   # Q16: per-site float scale
-    link = 4 * (links // 2) * per if precision != 0 else 4 * 9 * 16
-    corner = 0 if formulation == 0 else 8 * 9 * per
-    return nrhs * vec + link + corner
+    vec = nc * per + (4 if precision == 2 else 0)            # Q16: per-site float scale
+    xvec = nc * (8 if precision == 2 else per)
+    lper = 8 if (precision == 2 and links == 18) else per    # Q16 with FP32 18-real links
+    link = 4 * (links // 2) * lper if precision != 0 else 4 * 9 * 16
+    corner = 0 if formulation == 0 else 8 * 9 * (4 if precision == 2 else per)
+    per_rhs = 2 * vec if kernel == 0 else 4 * vec + 2 * xvec
+    return nrhs * per_rhs + link + corner
 
 
 NRHS_W = 36                      # Wilson systems per field: 12 sources x 3 masses
@@ -80,7 +86,7 @@ def stencil_source_hash():
     return h.hexdigest()
 
 
-def stored_traffic(storage, cfg):
+def stored_traffic(storage, links, cfg):
     """HBM bytes per launch from the committed counter readings, if they were
     taken on the current stencil sources with this configuration."""
     try:
@@ -89,6 +95,7 @@ def stored_traffic(storage, cfg):
     except OSError:
         return None
     if (p.get("source_sha256") != stencil_source_hash() or p.get("storage") != storage
+            or p.get("links") != links
             or p.get("rhs_per_thread") != cfg[0] or p.get("window") != cfg[1]
             or p.get("nrhs") != NRHS_W):
         return None
@@ -97,24 +104,36 @@ def stored_traffic(storage, cfg):
 
 def roofline(lq, g0, lat, mc, prec, links, storage, cfg, stream, reps=50):
     """Average launch time (HIP events on `stream`) of the batched CG's
-    dominant kernel -- the Wilson stencil t = M p with ||t||^2 over the 36
-    systems of one field, in the launch configuration the autotuner chose --
-    against the algorithmic bytes of one launch."""
+    dominant kernel -- the Wilson stencil q = M^dag t fused with the x and r
+    updates and ||r||^2, over the 36 systems of one field, in the launch
+    configuration the autotuner chose -- against the algorithmic bytes of one
+    launch; the iteration's other stencil (t = M p + ||t||^2) beside it."""
     K, win = cfg
-    ms = lq.time_dslash(g0, 0, mc["wilson"] + 0.1, dagger=False, precision=prec, links=links,
-                        nrhs=NRHS_W, reps=reps, rhs_per_thread=K, window=win, stream=stream)
-    per_site = bytes_per_site(0, prec, links, NRHS_W)
-    algo = per_site * lat.volume
+    out = {}
+    for kern in (2, 0):
+        ms = lq.time_dslash(g0, 0, mc["wilson"] + 0.1, precision=prec, links=links, nrhs=NRHS_W,
+                            reps=reps, rhs_per_thread=K, window=win, stream=stream, kernel=kern)
+        per_site = bytes_per_site(0, prec, links, NRHS_W, kern)
+        out[kern] = (ms, per_site, per_site * lat.volume)
+    ms, per_site, algo = out[2]
     achieved = algo / (ms * 1e-3) / 1e9
+    ms0, per0, algo0 = out[0]
+    pol = "Q16" if prec == lq.Q16 else "F32"
     return {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(storage, cfg),
-        "kernel": (f"stencil_kernel<WilsonOpR1<{'Q16' if prec == lq.Q16 else 'F32'}, 12>, "
-                   f"STORE_NORM, K={K}>: Wilson t = M p + ||t||^2, {NRHS_W} systems"),
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(storage, links, cfg),
+        "kernel": (f"stencil_kernel<WilsonOpR1<{pol}, {links}, true>, CG_UPDATE, K={K}>: "
+                   f"q = M^dag t, x += alpha p, r -= alpha q, ||r||^2; {NRHS_W} systems"),
         "rhs_per_thread": K, "window": win,
         "avg_launch_us": round(ms * 1e3, 2),
         "algorithmic_bytes_per_site": per_site,
         "algorithmic_bytes_per_launch": int(algo),
+        "other_stencil": {
+            "kernel": f"stencil_kernel<WilsonOpR1<{pol}, {links}, false>, STORE_NORM>: t = M p, ||t||^2",
+            "avg_launch_us": round(ms0 * 1e3, 2),
+            "algorithmic_bytes_per_site": per0,
+            "achieved_GBs": round(algo0 / (ms0 * 1e-3) / 1e9, 1),
+        },
     }
 
 
@@ -146,10 +165,12 @@ def summarize_profile(a, trace, fetch, write, cfetch, cwrite):
     fs, wsz = 256 << 20, 256 << 20
     fscale = fs / (copy_f * 1024.0)
     wscale = wsz / (copy_w * 1024.0)
-    f_kib, nf = per_dispatch(fetch, "FETCH_SIZE", lambda n: "stencil_kernel" in n)
-    w_kib, nw = per_dispatch(write, "WRITE_SIZE", lambda n: "stencil_kernel" in n)
+    dom = lambda n: "stencil_kernel" in n and ", true>, 2," in n
+    f_kib, nf = per_dispatch(fetch, "FETCH_SIZE", dom)
+    w_kib, nw = per_dispatch(write, "WRITE_SIZE", dom)
     out = {
-        "storage": a.precision, "rhs_per_thread": a.rhs_per_thread, "window": a.window,
+        "storage": a.precision, "links": a.links, "rhs_per_thread": a.rhs_per_thread,
+        "window": a.window,
         "nrhs": NRHS_W, "source_sha256": stencil_source_hash(),
         "kernel_stats": stats,
         "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib,
@@ -207,12 +228,15 @@ def main():
     ap.add_argument("--precision", default="q16", choices=["f32", "q16"],
                     help="storage of the batched CG's stencil and Krylov vectors "
                          "(arithmetic is FP32, reductions and reliable updates FP64)")
+    ap.add_argument("--links", type=int, default=12, choices=[12, 18],
+                    help="link storage of the batched stencil: 18 = FP32 18-real, "
+                         "12 = 12-real in the vector storage")
     ap.add_argument("--fields", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only time the dominant stencil (the launches a profiler should see)")
     ap.add_argument("--rhs-per-thread", type=int, default=1, help="with --roofline-only")
-    ap.add_argument("--window", type=int, default=2, help="with --roofline-only")
+    ap.add_argument("--window", type=int, default=0, help="with --roofline-only")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy five times (counter calibration)")
     ap.add_argument("--summarize-profile", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "CFETCH", "CWRITE"),
@@ -249,7 +273,7 @@ def main():
     mc = w["m_c"]
     seeds = w["batch_seeds"][: a.fields]
     prec = lq.F32 if a.precision == "f32" else lq.Q16
-    links = 12
+    links = a.links
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
 

@@ -181,9 +181,11 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t op, int32_t precision
 
 /* Average device time (ms) of one stencil launch on `nrhs` fields already in
  * the library layout, over `reps` back-to-back launches, measured with HIP
- * events on `stream`.  dagger = 0 times the kernel of the first matvec of a
- * CG iteration (t = M p fused with ||t||^2), dagger = 1 the plain M^dag
- * stencil -- the same kernels the solvers launch.  rhs_per_thread (1, 2, 4;
+ * events on `stream`.  kernel = 0 times the first stencil of a CG iteration
+ * (t = M p fused with ||t||^2), 1 the plain M^dag stencil, 2 the second
+ * stencil of a CG iteration (q = M^dag t fused with x += alpha p,
+ * r -= alpha q and ||r||^2, on zeroed solver state) -- the same kernels the
+ * solvers launch.  rhs_per_thread (1, 2, 4;
  * FP32/Q16 only) is the number of systems each thread serves, the choice the
  * solvers' autotuner makes per batch; window, the autotuner's other choice,
  * is the block order: w > 0 sweeps windows of w site blocks per XCD over all
@@ -193,7 +195,7 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t op, int32_t precision
  * lq_time_dslash_workspace_bytes (contents overwritten).  */
 size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t precision,
                                       int32_t nrhs);
-int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger,
+int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel,
                    int32_t precision, int32_t links, int32_t nrhs, int32_t rhs_per_thread,
                    int32_t window, int32_t reps, void* ws, size_t ws_bytes, double* avg_ms,
                    void* stream);

@@ -230,14 +230,17 @@ def apply(gauge, formulation, mass, psi, op=OP_M, r=1.0, g55=G55_CORNERS, precis
 
 
 def time_dslash(gauge, formulation, mass, dagger=False, r=1.0, g55=G55_CORNERS, precision=F64,
-                links=0, nrhs=1, reps=50, rhs_per_thread=1, window=0, stream=None):
-    """Average milliseconds per stencil launch (HIP events on the launch stream)."""
+                links=0, nrhs=1, reps=50, rhs_per_thread=1, window=0, stream=None, kernel=None):
+    """Average milliseconds per stencil launch (HIP events on the launch stream).
+    kernel: 0 = t = M p + ||t||^2, 1 = plain M^dag, 2 = M^dag t with the CG
+    update of r; default 1 if dagger else 0."""
     torch = _torch()
     nb = int(lib().lq_time_dslash_workspace_bytes(gauge._h, formulation, precision, nrhs))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     d = Dirac(formulation, g55, mass, r)
     ms = ctypes.c_double()
-    _check(lib().lq_time_dslash(gauge._h, ctypes.byref(d), int(dagger), precision, links, nrhs,
+    sel = kernel if kernel is not None else (1 if dagger else 0)
+    _check(lib().lq_time_dslash(gauge._h, ctypes.byref(d), sel, precision, links, nrhs,
                                 rhs_per_thread, window, reps, _ptr(ws), nb, ctypes.byref(ms),
                                 _stream(stream)))
     return ms.value

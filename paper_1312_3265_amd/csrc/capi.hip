@@ -217,14 +217,19 @@ size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, in
   if (!g || nrhs < 1 || precision < 0 || precision > 2) return 0;
   if (formulation != LQ_WILSON && formulation != LQ_STAGGERED_WILSON) return 0;
   const size_t v = (size_t)nrhs * field_bytes(g->g, precision, ncomp_of(formulation));
+  const size_t np = (size_t)nrhs * nbp_of(g->g.V) * sizeof(double);
   Carver c(nullptr);
   c.take(v);
   c.take(v);
-  c.take((size_t)nrhs * nbp_of(g->g.V) * sizeof(double));
+  c.take(np);
+  c.take(v);
+  c.take(np);
+  c.take((size_t)nrhs * sizeof(SlotState));
+  c.take((size_t)nrhs * ncomp_of(formulation) * g->g.Vp * store_bytes(precision == P16 ? P32 : precision));
   return c.size();
 }
 
-int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t precision,
+int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t precision,
                    int32_t links, int32_t nrhs, int32_t rhs_per_thread, int32_t window,
                    int32_t reps, void* ws, size_t ws_bytes, double* avg_ms, void* stream) {
   return guard([&] {
@@ -239,11 +244,17 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t
     const int nl = links_for(precision, links);
     const int nc = ncomp_of(d->formulation);
     const int op = opkind(d->formulation, d->g55_mode);
+    need(kernel >= 0 && kernel <= 2, "kernel selector must be 0, 1 or 2");
     const size_t v = (size_t)nrhs * field_bytes(g->g, precision, nc);
+    const size_t np = (size_t)nrhs * nbp_of(g->g.V) * sizeof(double);
     Carver c(ws);
     void* a = c.take(v);
     void* b = c.take(v);
-    double* part = (double*)c.take((size_t)nrhs * nbp_of(g->g.V) * sizeof(double));
+    double* part = (double*)c.take(np);
+    void* r = c.take(v);
+    double* part_in = (double*)c.take(np);
+    SlotState* st = (SlotState*)c.take((size_t)nrhs * sizeof(SlotState));
+    void* xlo = c.take((size_t)nrhs * nc * g->g.Vp * store_bytes(precision == P16 ? P32 : precision));
     if (ws_bytes < c.size())
       throw Error(LQ_ERR_WORKSPACE, "timing workspace too small: need " + std::to_string(c.size()));
     const OpArgs oa = make_op(g, d, precision, nl);
@@ -256,16 +267,26 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t
     e.part = part;
     e.rhs_per_thread = rhs_per_thread;
     e.window = window;
-    // the stencil of the first matvec of a CG iteration (t = M p with ||t||^2),
-    // or the plain M^dag stencil
-    const int epi = dagger ? EPI_STORE : EPI_STORE_NORM;
-    launch_stencil(op, precision, nl, dagger != 0, epi, oa, a, e, nrhs, s);   // warm-up
+    // 0: the first matvec of a CG iteration (t = M p with ||t||^2); 1: the
+    // plain M^dag stencil; 2: the second (q = M^dag t, x += alpha p,
+    // r -= alpha q, ||r||^2), on zeroed state (alpha = 0: the same loads,
+    // stores and arithmetic)
+    const int epi = kernel == 0 ? EPI_STORE_NORM : kernel == 1 ? EPI_STORE : EPI_CG_UPDATE;
+    if (kernel == 2) {
+      e.r = r;
+      e.x = xlo;
+      e.p = b;
+      e.part_in = part_in;
+      e.st = st;
+      e.state_mode = 0;
+    }
+    launch_stencil(op, precision, nl, kernel != 0, epi, oa, a, e, nrhs, s);   // warm-up
     hipEvent_t t0, t1;
     LQ_HIP(hipEventCreate(&t0));
     LQ_HIP(hipEventCreate(&t1));
     LQ_HIP(hipEventRecord(t0, s));
     for (int k = 0; k < reps; ++k)
-      launch_stencil(op, precision, nl, dagger != 0, epi, oa, a, e, nrhs, s);
+      launch_stencil(op, precision, nl, kernel != 0, epi, oa, a, e, nrhs, s);
     LQ_HIP(hipEventRecord(t1, s));
     LQ_HIP(hipEventSynchronize(t1));
     check_launch();

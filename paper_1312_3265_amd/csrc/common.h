@@ -52,29 +52,36 @@ template <typename C> __device__ __forceinline__ C cfmac(C a, C b, C acc) {
   return z;
 }
 template <typename C> __device__ __forceinline__ C cmul(C a, C b) { return cfma(a, b, czero<C>()); }
+// acc + a*s for a real scalar s
+template <typename C, typename R> __device__ __forceinline__ C cfmas(C a, R s, C acc) {
+  C z; z.x = acc.x + a.x * s; z.y = acc.y + a.y * s; return z;
+}
 template <typename C> __device__ __forceinline__ double cnorm2(C a) { return (double)a.x * a.x + (double)a.y * a.y; }
 
 // ---------------------------------------------------------- precision policy
 // Storage type S of a complex number and compute type C.  Fields of the
 // vector policies are read and written a whole site at a time (ld_site /
 // st_site below); links and corner matrices element by element (cvt / enc).
+// cvt_raw / kRawScale: a matrix entry decoded without its storage scale, and
+// that scale (1 except for the 16-bit matrices), so that a kernel can apply
+// the scale once to a product instead of to every entry.
 struct F64 {
   using S = double2; using C = double2; using R = double;
   static constexpr int id = 0;
   static constexpr bool kSiteScale = false;
+  static constexpr double kRawScale = 1.0;
   __device__ __forceinline__ static C cvt(S v) { return v; }
+  __device__ __forceinline__ static C cvt_raw(S v) { return v; }
   __device__ __forceinline__ static S enc(C v) { return v; }
-  __device__ __forceinline__ static C ld(const S* p) { return *p; }
-  __device__ __forceinline__ static void st(S* p, C v) { *p = v; }
 };
 struct F32 {
   using S = float2; using C = float2; using R = float;
   static constexpr int id = 1;
   static constexpr bool kSiteScale = false;
+  static constexpr float kRawScale = 1.0f;
   __device__ __forceinline__ static C cvt(S v) { return v; }
+  __device__ __forceinline__ static C cvt_raw(S v) { return v; }
   __device__ __forceinline__ static S enc(C v) { return v; }
-  __device__ __forceinline__ static C ld(const S* p) { return *p; }
-  __device__ __forceinline__ static void st(S* p, C v) { *p = v; }
 };
 
 // 16-bit fixed point.  A complex number is a pair of int16, value = q * s / 32767.
@@ -88,6 +95,19 @@ constexpr float kQ16 = 32767.0f;
 __device__ __forceinline__ short q16_round(float v) {
   return (short)max(-32767, min(32767, __float2int_rn(v)));
 }
+// Two values rounded to the nearest integer (ties to even) and packed as an
+// int16 pair, for |re|, |im| <= 32767: adding 1.5 * 2^23 leaves the rounded
+// integer, in two's complement, in the low mantissa bits.  fre, fim return
+// the rounded values as floats (exact).
+constexpr float kRoundMagic = 12582912.0f;
+__device__ __forceinline__ uint32_t q16_pack(float re, float im, float inv, float& fre,
+                                             float& fim) {
+  const float a = __builtin_fmaf(re, inv, kRoundMagic);
+  const float b = __builtin_fmaf(im, inv, kRoundMagic);
+  fre = a - kRoundMagic;
+  fim = b - kRoundMagic;
+  return (__float_as_uint(a) & 0xffffu) | (__float_as_uint(b) << 16);
+}
 struct Q16 {
   using S = short2; using C = float2; using R = float;
   static constexpr int id = 2;
@@ -97,9 +117,11 @@ struct Q16L {
   using S = short2; using C = float2; using R = float;
   static constexpr int id = 2;
   static constexpr bool kSiteScale = false;
+  static constexpr float kRawScale = 1.0f / kQ16;
   __device__ __forceinline__ static C cvt(S v) {
     return make_float2((float)v.x * (1.0f / kQ16), (float)v.y * (1.0f / kQ16));
   }
+  __device__ __forceinline__ static C cvt_raw(S v) { return make_float2((float)v.x, (float)v.y); }
   __device__ __forceinline__ static S enc(C v) {
     short2 q;
     q.x = q16_round(v.x * kQ16);
@@ -267,6 +289,13 @@ __device__ __forceinline__ typename P::C dec(const uint32_t* w) {
   return P::cvt(v);
 }
 template <class P>
+__device__ __forceinline__ typename P::C dec_raw(const uint32_t* w) {
+  using S = typename P::S;
+  S v;
+  __builtin_memcpy(&v, w, sizeof(S));
+  return P::cvt_raw(v);
+}
+template <class P>
 __device__ __forceinline__ void enc_to(uint32_t* w, typename P::C c) {
   const typename P::S v = P::enc(c);
   __builtin_memcpy(w, &v, sizeof(v));
@@ -333,16 +362,15 @@ __device__ __forceinline__ double st_site(typename P::S* __restrict__ f, int Vp,
     for (int q = 0; q < NC; ++q) m = fmaxf(m, fmaxf(fabsf(v[q].x), fabsf(v[q].y)));
     const float inv = m > 0.0f ? kQ16 / m : 0.0f;
     const float s = m * (1.0f / kQ16);
+    float sq = 0.0f;   // sum of the squared stored integers (exact up to FP32 rounding)
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      short2 z;
-      z.x = q16_round(v[q].x * inv);
-      z.y = q16_round(v[q].y * inv);
-      w[q] = __builtin_bit_cast(uint32_t, z);
-      const float a = (float)z.x * s, b = (float)z.y * s;
-      n2 += (double)a * a + (double)b * b;
+      float a, b;
+      w[q] = q16_pack(v[q].x, v[q].y, inv, a, b);
+      sq = __builtin_fmaf(a, a, __builtin_fmaf(b, b, sq));
     }
     w[NC] = __float_as_uint(m);
+    n2 = (double)sq * ((double)s * (double)s);
   } else {
     constexpr int WPC = sizeof(typename P::S) / 4;
 #pragma unroll
@@ -368,22 +396,29 @@ __device__ __forceinline__ int phi_sign(const Coord& c) { return ((c.x[1] + c.x[
 // starts at u + mu * Vp * NREAL/2 storage elements), each the row-major 3x3
 // matrix (18 reals) or its rows 0 and 1 (12 reals; row 2 = conj(row0 x row1),
 // exact for SU(3)).  Corner matrices: eight records of 9 complex numbers.
-template <class P, int NREAL>
+// RAW = true: the matrix times 1 / P::kRawScale (entries decoded without the
+// storage scale; the rebuilt row 2 brought to the same scale).
+template <class P, int NREAL, bool RAW = false>
 __device__ __forceinline__ void load_link(const typename P::S* __restrict__ u, int Vp, int mu,
                                           int site, typename P::C m[9]) {
   using C = typename P::C;
+  using R = typename P::R;
   constexpr int NCX = NREAL / 2;
   constexpr int BY = NCX * (int)sizeof(typename P::S);
   constexpr int WPC = sizeof(typename P::S) / 4;
   uint32_t w[BY / 4];
   ld_rec<BY>(u + (size_t)mu * NCX * Vp, Vp, site, w);
 #pragma unroll
-  for (int k = 0; k < NCX; ++k) m[k] = dec<P>(w + k * WPC);
+  for (int k = 0; k < NCX; ++k) m[k] = RAW ? dec_raw<P>(w + k * WPC) : dec<P>(w + k * WPC);
   if constexpr (NREAL == 12) {
     C a0 = m[0], a1 = m[1], a2 = m[2], b0 = m[3], b1 = m[4], b2 = m[5];
     m[6] = cconj(csub(cmul(a1, b2), cmul(a2, b1)));
     m[7] = cconj(csub(cmul(a2, b0), cmul(a0, b2)));
     m[8] = cconj(csub(cmul(a0, b1), cmul(a1, b0)));
+    if constexpr (RAW && P::kRawScale != (R)1) {
+#pragma unroll
+      for (int k = 6; k < 9; ++k) m[k] = cscale(m[k], (R)P::kRawScale);
+    }
   }
 }
 template <class P, int NREAL>
@@ -397,7 +432,7 @@ __device__ __forceinline__ void store_link(typename P::S* __restrict__ u, int Vp
   for (int k = 0; k < NCX; ++k) enc_to<P>(w + k * WPC, m[k]);
   st_rec<BY>(u + (size_t)mu * NCX * Vp, Vp, site, w);
 }
-template <class P>
+template <class P, bool RAW = false>
 __device__ __forceinline__ void load_corner(const typename P::S* __restrict__ c, int Vp, int cidx,
                                             int site, typename P::C m[9]) {
   constexpr int BY = 9 * (int)sizeof(typename P::S);
@@ -405,7 +440,7 @@ __device__ __forceinline__ void load_corner(const typename P::S* __restrict__ c,
   uint32_t w[BY / 4];
   ld_rec<BY>(c + (size_t)cidx * 9 * Vp, Vp, site, w);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) m[k] = dec<P>(w + k * WPC);
+  for (int k = 0; k < 9; ++k) m[k] = RAW ? dec_raw<P>(w + k * WPC) : dec<P>(w + k * WPC);
 }
 template <class P>
 __device__ __forceinline__ void store_corner(typename P::S* __restrict__ c, int Vp, int cidx,

@@ -114,7 +114,9 @@ struct WilsonOp {
     const bool flip = wrap && g.bc[MU] < 0;
     C lk[9];
     using LP = typename LinkPol<P, NL>::type;
-    load_link<LP, NL>((const typename LP::S*)a.links, g.Vp, MU, BACK ? j : i, lk);
+    // raw link: the storage scale joins the neighbour's site scale below
+    load_link<LP, NL, true>((const typename LP::S*)a.links, g.Vp, MU, BACK ? j : i, lk);
+    constexpr bool kScaled = P::kSiteScale || (LP::kRawScale != (typename LP::R)1);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (!((act >> k) & 1)) continue;
@@ -129,26 +131,22 @@ struct WilsonOp {
         h[0][cc] = TT > 0 ? cadd(psi[cc], b0) : csub(psi[cc], b0);
         h[1][cc] = TT > 0 ? cadd(psi[3 + cc], b1) : csub(psi[3 + cc], b1);
       }
-      if constexpr (P::kSiteScale) {
-        const R f = flip ? -sc : sc;
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) { h[0][cc] = cscale(h[0][cc], f); h[1][cc] = cscale(h[1][cc], f); }
-      } else if (g.bc[MU] < 0) {   // wavefront-uniform
-        const R f = flip ? (R)-1 : (R)1;
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) { h[0][cc] = cscale(h[0][cc], f); h[1][cc] = cscale(h[1][cc], f); }
-      }
+      // the site scale, the link's storage scale and the boundary sign enter
+      // as one factor f of the accumulating multiply-adds
+      R f = kScaled ? sc * (R)LP::kRawScale : (R)1;
+      if (flip) f = -f;
       C uh[2][3];
       if (BACK) { mvd(lk, h[0], uh[0]); mvd(lk, h[1], uh[1]); }
       else { mv(lk, h[0], uh[0]); mv(lk, h[1], uh[1]); }
+      const R ft = TT > 0 ? f : -f;
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) {
         C d0, d1;
         bdmul(MU, uh[0][cc], uh[1][cc], d0, d1);
-        acc[k][cc] = cadd(acc[k][cc], uh[0][cc]);
-        acc[k][3 + cc] = cadd(acc[k][3 + cc], uh[1][cc]);
-        acc[k][6 + cc] = TT > 0 ? cadd(acc[k][6 + cc], d0) : csub(acc[k][6 + cc], d0);
-        acc[k][9 + cc] = TT > 0 ? cadd(acc[k][9 + cc], d1) : csub(acc[k][9 + cc], d1);
+        acc[k][cc] = cfmas(uh[0][cc], f, acc[k][cc]);
+        acc[k][3 + cc] = cfmas(uh[1][cc], f, acc[k][3 + cc]);
+        acc[k][6 + cc] = cfmas(d0, ft, acc[k][6 + cc]);
+        acc[k][9 + cc] = cfmas(d1, ft, acc[k][9 + cc]);
       }
     }
   }
@@ -169,10 +167,12 @@ struct WilsonOp {
     for (int k = 0; k < K; ++k) {
       const R diag = (R)(rhs_mass(a, k0 + k) + 4.0 * a.r);
       C v[12];
-      if ((act >> k) & 1) ld_site<P, 12>(in0 + k * rstride, g.Vp, i, v);
+      R sc = (R)0;
+      if ((act >> k) & 1) ld_site_raw<P, 12>(in0 + k * rstride, g.Vp, i, v, sc);
+      const R coef = (R)-2 * diag * sc;
 #pragma unroll
       for (int q = 0; q < 12; ++q)
-        acc[k][q] = ((act >> k) & 1) ? cscale(v[q], (R)-2 * diag) : czero<C>();
+        acc[k][q] = ((act >> k) & 1) ? cscale(v[q], coef) : czero<C>();
     }
     if constexpr (!GENERAL_R) {
       // Each hop's code has its gamma structure and coordinates built in.
@@ -272,15 +272,18 @@ __device__ __forceinline__ void dst_site(const OpArgs& a, const typename P::S* _
     const R sg = ((wrap && g.bc[mu] < 0) ? (R)-1 : (R)1) * (back ? -eta : eta);
     C lk[9];
     using LP = typename LinkPol<P, NL>::type;
-    load_link<LP, NL>((const typename LP::S*)a.links, g.Vp, mu, back ? j : i, lk);
+    load_link<LP, NL, true>((const typename LP::S*)a.links, g.Vp, mu, back ? j : i, lk);
+    const R sgl = sg * (R)LP::kRawScale;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (!((act >> k) & 1)) continue;
       C v[3], y[3];
-      ld_site<P, 3>(in0 + k * rstride, g.Vp, j, v);
+      R sc;
+      ld_site_raw<P, 3>(in0 + k * rstride, g.Vp, j, v, sc);
       if (back) mvd(lk, v, y); else mv(lk, v, y);
+      const R f = sgl * sc;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) acc[k][q] = cadd(acc[k][q], cscale(y[q], sg));
+      for (int q = 0; q < 3; ++q) acc[k][q] = cadd(acc[k][q], cscale(y[q], f));
     }
   }
 }
@@ -337,15 +340,18 @@ struct SWCornerOp {
       int sign;
       const int j = diag_nb(g, c, s, sign);
       C w[9];
-      load_corner<CP>(W, g.Vp, cidx, refl ? j : i, w);
+      load_corner<CP, true>(W, g.Vp, cidx, refl ? j : i, w);   // raw: scale joins below
+      const R sgc = (R)sign * (R)CP::kRawScale;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (!((act >> k) & 1)) continue;
         C v[3], y[3];
-        ld_site<P, 3>(in0 + k * rstride, g.Vp, j, v);
+        R sc;
+        ld_site_raw<P, 3>(in0 + k * rstride, g.Vp, j, v, sc);
         if (refl) mvd(w, v, y); else mv(w, v, y);
+        const R f = sgc * sc;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) acc[k][q] = cadd(acc[k][q], cscale(y[q], (R)sign));
+        for (int q = 0; q < 3; ++q) acc[k][q] = cadd(acc[k][q], cscale(y[q], f));
       }
     }
     const R gcoef = (R)(a.r * phi_sign(c) / 16.0);

@@ -107,15 +107,16 @@ std::string tune_key(const Geom& g, int op, int prec, int nl, int nslots) {
   LQ_HIP(hipGetDevice(&dev));
   LQ_HIP(hipGetDeviceProperties(&prop, dev));
   std::ostringstream key;
-  key << "v4:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
+  key << "v5:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
       << ":op" << op << ":p" << prec << ":l" << nl << ":n" << nslots;
   std::string k = key.str();
   for (auto& ch : k) if (ch == ' ') ch = '_';
   return k;
 }
 
-// Time the CG stencil t = M p (+||t||^2) over all slots for K = 1, 2, 4 on the
-// (zeroed) solver buffers and keep the fastest.
+// Time the two stencils of a CG iteration (t = M p + ||t||^2, then the M^dag
+// stencil with the x, r updates) over all slots for every systems-per-thread
+// K and block order on the (zeroed) solver buffers, and keep the fastest.
 void Engine::tune(hipStream_t s) {
   rhs_per_thread = 1;
   window = 0;
@@ -128,6 +129,13 @@ void Engine::tune(hipStream_t s) {
   e.st = nullptr;
   e.out = t;
   e.part = part_t;
+  // the iteration's second stencil on the (zeroed) solver state: alpha = 0,
+  // the same traffic; slot loads rewrite every state word it touches
+  EpiArgs f = epi_base();
+  f.state_mode = 0;
+  f.part = part_r;
+  f.part_in = part_t;
+  f.x = xlo; f.r = rlo; f.p = p;
   hipEvent_t t0, t1;
   LQ_HIP(hipEventCreate(&t0));
   LQ_HIP(hipEventCreate(&t1));
@@ -136,12 +144,15 @@ void Engine::tune(hipStream_t s) {
   for (int kk : {1, 2, 4}) {
     if (kk > nslots) break;
     for (int w : {1, 2, 4, 0, -1, -2}) {
-      e.rhs_per_thread = kk;
-      e.window = w;
+      e.rhs_per_thread = f.rhs_per_thread = kk;
+      e.window = f.window = w;
       launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
+      launch_stencil(op, prec_lo, nl_lo, true, EPI_CG_UPDATE, oa, t, f, nslots, s);
       LQ_HIP(hipEventRecord(t0, s));
-      for (int r = 0; r < 5; ++r)
+      for (int r = 0; r < 4; ++r) {
         launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
+        launch_stencil(op, prec_lo, nl_lo, true, EPI_CG_UPDATE, oa, t, f, nslots, s);
+      }
       LQ_HIP(hipEventRecord(t1, s));
       LQ_HIP(hipEventSynchronize(t1));
       check_launch();

@@ -36,6 +36,8 @@ void launch_stencil(int op, int prec, int nl, bool dag, int epi, const OpArgs& o
 }
 
 // ------------------------------------------------------------- p update
+// Closes a CG iteration: beta = ||r_new||^2 / rho, p = r + beta p, and the
+// per-system state step.
 template <class P, int NC>
 __global__ void __launch_bounds__(256)
 p_update_kernel(const Geom g, SlotState* st, int par, const double* __restrict__ part, int nbp,

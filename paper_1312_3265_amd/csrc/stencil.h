@@ -6,6 +6,8 @@
 //   CG_UPDATE   q = op(in) kept in registers; alpha = rho/||t||^2 from the
 //               partials of the previous launch; x += alpha p, r -= alpha q;
 //               block partials of ||r||^2                          (M^dag t)
+//               (x rides here rather than in the p update: this kernel has
+//               memory bandwidth to spare behind the stencil arithmetic)
 //   RESID       out = b - op(in), partials of ||out||^2   (FP64 true residual)
 //   LANCZOS     w = op(in) - beta_prev v_prev, partials of Re<v, w>
 // Partial sums are FP64, reduced in a fixed order (wavefront butterfly, then
