@@ -74,14 +74,15 @@ def bytes_per_site(formulation, precision, links, nrhs, kernel=0):
 NRHS_W = 36                      # Wilson systems per field: 12 sources x 3 masses
 PROFILE_JSON = os.path.join(ROOT, "profiles", "stencil_wilson_batched_16x32_traffic.json")
 # sources whose change invalidates the stored counter readings of the stencil
-STENCIL_SOURCES = ["common.h", "dirac.h", "stencil.h", "stencil_dispatch.h", "k_stencil_wilson.hip"]
+STENCIL_SOURCES = ["csrc/common.h", "csrc/dirac.h", "csrc/stencil.h", "csrc/stencil_dispatch.h",
+                   "csrc/k_stencil_wilson.hip", "build.py"]
 
 
 def stencil_source_hash():
     import hashlib
     h = hashlib.sha256()
     for f in STENCIL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1312_3265_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(ROOT, "paper_1312_3265_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 

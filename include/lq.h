@@ -250,7 +250,12 @@ int lq_batch_fetch(lq_batch* b, int32_t slot, void* x, lq_solve_info* info, void
 int lq_batch_peek(lq_batch* b, int32_t slot, lq_solve_info* info, double* scale);
 void lq_batch_destroy(lq_batch* b);
 
-/* The launch configuration the solvers' autotuner chose for batches of
+/* Batched solvers tune their launch configuration once per (GPU, lattice,
+ * operator, storage, batch size) and cache it in the file LQ_TUNE_CACHE
+ * (default $HOME/.cache/lq_tune.txt).  The environment variable LQ_LAUNCH =
+ * "K,window" (K in {1, 2, 4}, window >= -2) forces a configuration instead.
+ *
+ * The launch configuration the solvers' autotuner chose for batches of
  * `nrhs` systems of this operator and storage on this lattice (in this
  * process or read back from the tuning cache): systems per thread and block
  * order, as lq_time_dslash takes them.  LQ_ERR_STATE if no batch of that

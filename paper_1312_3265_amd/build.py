@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "liblq.so")
 
 ARCH = os.environ.get("LQ_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=fast",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument", "-I" + os.path.join(ROOT, "include"),

@@ -7,6 +7,7 @@
 #include <fstream>
 #include <map>
 #include <mutex>
+#include <cstdio>
 #include <sstream>
 
 #include "engine.h"
@@ -121,6 +122,18 @@ void Engine::tune(hipStream_t s) {
   rhs_per_thread = 1;
   window = 0;
   if (prec_lo == P64 || nslots < 2) return;
+  // LQ_LAUNCH="K,window" forces the launch configuration (testing every
+  // block order against the tuned one); it is not remembered
+  if (const char* f = std::getenv("LQ_LAUNCH")) {
+    int kk = 1, w = 0;
+    if (std::sscanf(f, "%d,%d", &kk, &w) == 2 && (kk == 1 || kk == 2 || kk == 4) && w >= -2) {
+      rhs_per_thread = kk;
+      window = w;
+      return;
+    }
+    throw Error(LQ_ERR_ARG, std::string("LQ_LAUNCH must be \"K,window\" with K in {1,2,4} and "
+                                        "window >= -2, got ") + f);
+  }
   const std::string k = tune_key(gauge->g, op, prec_lo, nl_lo, nslots);
   const int cached = tuned_rhs_per_thread(k);   // encoded as K + 8 * (window + 3)
   if (cached) { rhs_per_thread = cached & 7; window = (cached >> 3) - 3; return; }

@@ -92,7 +92,7 @@ def test_fp64_matvec_general_r(r):
                                              (synth.STAGGERED_WILSON, lq.G55_CORNERS),
                                              (synth.STAGGERED_WILSON, lq.G55_ONTHEFLY)])
 @pytest.mark.parametrize("precision,links,bound", [(lq.F32, 18, 2e-6), (lq.F32, 12, 4e-6),
-                                                  (lq.Q16, 12, 1e-4)])
+                                                  (lq.Q16, 12, 1e-4), (lq.Q16, 18, 1e-4)])
 def test_low_precision_matvec_within_roundoff(formulation, g55, precision, links, bound):
     """FP32: u = 6e-8 per operation over O(30) accumulated terms; Q16 storage:
     each stored component is off by at most 2^-16 of its site's largest

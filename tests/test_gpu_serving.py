@@ -59,3 +59,46 @@ def test_server_rejects_what_cannot_fit():
     srv = serve.SolveServer(fields, mem_budget=1 << 10, slots=4)
     srv.run([serve.Request(0, dims, synth.WILSON, 0.5, chi, 1e-8)])
     assert srv.rejected == [0] and srv.report()["completed"] == 0
+
+
+def test_server_at_the_workload_lattice_sizes():
+    """Poisson stream over 8^3x16, 16^3x32 and 24^3x48 resident fields (both
+    formulations, point and Z2 sources, tolerances 1e-10..1e-6), 16-bit
+    storage, at two offered loads; every result meets its tolerance by the
+    oracle's FP64 residual.  (32^3x64 serves the same way; it is left out here
+    only to keep the oracle's residual checks short.)"""
+    dims_choices = [(8, 8, 8, 16), (16, 16, 16, 32), (24, 24, 24, 48)]
+    eps = 0.4359375
+    fields = {d: synth.gauge_field(d, "near_identity", 2000 + i, eps)
+              for i, d in enumerate(dims_choices)}
+    mc = {synth.WILSON: -0.4721359549995794, synth.STAGGERED_WILSON: -0.5167184270002523}
+    descs = synth.serving_requests(12, seed=42, dims_choices=dims_choices,
+                                   tol_range=(1e-10, 1e-6))
+    opts = lq.solve_opts(precision=lq.Q16, links=12, poll_interval=16)
+    reports = []
+    for rate in (20.0, 60.0):
+        arrivals = synth.poisson_arrivals(rate=rate, n=len(descs), seed=43)
+        reqs = []
+        for d, t in zip(descs, arrivals):
+            f = d["formulation"]
+            if d["source"] == "point":
+                chi = synth.point_source(d["dims"], f, d["alpha"])
+            else:
+                chi = synth.z2_source(d["dims"], f, d["source_seed"])
+            # delta >= 0.05 above the 16^3x32 m_c: safely above every size's m_c
+            reqs.append(serve.Request(d["id"], d["dims"], f, mc[f] + 0.05 + d["delta"], chi,
+                                      d["tol"], arrival=float(t)))
+        srv = serve.SolveServer(fields, opts=opts, mem_budget=8 << 30, slots=8, chunk=16)
+        results = srv.run(reqs)
+        rep = srv.report()
+        reports.append(rep)
+        assert rep["completed"] == len(reqs) and rep["converged"] == len(reqs)
+        assert rep["p99_latency_s"] >= rep["p50_latency_s"] > 0
+        if rate == 20.0:
+            by_id = {r.id: r for r in results}
+            for req in reqs:
+                r = by_id[req.id]
+                rn, _ = solvers.true_residual(req.formulation, fields[tuple(req.dims)], req.source,
+                                              r.x.cpu().numpy(), req.mass)
+                assert rn <= req.tol, (req.id, req.dims, rn, req.tol)
+    print("offered 20/s:", reports[0], "offered 60/s:", reports[1])

@@ -36,7 +36,8 @@ def _res(form, U, chi, x, m):
 
 
 @pytest.mark.parametrize("formulation", [synth.WILSON, synth.STAGGERED_WILSON])
-@pytest.mark.parametrize("precision,links", [(lq.F32, 18), (lq.F32, 12), (lq.Q16, 12)])
+@pytest.mark.parametrize("precision,links", [(lq.F32, 18), (lq.F32, 12), (lq.Q16, 12),
+                                             (lq.Q16, 18)])
 def test_mixed_precision_reaches_fp64_tolerance(formulation, precision, links):
     U, lat, g = _field()
     chi = synth.point_source(DIMS, formulation, 1)
@@ -160,3 +161,73 @@ def test_critical_mass_matches_oracle_search(formulation):
                                          ngolden=4)
     assert abs(mc - mco) <= 1e-9
     assert abs(th - tho) <= 1e-6 * abs(tho) + 1e-12
+
+
+@pytest.mark.parametrize("precision", [lq.F32, lq.Q16])
+@pytest.mark.parametrize("formulation", [synth.WILSON, synth.STAGGERED_WILSON])
+def test_every_launch_schedule_gives_the_same_solution(formulation, precision, monkeypatch):
+    """Every block order and systems-per-thread choice covers each (site block,
+    system) pair exactly once, so the batch's results are bitwise those of the
+    plain order; 5 systems leave partial groups for K = 2 and 4."""
+    dims = (8, 8, 8, 8)      # 16 site blocks: windows of 1, 2 and 4 blocks per XCD differ
+    U, lat, g = _field(dims, 9)
+    chis = np.stack([synth.point_source(dims, formulation, a) for a in range(3)] +
+                    [synth.z2_source(dims, formulation, 70 + s) for s in range(2)])
+    ms = [MASS[formulation] + 0.02 * k for k in range(5)]
+    opts = lq.solve_opts(precision=precision, links=12, poll_interval=8)
+    ref = None
+    for K in (1, 2, 4):
+        for w in (1, 2, 4, 0, -1, -2):
+            monkeypatch.setenv("LQ_LAUNCH", f"{K},{w}")
+            x, infos = lq.cg_solve_batch(g, formulation, ms, chis, [1e-8] * 5, opts=opts)
+            assert all(i["status"] == lq.OK for i in infos)
+            its = [i["iterations"] for i in infos]
+            if ref is None:
+                ref = (x, its)
+                for k in range(5):
+                    assert _res(formulation, U, chis[k], x[k], ms[k]) <= 1e-8
+            else:
+                assert its == ref[1], (K, w)
+                assert torch.equal(x, ref[0]), (K, w)
+
+
+def test_tuned_launch_and_stencil_timing():
+    """The autotuner's choice is reported for the batch shape it tuned, and the
+    three stencil timing modes run the solver's kernels."""
+    import os
+    if os.environ.get("LQ_LAUNCH"):
+        pytest.skip("launch configuration forced from the environment")
+    dims = (8, 8, 8, 8)
+    U, lat, g = _field(dims, 9)
+    chis = np.stack([synth.point_source(dims, synth.WILSON, a) for a in range(6)])
+    opts = lq.solve_opts(precision=lq.Q16, links=12, poll_interval=8)
+    x, infos = lq.cg_solve_batch(g, synth.WILSON, [-0.2] * 6, chis, [1e-8] * 6, opts=opts)
+    assert all(i["status"] == lq.OK for i in infos)
+    cfg = lq.tuned_launch(g, synth.WILSON, lq.Q16, 12, 6)
+    assert cfg is not None and cfg[0] in (1, 2, 4) and cfg[1] >= -2
+    assert lq.tuned_launch(g, synth.WILSON, lq.F64, 0, 6) == (1, 0)
+    for kern in (0, 1, 2):
+        ms = lq.time_dslash(g, synth.WILSON, -0.2, precision=lq.Q16, links=12, nrhs=6, reps=3,
+                            rhs_per_thread=cfg[0], window=cfg[1], kernel=kern)
+        assert 0.0 < ms < 100.0
+
+
+def test_critical_mass_of_the_frozen_workload():
+    """The GPU search on the 16^3 x 32 workload field reproduces the m_c the
+    oracle froze into tests/golden/workloads.json (same grid, same golden
+    section, same start vector)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "workloads.json")) as f:
+        w = json.load(f)
+    dims = tuple(w["dims"])
+    U = synth.gauge_field(dims, "near_identity", w["seed"], w["eps"])
+    lat = lq.Lattice(dims)
+    g = lq.Gauge(lat, U)
+    assert abs(g.plaquette() - w["plaquette"]) < 1e-12
+    for form, name in ((synth.WILSON, "wilson"), (synth.STAGGERED_WILSON, "staggered_wilson")):
+        v0 = synth.gaussian_field(dims, form, w["v0_seed"])
+        mc, th = lq.critical_mass(g, form, v0, -0.8, -0.2, steps=w["lanczos_steps"], ngrid=7,
+                                  ngolden=6)
+        assert abs(mc - w["m_c"][name]) <= 1e-9, (name, mc, w["m_c"][name])
+        assert abs(th - w["theta_min_at_m_c"][name]) <= 1e-5 * abs(w["theta_min_at_m_c"][name])
