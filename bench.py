@@ -233,6 +233,8 @@ def main():
                     help="link storage of the batched stencil: 18 = FP32 18-real, "
                          "12 = 12-real in the vector storage")
     ap.add_argument("--fields", type=int, default=8)
+    ap.add_argument("--concurrency", type=int, default=2,
+                    help="batches (gauge field x formulation) in flight at once")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only time the dominant stencil (the launches a profiler should see)")
@@ -309,27 +311,60 @@ def main():
         src[form] = torch.from_numpy(np.stack(chis)).to("cuda")
         masses[form] = ms
     opts = lq.solve_opts(precision=prec, links=links, poll_interval=16, use_graph=1)
-    ws = {}
-    for form in (0, 1):
-        n = len(masses[form])
-        ws[form] = torch.empty(lq.solve_workspace_bytes(fields[0], form, opts, n),
-                               dtype=torch.uint8, device="cuda")
+    # `concurrency` batches in flight, each on its own stream with its own
+    # workspace: a batch's instruction-bound stencil then shares the device
+    # with another batch's bandwidth-bound kernels
+    workers = []
+    for c in range(a.concurrency):
+        wsc = {}
+        for form in (0, 1):
+            n = len(masses[form])
+            wsc[form] = torch.empty(lq.solve_workspace_bytes(fields[0], form, opts, n),
+                                    dtype=torch.uint8, device="cuda")
+        workers.append((stream if c == 0 else torch.cuda.Stream(), wsc))
     torch.cuda.synchronize()
     log(f"setup {time.time() - t0:.1f}s plaquette {plaq:.4f} m_c {mc}")
 
     def one_step(record=None):
+        import queue
+        import threading
+        tasks = queue.Queue()
+        for form in (0, 1):            # longer Wilson batches first
+            for gi in range(len(fields)):
+                tasks.put((gi, form))
+        done, errors = [], []
+
+        def work(strm, wsc):
+            while True:
+                try:
+                    gi, form = tasks.get_nowait()
+                except queue.Empty:
+                    return
+                try:
+                    x, infos = lq.cg_solve_batch(fields[gi], form, masses[form], src[form],
+                                                 [TOL] * len(masses[form]), opts=opts,
+                                                 stream=strm, workspace=wsc[form])
+                    for k, inf in enumerate(infos):
+                        if inf["status"] != lq.OK or inf["true_residual"] > TOL:
+                            raise RuntimeError(f"field {gi} formulation {form} system {k}: {inf}")
+                    done.append((gi, form, infos))
+                except Exception as e:          # reported after the join
+                    errors.append(e)
+                    return
+
+        th = [threading.Thread(target=work, args=wk) for wk in workers]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        if errors:
+            raise errors[0]
         n = 0
-        for gi, g in enumerate(fields):
-            for form in (0, 1):
-                x, infos = lq.cg_solve_batch(g, form, masses[form], src[form],
-                                             [TOL] * len(masses[form]), opts=opts,
-                                             stream=stream, workspace=ws[form])
-                for k, inf in enumerate(infos):
-                    if inf["status"] != lq.OK or inf["true_residual"] > TOL:
-                        raise RuntimeError(f"field {gi} formulation {form} system {k}: {inf}")
-                    if record is not None:
-                        record.append((gi, form, k, inf["iterations"], inf["reliable_updates"]))
-                n += len(infos)
+        for gi, form, infos in done:
+            for k, inf in enumerate(infos):
+                if record is not None:
+                    record.append((gi, form, k, inf["iterations"], inf["reliable_updates"]))
+            n += len(infos)
         return n
 
     for i in range(a.warmup):
@@ -414,7 +449,7 @@ def main():
                          "W 12 + SW 3 point sources x 3 masses m_c+{0.02,0.05,0.1}, "
                          "tol 1e-8, batched CG with FP64 reliable updates"),
             "systems_per_step": nsolved // a.steps,
-            "storage": a.precision, "links": links,
+            "storage": a.precision, "links": links, "batches_in_flight": a.concurrency,
         },
         "roofline": roof,
         "cpu_baseline": cpu,
