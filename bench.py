@@ -233,6 +233,9 @@ def main():
                     help="link storage of the batched stencil: 18 = FP32 18-real, "
                          "12 = 12-real in the vector storage")
     ap.add_argument("--fields", type=int, default=8)
+    ap.add_argument("--reliable-interval", type=int, default=0,
+                    help="reliable update at least every this many iterations (0: library default)")
+    ap.add_argument("--poll-interval", type=int, default=16)
     ap.add_argument("--concurrency", type=int, default=2,
                     help="batches (gauge field x formulation) in flight at once")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -310,7 +313,8 @@ def main():
                 ms.append(mc[name] + d)
         src[form] = torch.from_numpy(np.stack(chis)).to("cuda")
         masses[form] = ms
-    opts = lq.solve_opts(precision=prec, links=links, poll_interval=16, use_graph=1)
+    opts = lq.solve_opts(precision=prec, links=links, poll_interval=a.poll_interval, use_graph=1,
+                         reliable_interval=a.reliable_interval)
     # `concurrency` batches in flight, each on its own stream with its own
     # workspace: a batch's instruction-bound stencil then shares the device
     # with another batch's bandwidth-bound kernels
@@ -400,12 +404,15 @@ def main():
                     for d in DELTAS)
     fp64_rate = 45.0 / per_field
     mixed_iters = {"wilson": {}, "staggered_wilson": {}}
+    mixed_ru = {"wilson": {}, "staggered_wilson": {}}
     for gi, form, k, it, ru in rec:
         if gi == 0:
             name = "wilson" if form == 0 else "staggered_wilson"
             d = str(DELTAS[k // (12 if form == 0 else 3)])
             mixed_iters[name].setdefault(d, []).append(it)
+            mixed_ru[name].setdefault(d, []).append(ru)
     mixed_iters = {n: {d: float(np.mean(v)) for d, v in dd.items()} for n, dd in mixed_iters.items()}
+    mixed_ru = {n: {d: float(np.mean(v)) for d, v in dd.items()} for n, dd in mixed_ru.items()}
 
     # --------------------------------------------- dominant kernel roofline
     reps = 50
@@ -450,6 +457,7 @@ def main():
                          "tol 1e-8, batched CG with FP64 reliable updates"),
             "systems_per_step": nsolved // a.steps,
             "storage": a.precision, "links": links, "batches_in_flight": a.concurrency,
+            "reliable_interval": a.reliable_interval or "default", "poll_interval": a.poll_interval,
         },
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -462,6 +470,7 @@ def main():
             "dslash_fp64_us": {"wilson": round(ms64 * 1e3, 1), "staggered_wilson_corners": round(ms64_sw * 1e3, 1)},
         },
         "mixed_iterations_field0": mixed_iters,
+        "mixed_reliable_updates_field0": mixed_ru,
         "paper_context": {
             "cg_iteration_ratio_W_over_SW": {str(d): round(v, 2) for d, v in iter_ratio.items()},
             "sqrt_kappa_ratio_W_over_SW_delta0.1": round((kap["wilson"] / kap["staggered_wilson"]) ** 0.5, 2),

@@ -35,6 +35,8 @@ void launch_stencil(int op, int prec, int nl, bool dag, int epi, const OpArgs& o
   }
 }
 
+constexpr double kGrowth2 = 1e4;   // squared residual growth that forces a reliable update
+
 // ------------------------------------------------------------- p update
 // Closes a CG iteration: beta = ||r_new||^2 / rho, p = r + beta p, and the
 // per-system state step.
@@ -77,6 +79,8 @@ p_update_kernel(const Geom g, SlotState* st, int par, const double* __restrict__
     st_site<P, NC>(p + off, g.Vp, i, pv);
   }
   if (sb == 0 && threadIdx.x == 0) {
+    const double rmax = fmax(s->rho_max, rr);
+    s->rho_max = rmax;
     s->rho[par ^ 1] = rr;
     s->iter += 1;
     s->apps += 1;
@@ -84,7 +88,14 @@ p_update_kernel(const Geom g, SlotState* st, int par, const double* __restrict__
     int stop = 0;
     if (!isfinite(rr) || (s->flags & 1)) { s->flags |= 1; stop = 1; }
     if (rr <= s->thr_lo2) stop = 1;
-    else if (s->delta2 > 0.0 && rr <= s->delta2 * s->rho_ru) { stop = 1; s->want_ru = 1; }
+    // reliable-update triggers of the low-precision iteration: the residual
+    // has dropped by delta from its largest value since the latest update,
+    // or has grown 100-fold above the value at that update (restart from the
+    // FP64 true residual before rounding drift can build up)
+    else if (s->delta2 > 0.0 && (rr <= s->delta2 * rmax || rr > kGrowth2 * s->rho_ru)) {
+      stop = 1;
+      s->want_ru = 1;
+    }
     if (s->iter >= s->maxiter) { s->flags |= 2; stop = 1; }
     s->stop[par ^ 1] = stop;
   }
@@ -207,6 +218,7 @@ __global__ void ru_commit_kernel(SlotState* st, const int* mask, const double* _
   if (threadIdx.x != 0) return;
   s->rho[0] = s->rho[1] = rr;
   s->rho_ru = rr;
+  s->rho_max = rr;
   s->stop[0] = s->stop[1] = 0;
   s->iter_res2 = rr * s->scale * s->scale;
 }

@@ -23,7 +23,8 @@ struct SlotState {
   double true_res2;  // ||b - A x_hi||^2 at the latest reliable update
   double iter_res2;  // ||r_lo||^2 * scale^2 at the latest iteration
   double rho_ru;     // ||r_lo||^2 right after the latest reliable update
-  double delta2;     // request a reliable update once rho <= delta2 * rho_ru (0: never)
+  double rho_max;    // largest ||r_lo||^2 since the latest reliable update
+  double delta2;     // request a reliable update once rho <= delta2 * rho_max (0: never)
   int32_t stop[2];   // ring: 1 = frozen until the next reliable update
   int32_t status;    // 0 empty, 1 running, 2 converged, 3 failed
   int32_t iter;      // CG iterations done
