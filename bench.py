@@ -65,7 +65,7 @@ def bytes_per_site(formulation, precision, links, nrhs, kernel=0):
     vec = nc * per + (4 if precision == 2 else 0)            # Q16: per-site float scale
     xvec = nc * (8 if precision == 2 else per)
     lper = 8 if (precision == 2 and links == 18) else per    # Q16 with FP32 18-real links
-    link = 4 * (links // 2) * lper if precision != 0 else 4 * 9 * 16
+    link = 4 * (links // 2) * lper                           # FP64: 12 = rows 0, 1 read
     corner = 0 if formulation == 0 else 8 * 9 * (4 if precision == 2 else per)
     per_rhs = 2 * vec if kernel == 0 else 4 * vec + 2 * xvec
     return nrhs * per_rhs + link + corner
@@ -419,11 +419,13 @@ def main():
     cfg = lq.tuned_launch(g0, 0, prec, links, NRHS_W)
     roof = roofline(lq, g0, lat, mc, prec, links, a.precision, cfg or (1, 2), stream)
     V = lat.volume
-    ms64 = lq.time_dslash(g0, 0, mc["wilson"] + 0.1, precision=lq.F64, reps=reps, stream=stream)
-    ms64_sw = lq.time_dslash(g0, 1, mc["staggered_wilson"] + 0.1, precision=lq.F64, reps=reps,
+    ms64 = lq.time_dslash(g0, 0, mc["wilson"] + 0.1, precision=lq.F64, links=12, reps=reps,
+                          stream=stream)
+    ms64_sw = lq.time_dslash(g0, 1, mc["staggered_wilson"] + 0.1, precision=lq.F64, links=12,
+                             reps=reps,
                              stream=stream)
-    gbs64 = bytes_per_site(0, 0, 18, 1) * V / (ms64 * 1e-3) / 1e9
-    gbs64_sw = bytes_per_site(1, 0, 18, 1) * V / (ms64_sw * 1e-3) / 1e9
+    gbs64 = bytes_per_site(0, 0, 12, 1) * V / (ms64 * 1e-3) / 1e9
+    gbs64_sw = bytes_per_site(1, 0, 12, 1) * V / (ms64_sw * 1e-3) / 1e9
 
     # ----------------------------------------------- condition numbers (context)
     kap = {}

@@ -86,7 +86,12 @@ extern "C" {
                            links and corners a fixed scale of 1; FP32 arithmetic */
 
 /* link storage: 18 reals (full 3x3) or 12 reals (two rows, third row
- * rebuilt in-kernel as conj(row0 x row1), valid for SU(3) links only) */
+ * rebuilt in-kernel as conj(row0 x row1), valid for SU(3) links only).
+ * 0 selects the default: 18 for FP32, 12 for Q16, and for FP64 12 when the
+ * field is SU(3) to 1e-12 (see lq_gauge_create), else 18.  FP64 with 12 reads
+ * two of the three stored rows (a third fewer link bytes).  The solvers'
+ * FP64 work (plain FP64 CG, sources, reliable updates, Lanczos) follows the
+ * same FP64 default. */
 #define LQ_LINKS_18 18
 #define LQ_LINKS_12 12
 
@@ -159,9 +164,14 @@ int64_t lq_lattice_volume(const lq_lattice* lat);
  *   `buf`, builds the FP32/16-bit copies and the staggered Wilson corner matrices
  *   W_s(x) = (1/24) sum over the 24 orderings of the one-link-per-direction
  *   path products from x to x + s, s in {+-1}^4 (8 are stored; the other 8 are
- *   W_{-s}(x+s)^dag).  U is only read during the call's stream work.
- *   Links must be SU(3) to use 12-real storage.  */
+ *   W_{-s}(x+s)^dag).  The call measures how far row 2 of every link is from
+ *   conj(row0 x row1) and synchronises `stream`; 12-real links are refused
+ *   (LQ_ERR_ARG) unless that deviation is <= 1e-12 (FP64) or 1e-6 (FP32,
+ *   Q16), i.e. unless the links are SU(3) to that accuracy.  */
 size_t lq_gauge_bytes(const lq_lattice* lat, uint32_t features);
+/* max over sites and directions of |row2 - conj(row0 x row1)| (real and
+ * imaginary parts), measured by lq_gauge_create. */
+int lq_gauge_su3_deviation(const lq_gauge* g, double* dev);
 int lq_gauge_create(const lq_lattice* lat, const void* U, uint32_t features,
                     void* buf, size_t buf_bytes, void* stream, lq_gauge** out);
 void lq_gauge_destroy(lq_gauge* g);

@@ -97,6 +97,7 @@ def lib():
         "lq_gauge_bytes": ([P, c.c_uint32], SZ),
         "lq_gauge_create": ([P, P, c.c_uint32, P, SZ, P, P], I32),
         "lq_gauge_destroy": ([P], None),
+        "lq_gauge_su3_deviation": ([P, P], I32),
         "lq_gauge_plaquette": ([P, P, P], I32),
         "lq_apply_workspace_bytes": ([P, I32, I32], SZ),
         "lq_apply": ([P, P, I32, I32, I32, P, P, P, SZ, P], I32),
@@ -195,6 +196,12 @@ class Gauge:
     def plaquette(self, stream=None):
         out = ctypes.c_double()
         _check(lib().lq_gauge_plaquette(self._h, ctypes.byref(out), _stream(stream)))
+        return out.value
+
+    def su3_deviation(self):
+        """max |row2 - conj(row0 x row1)| over the links (0 up to rounding for SU(3))."""
+        out = ctypes.c_double()
+        _check(lib().lq_gauge_su3_deviation(self._h, ctypes.byref(out)))
         return out.value
 
     def __del__(self):

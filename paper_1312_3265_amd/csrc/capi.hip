@@ -49,9 +49,9 @@ static void check_prec(int32_t prec, int32_t links) {
   need(links == 0 || links == LQ_LINKS_18 || links == LQ_LINKS_12, "links must be 18 or 12");
 }
 
-static int links_for(int32_t prec, int32_t links) {
-  if (prec == LQ_PREC_F64) return 18;
+static int links_for(const lq_gauge* g, int32_t prec, int32_t links) {
   if (links) return links;
+  if (prec == LQ_PREC_F64) return g->fp64_links();
   return prec == LQ_PREC_Q16 ? 12 : 18;
 }
 
@@ -117,6 +117,9 @@ int lq_gauge_create(const lq_lattice* lat, const void* U, uint32_t features, voi
     hipStream_t s = S(stream);
     launch_fill_zero(buf, nb, s);
     launch_gauge_in(g->g, U, g->u64, s);
+    launch_su3_deviation(g->g, g->u64, g->scratch, g->scratch + g->nbp + 1, s);
+    LQ_HIP(hipMemcpyAsync(&g->su3_dev, g->scratch + g->nbp + 1, sizeof(double),
+                          hipMemcpyDeviceToHost, s));
     if (features & LQ_FEAT_F32) {
       launch_links_convert(P32, 18, g->g, g->u64, g->u32_18, s);
       launch_links_convert(P32, 12, g->g, g->u64, g->u32_12, s);
@@ -128,12 +131,21 @@ int lq_gauge_create(const lq_lattice* lat, const void* U, uint32_t features, voi
       if (features & LQ_FEAT_Q16) launch_corners_convert(P16, g->g, g->c64, g->c16, s);
     }
     check_launch();
+    LQ_HIP(hipStreamSynchronize(s));   // su3_dev is read on the host
     *out = g.release();
     return LQ_OK;
   });
 }
 
 void lq_gauge_destroy(lq_gauge* g) { delete g; }
+
+int lq_gauge_su3_deviation(const lq_gauge* g, double* dev) {
+  return guard([&] {
+    need(g && dev, "null argument");
+    *dev = g->su3_dev;
+    return LQ_OK;
+  });
+}
 
 int lq_gauge_plaquette(const lq_gauge* g, double* plaquette, void* stream) {
   return guard([&] {
@@ -180,7 +192,7 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t opsel, int32_t precis
     need(opsel == LQ_OP_M || opsel == LQ_OP_MDAG || opsel == LQ_OP_MDAGM, "bad op");
     const size_t nb = lq_apply_workspace_bytes(g, d->formulation, precision);
     if (ws_bytes < nb) throw Error(LQ_ERR_WORKSPACE, "apply workspace too small: need " + std::to_string(nb));
-    const int nl = links_for(precision, links);
+    const int nl = links_for(g, precision, links);
     const int nc = ncomp_of(d->formulation);
     const int op = opkind(d->formulation, d->g55_mode);
     const OpArgs oa = make_op(g, d, precision, nl);
@@ -241,7 +253,7 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
          "rhs_per_thread must be 1, 2 or 4");
     need(rhs_per_thread == 1 || precision != LQ_PREC_F64, "FP64 stencils take one system per thread");
     need(window >= -2, "window must be >= -2");
-    const int nl = links_for(precision, links);
+    const int nl = links_for(g, precision, links);
     const int nc = ncomp_of(d->formulation);
     const int op = opkind(d->formulation, d->g55_mode);
     need(kernel >= 0 && kernel <= 2, "kernel selector must be 0, 1 or 2");
@@ -421,7 +433,7 @@ int lq_tuned_launch(const lq_gauge* g, const lq_dirac* d, int32_t precision, int
     *rhs_per_thread = 1;
     *window = 0;
     if (precision == LQ_PREC_F64 || nrhs < 2) return LQ_OK;
-    const int nl = links_for(precision, links);
+    const int nl = links_for(g, precision, links);
     const int v = tuned_rhs_per_thread(
         tune_key(g->g, opkind(d->formulation, d->g55_mode), precision, nl, nrhs));
     if (v == 0) throw Error(LQ_ERR_STATE, "no batch of this shape has been tuned");

@@ -404,10 +404,13 @@ __device__ __forceinline__ void load_link(const typename P::S* __restrict__ u, i
   using C = typename P::C;
   using R = typename P::R;
   constexpr int NCX = NREAL / 2;
+  // FP64 links are always stored with 18 reals (one slab per entry); the
+  // 12-real FP64 variant reads only the slabs of rows 0 and 1
+  constexpr int NSTORE = P::id == 0 ? 9 : NCX;
   constexpr int BY = NCX * (int)sizeof(typename P::S);
   constexpr int WPC = sizeof(typename P::S) / 4;
   uint32_t w[BY / 4];
-  ld_rec<BY>(u + (size_t)mu * NCX * Vp, Vp, site, w);
+  ld_rec<BY>(u + (size_t)mu * NSTORE * Vp, Vp, site, w);
 #pragma unroll
   for (int k = 0; k < NCX; ++k) m[k] = RAW ? dec_raw<P>(w + k * WPC) : dec<P>(w + k * WPC);
   if constexpr (NREAL == 12) {

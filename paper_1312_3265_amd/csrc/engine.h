@@ -83,8 +83,12 @@ struct lq_gauge_s {
   short2* c16 = nullptr;
   double* scratch = nullptr;  // plaquette partials + result
   int nbp = 0;
+  double su3_dev = 0.0;       // max |row2 - conj(row0 x row1)| over the links
 
   const void* links(int prec, int nl) const;
+  // FP64 links: rows 0, 1 only (row 2 rebuilt) when the field is SU(3) to
+  // rounding, which reads a third fewer link bytes, else all 18 reals
+  int fp64_links() const { return su3_dev <= 1e-12 ? 12 : 18; }
   const void* corners(int prec) const;
 };
 

@@ -15,11 +15,18 @@
 const void* lq_gauge_s::links(int prec, int nl) const {
   using namespace lq;
   const void* p = nullptr;
-  if (prec == P64 && nl == 18) p = u64;
+  if (prec == P64 && (nl == 18 || nl == 12)) p = u64;   // FP64 12-real reads rows 0, 1 of the 18
   if (prec == P32 && nl == 18) p = u32_18;
   if (prec == P32 && nl == 12) p = u32_12;
   if (prec == P16 && nl == 12) p = u16_12;
   if (prec == P16 && nl == 18) p = u32_18;   // FP32 18-real links with 16-bit vectors
+  if (p && nl == 12) {
+    // the third row is rebuilt as conj(row0 x row1): exact only for SU(3)
+    const double lim = prec == P64 ? 1e-12 : 1e-6;
+    if (!(su3_dev <= lim))
+      throw Error(LQ_ERR_ARG, "12-real links need SU(3) links: row 2 differs from conj(row0 x row1) "
+                              "by " + std::to_string(su3_dev));
+  }
   if (!p)
     throw Error(LQ_ERR_ARG, "gauge field was not built for precision " + std::to_string(prec) +
                                 " with " + std::to_string(nl) + "-real links (check features)");
@@ -212,7 +219,7 @@ void Engine::init(const lq_gauge_s* g, int form, int g55, double rr, int ns,
   nslots = ns;
   prec_lo = prec_of(opts);
   nl_lo = (opts && opts->links) ? opts->links : (prec_lo == P16 ? 12 : 18);
-  if (prec_lo == P64) nl_lo = 18;
+  if (prec_lo == P64) nl_lo = (opts && opts->links) ? opts->links : g->fp64_links();
   if (opts) {
     if (opts->reliable_interval > 0) reliable_interval = opts->reliable_interval;
     if (opts->poll_interval > 0) poll_every = opts->poll_interval;
@@ -316,7 +323,8 @@ void Engine::load(int slot, const void* chi, double mass, double tol, int maxite
   launch_field_in(P64, nc, g, chi, 1, t64, nbp, slot, 1, s);
   EpiArgs e = epi_base();
   e.out = b; e.part = part_u; e.k0 = slot; e.state_mode = 2;
-  launch_stencil(op, P64, 18, true, EPI_STORE_NORM, op_args(P64, 18), t64, e, 1, s);
+  launch_stencil(op, P64, gauge->fp64_links(), true, EPI_STORE_NORM,
+                 op_args(P64, gauge->fp64_links()), t64, e, 1, s);
   launch_load_prepare(prec_lo, nc, g, (double*)xhi, xlo, (double*)rhi, (const double*)b, nbp, slot,
                       1, s);
   const double ncomp = (double)nc * g.V;
@@ -356,21 +364,22 @@ void Engine::enqueue_iterations(int n, hipStream_t s) {
 
 void Engine::enqueue_reliable_update(hipStream_t s) {
   const Geom& g = gauge->g;
-  const OpArgs oa = op_args(P64, 18);
+  const int nl64 = gauge->fp64_links();
+  const OpArgs oa = op_args(P64, nl64);
   LQ_HIP(hipMemcpyAsync(mask, hmask, sizeof(int) * nslots, hipMemcpyHostToDevice, s));
   launch_ru_accumulate(prec_lo, nc, g, st, mask, (double*)xhi, xlo, nbp, 0, nslots, s);
   EpiArgs e = epi_base();
   e.state_mode = 2;
   e.ru_mask = mask;
   e.out = t64;
-  launch_stencil(op, P64, 18, false, EPI_STORE, oa, xhi, e, nslots, s);
+  launch_stencil(op, P64, nl64, false, EPI_STORE, oa, xhi, e, nslots, s);
   EpiArgs f = epi_base();
   f.state_mode = 2;
   f.ru_mask = mask;
   f.out = rhi;
   f.b = b;
   f.part = part_u;
-  launch_stencil(op, P64, 18, true, EPI_RESID, oa, t64, f, nslots, s);
+  launch_stencil(op, P64, nl64, true, EPI_RESID, oa, t64, f, nslots, s);
   launch_ru_finish(st, mask, part_u, nbp, 0, nslots, (double)nc * g.V, prec_lo != P64, max_cand, 0,
                    0, s);
   launch_ru_convert(prec_lo, nc, g, st, mask, (const double*)rhi, rlo, p, part_u, nbp, 0, 0, nslots,
@@ -515,7 +524,8 @@ int lanczos_run(const lq_gauge_s* gs, const lq_dirac* d, int steps, const void* 
 
   OpArgs oa;
   oa.g = g;
-  oa.links = gs->links(P64, 18);
+  const int nl64 = gs->fp64_links();
+  oa.links = gs->links(P64, nl64);
   oa.corners = op == OP_SW_CORNERS ? gs->corners(P64) : nullptr;
   oa.r = d->r;
   oa.mass0 = d->mass;
@@ -534,7 +544,7 @@ int lanczos_run(const lq_gauge_s* gs, const lq_dirac* d, int steps, const void* 
     std::memset(&e, 0, sizeof(e));
     e.nbp = nbp;
     e.out = t;
-    launch_stencil(op, P64, 18, false, EPI_STORE, oa, vj, e, 1, s);
+    launch_stencil(op, P64, nl64, false, EPI_STORE, oa, vj, e, 1, s);
     EpiArgs f;
     std::memset(&f, 0, sizeof(f));
     f.nbp = nbp;
@@ -543,7 +553,7 @@ int lanczos_run(const lq_gauge_s* gs, const lq_dirac* d, int steps, const void* 
     f.v = (const double*)vj;
     f.vprev = (const double*)(j > 0 ? vj - n : vj);
     f.beta_prev = j > 0 ? bd + (j - 1) : nullptr;
-    launch_stencil(op, P64, 18, true, EPI_LANCZOS, oa, t, f, 1, s);
+    launch_stencil(op, P64, nl64, true, EPI_LANCZOS, oa, t, f, 1, s);
     // w -= alpha v_j; two classical Gram-Schmidt passes against v_1..v_j
     launch_lz_dots(g, nc, V, j + 1, w, part_a, nbp, ad + j, part_h, kLzBlocks, s);
     launch_lz_reduce(part_h, j + 1, kLzBlocks, h, s);

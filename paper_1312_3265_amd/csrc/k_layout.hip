@@ -324,6 +324,48 @@ void launch_plaquette(const Geom& g, const double2* u64, double* part, int nbp, 
   hipLaunchKernelGGL(plaquette_finish_kernel, dim3(1), dim3(64), 0, s, part, nb, (double)g.V, out);
 }
 
+// ------------------------------------------------------ SU(3) check
+// Largest deviation, over sites and directions, of the stored row 2 from
+// conj(row0 x row1): zero up to rounding for SU(3) links, which is what the
+// 12-real storage relies on.
+__global__ void __launch_bounds__(256)
+su3_dev_kernel(const Geom g, const double2* __restrict__ u, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double dev = 0.0;
+  if (i < g.V) {
+    for (int mu = 0; mu < 4; ++mu) {
+      double2 m[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) m[k] = u[(size_t)(mu * 9 + k) * g.Vp + i];
+      const double2 r[3] = {cconj(csub(cmul(m[1], m[5]), cmul(m[2], m[4]))),
+                            cconj(csub(cmul(m[2], m[3]), cmul(m[0], m[5]))),
+                            cconj(csub(cmul(m[0], m[4]), cmul(m[1], m[3])))};
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        dev = fmax(dev, fmax(fabs(r[k].x - m[6 + k].x), fabs(r[k].y - m[6 + k].y)));
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dev;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ void max_finish_kernel(const double* __restrict__ part, int n, double* out) {
+  double v = 0.0;
+  for (int k = threadIdx.x; k < n; k += 64) v = fmax(v, part[k]);
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if (threadIdx.x == 0) *out = v;
+}
+
+void launch_su3_deviation(const Geom& g, const double2* u64, double* part, double* out,
+                          hipStream_t s) {
+  const int nb = (g.V + 255) / 256;
+  hipLaunchKernelGGL(su3_dev_kernel, dim3(nb), dim3(256), 0, s, g, u64, part);
+  hipLaunchKernelGGL(max_finish_kernel, dim3(1), dim3(64), 0, s, part, nb, out);
+}
+
 // ------------------------------------------------------------- filling
 __global__ void fill_zero_kernel(uint4* __restrict__ p, size_t n16) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n16;

@@ -48,6 +48,8 @@ void launch_links_convert(int prec, int nl, const Geom& g, const double2* u64, v
                           hipStream_t s);
 void launch_corners(const Geom& g, const double2* u64, double2* c64, hipStream_t s);
 void launch_corners_convert(int prec, const Geom& g, const double2* c64, void* dst, hipStream_t s);
+void launch_su3_deviation(const Geom& g, const double2* u64, double* part, double* out,
+                          hipStream_t s);
 void launch_plaquette(const Geom& g, const double2* u64, double* part, int nbp, double* out,
                       hipStream_t s);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s);

@@ -77,6 +77,7 @@ template <template <class, int, bool> class OpT>
 static void dispatch_prec(int prec, int nl, bool dag, int epi, const OpArgs& oa, const void* in,
                           const EpiArgs& ea, int nrhs, hipStream_t s) {
   if (prec == P64 && nl == 18) return dispatch_epi<OpT, F64, 18>(dag, epi, oa, in, ea, nrhs, s);
+  if (prec == P64 && nl == 12) return dispatch_epi<OpT, F64, 12>(dag, epi, oa, in, ea, nrhs, s);
   if (prec == P32 && nl == 18) return dispatch_epi<OpT, F32, 18>(dag, epi, oa, in, ea, nrhs, s);
   if (prec == P32 && nl == 12) return dispatch_epi<OpT, F32, 12>(dag, epi, oa, in, ea, nrhs, s);
   if (prec == P16 && nl == 12) return dispatch_epi<OpT, Q16, 12>(dag, epi, oa, in, ea, nrhs, s);

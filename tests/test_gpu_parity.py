@@ -68,11 +68,13 @@ CASES = [((4, 4, 4, 4), "haar", (1, 1, 1, 1)),
                                              (synth.STAGGERED_WILSON, lq.G55_CORNERS),
                                              (synth.STAGGERED_WILSON, lq.G55_ONTHEFLY)])
 @pytest.mark.parametrize("op", [lq.OP_M, lq.OP_MDAG, lq.OP_MDAGM])
-def test_fp64_matvec_matches_oracle(dims, kind, bc, formulation, g55, op):
+@pytest.mark.parametrize("links", [0, 18])
+def test_fp64_matvec_matches_oracle(dims, kind, bc, formulation, g55, op, links):
+    """links 0 = the FP64 default (12-real reads on these SU(3) fields), 18 = all rows."""
     U, lat, g = _gauge(dims, kind, 11, bc=bc, eps=0.436 if kind != "haar" else None)
     psi = synth.gaussian_field(dims, formulation, 5)
     m = 0.137
-    out = lq.apply(g, formulation, m, psi, op=op, g55=g55).cpu().numpy()
+    out = lq.apply(g, formulation, m, psi, op=op, g55=g55, links=links).cpu().numpy()
     ref = _oracle_apply(formulation, U, psi, m, op, 1.0, bc)
     assert _relerr(out, ref) <= 1e-13
 
@@ -117,6 +119,42 @@ def test_fp64_matvec_full_size_16x32():
         out = lq.apply(g, formulation, -0.4, psi, op=lq.OP_M, g55=g55).cpu().numpy()
         ref = _oracle_apply(formulation, U, psi, -0.4, lq.OP_M)
         assert _relerr(out, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 6, 8)])
+@pytest.mark.parametrize("formulation,g55", [(synth.WILSON, 0),
+                                             (synth.STAGGERED_WILSON, lq.G55_CORNERS),
+                                             (synth.STAGGERED_WILSON, lq.G55_ONTHEFLY)])
+@pytest.mark.parametrize("op", [lq.OP_M, lq.OP_MDAG])
+def test_fp64_twelve_real_links_match_oracle(dims, formulation, g55, op):
+    """FP64 stencils reading rows 0 and 1 of each link and rebuilding row 2:
+    still within 1e-13 of the oracle (which uses all 18 reals) on SU(3) links."""
+    U, lat, g = _gauge(dims, "haar", 41)
+    psi = synth.gaussian_field(dims, formulation, 4)
+    out = lq.apply(g, formulation, 0.2, psi, op=op, g55=g55, links=12).cpu().numpy()
+    ref = _oracle_apply(formulation, U, psi, 0.2, op)
+    assert _relerr(out, ref) <= 1e-13
+
+
+def test_twelve_real_links_refused_for_non_su3_field():
+    """Links with det != 1 (an SU(3) field times a U(1) phase) break the row-2
+    rebuild; 12-real storage is refused while 18-real still matches the oracle."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, "haar", 43) * np.exp(0.3j)
+    lat = lq.Lattice(dims)
+    g = lq.Gauge(lat, U)
+    m = U.reshape(-1, 3, 3)
+    d = np.conj(np.cross(m[:, 0, :], m[:, 1, :])) - m[:, 2, :]
+    expect = max(np.abs(d.real).max(), np.abs(d.imag).max())
+    assert abs(g.su3_deviation() - expect) <= 1e-12
+    U0, _, g0 = _gauge(dims, "haar", 41)
+    assert g0.su3_deviation() <= 1e-14
+    psi = synth.gaussian_field(dims, synth.WILSON, 5)
+    for prec, links in ((lq.F64, 12), (lq.F32, 12), (lq.Q16, 12)):
+        with pytest.raises(lq.LQError):
+            lq.apply(g, synth.WILSON, 0.2, psi, op=lq.OP_M, precision=prec, links=links)
+    out = lq.apply(g, synth.WILSON, 0.2, psi, op=lq.OP_M).cpu().numpy()
+    assert _relerr(out, _oracle_apply(synth.WILSON, U, psi, 0.2, lq.OP_M)) <= 1e-13
 
 
 # ------------------------------------------------------------------ solves
