@@ -201,7 +201,10 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t op, int32_t precision
  * is the block order: w > 0 sweeps windows of w site blocks per XCD over all
  * systems before moving on, 0 gives each XCD one contiguous site range, -1
  * gives each XCD a contiguous eighth of the system-major (system, site)
- * order, -2 the same with every other system swept backwards.  ws: device scratch of
+ * order, -2 the same with every other system swept backwards; -3 and -4 tile
+ * each XCD's eighth of the t range in chunks of two z-planes with t inner,
+ * systems outermost (-3) or innermost (-4) -- on lattices with whole x-y
+ * planes of 256-site blocks, L4 % 8 == 0 and even L3; elsewhere they act as 0.  ws: device scratch of
  * lq_time_dslash_workspace_bytes (contents overwritten).  */
 size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t precision,
                                       int32_t nrhs);
@@ -263,13 +266,13 @@ void lq_batch_destroy(lq_batch* b);
 /* Batched solvers tune their launch configuration once per (GPU, lattice,
  * operator, storage, batch size) and cache it in the file LQ_TUNE_CACHE
  * (default $HOME/.cache/lq_tune.txt).  The environment variable LQ_LAUNCH =
- * "K,window" (K in {1, 2, 4}, window >= -2) forces a configuration instead.
+ * "K,window" (K in {1, 2, 4}, window >= -4) forces a configuration instead.
  *
  * The launch configuration the solvers' autotuner chose for batches of
  * `nrhs` systems of this operator and storage on this lattice (in this
  * process or read back from the tuning cache): systems per thread and block
  * order, as lq_time_dslash takes them.  LQ_ERR_STATE if no batch of that
- * shape has been tuned yet; FP64 and single systems are never tuned (1, 0). */
+ * shape has been tuned yet; FP64 and single systems are never tuned (1, -3). */
 int lq_tuned_launch(const lq_gauge* g, const lq_dirac* d, int32_t precision, int32_t links,
                     int32_t nrhs, int32_t* rhs_per_thread, int32_t* window);
 

@@ -209,6 +209,7 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t opsel, int32_t precis
     EpiArgs e;
     std::memset(&e, 0, sizeof(e));
     e.nbp = nbp;
+    e.window = -3;   // tiled order where the lattice allows it
     if (opsel == LQ_OP_MDAGM) {
       e.out = tmp;
       launch_stencil(op, precision, nl, false, EPI_STORE, oa, a, e, 1, s);
@@ -252,7 +253,7 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     need(rhs_per_thread == 1 || rhs_per_thread == 2 || rhs_per_thread == 4,
          "rhs_per_thread must be 1, 2 or 4");
     need(rhs_per_thread == 1 || precision != LQ_PREC_F64, "FP64 stencils take one system per thread");
-    need(window >= -2, "window must be >= -2");
+    need(window >= -4, "window must be >= -4");
     const int nl = links_for(g, precision, links);
     const int nc = ncomp_of(d->formulation);
     const int op = opkind(d->formulation, d->g55_mode);
@@ -431,7 +432,7 @@ int lq_tuned_launch(const lq_gauge* g, const lq_dirac* d, int32_t precision, int
     check_prec(precision, links);
     need(nrhs >= 1, "nrhs must be >= 1");
     *rhs_per_thread = 1;
-    *window = 0;
+    *window = -3;   // what untuned launches use
     if (precision == LQ_PREC_F64 || nrhs < 2) return LQ_OK;
     const int nl = links_for(g, precision, links);
     const int v = tuned_rhs_per_thread(

@@ -102,6 +102,51 @@ struct WilsonOp {
   // h = sgn * scale * (psi_up + TT B psi_lo) (TT = -s forward, +s backward),
   // uh = L h, then acc += [uh; TT B^dag uh].  Only the link load is shared by
   // the K systems.
+  // Spin projection for a hop along MU: h = psi_up + TT B psi_lo.
+  template <int MU, int TT>
+  __device__ __forceinline__ static void project(const C psi[12], C h[2][3]) {
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      C b0, b1;
+      bmul(MU, psi[6 + cc], psi[9 + cc], b0, b1);
+      h[0][cc] = TT > 0 ? cadd(psi[cc], b0) : csub(psi[cc], b0);
+      h[1][cc] = TT > 0 ? cadd(psi[3 + cc], b1) : csub(psi[3 + cc], b1);
+    }
+  }
+
+  // acc += f [uh; TT B^dag uh], uh = L h with L = lk (forward) or lk^dag (BACK):
+  // the site scale, the link's storage scale and the boundary sign enter as
+  // the one factor f of the accumulating multiply-adds.
+  template <int MU, int TT, bool BACK>
+  __device__ __forceinline__ static void accumulate(const C lk[9], const C h[2][3], R f,
+                                                    C acc[12]) {
+    C uh[2][3];
+    if (BACK) { mvd(lk, h[0], uh[0]); mvd(lk, h[1], uh[1]); }
+    else { mv(lk, h[0], uh[0]); mv(lk, h[1], uh[1]); }
+    const R ft = TT > 0 ? f : -f;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      C d0, d1;
+      bdmul(MU, uh[0][cc], uh[1][cc], d0, d1);
+      acc[cc] = cfmas(uh[0][cc], f, acc[cc]);
+      acc[3 + cc] = cfmas(uh[1][cc], f, acc[3 + cc]);
+      acc[6 + cc] = cfmas(d0, ft, acc[6 + cc]);
+      acc[9 + cc] = cfmas(d1, ft, acc[9 + cc]);
+    }
+  }
+
+  // The factor f of a hop from a neighbour with site scale sc over links of
+  // policy LP, with the boundary sign when the hop wraps.
+  template <class LP>
+  __device__ __forceinline__ static R hop_factor(R sc, bool flip) {
+    constexpr bool kScaled = P::kSiteScale || (LP::kRawScale != (typename LP::R)1);
+    R f = kScaled ? sc * (R)LP::kRawScale : (R)1;
+    return flip ? -f : f;
+  }
+
+  // r = 1 hop along +-MU with the gamma structure fixed at compile time:
+  // TT = -s forward, +s backward.  Only the link load is shared by the K
+  // systems.
   template <int MU, bool BACK, int K>
   __device__ __forceinline__ static void hop_r1(const OpArgs& a, const S* __restrict__ in0,
                                                 size_t rstride, const Coord& c, int i,
@@ -114,9 +159,8 @@ struct WilsonOp {
     const bool flip = wrap && g.bc[MU] < 0;
     C lk[9];
     using LP = typename LinkPol<P, NL>::type;
-    // raw link: the storage scale joins the neighbour's site scale below
+    // raw link: its storage scale joins the neighbour's site scale in f
     load_link<LP, NL, true>((const typename LP::S*)a.links, g.Vp, MU, BACK ? j : i, lk);
-    constexpr bool kScaled = P::kSiteScale || (LP::kRawScale != (typename LP::R)1);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (!((act >> k) & 1)) continue;
@@ -124,30 +168,8 @@ struct WilsonOp {
       R sc;
       ld_site_raw<P, 12>(in0 + k * rstride, g.Vp, j, psi, sc);
       C h[2][3];
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) {
-        C b0, b1;
-        bmul(MU, psi[6 + cc], psi[9 + cc], b0, b1);
-        h[0][cc] = TT > 0 ? cadd(psi[cc], b0) : csub(psi[cc], b0);
-        h[1][cc] = TT > 0 ? cadd(psi[3 + cc], b1) : csub(psi[3 + cc], b1);
-      }
-      // the site scale, the link's storage scale and the boundary sign enter
-      // as one factor f of the accumulating multiply-adds
-      R f = kScaled ? sc * (R)LP::kRawScale : (R)1;
-      if (flip) f = -f;
-      C uh[2][3];
-      if (BACK) { mvd(lk, h[0], uh[0]); mvd(lk, h[1], uh[1]); }
-      else { mv(lk, h[0], uh[0]); mv(lk, h[1], uh[1]); }
-      const R ft = TT > 0 ? f : -f;
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) {
-        C d0, d1;
-        bdmul(MU, uh[0][cc], uh[1][cc], d0, d1);
-        acc[k][cc] = cfmas(uh[0][cc], f, acc[k][cc]);
-        acc[k][3 + cc] = cfmas(uh[1][cc], f, acc[k][3 + cc]);
-        acc[k][6 + cc] = cfmas(d0, ft, acc[k][6 + cc]);
-        acc[k][9 + cc] = cfmas(d1, ft, acc[k][9 + cc]);
-      }
+      project<MU, TT>(psi, h);
+      accumulate<MU, TT, BACK>(lk, h, hop_factor<LP>(sc, flip), acc[k]);
     }
   }
 

@@ -115,7 +115,7 @@ std::string tune_key(const Geom& g, int op, int prec, int nl, int nslots) {
   LQ_HIP(hipGetDevice(&dev));
   LQ_HIP(hipGetDeviceProperties(&prop, dev));
   std::ostringstream key;
-  key << "v5:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
+  key << "v7:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
       << ":op" << op << ":p" << prec << ":l" << nl << ":n" << nslots;
   std::string k = key.str();
   for (auto& ch : k) if (ch == ' ') ch = '_';
@@ -127,19 +127,19 @@ std::string tune_key(const Geom& g, int op, int prec, int nl, int nslots) {
 // K and block order on the (zeroed) solver buffers, and keep the fastest.
 void Engine::tune(hipStream_t s) {
   rhs_per_thread = 1;
-  window = 0;
+  window = -3;   // tiled order where the lattice allows it (the plain order elsewhere)
   if (prec_lo == P64 || nslots < 2) return;
   // LQ_LAUNCH="K,window" forces the launch configuration (testing every
   // block order against the tuned one); it is not remembered
   if (const char* f = std::getenv("LQ_LAUNCH")) {
     int kk = 1, w = 0;
-    if (std::sscanf(f, "%d,%d", &kk, &w) == 2 && (kk == 1 || kk == 2 || kk == 4) && w >= -2) {
+    if (std::sscanf(f, "%d,%d", &kk, &w) == 2 && (kk == 1 || kk == 2 || kk == 4) && w >= -4) {
       rhs_per_thread = kk;
       window = w;
       return;
     }
     throw Error(LQ_ERR_ARG, std::string("LQ_LAUNCH must be \"K,window\" with K in {1,2,4} and "
-                                        "window >= -2, got ") + f);
+                                        "window >= -4, got ") + f);
   }
   const std::string k = tune_key(gauge->g, op, prec_lo, nl_lo, nslots);
   const int cached = tuned_rhs_per_thread(k);   // encoded as K + 8 * (window + 3)
@@ -163,7 +163,7 @@ void Engine::tune(hipStream_t s) {
   int bestk = 1, bestw = 0;
   for (int kk : {1, 2, 4}) {
     if (kk > nslots) break;
-    for (int w : {1, 2, 4, 0, -1, -2}) {
+    for (int w : {1, 2, 4, 0, -1, -2, -3, -4}) {
       e.rhs_per_thread = f.rhs_per_thread = kk;
       e.window = f.window = w;
       launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);

@@ -45,7 +45,8 @@ struct EpiArgs {
   const double* vprev;    // LANCZOS: v_{j-1}
   const double* beta_prev;// LANCZOS: device scalar beta_{j-1} (null = 0)
   int rhs_per_thread;     // systems per thread (1, 2 or 4; FP32/Q16 CG kernels)
-  int window;             // block order (map_block): > 0 window width, 0 whole range, < 0 system-major
+  int window;             // block order: > 0 window width, 0 whole range, -1/-2 system-major,
+                          // -3/-4 tiled (map_block, map_block_tiled)
 };
 
 // blockIdx.x -> (site block sb, rhs k), XCD-aware.  Block b runs on XCD b % 8,
@@ -86,6 +87,36 @@ __device__ __forceinline__ void map_block(int nbp, int nrhs, int win, int& sb, i
   sb = 8 * w0 + xcd * width + (rem - k * width);
 }
 
+// win = -3 / -4: tiled orders for lattices whose x-y planes are whole site
+// blocks (L1*L2 a multiple of 256, L4 a multiple of 8, L3 even, V/256 a
+// multiple of 8).  XCD x owns the t-slices [x*L4/8, (x+1)*L4/8) and sweeps
+// them in chunks of two z-planes: for each chunk, t runs innermost-but-one,
+// so a block's t- and z-neighbours are visited by the same XCD within a few
+// dozen blocks and are still in its L2.  -3 takes the systems one after the
+// other (each XCD sweeps its slab once per system); -4 visits each tile for
+// all systems before moving on (links shared through L2, vectors not).
+// Returns false (and leaves sb, k unset) when the lattice does not qualify.
+__device__ __forceinline__ bool map_block_tiled(const Geom& g, int nbp, int nrhs, int win, int& sb,
+                                                int& k) {
+  const int plane = g.L[0] * g.L[1];
+  if ((plane & 255) || (g.L[3] & 7) || (g.L[2] & 1) || nbp * 256 != g.V) return false;
+  const int b = blockIdx.x;
+  const int xcd = b & 7, kk = b >> 3;
+  const int P = plane >> 8, Z = g.L[2], Tx = g.L[3] >> 3;
+  const int per = P * Z * Tx;             // blocks of one system on one XCD
+  int r;
+  if (win == -3) { k = kk / per; r = kk - k * per; }
+  else { k = kk % nrhs; r = kk / nrhs; }
+  const int p = r % P;
+  r /= P;
+  const int zi = r & 1;
+  r >>= 1;
+  const int tl = r % Tx;
+  const int zc = r / Tx;
+  sb = p + P * ((2 * zc + zi) + Z * (xcd * Tx + tl));
+  return true;
+}
+
 __device__ __forceinline__ bool slot_active(const SlotState* st, int k, int mode, int par,
                                             const int* mask) {
   if (mode == 0) return true;
@@ -105,50 +136,20 @@ __device__ __forceinline__ bool slot_active(const SlotState* st, int k, int mode
 template <class Op, int K>
 constexpr int stencil_waves() { return (Op::NC == 12 && K >= 4) ? 3 : Op::kWaves; }
 
+// The epilogue of one site for the K systems of a thread (see the header of
+// this file), with the block partial of the site block sb.  Every thread of
+// the block must call it (block_sum synchronises the block).
 template <class Op, int EPI, int K>
-__global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(stencil_waves<Op, K>(), 8)))
-stencil_kernel(const OpArgs oa, const typename Op::S* __restrict__ in, const EpiArgs ea,
-               int ngroups, int nrhs) {
+__device__ __forceinline__ void site_epilogue(const OpArgs& oa, const EpiArgs& ea, int k0,
+                                              unsigned act, int i, bool valid, int sb,
+                                              const typename Op::C o[K][Op::NC],
+                                              const double alpha[K], double* red) {
   using P_C = typename Op::C;
   using R = typename Op::R;
   using S = typename Op::S;
   constexpr int NC = Op::NC;
-  __shared__ double red[16];
-  int sb, kg;
-  map_block(ea.nbp, ngroups, ea.window, sb, kg);
-  const int k0 = ea.k0 + kg * K;
-  unsigned act = 0;
-#pragma unroll
-  for (int kk = 0; kk < K; ++kk) {
-    const int k = k0 + kk;
-    if (k < ea.k0 + nrhs && (!ea.st || slot_active(ea.st, k, ea.state_mode, ea.par, ea.ru_mask)))
-      act |= 1u << kk;
-  }
-  if (act == 0) return;   // uniform over the block
-
   const int Vp = oa.g.Vp;
-  const int i = sb * blockDim.x + threadIdx.x;
-  const bool valid = i < oa.g.V;
   const size_t rstride = (size_t)field_planes<typename Op::Pol>(NC) * Vp;
-
-  double alpha[K];
-  if constexpr (EPI == EPI_CG_UPDATE) {
-#pragma unroll
-    for (int kk = 0; kk < K; ++kk) {
-      alpha[kk] = 0.0;
-      if (!((act >> kk) & 1)) continue;
-      const int k = k0 + kk;
-      const double tt = sum_partials(ea.part_in + (size_t)k * ea.nbp, ea.nbp, red);
-      const double rho = ea.st[k].rho[ea.par];
-      alpha[kk] = (tt > 0.0 && isfinite(tt) && isfinite(rho)) ? rho / tt : 0.0;
-      if (!(tt > 0.0 && isfinite(tt)) && sb == 0 && threadIdx.x == 0) ea.st[k].flags |= 1;
-    }
-  }
-
-  P_C o[K][NC];
-  if (valid) Op::template site_multi<K>(oa, in + (size_t)k0 * rstride, rstride, i, k0, act, o);
-
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
     if (!((act >> kk) & 1)) continue;   // uniform over the block
@@ -211,6 +212,55 @@ stencil_kernel(const OpArgs oa, const typename Op::S* __restrict__ in, const Epi
       if (threadIdx.x == 0) ea.part[(size_t)k * ea.nbp + sb] = bs;
     }
   }
+}
+
+template <class Op, int EPI, int K>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(stencil_waves<Op, K>(), 8)))
+stencil_kernel(const OpArgs oa, const typename Op::S* __restrict__ in, const EpiArgs ea,
+               int ngroups, int nrhs) {
+  using P_C = typename Op::C;
+  using R = typename Op::R;
+  using S = typename Op::S;
+  constexpr int NC = Op::NC;
+  __shared__ double red[16];
+  int sb, kg;
+  if ((ea.window != -3 && ea.window != -4) ||
+      !map_block_tiled(oa.g, ea.nbp, ngroups, ea.window, sb, kg))
+    map_block(ea.nbp, ngroups, ea.window < -2 ? 0 : ea.window, sb, kg);
+  const int k0 = ea.k0 + kg * K;
+  unsigned act = 0;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int k = k0 + kk;
+    if (k < ea.k0 + nrhs && (!ea.st || slot_active(ea.st, k, ea.state_mode, ea.par, ea.ru_mask)))
+      act |= 1u << kk;
+  }
+  if (act == 0) return;   // uniform over the block
+
+  const int Vp = oa.g.Vp;
+  const int i = sb * blockDim.x + threadIdx.x;
+  const bool valid = i < oa.g.V;
+  const size_t rstride = (size_t)field_planes<typename Op::Pol>(NC) * Vp;
+
+  double alpha[K];
+  if constexpr (EPI == EPI_CG_UPDATE) {
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) {
+      alpha[kk] = 0.0;
+      if (!((act >> kk) & 1)) continue;
+      const int k = k0 + kk;
+      const double tt = sum_partials(ea.part_in + (size_t)k * ea.nbp, ea.nbp, red);
+      const double rho = ea.st[k].rho[ea.par];
+      alpha[kk] = (tt > 0.0 && isfinite(tt) && isfinite(rho)) ? rho / tt : 0.0;
+      if (!(tt > 0.0 && isfinite(tt)) && sb == 0 && threadIdx.x == 0) ea.st[k].flags |= 1;
+    }
+  }
+
+  P_C o[K][NC];
+  if (valid) Op::template site_multi<K>(oa, in + (size_t)k0 * rstride, rstride, i, k0, act, o);
+
+  site_epilogue<Op, EPI, K>(oa, ea, k0, act, i, valid, sb, o, alpha, red);
 }
 
 }  // namespace lq

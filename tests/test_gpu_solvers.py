@@ -163,13 +163,15 @@ def test_critical_mass_matches_oracle_search(formulation):
     assert abs(th - tho) <= 1e-6 * abs(tho) + 1e-12
 
 
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (16, 16, 4, 8)])
 @pytest.mark.parametrize("precision", [lq.F32, lq.Q16])
 @pytest.mark.parametrize("formulation", [synth.WILSON, synth.STAGGERED_WILSON])
-def test_every_launch_schedule_gives_the_same_solution(formulation, precision, monkeypatch):
+def test_every_launch_schedule_gives_the_same_solution(formulation, precision, dims, monkeypatch):
     """Every block order and systems-per-thread choice covers each (site block,
     system) pair exactly once, so the batch's results are bitwise those of the
-    plain order; 5 systems leave partial groups for K = 2 and 4."""
-    dims = (8, 8, 8, 8)      # 16 site blocks: windows of 1, 2 and 4 blocks per XCD differ
+    plain order; 5 systems leave partial groups for K = 2 and 4.  8^4 has 16
+    site blocks (windows of 1, 2, 4 differ); 16x16x4x8 has whole x-y planes of
+    blocks, where the tiled orders -3 and -4 apply."""
     U, lat, g = _field(dims, 9)
     chis = np.stack([synth.point_source(dims, formulation, a) for a in range(3)] +
                     [synth.z2_source(dims, formulation, 70 + s) for s in range(2)])
@@ -177,7 +179,7 @@ def test_every_launch_schedule_gives_the_same_solution(formulation, precision, m
     opts = lq.solve_opts(precision=precision, links=12, poll_interval=8)
     ref = None
     for K in (1, 2, 4):
-        for w in (1, 2, 4, 0, -1, -2):
+        for w in (1, 2, 4, 0, -1, -2, -3, -4):
             monkeypatch.setenv("LQ_LAUNCH", f"{K},{w}")
             x, infos = lq.cg_solve_batch(g, formulation, ms, chis, [1e-8] * 5, opts=opts)
             assert all(i["status"] == lq.OK for i in infos)
@@ -204,8 +206,8 @@ def test_tuned_launch_and_stencil_timing():
     x, infos = lq.cg_solve_batch(g, synth.WILSON, [-0.2] * 6, chis, [1e-8] * 6, opts=opts)
     assert all(i["status"] == lq.OK for i in infos)
     cfg = lq.tuned_launch(g, synth.WILSON, lq.Q16, 12, 6)
-    assert cfg is not None and cfg[0] in (1, 2, 4) and cfg[1] >= -2
-    assert lq.tuned_launch(g, synth.WILSON, lq.F64, 0, 6) == (1, 0)
+    assert cfg is not None and cfg[0] in (1, 2, 4) and cfg[1] >= -4
+    assert lq.tuned_launch(g, synth.WILSON, lq.F64, 0, 6) == (1, -3)
     for kern in (0, 1, 2):
         ms = lq.time_dslash(g, synth.WILSON, -0.2, precision=lq.Q16, links=12, nrhs=6, reps=3,
                             rhs_per_thread=cfg[0], window=cfg[1], kernel=kern)
