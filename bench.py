@@ -57,9 +57,10 @@ def load_workload():
 def bytes_per_site(formulation, precision, links, nrhs, kernel=0):
     """Compulsory HBM bytes per site of one stencil launch over nrhs fields:
     the links (and corners) once, and per RHS: kernel 0 (t = M p + ||t||^2)
-    reads p and writes t; kernel 2 (q = M^dag t, x += alpha p, r -= alpha q,
-    ||r||^2) reads t and p, reads and writes r and x (x is FP32 under 16-bit
-    storage)."""
+    reads p and writes t; kernel 2 (q = M^dag t, r -= alpha q, ||r||^2) reads
+    t and reads and writes r, and on every other launch also reads p_{k-1}
+    and p_k and reads and writes x (FP32 under 16-bit storage) -- per launch
+    on average 4 vectors and one x."""
     nc = 12 if formulation == 0 else 3
     per = {0: 16, 1: 8, 2: 4}[precision]
     vec = nc * per + (4 if precision == 2 else 0)            # Q16: per-site float scale
@@ -67,7 +68,7 @@ def bytes_per_site(formulation, precision, links, nrhs, kernel=0):
     lper = 8 if (precision == 2 and links == 18) else per    # Q16 with FP32 18-real links
     link = 4 * (links // 2) * lper                           # FP64: 12 = rows 0, 1 read
     corner = 0 if formulation == 0 else 8 * 9 * (4 if precision == 2 else per)
-    per_rhs = 2 * vec if kernel == 0 else 4 * vec + 2 * xvec
+    per_rhs = 2 * vec if kernel == 0 else 4 * vec + xvec
     return nrhs * per_rhs + link + corner
 
 
@@ -124,7 +125,8 @@ def roofline(lq, g0, lat, mc, prec, links, storage, cfg, stream, reps=50):
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(storage, links, cfg),
         "kernel": (f"stencil_kernel<WilsonOpR1<{pol}, {links}, true>, CG_UPDATE, K={K}>: "
-                   f"q = M^dag t, x += alpha p, r -= alpha q, ||r||^2; {NRHS_W} systems"),
+                   f"q = M^dag t, r -= alpha q, ||r||^2, x += alpha' p' + alpha p every "
+                   f"other launch; {NRHS_W} systems; average of the pair"),
         "rhs_per_thread": K, "window": win,
         "avg_launch_us": round(ms * 1e3, 2),
         "algorithmic_bytes_per_site": per_site,

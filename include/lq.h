@@ -193,9 +193,10 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t op, int32_t precision
  * the library layout, over `reps` back-to-back launches, measured with HIP
  * events on `stream`.  kernel = 0 times the first stencil of a CG iteration
  * (t = M p fused with ||t||^2), 1 the plain M^dag stencil, 2 the second
- * stencil of a CG iteration (q = M^dag t fused with x += alpha p,
- * r -= alpha q and ||r||^2, on zeroed solver state) -- the same kernels the
- * solvers launch.  rhs_per_thread (1, 2, 4;
+ * stencil of a CG iteration (q = M^dag t fused with r -= alpha q and
+ * ||r||^2, and on every other launch with x += alpha' p' + alpha p, the
+ * solvers' paired x update; on zeroed solver state) -- the same kernels the
+ * solvers launch; `reps` should be even for kernel 2.  rhs_per_thread (1, 2, 4;
  * FP32/Q16 only) is the number of systems each thread serves, the choice the
  * solvers' autotuner makes per batch; window, the autotuner's other choice,
  * is the block order: w > 0 sweeps windows of w site blocks per XCD over all

@@ -239,6 +239,7 @@ size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, in
   c.take(np);
   c.take((size_t)nrhs * sizeof(SlotState));
   c.take((size_t)nrhs * ncomp_of(formulation) * g->g.Vp * store_bytes(precision == P16 ? P32 : precision));
+  c.take(v);
   return c.size();
 }
 
@@ -268,6 +269,7 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     double* part_in = (double*)c.take(np);
     SlotState* st = (SlotState*)c.take((size_t)nrhs * sizeof(SlotState));
     void* xlo = c.take((size_t)nrhs * nc * g->g.Vp * store_bytes(precision == P16 ? P32 : precision));
+    void* pprev = c.take(v);
     if (ws_bytes < c.size())
       throw Error(LQ_ERR_WORKSPACE, "timing workspace too small: need " + std::to_string(c.size()));
     const OpArgs oa = make_op(g, d, precision, nl);
@@ -281,14 +283,16 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     e.rhs_per_thread = rhs_per_thread;
     e.window = window;
     // 0: the first matvec of a CG iteration (t = M p with ||t||^2); 1: the
-    // plain M^dag stencil; 2: the second (q = M^dag t, x += alpha p,
-    // r -= alpha q, ||r||^2), on zeroed state (alpha = 0: the same loads,
-    // stores and arithmetic)
+    // plain M^dag stencil; 2: the second (q = M^dag t, r -= alpha q, ||r||^2,
+    // and on every other launch x += alpha' p' + alpha p, as in the solver's
+    // iteration pairs), on zeroed state (alpha = 0: the same loads, stores
+    // and arithmetic)
     const int epi = kernel == 0 ? EPI_STORE_NORM : kernel == 1 ? EPI_STORE : EPI_CG_UPDATE;
     if (kernel == 2) {
       e.r = r;
       e.x = xlo;
       e.p = b;
+      e.pprev = pprev;
       e.part_in = part_in;
       e.st = st;
       e.state_mode = 0;
@@ -298,8 +302,10 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     LQ_HIP(hipEventCreate(&t0));
     LQ_HIP(hipEventCreate(&t1));
     LQ_HIP(hipEventRecord(t0, s));
-    for (int k = 0; k < reps; ++k)
+    for (int k = 0; k < reps; ++k) {
+      e.par = kernel == 2 ? (k & 1) : 0;
       launch_stencil(op, precision, nl, kernel != 0, epi, oa, a, e, nrhs, s);
+    }
     LQ_HIP(hipEventRecord(t1, s));
     LQ_HIP(hipEventSynchronize(t1));
     check_launch();

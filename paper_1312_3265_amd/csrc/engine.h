@@ -111,7 +111,7 @@ struct Engine {
   int window = 0;             // XCD window of the CG stencils' block order (autotuned)
   // device
   double2 *b = nullptr, *xhi = nullptr, *rhi = nullptr, *t64 = nullptr;
-  void *xlo = nullptr, *rlo = nullptr, *p = nullptr, *t = nullptr;
+  void *xlo = nullptr, *rlo = nullptr, *p = nullptr, *p1 = nullptr, *t = nullptr;  // p, p1: p_k by parity
   double *part_t = nullptr, *part_r = nullptr, *part_u = nullptr;
   SlotState* st = nullptr;
   int* mask = nullptr;        // per-slot reliable-update selection

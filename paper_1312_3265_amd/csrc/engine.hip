@@ -115,7 +115,7 @@ std::string tune_key(const Geom& g, int op, int prec, int nl, int nslots) {
   LQ_HIP(hipGetDevice(&dev));
   LQ_HIP(hipGetDeviceProperties(&prop, dev));
   std::ostringstream key;
-  key << "v7:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
+  key << "v8:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
       << ":op" << op << ":p" << prec << ":l" << nl << ":n" << nslots;
   std::string k = key.str();
   for (auto& ch : k) if (ch == ' ') ch = '_';
@@ -155,7 +155,7 @@ void Engine::tune(hipStream_t s) {
   f.state_mode = 0;
   f.part = part_r;
   f.part_in = part_t;
-  f.x = xlo; f.r = rlo; f.p = p;
+  f.x = xlo; f.r = rlo; f.p = p; f.pprev = p1;
   hipEvent_t t0, t1;
   LQ_HIP(hipEventCreate(&t0));
   LQ_HIP(hipEventCreate(&t1));
@@ -170,9 +170,11 @@ void Engine::tune(hipStream_t s) {
       launch_stencil(op, prec_lo, nl_lo, true, EPI_CG_UPDATE, oa, t, f, nslots, s);
       LQ_HIP(hipEventRecord(t0, s));
       for (int r = 0; r < 4; ++r) {
+        e.par = f.par = r & 1;   // odd iterations also advance x
         launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
         launch_stencil(op, prec_lo, nl_lo, true, EPI_CG_UPDATE, oa, t, f, nslots, s);
       }
+      e.par = f.par = 0;
       LQ_HIP(hipEventRecord(t1, s));
       LQ_HIP(hipEventSynchronize(t1));
       check_launch();
@@ -202,7 +204,7 @@ size_t Engine::workspace_bytes(const Geom& g, int formulation, const lq_solve_op
   c.take(vhi); c.take(vhi); c.take(vhi);      // b, x_hi, r_hi
   if (prec != P64) c.take(vhi);               // t64 (shares t when FP64)
   const size_t vx = (size_t)nslots * nc * g.Vp * store_bytes(prec == P16 ? P32 : prec);
-  c.take(vx); c.take(vlo); c.take(vlo); c.take(vlo);    // x_lo (FP32 under Q16), r_lo, p, t
+  c.take(vx); c.take(vlo); c.take(vlo); c.take(vlo); c.take(vlo);   // x_lo, r_lo, p (x2), t
   for (int k = 0; k < 3; ++k) c.take((size_t)nslots * nbp * sizeof(double));
   c.take((size_t)nslots * sizeof(SlotState));
   c.take((size_t)nslots * sizeof(int));
@@ -250,6 +252,7 @@ void Engine::init(const lq_gauge_s* g, int form, int g55, double rr, int ns,
   xlo = c.take((size_t)ns * nc * g->g.Vp * store_bytes(prec_lo == P16 ? P32 : prec_lo));
   rlo = c.take(vlo);
   p = c.take(vlo);
+  p1 = c.take(vlo);
   t = c.take(vlo);
   if (prec_lo == P64) t64 = (double2*)t;
   part_t = (double*)c.take((size_t)ns * nbp * sizeof(double));
@@ -329,7 +332,7 @@ void Engine::load(int slot, const void* chi, double mass, double tol, int maxite
                       1, s);
   const double ncomp = (double)nc * g.V;
   launch_ru_finish(st, nullptr, part_u, nbp, slot, 1, ncomp, prec_lo != P64, max_cand, 1, 0, s);
-  launch_ru_convert(prec_lo, nc, g, st, nullptr, (const double*)rhi, rlo, p, part_u, nbp, 1, slot,
+  launch_ru_convert(prec_lo, nc, g, st, nullptr, (const double*)rhi, rlo, p, p1, part_u, nbp, 1, slot,
                     1, s);
   launch_ru_commit(st, nullptr, part_u, nbp, slot, 1, s);
   check_launch();
@@ -338,9 +341,13 @@ void Engine::load(int slot, const void* chi, double mass, double tol, int maxite
 }
 
 void Engine::enqueue_iterations(int n, hipStream_t s) {
+  // n is even: a chunk starts and ends with p_k in buffer p; x advances on
+  // the odd iterations by both steps of the pair
   const OpArgs oa = op_args(prec_lo, nl_lo);
   for (int it = 0; it < n; ++it) {
     const int par = it & 1;
+    void* pk = par ? p1 : p;       // p_k
+    void* po = par ? p : p1;       // p_{k-1} on odd iterations; receives p_{k+1}
     EpiArgs e = epi_base();
     e.par = par;
     e.state_mode = 1;
@@ -348,7 +355,7 @@ void Engine::enqueue_iterations(int n, hipStream_t s) {
     e.part = part_t;
     e.rhs_per_thread = rhs_per_thread;
     e.window = window;
-    launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
+    launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, pk, e, nslots, s);
     EpiArgs f = epi_base();
     f.rhs_per_thread = rhs_per_thread;
     f.window = window;
@@ -356,9 +363,9 @@ void Engine::enqueue_iterations(int n, hipStream_t s) {
     f.state_mode = 1;
     f.part = part_r;
     f.part_in = part_t;
-    f.x = xlo; f.r = rlo; f.p = p;
+    f.x = xlo; f.r = rlo; f.p = pk; f.pprev = po;
     launch_stencil(op, prec_lo, nl_lo, true, EPI_CG_UPDATE, oa, t, f, nslots, s);
-    launch_p_update(prec_lo, nc, gauge->g, st, par, part_r, nbp, p, rlo, 0, nslots, s);
+    launch_p_update(prec_lo, nc, gauge->g, st, par, part_r, nbp, pk, po, rlo, 0, nslots, s);
   }
 }
 
@@ -367,7 +374,7 @@ void Engine::enqueue_reliable_update(hipStream_t s) {
   const int nl64 = gauge->fp64_links();
   const OpArgs oa = op_args(P64, nl64);
   LQ_HIP(hipMemcpyAsync(mask, hmask, sizeof(int) * nslots, hipMemcpyHostToDevice, s));
-  launch_ru_accumulate(prec_lo, nc, g, st, mask, (double*)xhi, xlo, nbp, 0, nslots, s);
+  launch_ru_accumulate(prec_lo, nc, g, st, mask, (double*)xhi, xlo, p, nbp, 0, nslots, s);
   EpiArgs e = epi_base();
   e.state_mode = 2;
   e.ru_mask = mask;
@@ -382,7 +389,7 @@ void Engine::enqueue_reliable_update(hipStream_t s) {
   launch_stencil(op, P64, nl64, true, EPI_RESID, oa, t64, f, nslots, s);
   launch_ru_finish(st, mask, part_u, nbp, 0, nslots, (double)nc * g.V, prec_lo != P64, max_cand, 0,
                    0, s);
-  launch_ru_convert(prec_lo, nc, g, st, mask, (const double*)rhi, rlo, p, part_u, nbp, 0, 0, nslots,
+  launch_ru_convert(prec_lo, nc, g, st, mask, (const double*)rhi, rlo, p, p1, part_u, nbp, 0, 0, nslots,
                     s);
   launch_ru_commit(st, mask, part_u, nbp, 0, nslots, s);
   check_launch();

@@ -43,8 +43,8 @@ constexpr double kGrowth2 = 1e4;   // squared residual growth that forces a reli
 template <class P, int NC>
 __global__ void __launch_bounds__(256)
 p_update_kernel(const Geom g, SlotState* st, int par, const double* __restrict__ part, int nbp,
-                typename P::S* __restrict__ p, const typename P::S* __restrict__ r, int k0,
-                int nrhs) {
+                const typename P::S* __restrict__ p, typename P::S* __restrict__ pout,
+                const typename P::S* __restrict__ r, int k0, int nrhs) {
   using C = typename P::C;
   using R = typename P::R;
   __shared__ double red[16];
@@ -76,7 +76,7 @@ p_update_kernel(const Geom g, SlotState* st, int par, const double* __restrict__
       pv[q].x = rv[q].x + bt * pv[q].x;
       pv[q].y = rv[q].y + bt * pv[q].y;
     }
-    st_site<P, NC>(p + off, g.Vp, i, pv);
+    st_site<P, NC>(pout + off, g.Vp, i, pv);
   }
   if (sb == 0 && threadIdx.x == 0) {
     const double rmax = fmax(s->rho_max, rr);
@@ -98,6 +98,9 @@ p_update_kernel(const Geom g, SlotState* st, int par, const double* __restrict__
     }
     if (s->iter >= s->maxiter) { s->flags |= 2; stop = 1; }
     s->stop[par ^ 1] = stop;
+    // x is advanced on odd iterations; stopping after an even one leaves
+    // alpha[0] * p (buffer 0) for the reliable update to add
+    if (stop) s->pend = (par == 0);
   }
 }
 
@@ -105,7 +108,8 @@ p_update_kernel(const Geom g, SlotState* st, int par, const double* __restrict__
 template <class P, int NC>
 __global__ void __launch_bounds__(256)
 ru_accumulate_kernel(const Geom g, const SlotState* st, const int* mask, double2* __restrict__ xhi,
-                     typename XPol<P>::type::S* __restrict__ xlo, int nbp, int k0, int nrhs) {
+                     typename XPol<P>::type::S* __restrict__ xlo,
+                     const typename P::S* __restrict__ p0, int nbp, int k0, int nrhs) {
   using XP = typename XPol<P>::type;
   using C = typename XP::C;
   int sb, kl;
@@ -113,17 +117,23 @@ ru_accumulate_kernel(const Geom g, const SlotState* st, const int* mask, double2
   const int k = k0 + kl;
   if (!ru_selected(st, mask, k)) return;
   const double sc = st[k].scale;
+  const bool pend = st[k].pend != 0;
+  const double a0 = st[k].alpha[0];
   const int i = sb * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
   const size_t off = (size_t)k * NC * g.Vp;
   C v[NC], z[NC];
+  typename P::C pv[NC];
   ld_site<XP, NC>(xlo + off, g.Vp, i, v);
+  if (pend) ld_site<P, NC>(p0 + (size_t)k * field_planes<P>(NC) * g.Vp, g.Vp, i, pv);
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
     const size_t e = off + (size_t)q * g.Vp + i;
     double2 h = xhi[e];
-    h.x += sc * (double)v[q].x;
-    h.y += sc * (double)v[q].y;
+    double vx = (double)v[q].x, vy = (double)v[q].y;
+    if (pend) { vx += a0 * (double)pv[q].x; vy += a0 * (double)pv[q].y; }
+    h.x += sc * vx;
+    h.y += sc * vy;
     xhi[e] = h;
     z[q] = czero<C>();
   }
@@ -168,8 +178,8 @@ template <class P, int NC>
 __global__ void __launch_bounds__(256)
 ru_convert_kernel(const Geom g, const SlotState* st, const int* mask,
                   const double2* __restrict__ rhi, typename P::S* __restrict__ rlo,
-                  typename P::S* __restrict__ p, double* __restrict__ part, int nbp, int init,
-                  int k0, int nrhs) {
+                  typename P::S* __restrict__ p, const typename P::S* __restrict__ p1,
+                  double* __restrict__ part, int nbp, int init, int k0, int nrhs) {
   using C = typename P::C;
   using R = typename P::R;
   __shared__ double red[16];
@@ -197,8 +207,10 @@ ru_convert_kernel(const Geom g, const SlotState* st, const int* mask,
       ld_site<P, NC>(rlo + off, g.Vp, i, vs);   // p starts as the stored r
       st_site<P, NC>(p + off, g.Vp, i, vs);
     } else {
+      // the current search direction: buffer 1 when the system stopped after
+      // an even iteration, else buffer 0; the next chunk starts in buffer 0
       C pv[NC];
-      ld_site<P, NC>(p + off, g.Vp, i, pv);
+      ld_site<P, NC>((st[k].pend ? p1 : p) + off, g.Vp, i, pv);
 #pragma unroll
       for (int q = 0; q < NC; ++q) { pv[q].x *= pr; pv[q].y *= pr; }
       st_site<P, NC>(p + off, g.Vp, i, pv);
@@ -220,6 +232,7 @@ __global__ void ru_commit_kernel(SlotState* st, const int* mask, const double* _
   s->rho_ru = rr;
   s->rho_max = rr;
   s->stop[0] = s->stop[1] = 0;
+  s->pend = 0;
   s->iter_res2 = rr * s->scale * s->scale;
 }
 
@@ -260,21 +273,24 @@ load_prepare_kernel(const Geom g, double2* __restrict__ xhi,
   } while (0)
 
 void launch_p_update(int prec, int nc, const Geom& g, SlotState* st, int par, const double* part,
-                     int nbp, void* p, const void* r, int k0, int nrhs, hipStream_t s) {
+                     int nbp, const void* p, void* pout, const void* r, int k0, int nrhs,
+                     hipStream_t s) {
   if (nbp * nrhs == 0) return;
   LQ_PREC_NC_SWITCH(prec, nc,
                     hipLaunchKernelGGL((p_update_kernel<PP, NCC>), dim3(nbp * nrhs), dim3(kBlock),
-                                       0, s, g, st, par, part, nbp, (typename PP::S*)p,
-                                       (const typename PP::S*)r, k0, nrhs));
+                                       0, s, g, st, par, part, nbp, (const typename PP::S*)p,
+                                       (typename PP::S*)pout, (const typename PP::S*)r, k0, nrhs));
 }
 
 void launch_ru_accumulate(int prec, int nc, const Geom& g, const SlotState* st, const int* mask,
-                          double* xhi, void* xlo, int nbp, int k0, int nrhs, hipStream_t s) {
+                          double* xhi, void* xlo, const void* p0, int nbp, int k0, int nrhs,
+                          hipStream_t s) {
   if (nbp * nrhs == 0) return;
   LQ_PREC_NC_SWITCH(prec, nc,
                     hipLaunchKernelGGL((ru_accumulate_kernel<PP, NCC>), dim3(nbp * nrhs),
                                        dim3(kBlock), 0, s, g, st, mask, (double2*)xhi,
-                                       (typename XPol<PP>::type::S*)xlo, nbp, k0, nrhs));
+                                       (typename XPol<PP>::type::S*)xlo,
+                                       (const typename PP::S*)p0, nbp, k0, nrhs));
 }
 
 void launch_ru_finish(SlotState* st, const int* mask, const double* part, int nbp, int k0,
@@ -286,14 +302,14 @@ void launch_ru_finish(SlotState* st, const int* mask, const double* part, int nb
 }
 
 void launch_ru_convert(int prec, int nc, const Geom& g, const SlotState* st, const int* mask,
-                       const double* rhi, void* rlo, void* p, double* part, int nbp, int init,
-                       int k0, int nrhs, hipStream_t s) {
+                       const double* rhi, void* rlo, void* p, const void* p1, double* part, int nbp,
+                       int init, int k0, int nrhs, hipStream_t s) {
   if (nbp * nrhs == 0) return;
   LQ_PREC_NC_SWITCH(prec, nc,
                     hipLaunchKernelGGL((ru_convert_kernel<PP, NCC>), dim3(nbp * nrhs),
                                        dim3(kBlock), 0, s, g, st, mask, (const double2*)rhi,
-                                       (typename PP::S*)rlo, (typename PP::S*)p, part, nbp, init,
-                                       k0, nrhs));
+                                       (typename PP::S*)rlo, (typename PP::S*)p,
+                                       (const typename PP::S*)p1, part, nbp, init, k0, nrhs));
 }
 
 void launch_ru_commit(SlotState* st, const int* mask, const double* part, int nbp, int k0,

@@ -22,16 +22,18 @@ void launch_stencil(int op, int prec, int nl, bool dag, int epi, const OpArgs& o
 
 // ---- CG vector kernels (templated on precision and components)
 void launch_p_update(int prec, int nc, const Geom& g, SlotState* st, int par, const double* part,
-                     int nbp, void* p, const void* r, int k0, int nrhs, hipStream_t s);
+                     int nbp, const void* p, void* pout, const void* r, int k0, int nrhs,
+                     hipStream_t s);
 // Reliable-update kernels act on running slots k with mask[k] != 0 (mask may be null).
 void launch_ru_accumulate(int prec, int nc, const Geom& g, const SlotState* st, const int* mask,
-                          double* xhi, void* xlo, int nbp, int k0, int nrhs, hipStream_t s);
+                          double* xhi, void* xlo, const void* p0, int nbp, int k0, int nrhs,
+                          hipStream_t s);
 void launch_ru_finish(SlotState* st, const int* mask, const double* part, int nbp, int k0,
                       int nrhs, double ncomp, int rescale, int max_cand, int init, int par,
                       hipStream_t s);
 void launch_ru_convert(int prec, int nc, const Geom& g, const SlotState* st, const int* mask,
-                       const double* rhi, void* rlo, void* p, double* part, int nbp, int init,
-                       int k0, int nrhs, hipStream_t s);
+                       const double* rhi, void* rlo, void* p, const void* p1, double* part, int nbp,
+                       int init, int k0, int nrhs, hipStream_t s);
 void launch_ru_commit(SlotState* st, const int* mask, const double* part, int nbp, int k0,
                       int nrhs, hipStream_t s);
 void launch_load_prepare(int prec, int nc, const Geom& g, double* xhi, void* xlo, double* rhi,

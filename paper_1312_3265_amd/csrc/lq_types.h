@@ -25,6 +25,7 @@ struct SlotState {
   double rho_ru;     // ||r_lo||^2 right after the latest reliable update
   double rho_max;    // largest ||r_lo||^2 since the latest reliable update
   double delta2;     // request a reliable update once rho <= delta2 * rho_max (0: never)
+  double alpha[2];   // alpha of the latest iteration of each parity (x is updated in pairs)
   int32_t stop[2];   // ring: 1 = frozen until the next reliable update
   int32_t status;    // 0 empty, 1 running, 2 converged, 3 failed
   int32_t iter;      // CG iterations done
@@ -35,7 +36,7 @@ struct SlotState {
   int32_t apps;      // applications of A (iterations + reliable updates + setup)
   int32_t ru_iter;   // iteration count at the latest reliable update
   int32_t want_ru;   // frozen because the residual dropped by delta (not converged)
-  int32_t pad;
+  int32_t pend;      // frozen after an even iteration: x still lacks alpha[0] * p (buffer 0)
 };
 
 enum SlotStatus { SLOT_EMPTY = 0, SLOT_RUNNING = 1, SLOT_DONE = 2, SLOT_FAILED = 3 };

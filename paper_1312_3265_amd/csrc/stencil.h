@@ -4,10 +4,14 @@
 //   STORE       out = op(in)
 //   STORE_NORM  out = op(in), block partials of ||out||^2          (t = M p)
 //   CG_UPDATE   q = op(in) kept in registers; alpha = rho/||t||^2 from the
-//               partials of the previous launch; x += alpha p, r -= alpha q;
-//               block partials of ||r||^2                          (M^dag t)
-//               (x rides here rather than in the p update: this kernel has
-//               memory bandwidth to spare behind the stencil arithmetic)
+//               partials of the previous launch; r -= alpha q; block
+//               partials of ||r||^2                                 (M^dag t)
+//               x is advanced every second iteration, by both steps at once:
+//               x += alpha_{k-1} p_{k-1} + alpha_k p_k on odd iterations
+//               (p is double-buffered), which halves the traffic of x, the
+//               widest vector of a low-precision solve (FP32 under Q16).
+//               The sum is formed in the arithmetic precision, as the two
+//               single steps would be.
 //   RESID       out = b - op(in), partials of ||out||^2   (FP64 true residual)
 //   LANCZOS     w = op(in) - beta_prev v_prev, partials of Re<v, w>
 // Partial sums are FP64, reduced in a fixed order (wavefront butterfly, then
@@ -39,7 +43,8 @@ struct EpiArgs {
   const int* ru_mask;     // per-RHS reliable-update selection (state_mode 2)
   void* x;                // CG_UPDATE: x_lo
   void* r;                // CG_UPDATE: r_lo
-  const void* p;          // CG_UPDATE: p
+  const void* p;          // CG_UPDATE: p_k
+  const void* pprev;      // CG_UPDATE: p_{k-1} (read on odd iterations)
   const void* b;          // RESID: b (FP64)
   const double* v;        // LANCZOS: v_j
   const double* vprev;    // LANCZOS: v_{j-1}
@@ -161,23 +166,31 @@ __device__ __forceinline__ void site_epilogue(const OpArgs& oa, const EpiArgs& e
         const double n2 = st_site<typename Op::Pol, NC>((S*)ea.out + off, Vp, i, o[kk]);
         if constexpr (EPI == EPI_STORE_NORM) acc = n2;
       } else if constexpr (EPI == EPI_CG_UPDATE) {
-        using XP = typename XPol<typename Op::Pol>::type;
-        typename XP::S* x = (typename XP::S*)ea.x + (size_t)k * NC * Vp;
         S* r = (S*)ea.r + off;
-        const S* p = (const S*)ea.p + off;
         const R a = (R)alpha[kk];
-        P_C pv[NC], rv[NC];
-        typename XP::C xv[NC];
-        ld_site<typename Op::Pol, NC>(p, Vp, i, pv);
+        P_C rv[NC];
         ld_site<typename Op::Pol, NC>(r, Vp, i, rv);
-        ld_site<XP, NC>(x, Vp, i, xv);
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
-          xv[q].x += a * pv[q].x; xv[q].y += a * pv[q].y;
           rv[q].x -= a * o[kk][q].x; rv[q].y -= a * o[kk][q].y;
         }
-        st_site<XP, NC>(x, Vp, i, xv);
         acc = st_site<typename Op::Pol, NC>(r, Vp, i, rv);
+        if (ea.par == 1) {   // wavefront-uniform
+          using XP = typename XPol<typename Op::Pol>::type;
+          typename XP::S* x = (typename XP::S*)ea.x + (size_t)k * NC * Vp;
+          const R a0 = (R)ea.st[k].alpha[0];
+          P_C pv[NC], qv[NC];
+          typename XP::C xv[NC];
+          ld_site<typename Op::Pol, NC>((const S*)ea.pprev + off, Vp, i, qv);
+          ld_site<typename Op::Pol, NC>((const S*)ea.p + off, Vp, i, pv);
+          ld_site<XP, NC>(x, Vp, i, xv);
+#pragma unroll
+          for (int q = 0; q < NC; ++q) {
+            xv[q].x += a0 * qv[q].x; xv[q].y += a0 * qv[q].y;
+            xv[q].x += a * pv[q].x; xv[q].y += a * pv[q].y;
+          }
+          st_site<XP, NC>(x, Vp, i, xv);
+        }
       } else if constexpr (EPI == EPI_RESID) {
         double2* out = (double2*)ea.out + off;
         const double2* b = (const double2*)ea.b + off;
@@ -253,7 +266,10 @@ stencil_kernel(const OpArgs oa, const typename Op::S* __restrict__ in, const Epi
       const double tt = sum_partials(ea.part_in + (size_t)k * ea.nbp, ea.nbp, red);
       const double rho = ea.st[k].rho[ea.par];
       alpha[kk] = (tt > 0.0 && isfinite(tt) && isfinite(rho)) ? rho / tt : 0.0;
-      if (!(tt > 0.0 && isfinite(tt)) && sb == 0 && threadIdx.x == 0) ea.st[k].flags |= 1;
+      if (sb == 0 && threadIdx.x == 0) {
+        if (!(tt > 0.0 && isfinite(tt))) ea.st[k].flags |= 1;
+        ea.st[k].alpha[ea.par] = alpha[kk];   // read by the next (odd) iteration
+      }
     }
   }
 
