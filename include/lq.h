@@ -121,7 +121,8 @@ typedef struct {
                                  12-real links, 18 = FP32 18-real links (needs
                                  LQ_FEAT_F32 on the gauge field)                 */
   int32_t reliable_interval;  /* iterations between FP64 reliable updates
-                                 (0 = default 64; unused for F64)                */
+                                 (0 = default 256: the residual triggers do most
+                                 of the work; unused for F64)                    */
   int32_t poll_interval;      /* iterations between host convergence polls
                                  (0 = default 16; rounded up to even)            */
   int32_t use_graph;          /* 1 = replay steady iteration chunks as hipGraphs */

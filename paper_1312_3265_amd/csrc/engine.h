@@ -104,7 +104,7 @@ struct Engine {
   double r = 1.0;
   int nslots = 0;
   int prec_lo = P64, nl_lo = 18;
-  int reliable_interval = 64, poll_every = 16, use_graph = 0, max_cand = 50;
+  int reliable_interval = 256, poll_every = 16, use_graph = 0, max_cand = 50;
   double delta = 0.0;
   int nbp = 0;
   int rhs_per_thread = 1;     // systems per thread of the CG stencils (autotuned)
