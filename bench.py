@@ -188,6 +188,64 @@ def summarize_profile(a, trace, fetch, write, cfetch, cwrite):
     print(json.dumps(out, indent=1))
 
 
+SERVING_DIMS = [(8, 8, 8, 16), (16, 16, 16, 32), (24, 24, 24, 48), (32, 32, 32, 64)]
+
+
+def serving(a, w):
+    """Continuous batching: requests drawn over four lattice sizes (one
+    resident near-identity field each, same spread as the workload), both
+    formulations, delta in {0.02, 0.05, 0.1} above the workload's m_c, point
+    or Z2 sources, tolerances log-uniform in [1e-10, 1e-6].  First all
+    requests at once (capacity, solves/s), then Poisson arrivals at 50% and
+    90% of that rate; p50/p99 latency from arrival to result."""
+    import numpy as np
+    import paper_1312_3265_amd as lq
+    import synth
+    from paper_1312_3265_amd import serve
+
+    eps = w["eps"]
+    mc = {0: w["m_c"]["wilson"], 1: w["m_c"]["staggered_wilson"]}
+    fields = {d: synth.gauge_field(d, "near_identity", 3000 + i, eps)
+              for i, d in enumerate(SERVING_DIMS)}
+    descs = synth.serving_requests(a.serving_requests, seed=42, dims_choices=SERVING_DIMS,
+                                   tol_range=(1e-10, 1e-6))
+    sources = []
+    for d in descs:
+        f = d["formulation"]
+        sources.append(synth.point_source(d["dims"], f, d["alpha"]) if d["source"] == "point"
+                       else synth.z2_source(d["dims"], f, d["source_seed"]))
+    opts = lq.solve_opts(precision=lq.Q16, links=12, poll_interval=16)
+
+    def run(arrivals):
+        reqs = [serve.Request(d["id"], d["dims"], d["formulation"], mc[d["formulation"]] + d["delta"],
+                              src, d["tol"], arrival=float(t), maxiter=20000)
+                for d, src, t in zip(descs, sources, arrivals)]
+        srv = serve.SolveServer(fields, opts=opts, mem_budget=96 << 30, slots=8, chunk=16)
+        results = srv.run(reqs)
+        rep = srv.report()
+        rep.pop("groups", None)
+        byid = {d["id"]: d for d in descs}
+        rep["not_converged"] = [
+            dict(dims=list(byid[r.id]["dims"]), formulation=byid[r.id]["formulation"],
+                 delta=byid[r.id]["delta"], tol=byid[r.id]["tol"], status=r.info["status"],
+                 iterations=r.info["iterations"], true_residual=r.info["true_residual"])
+            for r in results if r.info["status"] != 0]
+        return rep
+
+    log("serving: warm-up (tuning every group)")
+    run([0.0] * len(descs))
+    cap = run([0.0] * len(descs))
+    log(f"serving: capacity {cap['solves_per_s']:.2f} solves/s")
+    out = {"requests": len(descs), "dims": [list(d) for d in SERVING_DIMS], "storage": "q16",
+           "capacity": cap}
+    for frac in (0.5, 0.9):
+        rate = frac * cap["solves_per_s"]
+        out[f"offered_{int(frac * 100)}pct"] = dict(
+            offered_per_s=rate, **run(synth.poisson_arrivals(rate=rate, n=len(descs), seed=43)))
+        log(f"serving: {int(frac * 100)}% done")
+    return out
+
+
 def cpu_baseline(U, workload, iters_fp64):
     """The oracle, timed on the host on a bounded sample: a few CG iterations
     of each formulation at the delta = 0.1 mass, single-threaded BLAS."""
@@ -247,6 +305,10 @@ def main():
     ap.add_argument("--window", type=int, default=0, help="with --roofline-only")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy five times (counter calibration)")
+    ap.add_argument("--serving", action="store_true",
+                    help="only the continuous-batching measurement: Poisson arrivals over four "
+                         "lattice sizes at 50%% and 90%% of the measured capacity")
+    ap.add_argument("--serving-requests", type=int, default=64)
     ap.add_argument("--summarize-profile", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "CFETCH", "CWRITE"),
                     help="write the profile summary of the dominant stencil from rocprofv3 output "
                          "directories (kernel trace, FETCH_SIZE, WRITE_SIZE of --roofline-only; "
@@ -276,6 +338,9 @@ def main():
         return
 
     w = load_workload()
+    if a.serving:
+        print(json.dumps({"serving": serving(a, w)}), flush=True)
+        return
     dims = tuple(w["dims"])
     eps = w["eps"]
     mc = w["m_c"]

@@ -92,6 +92,7 @@ struct F32 {
 // matrix and of an average of products of SU(3) matrices is at most 1 in
 // modulus.  Arithmetic is FP32.
 constexpr float kQ16 = 32767.0f;
+constexpr float kQ16MinScale = 1e-30f;   // smallest site scale kept (see st_site)
 __device__ __forceinline__ short q16_round(float v) {
   return (short)max(-32767, min(32767, __float2int_rn(v)));
 }
@@ -360,6 +361,11 @@ __device__ __forceinline__ double st_site(typename P::S* __restrict__ f, int Vp,
     float m = 0.0f;
 #pragma unroll
     for (int q = 0; q < NC; ++q) m = fmaxf(m, fmaxf(fabsf(v[q].x), fabsf(v[q].y)));
+    // a site whose largest component is below kQ16MinScale (far below the
+    // per-system normalisation of the Krylov vectors, e.g. the exponential
+    // tail of a point source several dozen hops out) is stored as zero: its
+    // reciprocal would overflow FP32 and poison the site with inf and NaN
+    if (!(m >= kQ16MinScale)) m = 0.0f;
     const float inv = m > 0.0f ? kQ16 / m : 0.0f;
     const float s = m * (1.0f / kQ16);
     float sq = 0.0f;   // sum of the squared stored integers (exact up to FP32 rounding)

@@ -109,6 +109,25 @@ def test_low_precision_matvec_within_roundoff(formulation, g55, precision, links
     assert _relerr(out, ref) <= bound
 
 
+def test_q16_handles_vanishing_and_denormal_sites():
+    """Sites whose largest component is zero, FP32-denormal or tiny (the far
+    tail of a point-source solution on a large lattice) must not turn into inf
+    or NaN in 16-bit storage: they are stored as zero, far below the
+    rounding of the O(1) sites."""
+    dims = (6, 4, 6, 8)
+    U, lat, g = _gauge(dims, "near_identity", 21, eps=0.436)
+    psi = synth.gaussian_field(dims, synth.WILSON, 7).astype(np.complex64)
+    flat = psi.reshape(-1, 12)
+    flat[0] = 0.0
+    flat[1] = 1e-40      # FP32 denormal
+    flat[2] = 3e-39
+    flat[3] = 1e-33
+    out = lq.apply(g, synth.WILSON, 0.1, psi, op=lq.OP_M, precision=lq.Q16, links=12)
+    assert torch.isfinite(torch.view_as_real(out)).all()
+    ref = _oracle_apply(synth.WILSON, U, psi.astype(np.complex128), 0.1, lq.OP_M)
+    assert _relerr(out.cpu().numpy(), ref) <= 1e-4
+
+
 def test_fp64_matvec_full_size_16x32():
     """16^3 x 32 near-identity field: the whole field against the oracle."""
     dims = (16, 16, 16, 32)
