@@ -97,11 +97,12 @@ def stored_traffic(storage, links, cfg):
     except OSError:
         return None
     if (p.get("source_sha256") != stencil_source_hash() or p.get("storage") != storage
-            or p.get("links") != links
-            or p.get("rhs_per_thread") != cfg[0] or p.get("window") != cfg[1]
+            or p.get("links") != links or p.get("rhs_per_thread") != cfg[0]
             or p.get("nrhs") != NRHS_W):
-        return None
-    return p["fetch_bytes_per_launch"] + p["write_bytes_per_launch"]
+        return None, None
+    # the block order may differ from the one the autotuner picked on this
+    # GPU; the counters' own is reported beside the figure
+    return p["fetch_bytes_per_launch"] + p["write_bytes_per_launch"], p.get("window")
 
 
 def roofline(lq, g0, lat, mc, prec, links, storage, cfg, stream, reps=50):
@@ -121,9 +122,11 @@ def roofline(lq, g0, lat, mc, prec, links, storage, cfg, stream, reps=50):
     achieved = algo / (ms * 1e-3) / 1e9
     ms0, per0, algo0 = out[0]
     pol = "Q16" if prec == lq.Q16 else "F32"
+    traffic, traffic_window = stored_traffic(storage, links, cfg)
     return {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(storage, links, cfg),
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "traffic_counters_window": traffic_window,
         "kernel": (f"stencil_kernel<WilsonOpR1<{pol}, {links}, true>, CG_UPDATE, K={K}>: "
                    f"q = M^dag t, r -= alpha q, ||r||^2, x += alpha' p' + alpha p every "
                    f"other launch; {NRHS_W} systems; average of the pair"),
