@@ -289,6 +289,7 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     // and arithmetic)
     const int epi = kernel == 0 ? EPI_STORE_NORM : kernel == 1 ? EPI_STORE : EPI_CG_UPDATE;
     if (kernel == 2) {
+      e.stream = stream_cg_vectors(g->g, precision, nc, nrhs);
       e.r = r;
       e.x = xlo;
       e.p = b;

@@ -57,6 +57,18 @@ inline int field_planes_host(int prec, int nc) { return nc + (prec == P16 ? 1 : 
 inline size_t field_bytes(const Geom& g, int prec, int nc) {
   return (size_t)field_planes_host(prec, nc) * g.Vp * store_bytes(prec);
 }
+// Whether the second stencil of a low-precision CG iteration streams its
+// per-system vectors (non-temporal r, p_k, p_{k-1}, x): when those plus t
+// exceed the last-level cache (256 MiB of Infinity Cache on MI355X) none of
+// them survives to the next kernel anyway, and streaming keeps the links and
+// the stencil input in L2; below it they stay cached for the kernels that
+// follow.  FP64 kernels always cache.
+constexpr size_t kLastLevelCache = size_t(256) << 20;
+inline int stream_cg_vectors(const Geom& g, int prec, int nc, int nrhs) {
+  if (prec == P64) return 0;
+  const size_t x = (size_t)nc * g.Vp * store_bytes(prec == P16 ? P32 : prec);
+  return (size_t)nrhs * (4 * field_bytes(g, prec, nc) + x) > kLastLevelCache;
+}
 inline int ncomp_of(int formulation) { return formulation == LQ_WILSON ? 12 : 3; }
 inline int opkind(int formulation, int g55) {
   if (formulation == LQ_WILSON) return OP_WILSON;

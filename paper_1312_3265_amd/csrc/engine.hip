@@ -295,6 +295,7 @@ EpiArgs Engine::epi_base() const {
   std::memset(&e, 0, sizeof(e));
   e.nbp = nbp;
   e.st = st;
+  e.stream = stream_cg_vectors(gauge->g, prec_lo, nc, nslots);
   return e;
 }
 

@@ -52,6 +52,7 @@ struct EpiArgs {
   int rhs_per_thread;     // systems per thread (1, 2 or 4; FP32/Q16 CG kernels)
   int window;             // block order: > 0 window width, 0 whole range, -1/-2 system-major,
                           // -3/-4 tiled (map_block, map_block_tiled)
+  int stream;             // CG_UPDATE, FP32/Q16: 1 = r, p, x loaded and stored non-temporal
 };
 
 // blockIdx.x -> (site block sb, rhs k), XCD-aware.  Block b runs on XCD b % 8,
@@ -141,10 +142,53 @@ __device__ __forceinline__ bool slot_active(const SlotState* st, int k, int mode
 template <class Op, int K>
 constexpr int stencil_waves() { return (Op::NC == 12 && K >= 4) ? 3 : Op::kWaves; }
 
+// CG_UPDATE at one site for system k (offset off into the batched fields):
+// r -= alpha q with ||r||^2 returned, and on odd iterations
+// x += alpha_prev p_{k-1} + alpha p_k.  r, p and x are each touched once per
+// launch; CP = kStream marks them non-temporal so that, when the batch's
+// vectors overflow the caches anyway, they do not displace the links and the
+// stencil input from L2.
+template <class Op, int CP>
+__device__ __forceinline__ double cg_update_site(const EpiArgs& ea, int Vp, int k, size_t off,
+                                                 int i, double alpha,
+                                                 const typename Op::C q[Op::NC]) {
+  using P_C = typename Op::C;
+  using R = typename Op::R;
+  using S = typename Op::S;
+  using Pol = typename Op::Pol;
+  constexpr int NC = Op::NC;
+  S* r = (S*)ea.r + off;
+  const R a = (R)alpha;
+  P_C rv[NC];
+  ld_site<Pol, NC, CP>(r, Vp, i, rv);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    rv[c].x -= a * q[c].x; rv[c].y -= a * q[c].y;
+  }
+  const double n2 = st_site<Pol, NC, CP>(r, Vp, i, rv);
+  if (ea.par == 1) {   // wavefront-uniform
+    using XP = typename XPol<Pol>::type;
+    typename XP::S* x = (typename XP::S*)ea.x + (size_t)k * NC * Vp;
+    const R a0 = (R)ea.st[k].alpha[0];
+    P_C pv[NC], qv[NC];
+    typename XP::C xv[NC];
+    ld_site<Pol, NC, CP>((const S*)ea.pprev + off, Vp, i, qv);
+    ld_site<Pol, NC, CP>((const S*)ea.p + off, Vp, i, pv);
+    ld_site<XP, NC, CP>(x, Vp, i, xv);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      xv[c].x += a0 * qv[c].x; xv[c].y += a0 * qv[c].y;
+      xv[c].x += a * pv[c].x; xv[c].y += a * pv[c].y;
+    }
+    st_site<XP, NC, CP>(x, Vp, i, xv);
+  }
+  return n2;
+}
+
 // The epilogue of one site for the K systems of a thread (see the header of
 // this file), with the block partial of the site block sb.  Every thread of
 // the block must call it (block_sum synchronises the block).
-template <class Op, int EPI, int K>
+template <class Op, int EPI, int K, int CP>
 __device__ __forceinline__ void site_epilogue(const OpArgs& oa, const EpiArgs& ea, int k0,
                                               unsigned act, int i, bool valid, int sb,
                                               const typename Op::C o[K][Op::NC],
@@ -166,31 +210,7 @@ __device__ __forceinline__ void site_epilogue(const OpArgs& oa, const EpiArgs& e
         const double n2 = st_site<typename Op::Pol, NC>((S*)ea.out + off, Vp, i, o[kk]);
         if constexpr (EPI == EPI_STORE_NORM) acc = n2;
       } else if constexpr (EPI == EPI_CG_UPDATE) {
-        S* r = (S*)ea.r + off;
-        const R a = (R)alpha[kk];
-        P_C rv[NC];
-        ld_site<typename Op::Pol, NC>(r, Vp, i, rv);
-#pragma unroll
-        for (int q = 0; q < NC; ++q) {
-          rv[q].x -= a * o[kk][q].x; rv[q].y -= a * o[kk][q].y;
-        }
-        acc = st_site<typename Op::Pol, NC>(r, Vp, i, rv);
-        if (ea.par == 1) {   // wavefront-uniform
-          using XP = typename XPol<typename Op::Pol>::type;
-          typename XP::S* x = (typename XP::S*)ea.x + (size_t)k * NC * Vp;
-          const R a0 = (R)ea.st[k].alpha[0];
-          P_C pv[NC], qv[NC];
-          typename XP::C xv[NC];
-          ld_site<typename Op::Pol, NC>((const S*)ea.pprev + off, Vp, i, qv);
-          ld_site<typename Op::Pol, NC>((const S*)ea.p + off, Vp, i, pv);
-          ld_site<XP, NC>(x, Vp, i, xv);
-#pragma unroll
-          for (int q = 0; q < NC; ++q) {
-            xv[q].x += a0 * qv[q].x; xv[q].y += a0 * qv[q].y;
-            xv[q].x += a * pv[q].x; xv[q].y += a * pv[q].y;
-          }
-          st_site<XP, NC>(x, Vp, i, xv);
-        }
+        acc = cg_update_site<Op, CP>(ea, Vp, k, off, i, alpha[kk], o[kk]);
       } else if constexpr (EPI == EPI_RESID) {
         double2* out = (double2*)ea.out + off;
         const double2* b = (const double2*)ea.b + off;
@@ -227,7 +247,7 @@ __device__ __forceinline__ void site_epilogue(const OpArgs& oa, const EpiArgs& e
   }
 }
 
-template <class Op, int EPI, int K>
+template <class Op, int EPI, int K, int CP>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(stencil_waves<Op, K>(), 8)))
 stencil_kernel(const OpArgs oa, const typename Op::S* __restrict__ in, const EpiArgs ea,
@@ -276,7 +296,7 @@ stencil_kernel(const OpArgs oa, const typename Op::S* __restrict__ in, const Epi
   P_C o[K][NC];
   if (valid) Op::template site_multi<K>(oa, in + (size_t)k0 * rstride, rstride, i, k0, act, o);
 
-  site_epilogue<Op, EPI, K>(oa, ea, k0, act, i, valid, sb, o, alpha, red);
+  site_epilogue<Op, EPI, K, CP>(oa, ea, k0, act, i, valid, sb, o, alpha, red);
 }
 
 }  // namespace lq

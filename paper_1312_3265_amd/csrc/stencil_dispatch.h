@@ -15,6 +15,7 @@
 namespace lq {
 
 // Systems per thread (K) for the low-precision CG kernels; 1 elsewhere.
+// The low-precision CG_UPDATE kernels come in two cache policies (ea.stream).
 template <template <class, int, bool> class OpT, class P, int NL, bool DAG, int EPI, int K>
 static void launch_k(const OpArgs& oa, const void* in, const EpiArgs& ea, int nrhs,
                      hipStream_t s) {
@@ -22,7 +23,14 @@ static void launch_k(const OpArgs& oa, const void* in, const EpiArgs& ea, int nr
   const int ngroups = (nrhs + K - 1) / K;
   const int grid = ea.nbp * ngroups;
   if (grid == 0) return;
-  hipLaunchKernelGGL((stencil_kernel<Op, EPI, K>), dim3(grid), dim3(kBlock), 0, s, oa,
+  if constexpr (EPI == EPI_CG_UPDATE && P::id != 0) {
+    if (ea.stream) {
+      hipLaunchKernelGGL((stencil_kernel<Op, EPI, K, kStream>), dim3(grid), dim3(kBlock), 0, s,
+                         oa, (const typename Op::S*)in, ea, ngroups, nrhs);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((stencil_kernel<Op, EPI, K, 0>), dim3(grid), dim3(kBlock), 0, s, oa,
                      (const typename Op::S*)in, ea, ngroups, nrhs);
 }
 
