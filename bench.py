@@ -65,8 +65,7 @@ def bytes_per_site(formulation, precision, links, nrhs, kernel=0):
     per = {0: 16, 1: 8, 2: 4}[precision]
     vec = nc * per + (4 if precision == 2 else 0)            # Q16: per-site float scale
     xvec = nc * (8 if precision == 2 else per)
-    lper = 8 if (precision == 2 and links == 18) else per    # Q16 with FP32 18-real links
-    link = 4 * (links // 2) * lper                           # FP64: 12 = rows 0, 1 read
+    link = 4 * (links // 2) * per                            # FP64: 12 = rows 0, 1 read
     corner = 0 if formulation == 0 else 8 * 9 * (4 if precision == 2 else per)
     per_rhs = 2 * vec if kernel == 0 else 4 * vec + xvec
     return nrhs * per_rhs + link + corner
@@ -293,7 +292,7 @@ def main():
                     help="storage of the batched CG's stencil and Krylov vectors "
                          "(arithmetic is FP32, reductions and reliable updates FP64)")
     ap.add_argument("--links", type=int, default=12, choices=[12, 18],
-                    help="link storage of the batched stencil: 18 = FP32 18-real, "
+                    help="link storage of the batched stencil (16-bit with q16): 18 = 18-real, "
                          "12 = 12-real in the vector storage")
     ap.add_argument("--fields", type=int, default=8)
     ap.add_argument("--reliable-interval", type=int, default=0,

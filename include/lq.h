@@ -98,7 +98,7 @@ extern "C" {
 /* gauge features: which device copies lq_gauge_create builds */
 #define LQ_FEAT_CORNERS 0x1u  /* corner matrices W_s(x) in every built precision */
 #define LQ_FEAT_F32 0x2u      /* FP32 links, 18-real and 12-real               */
-#define LQ_FEAT_Q16 0x4u      /* 16-bit fixed-point links (12-real) and corners  */
+#define LQ_FEAT_Q16 0x4u      /* 16-bit fixed-point links (12- and 18-real), corners */
 
 typedef struct lq_lattice_s lq_lattice;
 typedef struct lq_gauge_s lq_gauge;
@@ -117,9 +117,8 @@ typedef struct {
 typedef struct {
   int32_t precision;          /* LQ_PREC_*: F64 = plain FP64 CG; F32/Q16 = inner
                                  CG in that storage with FP64 reliable updates   */
-  int32_t links;              /* LQ_LINKS_18 or LQ_LINKS_12; with Q16, 12 = 16-bit
-                                 12-real links, 18 = FP32 18-real links (needs
-                                 LQ_FEAT_F32 on the gauge field)                 */
+  int32_t links;              /* LQ_LINKS_18 or LQ_LINKS_12; with Q16 both are
+                                 16-bit (12 rebuilds row 2 per hop, 18 stores it) */
   int32_t reliable_interval;  /* iterations between FP64 reliable updates
                                  (0 = default 256: the residual triggers do most
                                  of the work; unused for F64)                    */

@@ -124,7 +124,10 @@ int lq_gauge_create(const lq_lattice* lat, const void* U, uint32_t features, voi
       launch_links_convert(P32, 18, g->g, g->u64, g->u32_18, s);
       launch_links_convert(P32, 12, g->g, g->u64, g->u32_12, s);
     }
-    if (features & LQ_FEAT_Q16) launch_links_convert(P16, 12, g->g, g->u64, g->u16_12, s);
+    if (features & LQ_FEAT_Q16) {
+      launch_links_convert(P16, 12, g->g, g->u64, g->u16_12, s);
+      launch_links_convert(P16, 18, g->g, g->u64, g->u16_18, s);
+    }
     if (features & LQ_FEAT_CORNERS) {
       launch_corners(g->g, g->u64, g->c64, s);
       if (features & LQ_FEAT_F32) launch_corners_convert(P32, g->g, g->c64, g->c32, s);

@@ -33,6 +33,7 @@ template <typename C> __device__ __forceinline__ C czero() { C z; z.x = 0; z.y =
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { C z; z.x = a.x + b.x; z.y = a.y + b.y; return z; }
 template <typename C> __device__ __forceinline__ C csub(C a, C b) { C z; z.x = a.x - b.x; z.y = a.y - b.y; return z; }
 template <typename C> __device__ __forceinline__ C cconj(C a) { C z; z.x = a.x; z.y = -a.y; return z; }
+template <typename C> __device__ __forceinline__ C cneg(C a) { C z; z.x = -a.x; z.y = -a.y; return z; }
 // i*a and -i*a
 template <typename C> __device__ __forceinline__ C cmuli(C a) { C z; z.x = -a.y; z.y = a.x; return z; }
 template <typename C> __device__ __forceinline__ C cmulmi(C a) { C z; z.x = a.y; z.y = -a.x; return z; }
@@ -132,13 +133,12 @@ struct Q16L {
 };
 
 // Storage of the links (NL reals) and of the corner matrices used with
-// vectors of policy P.  16-bit vectors take 16-bit 12-real links, or FP32
-// 18-real links: in a batch the links are read once for many systems, so
-// their bytes hardly count, while their conversion and row-2 rebuild are paid
-// per system and hop.
+// vectors of policy P.  16-bit vectors take 16-bit links of 12 or 18 reals:
+// the 18-real form costs 6 more conversions per hop and saves the row-2
+// rebuild (24 multiply-adds per hop), for 48 more bytes per site.
 template <class P, int NL> struct LinkPol { using type = P; };
 template <> struct LinkPol<Q16, 12> { using type = Q16L; };
-template <> struct LinkPol<Q16, 18> { using type = F32; };
+template <> struct LinkPol<Q16, 18> { using type = Q16L; };
 template <class P> struct CornerPol { using type = P; };
 template <> struct CornerPol<Q16> { using type = Q16L; };
 

@@ -38,7 +38,7 @@ __device__ __forceinline__ void bmul(int mu, const C lo0, const C lo1, C& o0, C&
   // (o0, o1) = B_mu (lo0, lo1)
   switch (mu) {
     case 0: o0 = cmuli(lo1); o1 = cmuli(lo0); break;
-    case 1: o0 = cscale(lo1, -1.0f); o1 = lo0; break;
+    case 1: o0 = cneg(lo1); o1 = lo0; break;
     case 2: o0 = cmuli(lo0); o1 = cmulmi(lo1); break;
     default: o0 = lo0; o1 = lo1; break;
   }
@@ -48,7 +48,7 @@ __device__ __forceinline__ void bdmul(int mu, const C h0, const C h1, C& o0, C& 
   // (o0, o1) = B_mu^dag (h0, h1)
   switch (mu) {
     case 0: o0 = cmulmi(h1); o1 = cmulmi(h0); break;
-    case 1: o0 = h1; o1 = cscale(h0, -1.0f); break;
+    case 1: o0 = h1; o1 = cneg(h0); break;
     case 2: o0 = cmulmi(h0); o1 = cmuli(h1); break;
     default: o0 = h0; o1 = h1; break;
   }
@@ -114,6 +114,30 @@ struct WilsonOp {
     }
   }
 
+  // project<MU, TT> of the 16-bit site j, on the stored integers: sums and
+  // differences of two int16 are exact in int32 and convert exactly to FP32,
+  // so h is bitwise what projecting the converted components gives, from 12
+  // conversions instead of 24.  sc = the site's scale.
+  template <int MU, int TT>
+  __device__ __forceinline__ static void project_q16(const S* __restrict__ f, int Vp, int j,
+                                                     C h[2][3], R& sc) {
+    constexpr int BY = vec_rec_bytes<P>(12);
+    uint32_t w[BY / 4];
+    ld_rec<BY>(f, Vp, j, w);
+    sc = __uint_as_float(w[12]) * (1.0f / kQ16);
+    const auto i16x2 = [](uint32_t v) { return make_int2((int)(short)(v & 0xffffu), (int)v >> 16); };
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      int2 b0, b1;
+      bmul(MU, i16x2(w[6 + cc]), i16x2(w[9 + cc]), b0, b1);
+      const int2 u0 = i16x2(w[cc]), u1 = i16x2(w[3 + cc]);
+      const int2 h0 = TT > 0 ? cadd(u0, b0) : csub(u0, b0);
+      const int2 h1 = TT > 0 ? cadd(u1, b1) : csub(u1, b1);
+      h[0][cc] = make_float2((float)h0.x, (float)h0.y);
+      h[1][cc] = make_float2((float)h1.x, (float)h1.y);
+    }
+  }
+
   // acc += f [uh; TT B^dag uh], uh = L h with L = lk (forward) or lk^dag (BACK):
   // the site scale, the link's storage scale and the boundary sign enter as
   // the one factor f of the accumulating multiply-adds.
@@ -164,11 +188,15 @@ struct WilsonOp {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (!((act >> k) & 1)) continue;
-      C psi[12];
       R sc;
-      ld_site_raw<P, 12>(in0 + k * rstride, g.Vp, j, psi, sc);
       C h[2][3];
-      project<MU, TT>(psi, h);
+      if constexpr (P::kSiteScale) {
+        project_q16<MU, TT>(in0 + k * rstride, g.Vp, j, h, sc);
+      } else {
+        C psi[12];
+        ld_site_raw<P, 12>(in0 + k * rstride, g.Vp, j, psi, sc);
+        project<MU, TT>(psi, h);
+      }
       accumulate<MU, TT, BACK>(lk, h, hop_factor<LP>(sc, flip), acc[k]);
     }
   }

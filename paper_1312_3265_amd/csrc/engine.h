@@ -90,6 +90,7 @@ struct lq_gauge_s {
   float2* u32_18 = nullptr;
   float2* u32_12 = nullptr;
   short2* u16_12 = nullptr;     // 16-bit fixed point, 12-real
+  short2* u16_18 = nullptr;     // 16-bit fixed point, 18-real
   double2* c64 = nullptr;     // corners
   float2* c32 = nullptr;
   short2* c16 = nullptr;

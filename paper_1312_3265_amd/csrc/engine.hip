@@ -19,7 +19,7 @@ const void* lq_gauge_s::links(int prec, int nl) const {
   if (prec == P32 && nl == 18) p = u32_18;
   if (prec == P32 && nl == 12) p = u32_12;
   if (prec == P16 && nl == 12) p = u16_12;
-  if (prec == P16 && nl == 18) p = u32_18;   // FP32 18-real links with 16-bit vectors
+  if (prec == P16 && nl == 18) p = u16_18;
   if (p && nl == 12) {
     // the third row is rebuilt as conj(row0 x row1): exact only for SU(3)
     const double lim = prec == P64 ? 1e-12 : 1e-6;
@@ -49,13 +49,16 @@ size_t gauge_layout(const Geom& g, uint32_t f, void* base, lq_gauge_s* out) {
   const size_t Vp = g.Vp;
   double2* u64 = (double2*)c.take(36 * Vp * 16);
   float2 *u32_18 = nullptr, *u32_12 = nullptr, *c32 = nullptr;
-  short2 *u16_12 = nullptr, *c16 = nullptr;
+  short2 *u16_12 = nullptr, *u16_18 = nullptr, *c16 = nullptr;
   double2* c64 = nullptr;
   if (f & LQ_FEAT_F32) {
     u32_18 = (float2*)c.take(36 * Vp * 8);
     u32_12 = (float2*)c.take(24 * Vp * 8);
   }
-  if (f & LQ_FEAT_Q16) u16_12 = (short2*)c.take(24 * Vp * 4);
+  if (f & LQ_FEAT_Q16) {
+    u16_12 = (short2*)c.take(24 * Vp * 4);
+    u16_18 = (short2*)c.take(36 * Vp * 4);
+  }
   if (f & LQ_FEAT_CORNERS) {
     c64 = (double2*)c.take(72 * Vp * 16);
     if (f & LQ_FEAT_F32) c32 = (float2*)c.take(72 * Vp * 8);
@@ -67,6 +70,7 @@ size_t gauge_layout(const Geom& g, uint32_t f, void* base, lq_gauge_s* out) {
     out->g = g;
     out->features = f;
     out->u64 = u64; out->u32_18 = u32_18; out->u32_12 = u32_12; out->u16_12 = u16_12;
+    out->u16_18 = u16_18;
     out->c64 = c64; out->c32 = c32; out->c16 = c16;
     out->scratch = scratch;
     out->nbp = nbp;
@@ -115,7 +119,7 @@ std::string tune_key(const Geom& g, int op, int prec, int nl, int nslots) {
   LQ_HIP(hipGetDevice(&dev));
   LQ_HIP(hipGetDeviceProperties(&prop, dev));
   std::ostringstream key;
-  key << "v8:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
+  key << "v9:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
       << ":op" << op << ":p" << prec << ":l" << nl << ":n" << nslots;
   std::string k = key.str();
   for (auto& ch : k) if (ch == ' ') ch = '_';

@@ -133,6 +133,8 @@ void launch_links_convert(int prec, int nl, const Geom& g, const double2* u64, v
     hipLaunchKernelGGL((links_convert_kernel<F32, 12>), grid, blk, 0, s, g, u64, (float2*)dst);
   else if (prec == P16 && nl == 12)
     hipLaunchKernelGGL((links_convert_kernel<Q16L, 12>), grid, blk, 0, s, g, u64, (short2*)dst);
+  else if (prec == P16 && nl == 18)
+    hipLaunchKernelGGL((links_convert_kernel<Q16L, 18>), grid, blk, 0, s, g, u64, (short2*)dst);
   else
     throw std::runtime_error("links_convert: unsupported precision/storage");
 }

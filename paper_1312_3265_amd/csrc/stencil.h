@@ -140,7 +140,7 @@ __device__ __forceinline__ bool slot_active(const SlotState* st, int k, int mode
 // partial sums, so the result of a system does not depend on K or on the
 // other systems.
 template <class Op, int K>
-constexpr int stencil_waves() { return (Op::NC == 12 && K >= 4) ? 3 : Op::kWaves; }
+constexpr int stencil_waves() { return (Op::NC == 12 && K >= 2) ? 3 : Op::kWaves; }
 
 // CG_UPDATE at one site for system k (offset off into the batched fields):
 // r -= alpha q with ||r||^2 returned, and on odd iterations
