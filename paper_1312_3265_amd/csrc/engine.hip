@@ -119,7 +119,7 @@ std::string tune_key(const Geom& g, int op, int prec, int nl, int nslots) {
   LQ_HIP(hipGetDevice(&dev));
   LQ_HIP(hipGetDeviceProperties(&prop, dev));
   std::ostringstream key;
-  key << "v9:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
+  key << "v10:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
       << ":op" << op << ":p" << prec << ":l" << nl << ":n" << nslots;
   std::string k = key.str();
   for (auto& ch : k) if (ch == ' ') ch = '_';
@@ -128,7 +128,8 @@ std::string tune_key(const Geom& g, int op, int prec, int nl, int nslots) {
 
 // Time the two stencils of a CG iteration (t = M p + ||t||^2, then the M^dag
 // stencil with the x, r updates) over all slots for every systems-per-thread
-// K and block order on the (zeroed) solver buffers, and keep the fastest.
+// K and block order that keeps the links in L2 across systems, on the
+// (zeroed) solver buffers, and keep the fastest.
 void Engine::tune(hipStream_t s) {
   rhs_per_thread = 1;
   window = -3;   // tiled order where the lattice allows it (the plain order elsewhere)
@@ -167,7 +168,11 @@ void Engine::tune(hipStream_t s) {
   int bestk = 1, bestw = 0;
   for (int kk : {1, 2, 4}) {
     if (kk > nslots) break;
-    for (int w : {1, 2, 4, 0, -1, -2, -3, -4}) {
+    // the system-major orders (-1, -2) are left out: every XCD then needs all
+    // the links, which alone on the GPU the last-level cache hides, but with
+    // other batches in flight they are fetched again per system (16^3x32, 36
+    // Wilson systems, two batches in flight: 84 solves/s with -2, 100 with -3)
+    for (int w : {1, 2, 4, 0, -3, -4}) {
       e.rhs_per_thread = f.rhs_per_thread = kk;
       e.window = f.window = w;
       launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
