@@ -99,6 +99,8 @@ extern "C" {
 #define LQ_FEAT_CORNERS 0x1u  /* corner matrices W_s(x) in every built precision */
 #define LQ_FEAT_F32 0x2u      /* FP32 links, 18-real and 12-real               */
 #define LQ_FEAT_Q16 0x4u      /* 16-bit fixed-point links (12- and 18-real), corners */
+#define LQ_FEAT_EO 0x8u       /* even-odd copies of the links (FP64, and F32/Q16 when
+                                 those are built): per parity, half-lattice records */
 
 typedef struct lq_lattice_s lq_lattice;
 typedef struct lq_gauge_s lq_gauge;
@@ -188,6 +190,20 @@ size_t lq_apply_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t 
 int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t op, int32_t precision,
              int32_t links, const void* in, void* out, void* ws, size_t ws_bytes,
              void* stream);
+
+/* ------------------------------------------------------- even-odd blocks
+ * The Schur complement of the even-odd preconditioned Wilson solve (the
+ * preconditioning of the footnote to eq. (2), Sec. 3; r = 1): with sites split
+ * by the parity of x1+x2+x3+x4 and M = [[d, M_eo], [M_oe, d]], d = m + 4,
+ *     out_e = M^ in_e = d in_e - M_eo M_oe in_e / d     (M^dag when dagger),
+ * out_o = 0.  in/out: device canonical full-lattice fields as for lq_apply;
+ * only the even sites of `in` are read.  Needs a Wilson d with r = 1 and a
+ * gauge field built with LQ_FEAT_EO (and the precision's own feature).  `ws`
+ * is device scratch of lq_schur_workspace_bytes.  Asynchronous. */
+size_t lq_schur_workspace_bytes(const lq_gauge* g, int32_t precision);
+int lq_schur_apply(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t precision,
+                   int32_t links, const void* in, void* out, void* ws, size_t ws_bytes,
+                   void* stream);
 
 /* Average device time (ms) of one stencil launch on `nrhs` fields already in
  * the library layout, over `reps` back-to-back launches, measured with HIP

@@ -25,7 +25,7 @@ STAGGERED_WILSON = 1
 OP_M, OP_MDAG, OP_MDAGM = 0, 1, 2
 G55_CORNERS, G55_ONTHEFLY = 0, 1
 F64, F32, Q16 = 0, 1, 2
-FEAT_CORNERS, FEAT_F32, FEAT_Q16 = 1, 2, 4
+FEAT_CORNERS, FEAT_F32, FEAT_Q16, FEAT_EO = 1, 2, 4, 8
 OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_WORKSPACE, ERR_DEVICE, ERR_BREAKDOWN, ERR_STATE = -1, -2, -3, -4, -5
 SLOT_EMPTY, SLOT_RUNNING, SLOT_DONE, SLOT_FAILED = 0, 1, 2, 3
@@ -101,6 +101,8 @@ def lib():
         "lq_gauge_plaquette": ([P, P, P], I32),
         "lq_apply_workspace_bytes": ([P, I32, I32], SZ),
         "lq_apply": ([P, P, I32, I32, I32, P, P, P, SZ, P], I32),
+        "lq_schur_workspace_bytes": ([P, I32], SZ),
+        "lq_schur_apply": ([P, P, I32, I32, I32, P, P, P, SZ, P], I32),
         "lq_time_dslash": ([P, P, I32, I32, I32, I32, I32, I32, I32, P, SZ, P, P], I32),
         "lq_time_dslash_workspace_bytes": ([P, I32, I32, I32], SZ),
         "lq_tuned_launch": ([P, P, I32, I32, I32, P, P], I32),
@@ -232,6 +234,23 @@ def apply(gauge, formulation, mass, psi, op=OP_M, r=1.0, g55=G55_CORNERS, precis
     d = Dirac(formulation, g55, mass, r)
     _check(lib().lq_apply(gauge._h, ctypes.byref(d), op, precision, links, _ptr(x), _ptr(out),
                           _ptr(ws), nb, _stream(stream)))
+    _stream_sync(stream)
+    return out
+
+
+def schur_apply(gauge, mass, psi, dagger=False, precision=F64, links=0, stream=None):
+    """M^ psi_e (M^dag with dagger): the even-odd Schur complement of the
+    Wilson matrix (r = 1) on the even sites of the full-lattice field psi;
+    the odd sites of the result are zero.  Needs a gauge built with FEAT_EO."""
+    torch = _torch()
+    dt = torch.complex128 if precision == F64 else torch.complex64
+    x = _device_tensor(psi, dt)
+    out = torch.empty_like(x)
+    nb = int(lib().lq_schur_workspace_bytes(gauge._h, precision))
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    d = Dirac(WILSON, G55_CORNERS, mass, 1.0)
+    _check(lib().lq_schur_apply(gauge._h, ctypes.byref(d), int(dagger), precision, links, _ptr(x),
+                                _ptr(out), _ptr(ws), nb, _stream(stream)))
     _stream_sync(stream)
     return out
 

@@ -108,7 +108,7 @@ int lq_gauge_create(const lq_lattice* lat, const void* U, uint32_t features, voi
                     size_t buf_bytes, void* stream, lq_gauge** out) {
   return guard([&] {
     need(lat && U && buf && out, "null argument");
-    need((features & ~7u) == 0, "unknown feature bits");
+    need((features & ~15u) == 0, "unknown feature bits");
     const size_t nb = gauge_layout(lat->g, features, nullptr, nullptr);
     if (buf_bytes < nb)
       throw Error(LQ_ERR_WORKSPACE, "gauge buffer too small: need " + std::to_string(nb));
@@ -127,6 +127,18 @@ int lq_gauge_create(const lq_lattice* lat, const void* U, uint32_t features, voi
     if (features & LQ_FEAT_Q16) {
       launch_links_convert(P16, 12, g->g, g->u64, g->u16_12, s);
       launch_links_convert(P16, 18, g->g, g->u64, g->u16_18, s);
+    }
+    if (features & LQ_FEAT_EO) {
+      const int Vhp = half_geom(g->g).Vp;
+      launch_links_eo(P64, 18, g->g, Vhp, g->u64, g->eo64, s);
+      if (features & LQ_FEAT_F32) {
+        launch_links_eo(P32, 18, g->g, Vhp, g->u64, g->eo32_18, s);
+        launch_links_eo(P32, 12, g->g, Vhp, g->u64, g->eo32_12, s);
+      }
+      if (features & LQ_FEAT_Q16) {
+        launch_links_eo(P16, 12, g->g, Vhp, g->u64, g->eo16_12, s);
+        launch_links_eo(P16, 18, g->g, Vhp, g->u64, g->eo16_18, s);
+      }
     }
     if (features & LQ_FEAT_CORNERS) {
       launch_corners(g->g, g->u64, g->c64, s);
@@ -223,6 +235,48 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t opsel, int32_t precis
       launch_stencil(op, precision, nl, opsel == LQ_OP_MDAG, EPI_STORE, oa, a, e, 1, s);
     }
     launch_field_out(precision, nc, g->g, b, out, f64, nbp, 0, 1, s);
+    check_launch();
+    return LQ_OK;
+  });
+}
+
+size_t lq_schur_workspace_bytes(const lq_gauge* g, int32_t precision) {
+  if (!g || precision < 0 || precision > 2) return 0;
+  const size_t v = field_bytes(half_geom(g->g), precision, 12);
+  Carver c(nullptr);
+  c.take(v); c.take(v); c.take(v);
+  return c.size();
+}
+
+int lq_schur_apply(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t precision,
+                   int32_t links, const void* in, void* out, void* ws, size_t ws_bytes,
+                   void* stream) {
+  return guard([&] {
+    need(g && in && out && ws, "null argument");
+    check_dirac(d);
+    check_prec(precision, links);
+    need(d->formulation == LQ_WILSON && d->r == 1.0, "the even-odd blocks are built for Wilson, r = 1");
+    const size_t nb = lq_schur_workspace_bytes(g, precision);
+    if (ws_bytes < nb) throw Error(LQ_ERR_WORKSPACE, "schur workspace too small: need " + std::to_string(nb));
+    const int nl = links_for(g, precision, links);
+    const Geom gh = half_geom(g->g);
+    const size_t v = field_bytes(gh, precision, 12);
+    Carver c(ws);
+    void* a = c.take(v);
+    void* w = c.take(v);
+    void* b = c.take(v);
+    hipStream_t s = S(stream);
+    const int nbp = nbp_of(gh.V);
+    const int f64 = precision == LQ_PREC_F64;
+    launch_field_in(precision, 12, gh, in, f64, a, nbp, 0, 1, s, 0);
+    OpArgs base = make_op(g, d, precision, nl);
+    EpiArgs e;
+    std::memset(&e, 0, sizeof(e));
+    e.nbp = nbp;
+    e.out = b;
+    enqueue_schur(g, base, precision, nl, dagger != 0, EPI_STORE, a, w, e, 1, s);
+    launch_fill_zero(out, (size_t)g->g.V * 12 * (f64 ? 16 : 8), s);
+    launch_field_out(precision, 12, gh, b, out, f64, nbp, 0, 1, s, 0);
     check_launch();
     return LQ_OK;
   });

@@ -19,6 +19,12 @@ struct OpArgs {
   double mass0;          // mass when `mass` is null
   const double* mass;    // per-RHS mass, mass[k * mass_stride]
   int mass_stride;
+  // even-odd blocks (WilsonEOOp): links of the other parity, the field
+  // multiplying d in the Schur form, the output parity, and the form
+  const void* links_nb = nullptr;
+  const void* diag_in = nullptr;
+  int eo_par = 0;
+  int eo_schur = 0;
 };
 
 __device__ __forceinline__ double rhs_mass(const OpArgs& a, int k) {
@@ -279,6 +285,136 @@ struct WilsonOp {
 #pragma unroll
         for (int k = 0; k < K; ++k)
           if ((act >> k) & 1) hop(a, in0 + k * rstride, j, mu, back, back ? s : -s, sg, lk, acc[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int q = 0; q < 12; ++q) out[k][q] = cscale(acc[k][q], (R)-0.5);
+  }
+};
+
+// ------------------------------------------------ Wilson, even-odd blocks
+// Half-lattice Wilson blocks for the even-odd preconditioned solve (the
+// preconditioning of the footnote to eq. (2), Sec. 3; r = 1).  A field holds
+// the sites of one parity: half site h is whichever of the lexicographic sites
+// 2h, 2h + 1 has that parity (the two share x2, x3, x4, and L1 is even).
+// Output sites have parity a.eo_par and `in` holds the other parity; with
+// d = m + 4 and M_W = [[d, M_eo], [M_oe, d]] in (even, odd) blocks,
+//   eo_schur = 0:  out = M_{par, 1-par} in          (= -H in / 2)
+//   eo_schur = 1:  out = d y - M_{par, 1-par} in / d,  y = a.diag_in (parity par)
+// so that in = M_oe y turns the second form into the Schur complement
+// M^ y = (d - M_eo M_oe / d) y.  Links are stored per parity and half site:
+// a.links those of the output parity (forward hops, U_mu(x)), a.links_nb the
+// other parity's (backward hops, U_mu(x - mu)).  The geometry's V and Vp are
+// those of the half-lattice fields, its extents those of the lattice.
+template <class P, int NL, bool DAG>
+struct WilsonEOOp {
+  using W = WilsonOp<P, NL, DAG, false>;
+  using Pol = P;
+  static constexpr int NC = 12;
+  static constexpr int kWaves = W::kWaves;
+  using C = typename P::C;
+  using R = typename P::R;
+  using S = typename P::S;
+
+  // Coordinates and lexicographic index of half site h of parity par.
+  __device__ __forceinline__ static Coord coords_of(const Geom& g, int h, int par, int& i) {
+    Coord c = site_coords(g, 2 * h);
+    const int b = (c.x[1] + c.x[2] + c.x[3] + par) & 1;
+    c.x[0] += b;
+    i = 2 * h + b;
+    return c;
+  }
+
+  // One r = 1 hop along +-MU for K systems, as WilsonOp::hop_r1 with the
+  // neighbour and its link read from their parity's half-lattice arrays and
+  // the hop factor times fm[k].
+  template <int MU, bool BACK, int K>
+  __device__ __forceinline__ static void hop_eo(const OpArgs& a, const S* __restrict__ in0,
+                                                size_t rstride, const Coord& c, int i, int h,
+                                                unsigned act, const R fm[K], C acc[K][12]) {
+    constexpr int s = DAG ? -1 : 1;
+    constexpr int TT = BACK ? s : -s;
+    const Geom& g = a.g;
+    bool wrap;
+    const int jh = (BACK ? nb_bwd(g, c, i, MU, wrap) : nb_fwd(g, c, i, MU, wrap)) >> 1;
+    const bool flip = wrap && g.bc[MU] < 0;
+    C lk[9];
+    using LP = typename LinkPol<P, NL>::type;
+    load_link<LP, NL, true>((const typename LP::S*)(BACK ? a.links_nb : a.links), g.Vp, MU,
+                            BACK ? jh : h, lk);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!((act >> k) & 1)) continue;
+      R sc;
+      C hh[2][3];
+      if constexpr (P::kSiteScale) {
+        W::template project_q16<MU, TT>(in0 + k * rstride, g.Vp, jh, hh, sc);
+      } else {
+        C psi[12];
+        ld_site_raw<P, 12>(in0 + k * rstride, g.Vp, jh, psi, sc);
+        W::template project<MU, TT>(psi, hh);
+      }
+      W::template accumulate<MU, TT, BACK>(lk, hh, W::template hop_factor<LP>(sc, flip) * fm[k],
+                                           acc[k]);
+    }
+  }
+
+  template <int K>
+  __device__ __forceinline__ static void site_multi(const OpArgs& a, const S* __restrict__ in0,
+                                                    size_t rstride, int h, int k0, unsigned act,
+                                                    C out[K][12]) {
+    const Geom& g = a.g;
+    int i;
+    const Coord c = coords_of(g, h, a.eo_par, i);
+    // acc = -2 out: starts at -2 d y (Schur form) or 0, and the hops enter
+    // with factor -1/d (Schur form) or 1
+    C acc[K][12];
+    R fm[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double d = rhs_mass(a, k0 + k) + 4.0;
+      fm[k] = a.eo_schur ? (R)(-1.0 / d) : (R)1;
+      C v[12];
+      R sc = (R)0;
+      const bool diag = a.eo_schur && ((act >> k) & 1);
+      if (diag) ld_site_raw<P, 12>((const S*)a.diag_in + (size_t)(k0 + k) * rstride, g.Vp, h, v, sc);
+      const R coef = (R)(-2.0 * d) * sc;
+#pragma unroll
+      for (int q = 0; q < 12; ++q) acc[k][q] = diag ? cscale(v[q], coef) : czero<C>();
+    }
+    if constexpr (W::template kHopPairs<K>()) {
+#pragma unroll 1
+      for (int m0 = 0; m0 < 4; ++m0) {
+        int mu = m0;
+        asm volatile("" : "+s"(mu));
+        switch (mu) {
+          case 0: hop_eo<0, false, K>(a, in0, rstride, c, i, h, act, fm, acc);
+                  hop_eo<0, true, K>(a, in0, rstride, c, i, h, act, fm, acc); break;
+          case 1: hop_eo<1, false, K>(a, in0, rstride, c, i, h, act, fm, acc);
+                  hop_eo<1, true, K>(a, in0, rstride, c, i, h, act, fm, acc); break;
+          case 2: hop_eo<2, false, K>(a, in0, rstride, c, i, h, act, fm, acc);
+                  hop_eo<2, true, K>(a, in0, rstride, c, i, h, act, fm, acc); break;
+          default: hop_eo<3, false, K>(a, in0, rstride, c, i, h, act, fm, acc);
+                   hop_eo<3, true, K>(a, in0, rstride, c, i, h, act, fm, acc); break;
+        }
+      }
+    } else {
+#pragma unroll 1
+      for (int h0 = 0; h0 < 8; ++h0) {
+        int hp = h0;
+        asm volatile("" : "+s"(hp));
+        switch (hp) {
+          case 0: hop_eo<0, false, K>(a, in0, rstride, c, i, h, act, fm, acc); break;
+          case 1: hop_eo<0, true, K>(a, in0, rstride, c, i, h, act, fm, acc); break;
+          case 2: hop_eo<1, false, K>(a, in0, rstride, c, i, h, act, fm, acc); break;
+          case 3: hop_eo<1, true, K>(a, in0, rstride, c, i, h, act, fm, acc); break;
+          case 4: hop_eo<2, false, K>(a, in0, rstride, c, i, h, act, fm, acc); break;
+          case 5: hop_eo<2, true, K>(a, in0, rstride, c, i, h, act, fm, acc); break;
+          case 6: hop_eo<3, false, K>(a, in0, rstride, c, i, h, act, fm, acc); break;
+          default: hop_eo<3, true, K>(a, in0, rstride, c, i, h, act, fm, acc); break;
+        }
       }
     }
 #pragma unroll

@@ -69,6 +69,14 @@ inline int stream_cg_vectors(const Geom& g, int prec, int nc, int nrhs) {
   const size_t x = (size_t)nc * g.Vp * store_bytes(prec == P16 ? P32 : prec);
   return (size_t)nrhs * (4 * field_bytes(g, prec, nc) + x) > kLastLevelCache;
 }
+// Geometry of the half-lattice fields of the even-odd blocks: the lattice's
+// extents, half its sites, the same plane padding rule.
+inline Geom half_geom(const Geom& g) {
+  Geom h = g;
+  h.V = g.V / 2;
+  h.Vp = ((h.V + 63) / 64) * 64 + 64;
+  return h;
+}
 inline int ncomp_of(int formulation) { return formulation == LQ_WILSON ? 12 : 3; }
 inline int opkind(int formulation, int g55) {
   if (formulation == LQ_WILSON) return OP_WILSON;
@@ -91,6 +99,12 @@ struct lq_gauge_s {
   float2* u32_12 = nullptr;
   short2* u16_12 = nullptr;     // 16-bit fixed point, 12-real
   short2* u16_18 = nullptr;     // 16-bit fixed point, 18-real
+  // even-odd copies (LQ_FEAT_EO): per parity, half-lattice records
+  void* eo64 = nullptr;
+  void* eo32_18 = nullptr;
+  void* eo32_12 = nullptr;
+  void* eo16_12 = nullptr;
+  void* eo16_18 = nullptr;
   double2* c64 = nullptr;     // corners
   float2* c32 = nullptr;
   short2* c16 = nullptr;
@@ -99,6 +113,8 @@ struct lq_gauge_s {
   double su3_dev = 0.0;       // max |row2 - conj(row0 x row1)| over the links
 
   const void* links(int prec, int nl) const;
+  // links of parity par for the even-odd blocks (LQ_FEAT_EO)
+  const void* links_eo(int prec, int nl, int par) const;
   // FP64 links: rows 0, 1 only (row 2 rebuilt) when the field is SU(3) to
   // rounding, which reads a third fewer link bytes, else all 18 reals
   int fp64_links() const { return su3_dev <= 1e-12 ? 12 : 18; }
@@ -162,6 +178,14 @@ struct Engine {
 // device once per (GPU, lattice, operator, precision, links, batch size) and
 // remembered in memory and in a small text cache file (LQ_TUNE_CACHE, default
 // $HOME/.cache/lq_tune.txt).
+// The Schur complement of the even-odd blocks (Wilson, r = 1) on half-lattice
+// fields of the even sites: out = M^ in = d in - M_eo M_oe in / d (M^dag with
+// dag).  The odd half-lattice field w receives M_oe in; the second launch
+// applies epilogue `epi` with `e` (its output, partials, solver state).
+// `base` carries the masses and r; the links are the gauge field's even-odd copies.
+void enqueue_schur(const lq_gauge_s* g, const OpArgs& base, int prec, int nl, bool dag, int epi,
+                   const void* in, void* w, const EpiArgs& e, int nrhs, hipStream_t s);
+
 int tuned_rhs_per_thread(const std::string& key);   // 0: not tuned; else K + 8 * (window + 3)
 std::string tune_key(const Geom& g, int op, int prec, int nl, int nslots);
 void remember_rhs_per_thread(const std::string& key, int k);

@@ -33,6 +33,26 @@ const void* lq_gauge_s::links(int prec, int nl) const {
   return p;
 }
 
+const void* lq_gauge_s::links_eo(int prec, int nl, int par) const {
+  using namespace lq;
+  if (!(features & LQ_FEAT_EO))
+    throw Error(LQ_ERR_ARG, "gauge field has no even-odd link copies (LQ_FEAT_EO)");
+  (void)links(prec, nl);   // the same storage checks as the lexicographic links
+  const void* base = nullptr;
+  int nstore = 0;
+  size_t el = 0;
+  if (prec == P64) { base = eo64; nstore = 9; el = 16; }
+  if (prec == P32 && nl == 18) { base = eo32_18; nstore = 9; el = 8; }
+  if (prec == P32 && nl == 12) { base = eo32_12; nstore = 6; el = 8; }
+  if (prec == P16 && nl == 12) { base = eo16_12; nstore = 6; el = 4; }
+  if (prec == P16 && nl == 18) { base = eo16_18; nstore = 9; el = 4; }
+  if (!base)
+    throw Error(LQ_ERR_ARG, "gauge field has no even-odd links for precision " +
+                                std::to_string(prec) + " with " + std::to_string(nl) + " reals");
+  const size_t half = (size_t)4 * nstore * half_geom(g).Vp * el;
+  return (const char*)base + par * half;
+}
+
 const void* lq_gauge_s::corners(int prec) const {
   using namespace lq;
   const void* p = prec == P64 ? (const void*)c64 : prec == P32 ? (const void*)c32 : (const void*)c16;
@@ -59,6 +79,20 @@ size_t gauge_layout(const Geom& g, uint32_t f, void* base, lq_gauge_s* out) {
     u16_12 = (short2*)c.take(24 * Vp * 4);
     u16_18 = (short2*)c.take(36 * Vp * 4);
   }
+  void *eo64 = nullptr, *eo32_18 = nullptr, *eo32_12 = nullptr, *eo16_12 = nullptr,
+       *eo16_18 = nullptr;
+  if (f & LQ_FEAT_EO) {
+    const size_t Vhp = half_geom(g).Vp;
+    eo64 = c.take(2 * 36 * Vhp * 16);
+    if (f & LQ_FEAT_F32) {
+      eo32_18 = c.take(2 * 36 * Vhp * 8);
+      eo32_12 = c.take(2 * 24 * Vhp * 8);
+    }
+    if (f & LQ_FEAT_Q16) {
+      eo16_12 = c.take(2 * 24 * Vhp * 4);
+      eo16_18 = c.take(2 * 36 * Vhp * 4);
+    }
+  }
   if (f & LQ_FEAT_CORNERS) {
     c64 = (double2*)c.take(72 * Vp * 16);
     if (f & LQ_FEAT_F32) c32 = (float2*)c.take(72 * Vp * 8);
@@ -71,6 +105,8 @@ size_t gauge_layout(const Geom& g, uint32_t f, void* base, lq_gauge_s* out) {
     out->features = f;
     out->u64 = u64; out->u32_18 = u32_18; out->u32_12 = u32_12; out->u16_12 = u16_12;
     out->u16_18 = u16_18;
+    out->eo64 = eo64; out->eo32_18 = eo32_18; out->eo32_12 = eo32_12;
+    out->eo16_12 = eo16_12; out->eo16_18 = eo16_18;
     out->c64 = c64; out->c32 = c32; out->c16 = c16;
     out->scratch = scratch;
     out->nbp = nbp;
@@ -197,6 +233,28 @@ void Engine::tune(hipStream_t s) {
   rhs_per_thread = bestk;
   window = bestw;
   remember_rhs_per_thread(k, bestk + 8 * (bestw + 3));
+}
+
+// ======================================================== even-odd blocks
+void enqueue_schur(const lq_gauge_s* g, const OpArgs& base, int prec, int nl, bool dag, int epi,
+                   const void* in, void* w, const EpiArgs& e, int nrhs, hipStream_t s) {
+  OpArgs o1 = base;
+  o1.g = half_geom(g->g);
+  o1.links = g->links_eo(prec, nl, 1);
+  o1.links_nb = g->links_eo(prec, nl, 0);
+  o1.eo_par = 1;
+  o1.eo_schur = 0;
+  o1.diag_in = nullptr;
+  EpiArgs e1 = e;
+  e1.out = w;
+  launch_stencil(OP_WILSON_EO, prec, nl, dag, EPI_STORE, o1, in, e1, nrhs, s);
+  OpArgs o2 = o1;
+  o2.links = g->links_eo(prec, nl, 0);
+  o2.links_nb = g->links_eo(prec, nl, 1);
+  o2.eo_par = 0;
+  o2.eo_schur = 1;
+  o2.diag_in = in;
+  launch_stencil(OP_WILSON_EO, prec, nl, dag, epi, o2, w, e, nrhs, s);
 }
 
 // ================================================================ Engine

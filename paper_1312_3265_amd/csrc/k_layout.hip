@@ -8,10 +8,22 @@
 namespace lq {
 
 // ------------------------------------------------------------ fermions
-template <class P, int NC, bool F64SRC>
+// Canonical site of field site i: i itself, or for a half-lattice field of
+// parity par (EO) the lexicographic site of that parity in the pair (2i, 2i+1).
+template <bool EO>
+__device__ __forceinline__ size_t canon_site(const Geom& g, int i, int par, int kl) {
+  if constexpr (EO) {
+    const Coord c = site_coords(g, 2 * i);
+    return (size_t)kl * 2 * g.V + 2 * i + ((c.x[1] + c.x[2] + c.x[3] + par) & 1);
+  } else {
+    return (size_t)kl * g.V + i;
+  }
+}
+
+template <class P, int NC, bool F64SRC, bool EO>
 __global__ void __launch_bounds__(256)
 field_in_kernel(const Geom g, const void* __restrict__ canon, typename P::S* __restrict__ soa,
-                int nbp, int k0, int nrhs) {
+                int par, int nbp, int k0, int nrhs) {
   using C = typename P::C;
   using R = typename P::R;
   int sb, kl;
@@ -19,7 +31,7 @@ field_in_kernel(const Geom g, const void* __restrict__ canon, typename P::S* __r
   const int k = k0 + kl;
   const int i = sb * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
-  const size_t cbase = ((size_t)kl * g.V + i) * NC;
+  const size_t cbase = canon_site<EO>(g, i, par, kl) * NC;
   C v[NC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
@@ -34,17 +46,17 @@ field_in_kernel(const Geom g, const void* __restrict__ canon, typename P::S* __r
   st_site<P, NC>(soa + (size_t)k * field_planes<P>(NC) * g.Vp, g.Vp, i, v);
 }
 
-template <class P, int NC, bool F64DST>
+template <class P, int NC, bool F64DST, bool EO>
 __global__ void __launch_bounds__(256)
 field_out_kernel(const Geom g, const typename P::S* __restrict__ soa, void* __restrict__ canon,
-                 int nbp, int k0, int nrhs) {
+                 int par, int nbp, int k0, int nrhs) {
   using C = typename P::C;
   int sb, kl;
   map_block(nbp, nrhs, 1, sb, kl);
   const int k = k0 + kl;
   const int i = sb * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
-  const size_t cbase = ((size_t)kl * g.V + i) * NC;
+  const size_t cbase = canon_site<EO>(g, i, par, kl) * NC;
   C v[NC];
   ld_site<P, NC>(soa + (size_t)k * field_planes<P>(NC) * g.Vp, g.Vp, i, v);
 #pragma unroll
@@ -65,30 +77,30 @@ field_out_kernel(const Geom g, const typename P::S* __restrict__ soa, void* __re
     else throw std::runtime_error("unsupported precision/components");                \
   } while (0)
 
+#define LQ_FIELD_LAUNCH(KERNEL, F64FLAG, SRC, DST)                                          \
+  do {                                                                                    \
+    if (par < 0)                                                                          \
+      LQ_PNC(prec, nc, hipLaunchKernelGGL((KERNEL<PP, NCC, F64FLAG, false>),              \
+                                          dim3(nbp * nrhs), dim3(kBlock), 0, s, g, SRC, DST, \
+                                          par, nbp, k0, nrhs));                           \
+    else                                                                                  \
+      LQ_PNC(prec, nc, hipLaunchKernelGGL((KERNEL<PP, NCC, F64FLAG, true>),               \
+                                          dim3(nbp * nrhs), dim3(kBlock), 0, s, g, SRC, DST, \
+                                          par, nbp, k0, nrhs));                           \
+  } while (0)
+
 void launch_field_in(int prec, int nc, const Geom& g, const void* canon, int canon_f64, void* soa,
-                     int nbp, int k0, int nrhs, hipStream_t s) {
+                     int nbp, int k0, int nrhs, hipStream_t s, int par) {
   if (nbp * nrhs == 0) return;
-  if (canon_f64)
-    LQ_PNC(prec, nc, hipLaunchKernelGGL((field_in_kernel<PP, NCC, true>), dim3(nbp * nrhs),
-                                        dim3(kBlock), 0, s, g, canon, (typename PP::S*)soa, nbp,
-                                        k0, nrhs));
-  else
-    LQ_PNC(prec, nc, hipLaunchKernelGGL((field_in_kernel<PP, NCC, false>), dim3(nbp * nrhs),
-                                        dim3(kBlock), 0, s, g, canon, (typename PP::S*)soa, nbp,
-                                        k0, nrhs));
+  if (canon_f64) LQ_FIELD_LAUNCH(field_in_kernel, true, canon, (typename PP::S*)soa);
+  else LQ_FIELD_LAUNCH(field_in_kernel, false, canon, (typename PP::S*)soa);
 }
 
 void launch_field_out(int prec, int nc, const Geom& g, const void* soa, void* canon, int canon_f64,
-                      int nbp, int k0, int nrhs, hipStream_t s) {
+                      int nbp, int k0, int nrhs, hipStream_t s, int par) {
   if (nbp * nrhs == 0) return;
-  if (canon_f64)
-    LQ_PNC(prec, nc, hipLaunchKernelGGL((field_out_kernel<PP, NCC, true>), dim3(nbp * nrhs),
-                                        dim3(kBlock), 0, s, g, (const typename PP::S*)soa, canon,
-                                        nbp, k0, nrhs));
-  else
-    LQ_PNC(prec, nc, hipLaunchKernelGGL((field_out_kernel<PP, NCC, false>), dim3(nbp * nrhs),
-                                        dim3(kBlock), 0, s, g, (const typename PP::S*)soa, canon,
-                                        nbp, k0, nrhs));
+  if (canon_f64) LQ_FIELD_LAUNCH(field_out_kernel, true, (const typename PP::S*)soa, canon);
+  else LQ_FIELD_LAUNCH(field_out_kernel, false, (const typename PP::S*)soa, canon);
 }
 
 // --------------------------------------------------------------- links
@@ -137,6 +149,49 @@ void launch_links_convert(int prec, int nl, const Geom& g, const double2* u64, v
     hipLaunchKernelGGL((links_convert_kernel<Q16L, 18>), grid, blk, 0, s, g, u64, (short2*)dst);
   else
     throw std::runtime_error("links_convert: unsupported precision/storage");
+}
+
+// FP64 18-real links -> per-parity half-lattice records of precision P with
+// NL reals (the even-odd blocks): link mu of site i goes to half site i / 2 of
+// its parity's array, which starts at dst + par * 4 * NSTORE * Vhp elements.
+template <class P, int NL>
+__global__ void __launch_bounds__(256)
+links_eo_kernel(const Geom g, int Vhp, const double2* __restrict__ u64,
+                typename P::S* __restrict__ dst) {
+  using C = typename P::C;
+  using R = typename P::R;
+  constexpr int NSTORE = P::id == 0 ? 9 : NL / 2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  const Coord c = site_coords(g, i);
+  const int par = (c.x[0] + c.x[1] + c.x[2] + c.x[3]) & 1;
+  typename P::S* d = dst + (size_t)par * 4 * NSTORE * Vhp;
+  for (int mu = 0; mu < 4; ++mu) {
+    C m[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double2 z = u64[(size_t)(mu * 9 + k) * g.Vp + i];
+      m[k].x = (R)z.x; m[k].y = (R)z.y;
+    }
+    store_link<P, P::id == 0 ? 18 : NL>(d, Vhp, mu, i >> 1, m);
+  }
+}
+
+void launch_links_eo(int prec, int nl, const Geom& g, int Vhp, const double2* u64, void* dst,
+                     hipStream_t s) {
+  dim3 grid((g.V + 255) / 256), blk(256);
+  if (prec == P64)
+    hipLaunchKernelGGL((links_eo_kernel<F64, 18>), grid, blk, 0, s, g, Vhp, u64, (double2*)dst);
+  else if (prec == P32 && nl == 18)
+    hipLaunchKernelGGL((links_eo_kernel<F32, 18>), grid, blk, 0, s, g, Vhp, u64, (float2*)dst);
+  else if (prec == P32 && nl == 12)
+    hipLaunchKernelGGL((links_eo_kernel<F32, 12>), grid, blk, 0, s, g, Vhp, u64, (float2*)dst);
+  else if (prec == P16 && nl == 12)
+    hipLaunchKernelGGL((links_eo_kernel<Q16L, 12>), grid, blk, 0, s, g, Vhp, u64, (short2*)dst);
+  else if (prec == P16 && nl == 18)
+    hipLaunchKernelGGL((links_eo_kernel<Q16L, 18>), grid, blk, 0, s, g, Vhp, u64, (short2*)dst);
+  else
+    throw std::runtime_error("links_eo: unsupported precision/storage");
 }
 
 // ---------------------------------------------------------- corners (K3)

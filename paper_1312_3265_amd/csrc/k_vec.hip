@@ -24,6 +24,8 @@ void launch_stencil_sw(int, int, bool, int, const OpArgs&, const void*, const Ep
                        hipStream_t);
 void launch_stencil_otf(int, int, bool, int, const OpArgs&, const void*, const EpiArgs&, int,
                         hipStream_t);
+void launch_stencil_wilson_eo(int, int, bool, int, const OpArgs&, const void*, const EpiArgs&, int,
+                              hipStream_t);
 
 void launch_stencil(int op, int prec, int nl, bool dag, int epi, const OpArgs& oa, const void* in,
                     const EpiArgs& ea, int nrhs, hipStream_t s) {
@@ -31,6 +33,7 @@ void launch_stencil(int op, int prec, int nl, bool dag, int epi, const OpArgs& o
     case OP_WILSON: return launch_stencil_wilson(prec, nl, dag, epi, oa, in, ea, nrhs, s);
     case OP_SW_CORNERS: return launch_stencil_sw(prec, nl, dag, epi, oa, in, ea, nrhs, s);
     case OP_SW_OTF: return launch_stencil_otf(prec, nl, dag, epi, oa, in, ea, nrhs, s);
+    case OP_WILSON_EO: return launch_stencil_wilson_eo(prec, nl, dag, epi, oa, in, ea, nrhs, s);
     default: throw std::runtime_error("unknown operator " + std::to_string(op));
   }
 }

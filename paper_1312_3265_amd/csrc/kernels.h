@@ -41,13 +41,17 @@ void launch_load_prepare(int prec, int nc, const Geom& g, double* xhi, void* xlo
 
 // ---- layout / conversion
 // canonical (V, nc) complex (c128 if src_f64 else c64) -> SoA field (prec) for rhs k0..
+// par >= 0: g is a half-lattice geometry and the SoA field holds the sites of
+// that parity of the canonical (2 g.V, nc) field (even-odd blocks)
 void launch_field_in(int prec, int nc, const Geom& g, const void* canon, int canon_f64, void* soa,
-                     int nbp, int k0, int nrhs, hipStream_t s);
+                     int nbp, int k0, int nrhs, hipStream_t s, int par = -1);
 void launch_field_out(int prec, int nc, const Geom& g, const void* soa, void* canon, int canon_f64,
-                      int nbp, int k0, int nrhs, hipStream_t s);
+                      int nbp, int k0, int nrhs, hipStream_t s, int par = -1);
 void launch_gauge_in(const Geom& g, const void* canon, double2* u64, hipStream_t s);
 void launch_links_convert(int prec, int nl, const Geom& g, const double2* u64, void* dst,
                           hipStream_t s);
+void launch_links_eo(int prec, int nl, const Geom& g, int Vhp, const double2* u64, void* dst,
+                     hipStream_t s);
 void launch_corners(const Geom& g, const double2* u64, double2* c64, hipStream_t s);
 void launch_corners_convert(int prec, const Geom& g, const double2* c64, void* dst, hipStream_t s);
 void launch_su3_deviation(const Geom& g, const double2* u64, double* part, double* out,

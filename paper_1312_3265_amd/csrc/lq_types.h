@@ -5,7 +5,7 @@
 
 namespace lq {
 
-enum OpKind { OP_WILSON = 0, OP_SW_CORNERS = 1, OP_SW_OTF = 2, OP_WILSON_R = 3 };
+enum OpKind { OP_WILSON = 0, OP_SW_CORNERS = 1, OP_SW_OTF = 2, OP_WILSON_R = 3, OP_WILSON_EO = 4 };
 enum Prec { P64 = 0, P32 = 1, P16 = 2 };
 
 // Per-system solver state in device memory.  Written only by single-block

@@ -110,6 +110,7 @@ __device__ __forceinline__ bool map_block_tiled(const Geom& g, int nbp, int nrhs
   const int xcd = b & 7, kk = b >> 3;
   const int P = plane >> 8, Z = g.L[2], Tx = g.L[3] >> 3;
   const int per = P * Z * Tx;             // blocks of one system on one XCD
+  if (8 * per != nbp) return false;       // fields of a sublattice (even-odd halves)
   int r;
   if (win == -3) { k = kk / per; r = kk - k * per; }
   else { k = kk % nrhs; r = kk / nrhs; }
