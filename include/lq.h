@@ -132,6 +132,14 @@ typedef struct {
   double reliable_delta;      /* also update once the iterated residual has
                                  dropped by this factor since the last update
                                  (0 = default: 0.1 for Q16, 1e-3 for F32)        */
+  int32_t evenodd;            /* 1 = even-odd preconditioned (Wilson, r = 1, gauge
+                                 built with LQ_FEAT_EO): CG on the normal
+                                 equations of the Schur complement (see
+                                 lq_schur_apply), M^dag M^ x_e = M^dag b^_e with
+                                 b^_e = chi_e - M_eo chi_o / d; tol, the
+                                 residuals and b in lq_solve_info refer to that
+                                 system; x (both halves, x_o = (chi_o -
+                                 M_oe x_e) / d) is returned as usual           */
 } lq_solve_opts;
 
 /* Per-solve report.  The residuals are relative: ||b - A x|| / ||b|| with

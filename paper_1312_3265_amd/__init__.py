@@ -46,7 +46,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("links", ctypes.c_int32),
                 ("reliable_interval", ctypes.c_int32), ("poll_interval", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
-                ("reliable_delta", ctypes.c_double)]
+                ("reliable_delta", ctypes.c_double), ("evenodd", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -286,9 +286,9 @@ def tuned_launch(gauge, formulation, precision, links, nrhs, g55=G55_CORNERS):
 
 
 def solve_opts(precision=F64, links=0, reliable_interval=0, poll_interval=0, use_graph=0,
-               max_restarts=0, reliable_delta=0.0):
+               max_restarts=0, reliable_delta=0.0, evenodd=0):
     return SolveOpts(precision, links, reliable_interval, poll_interval, use_graph, max_restarts,
-                     reliable_delta)
+                     reliable_delta, int(evenodd))
 
 
 def solve_workspace_bytes(gauge, formulation, opts, nrhs):

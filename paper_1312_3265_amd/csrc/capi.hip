@@ -391,6 +391,7 @@ static void check_opts(const lq_solve_opts* o) {
        "negative option");
   need(std::isfinite(o->reliable_delta) && o->reliable_delta >= 0.0 && o->reliable_delta < 1.0,
        "reliable_delta must be in [0, 1)");
+  need(o->evenodd == 0 || o->evenodd == 1, "evenodd must be 0 or 1");
 }
 
 int lq_cg_solve(const lq_gauge* g, const lq_dirac* d, const void* chi, void* x, double tol,

@@ -302,9 +302,11 @@ struct WilsonOp {
 // Output sites have parity a.eo_par and `in` holds the other parity; with
 // d = m + 4 and M_W = [[d, M_eo], [M_oe, d]] in (even, odd) blocks,
 //   eo_schur = 0:  out = M_{par, 1-par} in          (= -H in / 2)
-//   eo_schur = 1:  out = d y - M_{par, 1-par} in / d,  y = a.diag_in (parity par)
-// so that in = M_oe y turns the second form into the Schur complement
-// M^ y = (d - M_eo M_oe / d) y.  Links are stored per parity and half site:
+//   eo_schur > 0:  out = c y - M_{par, 1-par} in / d,  y = a.diag_in (parity par),
+//                  c = d, 1, 1/d for eo_schur = 1, 2, 3
+// so that with in = M_oe y the first Schur form is the complement
+// M^ y = (d - M_eo M_oe / d) y; the others give the preconditioned source
+// chi_e - M_eo chi_o / d and the odd half (chi_o - M_oe x_e) / d.  Links are stored per parity and half site:
 // a.links those of the output parity (forward hops, U_mu(x)), a.links_nb the
 // other parity's (backward hops, U_mu(x - mu)).  The geometry's V and Vp are
 // those of the half-lattice fields, its extents those of the lattice.
@@ -368,8 +370,8 @@ struct WilsonEOOp {
     const Geom& g = a.g;
     int i;
     const Coord c = coords_of(g, h, a.eo_par, i);
-    // acc = -2 out: starts at -2 d y (Schur form) or 0, and the hops enter
-    // with factor -1/d (Schur form) or 1
+    // acc = -2 out: starts at -2 c y (Schur forms) or 0, and the hops enter
+    // with factor -1/d (Schur forms) or 1
     C acc[K][12];
     R fm[K];
 #pragma unroll
@@ -380,7 +382,8 @@ struct WilsonEOOp {
       R sc = (R)0;
       const bool diag = a.eo_schur && ((act >> k) & 1);
       if (diag) ld_site_raw<P, 12>((const S*)a.diag_in + (size_t)(k0 + k) * rstride, g.Vp, h, v, sc);
-      const R coef = (R)(-2.0 * d) * sc;
+      const double cd = a.eo_schur == 1 ? d : a.eo_schur == 2 ? 1.0 : 1.0 / d;
+      const R coef = (R)(-2.0 * cd) * sc;
 #pragma unroll
       for (int q = 0; q < 12; ++q) acc[k][q] = diag ? cscale(v[q], coef) : czero<C>();
     }

@@ -138,6 +138,12 @@ struct Engine {
   int nbp = 0;
   int rhs_per_thread = 1;     // systems per thread of the CG stencils (autotuned)
   int window = 0;             // XCD window of the CG stencils' block order (autotuned)
+  // even-odd preconditioning (Wilson, r = 1): the vectors hold the even sites
+  // and the operator is the Schur complement M^ (vg is the half lattice)
+  bool eo = false;
+  Geom vg{};                  // geometry of the solver's vectors
+  double2 *wbuf = nullptr;    // eo: odd half-lattice intermediate of a Schur pair
+  double2 *chio = nullptr;    // eo: odd half of each source, for the solution's odd half
   // device
   double2 *b = nullptr, *xhi = nullptr, *rhi = nullptr, *t64 = nullptr;
   void *xlo = nullptr, *rlo = nullptr, *p = nullptr, *p1 = nullptr, *t = nullptr;  // p, p1: p_k by parity
@@ -166,6 +172,12 @@ struct Engine {
 
  private:
   OpArgs op_args(int prec, int nl) const;
+  // one application of the solver's operator (M, or M^ when eo) with epilogue epi
+  void stencil(int prec, int nl, bool dag, int epi, const void* in, const EpiArgs& e, int nrhs,
+               hipStream_t s) const;
+  // the even-odd blocks in one of their forms (see WilsonEOOp), FP64, slot `slot`
+  void eo_form(int par, int form, const void* diag, const void* in, void* out, int slot,
+               hipStream_t s) const;
   EpiArgs epi_base() const;
   void enqueue_iterations(int n, hipStream_t s);
   void enqueue_reliable_update(hipStream_t s);

@@ -185,7 +185,6 @@ void Engine::tune(hipStream_t s) {
   const std::string k = tune_key(gauge->g, op, prec_lo, nl_lo, nslots);
   const int cached = tuned_rhs_per_thread(k);   // encoded as K + 8 * (window + 3)
   if (cached) { rhs_per_thread = cached & 7; window = (cached >> 3) - 3; return; }
-  OpArgs oa = op_args(prec_lo, nl_lo);
   EpiArgs e = epi_base();
   e.st = nullptr;
   e.out = t;
@@ -211,13 +210,13 @@ void Engine::tune(hipStream_t s) {
     for (int w : {1, 2, 4, 0, -3, -4}) {
       e.rhs_per_thread = f.rhs_per_thread = kk;
       e.window = f.window = w;
-      launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
-      launch_stencil(op, prec_lo, nl_lo, true, EPI_CG_UPDATE, oa, t, f, nslots, s);
+      stencil(prec_lo, nl_lo, false, EPI_STORE_NORM, p, e, nslots, s);
+      stencil(prec_lo, nl_lo, true, EPI_CG_UPDATE, t, f, nslots, s);
       LQ_HIP(hipEventRecord(t0, s));
       for (int r = 0; r < 4; ++r) {
         e.par = f.par = r & 1;   // odd iterations also advance x
-        launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, p, e, nslots, s);
-        launch_stencil(op, prec_lo, nl_lo, true, EPI_CG_UPDATE, oa, t, f, nslots, s);
+        stencil(prec_lo, nl_lo, false, EPI_STORE_NORM, p, e, nslots, s);
+        stencil(prec_lo, nl_lo, true, EPI_CG_UPDATE, t, f, nslots, s);
       }
       e.par = f.par = 0;
       LQ_HIP(hipEventRecord(t1, s));
@@ -260,15 +259,19 @@ void enqueue_schur(const lq_gauge_s* g, const OpArgs& base, int prec, int nl, bo
 // ================================================================ Engine
 static int prec_of(const lq_solve_opts* o) { return o ? o->precision : LQ_PREC_F64; }
 
-size_t Engine::workspace_bytes(const Geom& g, int formulation, const lq_solve_opts* opts,
+size_t Engine::workspace_bytes(const Geom& g0, int formulation, const lq_solve_opts* opts,
                                int nslots) {
   const int nc = ncomp_of(formulation);
   const int prec = prec_of(opts);
+  const bool eo = opts && opts->evenodd;
+  const Geom vg = eo ? half_geom(g0) : g0;
+  const Geom& g = vg;
   const size_t vhi = (size_t)nslots * nc * g.Vp * 16;
   const size_t vlo = (size_t)nslots * field_bytes(g, prec, nc);
   const int nbp = nbp_of(g.V);
   Carver c(nullptr);
   c.take(vhi); c.take(vhi); c.take(vhi);      // b, x_hi, r_hi
+  if (eo) { c.take(vhi); c.take(vhi); }       // wbuf, chio
   if (prec != P64) c.take(vhi);               // t64 (shares t when FP64)
   const size_t vx = (size_t)nslots * nc * g.Vp * store_bytes(prec == P16 ? P32 : prec);
   c.take(vx); c.take(vlo); c.take(vlo); c.take(vlo); c.take(vlo);   // x_lo, r_lo, p (x2), t
@@ -286,6 +289,13 @@ void Engine::init(const lq_gauge_s* g, int form, int g55, double rr, int ns,
   nc = ncomp_of(form);
   r = rr;
   nslots = ns;
+  eo = opts && opts->evenodd;
+  if (eo) {
+    if (form != LQ_WILSON || rr != 1.0)
+      throw Error(LQ_ERR_ARG, "even-odd preconditioning is built for Wilson with r = 1");
+    op = OP_WILSON_EO;
+  }
+  vg = eo ? half_geom(g->g) : g->g;
   prec_lo = prec_of(opts);
   nl_lo = (opts && opts->links) ? opts->links : (prec_lo == P16 ? 12 : 18);
   if (prec_lo == P64) nl_lo = (opts && opts->links) ? opts->links : g->fp64_links();
@@ -302,21 +312,26 @@ void Engine::init(const lq_gauge_s* g, int form, int g55, double rr, int ns,
   // validate the stencil storage now (throws for a missing feature)
   (void)g->links(prec_lo, nl_lo);
   (void)g->links(P64, 18);
+  if (eo) { (void)g->links_eo(prec_lo, nl_lo, 0); (void)g->links_eo(P64, g->fp64_links(), 0); }
   if (op == OP_SW_CORNERS) { (void)g->corners(prec_lo); (void)g->corners(P64); }
 
   const size_t need = workspace_bytes(g->g, form, opts, ns);
   if (!ws || ws_bytes < need)
     throw Error(LQ_ERR_WORKSPACE, "solver workspace too small: need " + std::to_string(need) +
                                       " bytes, got " + std::to_string(ws_bytes));
-  nbp = nbp_of(g->g.V);
-  const size_t vhi = (size_t)ns * nc * g->g.Vp * 16;
-  const size_t vlo = (size_t)ns * field_bytes(g->g, prec_lo, nc);
+  nbp = nbp_of(vg.V);
+  const size_t vhi = (size_t)ns * nc * vg.Vp * 16;
+  const size_t vlo = (size_t)ns * field_bytes(vg, prec_lo, nc);
   Carver c(ws);
   b = (double2*)c.take(vhi);
   xhi = (double2*)c.take(vhi);
   rhi = (double2*)c.take(vhi);
+  if (eo) {
+    wbuf = (double2*)c.take(vhi);
+    chio = (double2*)c.take(vhi);
+  }
   if (prec_lo != P64) t64 = (double2*)c.take(vhi);
-  xlo = c.take((size_t)ns * nc * g->g.Vp * store_bytes(prec_lo == P16 ? P32 : prec_lo));
+  xlo = c.take((size_t)ns * nc * vg.Vp * store_bytes(prec_lo == P16 ? P32 : prec_lo));
   rlo = c.take(vlo);
   p = c.take(vlo);
   p1 = c.take(vlo);
@@ -357,12 +372,35 @@ OpArgs Engine::op_args(int prec, int nl) const {
   return a;
 }
 
+void Engine::stencil(int prec, int nl, bool dag, int epi, const void* in, const EpiArgs& e,
+                     int n, hipStream_t s) const {
+  if (eo) enqueue_schur(gauge, op_args(prec, nl), prec, nl, dag, epi, in, wbuf, e, n, s);
+  else launch_stencil(op, prec, nl, dag, epi, op_args(prec, nl), in, e, n, s);
+}
+
+void Engine::eo_form(int par, int form, const void* diag, const void* in, void* out, int slot,
+                     hipStream_t s) const {
+  const int nl = gauge->fp64_links();
+  OpArgs o = op_args(P64, nl);
+  o.g = vg;
+  o.links = gauge->links_eo(P64, nl, par);
+  o.links_nb = gauge->links_eo(P64, nl, par ^ 1);
+  o.eo_par = par;
+  o.eo_schur = form;
+  o.diag_in = diag;
+  EpiArgs e = epi_base();
+  e.out = out;
+  e.k0 = slot;
+  e.state_mode = 0;   // the slot's mass from its state, whatever its status
+  launch_stencil(OP_WILSON_EO, P64, nl, false, EPI_STORE, o, in, e, 1, s);
+}
+
 EpiArgs Engine::epi_base() const {
   EpiArgs e;
   std::memset(&e, 0, sizeof(e));
   e.nbp = nbp;
   e.st = st;
-  e.stream = stream_cg_vectors(gauge->g, prec_lo, nc, nslots);
+  e.stream = stream_cg_vectors(vg, prec_lo, nc, nslots);
   return e;
 }
 
@@ -389,13 +427,22 @@ void Engine::load(int slot, const void* chi, double mass, double tol, int maxite
   init.delta2 = delta * delta;
   hst[slot] = init;
   LQ_HIP(hipMemcpyAsync(st + slot, hst + slot, sizeof(SlotState), hipMemcpyHostToDevice, s));
-  const Geom& g = gauge->g;
-  // chi -> FP64 SoA (in t64), b = M^dag chi with ||b||^2
-  launch_field_in(P64, nc, g, chi, 1, t64, nbp, slot, 1, s);
+  const Geom& g = vg;
+  const int nl64 = gauge->fp64_links();
   EpiArgs e = epi_base();
   e.out = b; e.part = part_u; e.k0 = slot; e.state_mode = 2;
-  launch_stencil(op, P64, gauge->fp64_links(), true, EPI_STORE_NORM,
-                 op_args(P64, gauge->fp64_links()), t64, e, 1, s);
+  if (eo) {
+    // chi_e (in t64), chi_o (kept); b^_e = chi_e - M_eo chi_o / d (in r_hi);
+    // b = M^dag b^_e with ||b||^2
+    launch_field_in(P64, nc, g, chi, 1, t64, nbp, slot, 1, s, 0);
+    launch_field_in(P64, nc, g, chi, 1, chio, nbp, slot, 1, s, 1);
+    eo_form(0, 2, t64, chio, rhi, slot, s);
+    stencil(P64, nl64, true, EPI_STORE_NORM, rhi, e, 1, s);
+  } else {
+    // chi -> FP64 SoA (in t64), b = M^dag chi with ||b||^2
+    launch_field_in(P64, nc, g, chi, 1, t64, nbp, slot, 1, s);
+    stencil(P64, nl64, true, EPI_STORE_NORM, t64, e, 1, s);
+  }
   launch_load_prepare(prec_lo, nc, g, (double*)xhi, xlo, (double*)rhi, (const double*)b, nbp, slot,
                       1, s);
   const double ncomp = (double)nc * g.V;
@@ -411,7 +458,6 @@ void Engine::load(int slot, const void* chi, double mass, double tol, int maxite
 void Engine::enqueue_iterations(int n, hipStream_t s) {
   // n is even: a chunk starts and ends with p_k in buffer p; x advances on
   // the odd iterations by both steps of the pair
-  const OpArgs oa = op_args(prec_lo, nl_lo);
   for (int it = 0; it < n; ++it) {
     const int par = it & 1;
     void* pk = par ? p1 : p;       // p_k
@@ -423,7 +469,7 @@ void Engine::enqueue_iterations(int n, hipStream_t s) {
     e.part = part_t;
     e.rhs_per_thread = rhs_per_thread;
     e.window = window;
-    launch_stencil(op, prec_lo, nl_lo, false, EPI_STORE_NORM, oa, pk, e, nslots, s);
+    stencil(prec_lo, nl_lo, false, EPI_STORE_NORM, pk, e, nslots, s);
     EpiArgs f = epi_base();
     f.rhs_per_thread = rhs_per_thread;
     f.window = window;
@@ -432,29 +478,28 @@ void Engine::enqueue_iterations(int n, hipStream_t s) {
     f.part = part_r;
     f.part_in = part_t;
     f.x = xlo; f.r = rlo; f.p = pk; f.pprev = po;
-    launch_stencil(op, prec_lo, nl_lo, true, EPI_CG_UPDATE, oa, t, f, nslots, s);
-    launch_p_update(prec_lo, nc, gauge->g, st, par, part_r, nbp, pk, po, rlo, 0, nslots, s);
+    stencil(prec_lo, nl_lo, true, EPI_CG_UPDATE, t, f, nslots, s);
+    launch_p_update(prec_lo, nc, vg, st, par, part_r, nbp, pk, po, rlo, 0, nslots, s);
   }
 }
 
 void Engine::enqueue_reliable_update(hipStream_t s) {
-  const Geom& g = gauge->g;
+  const Geom& g = vg;
   const int nl64 = gauge->fp64_links();
-  const OpArgs oa = op_args(P64, nl64);
   LQ_HIP(hipMemcpyAsync(mask, hmask, sizeof(int) * nslots, hipMemcpyHostToDevice, s));
   launch_ru_accumulate(prec_lo, nc, g, st, mask, (double*)xhi, xlo, p, nbp, 0, nslots, s);
   EpiArgs e = epi_base();
   e.state_mode = 2;
   e.ru_mask = mask;
   e.out = t64;
-  launch_stencil(op, P64, nl64, false, EPI_STORE, oa, xhi, e, nslots, s);
+  stencil(P64, nl64, false, EPI_STORE, xhi, e, nslots, s);
   EpiArgs f = epi_base();
   f.state_mode = 2;
   f.ru_mask = mask;
   f.out = rhi;
   f.b = b;
   f.part = part_u;
-  launch_stencil(op, P64, nl64, true, EPI_RESID, oa, t64, f, nslots, s);
+  stencil(P64, nl64, true, EPI_RESID, t64, f, nslots, s);
   launch_ru_finish(st, mask, part_u, nbp, 0, nslots, (double)nc * g.V, prec_lo != P64, max_cand, 0,
                    0, s);
   launch_ru_convert(prec_lo, nc, g, st, mask, (const double*)rhi, rlo, p, p1, part_u, nbp, 0, 0, nslots,
@@ -535,7 +580,14 @@ void Engine::fetch(int slot, void* x, lq_solve_info* info, hipStream_t s) {
   SlotState& h = hst[slot];
   if (h.status == SLOT_EMPTY) throw Error(LQ_ERR_STATE, "slot is empty");
   if (h.status == SLOT_RUNNING) throw Error(LQ_ERR_STATE, "slot is still running");
-  if (x) launch_field_out(P64, nc, gauge->g, xhi, x, 1, nbp, slot, 1, s);
+  if (x && eo) {
+    // x_e, and x_o = (chi_o - M_oe x_e) / d
+    eo_form(1, 3, chio, xhi, wbuf, slot, s);
+    launch_field_out(P64, nc, vg, xhi, x, 1, nbp, slot, 1, s, 0);
+    launch_field_out(P64, nc, vg, wbuf, x, 1, nbp, slot, 1, s, 1);
+  } else if (x) {
+    launch_field_out(P64, nc, vg, xhi, x, 1, nbp, slot, 1, s);
+  }
   check_launch();
   if (info) {
     const double bn = h.bnorm2 > 0 ? h.bnorm2 : 1.0;

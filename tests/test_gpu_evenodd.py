@@ -71,3 +71,69 @@ def test_schur_needs_the_even_odd_links():
     g = lq.Gauge(lq.Lattice(dims), U, lq.FEAT_F32)
     with pytest.raises(lq.LQError):
         lq.schur_apply(g, 0.1, synth.gaussian_field(dims, synth.WILSON, 1))
+
+
+# ------------------------------------------------------------------ solves
+def test_fp64_eo_cg_4x4_matches_oracle():
+    dims = (4, 4, 4, 4)
+    U, g = _gauge(dims, "haar", 1000)
+    chi = synth.point_source(dims, synth.WILSON, 0)
+    m, tol = 0.5, 1e-10
+    opts = lq.solve_opts(evenodd=1)
+    x, info = lq.cg_solve(g, synth.WILSON, m, chi, tol, opts=opts)
+    assert info["status"] == lq.OK
+    xo, oinfo = EO.cgnr(U, chi, m, tol, 10000)
+    assert abs(info["iterations"] - oinfo["iterations"]) <= 2
+    assert np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo) <= 1e-8
+    # the solution of eq. (2) itself, judged in FP64 by the oracle
+    from oracle import solvers
+    rn, rd = solvers.true_residual(synth.WILSON, U, chi, x.cpu().numpy(), m)
+    assert rn <= 10 * tol and rd <= 10 * tol
+
+
+@pytest.mark.parametrize("precision", [lq.F32, lq.Q16])
+def test_mixed_eo_batch_solves_eq2_with_fewer_iterations(precision):
+    """Point sources over several masses near m_c on a near-identity field:
+    every system's full solution meets eq. (2) (FP64, oracle), and the
+    preconditioned iteration count is below half the unpreconditioned one."""
+    from oracle import solvers
+    dims = (8, 8, 8, 8)
+    U, g = _gauge(dims, "near_identity", 2000, eps=0.4359375)
+    ms = [-0.30, -0.25, -0.20, -0.30]
+    chis = np.stack([synth.point_source(dims, synth.WILSON, a) for a in (0, 5, 7)]
+                    + [synth.z2_source(dims, synth.WILSON, 3)])
+    tol = 1e-8
+    x, infos = lq.cg_solve_batch(g, synth.WILSON, ms, chis, [tol / 4] * 4,
+                                 opts=lq.solve_opts(precision=precision, evenodd=1))
+    x0, infos0 = lq.cg_solve_batch(g, synth.WILSON, ms, chis, [tol] * 4,
+                                   opts=lq.solve_opts(precision=precision))
+    for k in range(4):
+        assert infos[k]["status"] == lq.OK
+        rn, _ = solvers.true_residual(synth.WILSON, U, chis[k], x[k].cpu().numpy(), ms[k])
+        assert rn <= tol
+        assert infos[k]["iterations"] < 0.5 * infos0[k]["iterations"]
+
+
+def test_eo_batch_result_is_bitwise_the_single_result():
+    dims = (8, 8, 8, 8)
+    U, g = _gauge(dims, "near_identity", 2000, eps=0.4359375)
+    ms = [-0.25, -0.1, -0.3]
+    chis = np.stack([synth.point_source(dims, synth.WILSON, a) for a in (1, 4, 11)])
+    opts = lq.solve_opts(precision=lq.Q16, evenodd=1, reliable_interval=40)
+    xb, ib = lq.cg_solve_batch(g, synth.WILSON, ms, chis, [1e-8, 1e-9, 1e-7], opts=opts)
+    for k, t in enumerate([1e-8, 1e-9, 1e-7]):
+        xs, is_ = lq.cg_solve(g, synth.WILSON, ms[k], chis[k], t, opts=opts)
+        assert is_["iterations"] == ib[k]["iterations"]
+        assert torch.equal(xs, xb[k])
+
+
+def test_eo_refused_outside_wilson_r1():
+    dims = (4, 4, 4, 4)
+    U, g = _gauge(dims, "haar", 1000)
+    opts = lq.solve_opts(evenodd=1)
+    with pytest.raises(lq.LQError):
+        lq.cg_solve(g, synth.STAGGERED_WILSON, 0.5, synth.point_source(dims, synth.STAGGERED_WILSON, 0),
+                    1e-8, opts=opts)
+    with pytest.raises(lq.LQError):
+        lq.cg_solve(g, synth.WILSON, 0.5, synth.point_source(dims, synth.WILSON, 0), 1e-8, opts=opts,
+                    r=0.7)
