@@ -248,6 +248,78 @@ def serving(a, w):
     return out
 
 
+def evenodd_wilson(lq, fields, src, masses, dims, mc, prec, links, stream, t64w):
+    """The Wilson part of the mix with and without even-odd preconditioning
+    (the footnote to eq. (2), Sec. 3): the 36 systems of each of the 8 fields
+    batched in the benchmark's storage, one batch at a time on one stream, and
+    FP64 single-RHS on field 0 (t64w: the unpreconditioned FP64 seconds).  Both
+    stop on eq. (2)'s residual ||b - A x|| / ||b|| <= TOL for the whole solution
+    (b = M^dag chi), which is recomputed here in FP64 for every system."""
+    import numpy as np
+    import torch
+
+    def eq2_residual(g, m, chi, x):
+        b = lq.apply(g, 0, m, chi, op=lq.OP_MDAG, stream=stream)
+        ax = lq.apply(g, 0, m, x, op=lq.OP_MDAGM, stream=stream)
+        return float(torch.linalg.vector_norm(b - ax) / torch.linalg.vector_norm(b))
+
+    n = len(masses[0])
+    out = {}
+    for eo in (0, 1):
+        opts = lq.solve_opts(precision=prec, links=links, poll_interval=16, use_graph=1,
+                             evenodd=eo)
+        ws = torch.empty(lq.solve_workspace_bytes(fields[0], 0, opts, n), dtype=torch.uint8,
+                         device="cuda")
+        tol = TOL
+        lq.cg_solve_batch(fields[0], 0, masses[0], src[0], [tol] * n, opts=opts, stream=stream,
+                          workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        res, its = [], []
+        for g in fields:
+            x, infos = lq.cg_solve_batch(g, 0, masses[0], src[0], [tol] * n, opts=opts,
+                                         stream=stream, workspace=ws)
+            if any(i["status"] != lq.OK for i in infos):
+                raise RuntimeError(f"even-odd={eo}: a Wilson system did not converge")
+            its.append([i["iterations"] for i in infos])
+            res.append(x)
+        torch.cuda.synchronize()
+        el = time.time() - t0
+        worst = max(eq2_residual(g, masses[0][k], src[0][k], x[k])
+                    for g, x in zip(fields, res) for k in range(n))
+        if worst > TOL:
+            raise RuntimeError(f"even-odd={eo}: eq. (2) residual {worst:.2e} above {TOL}")
+        out["evenodd" if eo else "unpreconditioned"] = {
+            "solves_per_s": round(len(fields) * n / el, 2),
+            "mean_iterations": round(float(np.mean(its)), 1),
+            "worst_eq2_residual": worst,
+        }
+    # FP64 single-RHS, point source alpha = 0 on field 0
+    opts = lq.solve_opts(evenodd=1)
+    t64e, it64e = {}, {}
+    for d in DELTAS:
+        m = mc["wilson"] + d
+        chi = src[0][DELTAS.index(d) * 12]
+        lq.cg_solve(fields[0], 0, m, chi, TOL, opts=opts, stream=stream)
+        torch.cuda.synchronize()
+        ts = time.time()
+        x, inf = lq.cg_solve(fields[0], 0, m, chi, TOL, opts=opts, stream=stream)
+        torch.cuda.synchronize()
+        t64e[str(d)] = time.time() - ts
+        it64e[str(d)] = inf["iterations"]
+        r = eq2_residual(fields[0], m, chi, x)
+        if inf["status"] != lq.OK or r > TOL:
+            raise RuntimeError(f"FP64 even-odd delta={d}: status {inf['status']}, residual {r:.2e}")
+    rate0 = 3.0 / sum(t64w[str(d)] for d in DELTAS)
+    rate1 = 3.0 / sum(t64e.values())
+    out["speedup_batched"] = round(out["evenodd"]["solves_per_s"] /
+                                   out["unpreconditioned"]["solves_per_s"], 2)
+    out["fp64_single_rhs"] = {"solves_per_s_unpreconditioned": round(rate0, 2),
+                              "solves_per_s_evenodd": round(rate1, 2),
+                              "speedup": round(rate1 / rate0, 2), "iterations_evenodd": it64e}
+    return out
+
+
 def cpu_baseline(U, workload, iters_fp64):
     """The oracle, timed on the host on a bounded sample: a few CG iterations
     of each formulation at the delta = 0.1 mass, single-threaded BLAS."""
@@ -369,7 +441,7 @@ def main():
         U = synth.gauge_field(dims, "near_identity", s, eps)
         if U0 is None:
             U0 = U
-        fields.append(lq.Gauge(lat, U, lq.FEAT_CORNERS | lq.FEAT_F32 | lq.FEAT_Q16,
+        fields.append(lq.Gauge(lat, U, lq.FEAT_CORNERS | lq.FEAT_F32 | lq.FEAT_Q16 | lq.FEAT_EO,
                                stream=stream))
     plaq = fields[0].plaquette(stream=stream)
     src = {}
@@ -483,6 +555,10 @@ def main():
     mixed_iters = {n: {d: float(np.mean(v)) for d, v in dd.items()} for n, dd in mixed_iters.items()}
     mixed_ru = {n: {d: float(np.mean(v)) for d, v in dd.items()} for n, dd in mixed_ru.items()}
 
+    # ------------------------------- even-odd preconditioned Wilson (beside)
+    eo_w = evenodd_wilson(lq, fields, src, masses, dims, mc, prec, links, stream, t64["wilson"])
+    log(f"even-odd Wilson: {eo_w}")
+
     # --------------------------------------------- dominant kernel roofline
     reps = 50
     cfg = lq.tuned_launch(g0, 0, prec, links, NRHS_W)
@@ -540,6 +616,7 @@ def main():
             "dslash_fp64_gbs": {"wilson": round(gbs64, 1), "staggered_wilson_corners": round(gbs64_sw, 1)},
             "dslash_fp64_us": {"wilson": round(ms64 * 1e3, 1), "staggered_wilson_corners": round(ms64_sw * 1e3, 1)},
         },
+        "evenodd_wilson": eo_w,
         "mixed_iterations_field0": mixed_iters,
         "mixed_reliable_updates_field0": mixed_ru,
         "paper_context": {

@@ -136,10 +136,14 @@ typedef struct {
                                  built with LQ_FEAT_EO): CG on the normal
                                  equations of the Schur complement (see
                                  lq_schur_apply), M^dag M^ x_e = M^dag b^_e with
-                                 b^_e = chi_e - M_eo chi_o / d; tol, the
-                                 residuals and b in lq_solve_info refer to that
-                                 system; x (both halves, x_o = (chi_o -
-                                 M_oe x_e) / d) is returned as usual           */
+                                 b^_e = chi_e - M_eo chi_o / d, x_o = (chi_o -
+                                 M_oe x_e) / d.  The stopping rule stays that of
+                                 eq. (2) for the whole x: true_residual is
+                                 ||b - A x|| / ||b|| with b = M^dag chi,
+                                 evaluated in FP64 at each reliable update from
+                                 r^ = b^_e - M^ x_e; the Schur system's target
+                                 is lowered until it holds.  iterated_residual
+                                 is the Schur system's.                        */
 } lq_solve_opts;
 
 /* Per-solve report.  The residuals are relative: ||b - A x|| / ||b|| with

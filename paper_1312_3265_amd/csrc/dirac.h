@@ -302,11 +302,13 @@ struct WilsonOp {
 // Output sites have parity a.eo_par and `in` holds the other parity; with
 // d = m + 4 and M_W = [[d, M_eo], [M_oe, d]] in (even, odd) blocks,
 //   eo_schur = 0:  out = M_{par, 1-par} in          (= -H in / 2)
-//   eo_schur > 0:  out = c y - M_{par, 1-par} in / d,  y = a.diag_in (parity par),
-//                  c = d, 1, 1/d for eo_schur = 1, 2, 3
+//   eo_schur = 1..3: out = c y - M_{par, 1-par} in / d,  y = a.diag_in (parity par),
+//                  c = d, 1, 1/d
+//   eo_schur = 4:  out = d y + M_{par, 1-par} in      (the parity-par half of M_W)
 // so that with in = M_oe y the first Schur form is the complement
 // M^ y = (d - M_eo M_oe / d) y; the others give the preconditioned source
-// chi_e - M_eo chi_o / d and the odd half (chi_o - M_oe x_e) / d.  Links are stored per parity and half site:
+// chi_e - M_eo chi_o / d, the odd half (chi_o - M_oe x_e) / d, and the halves
+// of M_W (M_W^dag with DAG) applied to a whole field.  Links are stored per parity and half site:
 // a.links those of the output parity (forward hops, U_mu(x)), a.links_nb the
 // other parity's (backward hops, U_mu(x - mu)).  The geometry's V and Vp are
 // those of the half-lattice fields, its extents those of the lattice.
@@ -377,12 +379,12 @@ struct WilsonEOOp {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const double d = rhs_mass(a, k0 + k) + 4.0;
-      fm[k] = a.eo_schur ? (R)(-1.0 / d) : (R)1;
+      fm[k] = (a.eo_schur >= 1 && a.eo_schur <= 3) ? (R)(-1.0 / d) : (R)1;
       C v[12];
       R sc = (R)0;
       const bool diag = a.eo_schur && ((act >> k) & 1);
       if (diag) ld_site_raw<P, 12>((const S*)a.diag_in + (size_t)(k0 + k) * rstride, g.Vp, h, v, sc);
-      const double cd = a.eo_schur == 1 ? d : a.eo_schur == 2 ? 1.0 : 1.0 / d;
+      const double cd = (a.eo_schur == 1 || a.eo_schur == 4) ? d : a.eo_schur == 2 ? 1.0 : 1.0 / d;
       const R coef = (R)(-2.0 * cd) * sc;
 #pragma unroll
       for (int q = 0; q < 12; ++q) acc[k][q] = diag ? cscale(v[q], coef) : czero<C>();

@@ -144,6 +144,8 @@ struct Engine {
   Geom vg{};                  // geometry of the solver's vectors
   double2 *wbuf = nullptr;    // eo: odd half-lattice intermediate of a Schur pair
   double2 *chio = nullptr;    // eo: odd half of each source, for the solution's odd half
+  double2 *bhat = nullptr;    // eo: b^_e = chi_e - M_eo chi_o / d
+  double *part_f = nullptr, *part_g = nullptr;   // eo: norms behind eq. (2)'s residual
   // device
   double2 *b = nullptr, *xhi = nullptr, *rhi = nullptr, *t64 = nullptr;
   void *xlo = nullptr, *rlo = nullptr, *p = nullptr, *p1 = nullptr, *t = nullptr;  // p, p1: p_k by parity
@@ -175,9 +177,10 @@ struct Engine {
   // one application of the solver's operator (M, or M^ when eo) with epilogue epi
   void stencil(int prec, int nl, bool dag, int epi, const void* in, const EpiArgs& e, int nrhs,
                hipStream_t s) const;
-  // the even-odd blocks in one of their forms (see WilsonEOOp), FP64, slot `slot`
-  void eo_form(int par, int form, const void* diag, const void* in, void* out, int slot,
-               hipStream_t s) const;
+  // the even-odd blocks in one of their forms (see WilsonEOOp), FP64, with
+  // epilogue STORE or STORE_NORM (into part) over the slots e selects
+  void eo_form(int par, int form, bool dag, const void* diag, const void* in, EpiArgs e, int epi,
+               int nrhs, hipStream_t s) const;
   EpiArgs epi_base() const;
   void enqueue_iterations(int n, hipStream_t s);
   void enqueue_reliable_update(hipStream_t s);

@@ -271,7 +271,11 @@ size_t Engine::workspace_bytes(const Geom& g0, int formulation, const lq_solve_o
   const int nbp = nbp_of(g.V);
   Carver c(nullptr);
   c.take(vhi); c.take(vhi); c.take(vhi);      // b, x_hi, r_hi
-  if (eo) { c.take(vhi); c.take(vhi); }       // wbuf, chio
+  if (eo) {                                   // wbuf, chio, bhat, part_f, part_g
+    c.take(vhi); c.take(vhi); c.take(vhi);
+    c.take((size_t)nslots * nbp * sizeof(double));
+    c.take((size_t)nslots * nbp * sizeof(double));
+  }
   if (prec != P64) c.take(vhi);               // t64 (shares t when FP64)
   const size_t vx = (size_t)nslots * nc * g.Vp * store_bytes(prec == P16 ? P32 : prec);
   c.take(vx); c.take(vlo); c.take(vlo); c.take(vlo); c.take(vlo);   // x_lo, r_lo, p (x2), t
@@ -329,6 +333,9 @@ void Engine::init(const lq_gauge_s* g, int form, int g55, double rr, int ns,
   if (eo) {
     wbuf = (double2*)c.take(vhi);
     chio = (double2*)c.take(vhi);
+    bhat = (double2*)c.take(vhi);
+    part_f = (double*)c.take((size_t)ns * nbp * sizeof(double));
+    part_g = (double*)c.take((size_t)ns * nbp * sizeof(double));
   }
   if (prec_lo != P64) t64 = (double2*)c.take(vhi);
   xlo = c.take((size_t)ns * nc * vg.Vp * store_bytes(prec_lo == P16 ? P32 : prec_lo));
@@ -378,8 +385,8 @@ void Engine::stencil(int prec, int nl, bool dag, int epi, const void* in, const 
   else launch_stencil(op, prec, nl, dag, epi, op_args(prec, nl), in, e, n, s);
 }
 
-void Engine::eo_form(int par, int form, const void* diag, const void* in, void* out, int slot,
-                     hipStream_t s) const {
+void Engine::eo_form(int par, int form, bool dag, const void* diag, const void* in, EpiArgs e,
+                     int epi, int nrhs, hipStream_t s) const {
   const int nl = gauge->fp64_links();
   OpArgs o = op_args(P64, nl);
   o.g = vg;
@@ -388,11 +395,7 @@ void Engine::eo_form(int par, int form, const void* diag, const void* in, void* 
   o.eo_par = par;
   o.eo_schur = form;
   o.diag_in = diag;
-  EpiArgs e = epi_base();
-  e.out = out;
-  e.k0 = slot;
-  e.state_mode = 0;   // the slot's mass from its state, whatever its status
-  launch_stencil(OP_WILSON_EO, P64, nl, false, EPI_STORE, o, in, e, 1, s);
+  launch_stencil(OP_WILSON_EO, P64, nl, dag, epi, o, in, e, nrhs, s);
 }
 
 EpiArgs Engine::epi_base() const {
@@ -436,8 +439,16 @@ void Engine::load(int slot, const void* chi, double mass, double tol, int maxite
     // b = M^dag b^_e with ||b||^2
     launch_field_in(P64, nc, g, chi, 1, t64, nbp, slot, 1, s, 0);
     launch_field_in(P64, nc, g, chi, 1, chio, nbp, slot, 1, s, 1);
-    eo_form(0, 2, t64, chio, rhi, slot, s);
-    stencil(P64, nl64, true, EPI_STORE_NORM, rhi, e, 1, s);
+    EpiArgs h = e;
+    h.out = bhat;
+    eo_form(0, 2, false, t64, chio, h, EPI_STORE, 1, s);
+    stencil(P64, nl64, true, EPI_STORE_NORM, bhat, e, 1, s);
+    // ||M^dag chi||^2 of eq. (2) from its even and odd halves
+    h.out = wbuf;
+    h.part = part_f;
+    eo_form(0, 4, true, t64, chio, h, EPI_STORE_NORM, 1, s);
+    h.part = part_g;
+    eo_form(1, 4, true, chio, t64, h, EPI_STORE_NORM, 1, s);
   } else {
     // chi -> FP64 SoA (in t64), b = M^dag chi with ||b||^2
     launch_field_in(P64, nc, g, chi, 1, t64, nbp, slot, 1, s);
@@ -446,7 +457,8 @@ void Engine::load(int slot, const void* chi, double mass, double tol, int maxite
   launch_load_prepare(prec_lo, nc, g, (double*)xhi, xlo, (double*)rhi, (const double*)b, nbp, slot,
                       1, s);
   const double ncomp = (double)nc * g.V;
-  launch_ru_finish(st, nullptr, part_u, nbp, slot, 1, ncomp, prec_lo != P64, max_cand, 1, 0, s);
+  launch_ru_finish(st, nullptr, part_u, eo ? part_f : nullptr, eo ? part_g : nullptr, nbp, slot, 1,
+                   ncomp, prec_lo != P64, max_cand, 1, 0, s);
   launch_ru_convert(prec_lo, nc, g, st, nullptr, (const double*)rhi, rlo, p, p1, part_u, nbp, 1, slot,
                     1, s);
   launch_ru_commit(st, nullptr, part_u, nbp, slot, 1, s);
@@ -491,17 +503,31 @@ void Engine::enqueue_reliable_update(hipStream_t s) {
   EpiArgs e = epi_base();
   e.state_mode = 2;
   e.ru_mask = mask;
-  e.out = t64;
-  stencil(P64, nl64, false, EPI_STORE, xhi, e, nslots, s);
   EpiArgs f = epi_base();
   f.state_mode = 2;
   f.ru_mask = mask;
   f.out = rhi;
-  f.b = b;
   f.part = part_u;
-  stencil(P64, nl64, true, EPI_RESID, t64, f, nslots, s);
-  launch_ru_finish(st, mask, part_u, nbp, 0, nslots, (double)nc * g.V, prec_lo != P64, max_cand, 0,
-                   0, s);
+  if (eo) {
+    // r^ = b^ - M^ x_hi (in t64) with ||r^||^2, ||M_eo^dag r^||^2, and the
+    // residual of the iterated normal equations r_hi = M^dag r^
+    e.out = t64;
+    e.b = bhat;
+    e.part = part_f;
+    stencil(P64, nl64, false, EPI_RESID, xhi, e, nslots, s);
+    EpiArgs h = e;
+    h.out = wbuf;
+    h.part = part_g;
+    eo_form(1, 0, true, nullptr, t64, h, EPI_STORE_NORM, nslots, s);
+    stencil(P64, nl64, true, EPI_STORE_NORM, t64, f, nslots, s);
+  } else {
+    e.out = t64;
+    stencil(P64, nl64, false, EPI_STORE, xhi, e, nslots, s);
+    f.b = b;
+    stencil(P64, nl64, true, EPI_RESID, t64, f, nslots, s);
+  }
+  launch_ru_finish(st, mask, part_u, eo ? part_f : nullptr, eo ? part_g : nullptr, nbp, 0, nslots,
+                   (double)nc * g.V, prec_lo != P64, max_cand, 0, 0, s);
   launch_ru_convert(prec_lo, nc, g, st, mask, (const double*)rhi, rlo, p, p1, part_u, nbp, 0, 0, nslots,
                     s);
   launch_ru_commit(st, mask, part_u, nbp, 0, nslots, s);
@@ -582,7 +608,11 @@ void Engine::fetch(int slot, void* x, lq_solve_info* info, hipStream_t s) {
   if (h.status == SLOT_RUNNING) throw Error(LQ_ERR_STATE, "slot is still running");
   if (x && eo) {
     // x_e, and x_o = (chi_o - M_oe x_e) / d
-    eo_form(1, 3, chio, xhi, wbuf, slot, s);
+    EpiArgs e = epi_base();
+    e.out = wbuf;
+    e.k0 = slot;
+    e.state_mode = 0;   // the slot's mass from its state, whatever its status
+    eo_form(1, 3, false, chio, xhi, e, EPI_STORE, 1, s);
     launch_field_out(P64, nc, vg, xhi, x, 1, nbp, slot, 1, s, 0);
     launch_field_out(P64, nc, vg, wbuf, x, 1, nbp, slot, 1, s, 1);
   } else if (x) {
@@ -598,7 +628,10 @@ void Engine::fetch(int slot, void* x, lq_solve_info* info, hipStream_t s) {
     info->reliable_updates = h.ru;
     info->applications = h.apps + 1;   // + b = M^dag chi
     info->iterated_residual = std::sqrt(h.iter_res2 / bn);
-    info->true_residual = std::sqrt(h.true_res2 / bn);
+    // the residual of eq. (2) for the whole solution (with even-odd
+    // preconditioning too; the iterated residual is then the Schur system's)
+    info->true_residual = eo ? std::sqrt(h.full_res2 / (h.bfull2 > 0 ? h.bfull2 : 1.0))
+                             : std::sqrt(h.true_res2 / bn);
     info->seconds = 0.0;
   }
   h.status = SLOT_EMPTY;

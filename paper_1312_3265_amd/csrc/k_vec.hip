@@ -143,18 +143,31 @@ ru_accumulate_kernel(const Geom g, const SlotState* st, const int* mask, double2
   st_site<XP, NC>(xlo + off, g.Vp, i, z);
 }
 
+// part: ||r||^2 of the normal equations being iterated.  Even-odd (part_f
+// and part_g non-null): with init, ||M^dag chi||^2 = sum f + sum g; later,
+// eq. (2)'s own residual ||b - A x||^2 = d^2 sum f + sum g (f: ||r^||^2 of the
+// Schur system, g: ||M_eo^dag r^||^2) decides convergence, and while it is
+// not met the Schur system's target is lowered in proportion.
 __global__ void ru_finish_kernel(SlotState* st, const int* mask, const double* __restrict__ part,
-                                 int nbp, int k0, double ncomp, int rescale, int max_cand,
-                                 int init, int par) {
+                                 const double* __restrict__ part_f,
+                                 const double* __restrict__ part_g, int nbp, int k0, double ncomp,
+                                 int rescale, int max_cand, int init, int par) {
   __shared__ double red[16];
   const int k = k0 + blockIdx.x;
   SlotState* s = st + k;
   if (!ru_selected(st, mask, k)) return;
   const double rr = sum_partials(part + (size_t)k * nbp, nbp, red);
+  const bool eo = part_f != nullptr;
+  double f2 = 0.0, g2 = 0.0;
+  if (eo) {
+    f2 = sum_partials(part_f + (size_t)k * nbp, nbp, red);
+    g2 = sum_partials(part_g + (size_t)k * nbp, nbp, red);
+  }
   if (threadIdx.x != 0) return;
   if (init) {
     s->bnorm2 = rr;
     s->thr2 = s->tol * s->tol * rr;
+    if (eo) s->bfull2 = f2 + g2;
   } else {
     s->ru += 1;
     s->apps += 1;
@@ -162,7 +175,17 @@ __global__ void ru_finish_kernel(SlotState* st, const int* mask, const double* _
   s->ru_iter = s->iter;
   s->true_res2 = rr;
   if (!isfinite(rr)) { s->flags |= 1; s->status = SLOT_FAILED; return; }
-  if (rr <= s->thr2) { s->status = SLOT_DONE; return; }
+  if (eo && !init) {
+    const double d = s->mass + 4.0;
+    const double full2 = d * d * f2 + g2;
+    const double goal = s->tol * s->tol * s->bfull2;
+    s->full_res2 = full2;
+    if (full2 <= goal) { s->status = SLOT_DONE; return; }
+    if (rr <= s->thr2 && isfinite(full2)) s->thr2 = 0.25 * rr * goal / full2;
+  } else if (rr <= s->thr2) {
+    s->status = SLOT_DONE;
+    return;
+  }
   if (s->flags) { s->status = SLOT_FAILED; return; }
   if (!init && s->stop[par] && !s->want_ru) {
     // the iterated residual met tol but the true residual did not
@@ -296,12 +319,12 @@ void launch_ru_accumulate(int prec, int nc, const Geom& g, const SlotState* st, 
                                        (const typename PP::S*)p0, nbp, k0, nrhs));
 }
 
-void launch_ru_finish(SlotState* st, const int* mask, const double* part, int nbp, int k0,
-                      int nrhs, double ncomp, int rescale, int max_cand, int init, int par,
-                      hipStream_t s) {
+void launch_ru_finish(SlotState* st, const int* mask, const double* part, const double* part_f,
+                      const double* part_g, int nbp, int k0, int nrhs, double ncomp, int rescale,
+                      int max_cand, int init, int par, hipStream_t s) {
   if (nrhs == 0) return;
-  hipLaunchKernelGGL(ru_finish_kernel, dim3(nrhs), dim3(64), 0, s, st, mask, part, nbp, k0, ncomp,
-                     rescale, max_cand, init, par);
+  hipLaunchKernelGGL(ru_finish_kernel, dim3(nrhs), dim3(64), 0, s, st, mask, part, part_f, part_g,
+                     nbp, k0, ncomp, rescale, max_cand, init, par);
 }
 
 void launch_ru_convert(int prec, int nc, const Geom& g, const SlotState* st, const int* mask,

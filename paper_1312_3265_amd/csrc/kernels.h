@@ -28,9 +28,10 @@ void launch_p_update(int prec, int nc, const Geom& g, SlotState* st, int par, co
 void launch_ru_accumulate(int prec, int nc, const Geom& g, const SlotState* st, const int* mask,
                           double* xhi, void* xlo, const void* p0, int nbp, int k0, int nrhs,
                           hipStream_t s);
-void launch_ru_finish(SlotState* st, const int* mask, const double* part, int nbp, int k0,
-                      int nrhs, double ncomp, int rescale, int max_cand, int init, int par,
-                      hipStream_t s);
+// part_f, part_g: the even-odd norms (null otherwise), see ru_finish_kernel
+void launch_ru_finish(SlotState* st, const int* mask, const double* part, const double* part_f,
+                      const double* part_g, int nbp, int k0, int nrhs, double ncomp, int rescale,
+                      int max_cand, int init, int par, hipStream_t s);
 void launch_ru_convert(int prec, int nc, const Geom& g, const SlotState* st, const int* mask,
                        const double* rhi, void* rlo, void* p, const void* p1, double* part, int nbp,
                        int init, int k0, int nrhs, hipStream_t s);

@@ -26,6 +26,8 @@ struct SlotState {
   double rho_max;    // largest ||r_lo||^2 since the latest reliable update
   double delta2;     // request a reliable update once rho <= delta2 * rho_max (0: never)
   double alpha[2];   // alpha of the latest iteration of each parity (x is updated in pairs)
+  double bfull2;     // even-odd: ||M^dag chi||^2, the b of eq. (2) for the whole lattice
+  double full_res2;  // even-odd: ||b - A x||^2 of eq. (2) at the latest reliable update
   int32_t stop[2];   // ring: 1 = frozen until the next reliable update
   int32_t status;    // 0 empty, 1 running, 2 converged, 3 failed
   int32_t iter;      // CG iterations done
