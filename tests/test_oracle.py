@@ -21,6 +21,7 @@ import synth
 from oracle import dense, freefield, gauge, lattice, solvers
 from oracle import staggered_wilson as SW
 from oracle import evenodd as EO
+from oracle import spectroscopy as SP
 from oracle import wilson as W
 
 RNG = np.random.default_rng(12345)
@@ -412,3 +413,35 @@ def test_evenodd_more_than_halves_cg_iterations():
     assert i0["status"] == solvers.CONVERGED and i1["status"] == solvers.CONVERGED
     assert i1["iterations"] < 0.5 * i0["iterations"]
     assert np.linalg.norm(x1 - x0) / np.linalg.norm(x0) < 1e-5
+
+
+# --------------------------------------------------------- pion correlator
+def test_pion_correlator_free_field_closed_form():
+    """Propagators solved by the oracle's CG at U = 1 against the momentum-space
+    closed form (antiperiodic time, so p4 != 0 and the spectrum has no zero)."""
+    dims = (4, 4, 4, 8)
+    bc = (1, 1, 1, -1)
+    U = np.zeros(synth.site_shape(dims) + (4, 3, 3), dtype=np.complex128)
+    U[...] = np.eye(3)
+    m = 0.2
+    props = []
+    for a in range(12):
+        chi = synth.point_source(dims, synth.WILSON, a)
+        x, info = solvers.cgnr(synth.WILSON, U, chi, m, 1e-12, 5000, bc=bc)
+        assert info["status"] == solvers.CONVERGED
+        props.append(x)
+    C = SP.pion_correlator(np.stack(props))
+    ref = SP.free_pion_correlator(dims, m, bc)
+    assert np.abs(C - ref).max() / ref.max() < 1e-9
+    # time reflection of the free field: C(t) = C(L4 - t)
+    assert np.abs(C[1:] - C[1:][::-1]).max() / C.max() < 1e-9
+
+
+def test_effective_mass_of_a_cosh_is_its_mass():
+    L, mass = 16, 0.37
+    t = np.arange(L)
+    C = 2.5 * np.cosh(mass * (t - L / 2))
+    meff = SP.effective_mass(C)
+    # t = 0 is the wrap-around kink of the periodic cosh: no real solution there
+    assert np.abs(meff[1:] - mass).max() < 1e-12 and np.isnan(meff[0])
+    assert np.isnan(SP.effective_mass(np.array([1.0, 5.0, 1.0, 5.0]))[1])
