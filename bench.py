@@ -265,6 +265,7 @@ def evenodd_wilson(lq, fields, src, masses, dims, mc, prec, links, stream, t64w)
 
     n = len(masses[0])
     out = {}
+    props0 = None
     for eo in (0, 1):
         opts = lq.solve_opts(precision=prec, links=links, poll_interval=16, use_graph=1,
                              evenodd=eo)
@@ -289,6 +290,7 @@ def evenodd_wilson(lq, fields, src, masses, dims, mc, prec, links, stream, t64w)
                     for g, x in zip(fields, res) for k in range(n))
         if worst > TOL:
             raise RuntimeError(f"even-odd={eo}: eq. (2) residual {worst:.2e} above {TOL}")
+        props0 = res[0]
         out["evenodd" if eo else "unpreconditioned"] = {
             "solves_per_s": round(len(fields) * n / el, 2),
             "mean_iterations": round(float(np.mean(its)), 1),
@@ -317,6 +319,40 @@ def evenodd_wilson(lq, fields, src, masses, dims, mc, prec, links, stream, t64w)
     out["fp64_single_rhs"] = {"solves_per_s_unpreconditioned": round(rate0, 2),
                               "solves_per_s_evenodd": round(rate1, 2),
                               "speedup": round(rate1 / rate0, 2), "iterations_evenodd": it64e}
+    return out, props0
+
+
+def pion_section(lq, lat, props, masses, stream):
+    """Fig. 1(a)'s observable for the Wilson part of field 0: the pion
+    correlator of the 12 point-source propagators at each mass, its effective
+    mass averaged over t in [L4/4, L4/2), and the device reduction's rate
+    (propagator bytes read per second, HIP events on the stream)."""
+    import numpy as np
+    import torch
+    L4 = lat.dims[3]
+    out = {"m_eff_window": [L4 // 4, L4 // 2 - 1], "per_mass": []}
+    for di, d in enumerate(DELTAS):
+        p = props[12 * di:12 * di + 12]
+        C, meff = lq.pion_correlator(lat, p, stream=stream)
+        w = meff[L4 // 4:L4 // 2]
+        out["per_mass"].append({"delta": d, "mass": masses[12 * di],
+                                "m_eff": round(float(np.nanmean(w)), 5),
+                                "m_pi2": round(float(np.nanmean(w)) ** 2, 5),
+                                "C_over_C0": [round(float(c / C[0]), 8) for c in C[:L4 // 2 + 1]]})
+    p = props[:12]
+    reps = 20
+    lq.pion_correlator(lat, p, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record()
+        for _ in range(reps):
+            lq.pion_correlator(lat, p, stream=stream)
+        e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 12 * lat.volume * 12 * 16
+    out["correlator_ms_incl_host_sync"] = round(ms, 4)
+    out["correlator_GBs_incl_host_sync"] = round(nbytes / (ms * 1e-3) / 1e9, 1)
     return out
 
 
@@ -556,8 +592,11 @@ def main():
     mixed_ru = {n: {d: float(np.mean(v)) for d, v in dd.items()} for n, dd in mixed_ru.items()}
 
     # ------------------------------- even-odd preconditioned Wilson (beside)
-    eo_w = evenodd_wilson(lq, fields, src, masses, dims, mc, prec, links, stream, t64["wilson"])
+    eo_w, props0 = evenodd_wilson(lq, fields, src, masses, dims, mc, prec, links, stream,
+                                  t64["wilson"])
     log(f"even-odd Wilson: {eo_w}")
+    pion = pion_section(lq, lat, props0, masses[0], stream)
+    log(f"pion: {pion['per_mass'][0]['m_eff']} ... {pion['correlator_GBs_incl_host_sync']} GB/s")
 
     # --------------------------------------------- dominant kernel roofline
     reps = 50
@@ -617,6 +656,7 @@ def main():
             "dslash_fp64_us": {"wilson": round(ms64 * 1e3, 1), "staggered_wilson_corners": round(ms64_sw * 1e3, 1)},
         },
         "evenodd_wilson": eo_w,
+        "pion_wilson_field0": pion,
         "mixed_iterations_field0": mixed_iters,
         "mixed_reliable_updates_field0": mixed_ru,
         "paper_context": {

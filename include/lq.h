@@ -305,6 +305,21 @@ void lq_batch_destroy(lq_batch* b);
 int lq_tuned_launch(const lq_gauge* g, const lq_dirac* d, int32_t precision, int32_t links,
                     int32_t nrhs, int32_t* rhs_per_thread, int32_t* window);
 
+/* ----------------------------------------------------- pion correlator
+ * The Wilson pion correlator behind the m_pi^2 against m plot (Fig. 1(a),
+ * Sec. 3), read as the pseudoscalar two-point function of the point-source
+ * propagators G(x, 0) = M^{-1} chi^(alpha) (the solutions of eq. (2)): by
+ * gamma_5-hermiticity C(t) = sum over x vec, the nsrc propagators and their
+ * 12 components of |G(x vec, t)|^2.  props: nsrc device canonical complex128
+ * Wilson fields back to back (as lq_cg_solve_batch returns them).  corr[t]
+ * (host, L4 entries) receives C(t) (FP64, summed in a fixed order); meff (host,
+ * may be NULL) the periodic effective mass arccosh((C(t-1) + C(t+1)) / (2 C(t))),
+ * NaN where that argument is below 1.  `ws` is device scratch of
+ * lq_pion_workspace_bytes.  Synchronises `stream`. */
+size_t lq_pion_workspace_bytes(const lq_lattice* lat);
+int lq_pion_correlator(const lq_lattice* lat, int32_t nsrc, const void* props, double* corr,
+                       double* meff, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------- condition number
  * Lanczos with full reorthogonalisation (classical Gram-Schmidt, twice) on
  * A = M^dag M from the caller's start vector v0 (device canonical complex128),

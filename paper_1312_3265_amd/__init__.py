@@ -103,6 +103,8 @@ def lib():
         "lq_apply": ([P, P, I32, I32, I32, P, P, P, SZ, P], I32),
         "lq_schur_workspace_bytes": ([P, I32], SZ),
         "lq_schur_apply": ([P, P, I32, I32, I32, P, P, P, SZ, P], I32),
+        "lq_pion_workspace_bytes": ([P], SZ),
+        "lq_pion_correlator": ([P, I32, P, P, P, P, SZ, P], I32),
         "lq_time_dslash": ([P, P, I32, I32, I32, I32, I32, I32, I32, P, SZ, P, P], I32),
         "lq_time_dslash_workspace_bytes": ([P, I32, I32, I32], SZ),
         "lq_tuned_launch": ([P, P, I32, I32, I32, P, P], I32),
@@ -253,6 +255,25 @@ def schur_apply(gauge, mass, psi, dagger=False, precision=F64, links=0, stream=N
                                 _ptr(out), _ptr(ws), nb, _stream(stream)))
     _stream_sync(stream)
     return out
+
+
+def pion_correlator(lattice, props, stream=None):
+    """(C, m_eff): the Wilson pion correlator of point-source propagators
+    props (leading source axis, canonical Wilson fields) and its periodic
+    effective mass, numpy arrays of length L4."""
+    import numpy as np
+    torch = _torch()
+    p = _device_tensor(props, torch.complex128)
+    L4 = lattice.dims[3]
+    corr = np.zeros(L4)
+    meff = np.zeros(L4)
+    nb = int(lib().lq_pion_workspace_bytes(lattice._h))
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    _check(lib().lq_pion_correlator(lattice._h, p.shape[0], _ptr(p),
+                                    corr.ctypes.data_as(ctypes.c_void_p),
+                                    meff.ctypes.data_as(ctypes.c_void_p), _ptr(ws), nb,
+                                    _stream(stream)))
+    return corr, meff
 
 
 def time_dslash(gauge, formulation, mass, dagger=False, r=1.0, g55=G55_CORNERS, precision=F64,

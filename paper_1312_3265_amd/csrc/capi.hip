@@ -439,6 +439,43 @@ int lq_cg_solve_batch(const lq_gauge* g, int32_t formulation, int32_t g55_mode, 
   });
 }
 
+// ------------------------------------------------------ pion correlator
+size_t lq_pion_workspace_bytes(const lq_lattice* lat) {
+  if (!lat) return 0;
+  const int L4 = lat->g.L[3];
+  Carver c(nullptr);
+  c.take((size_t)L4 * pion_blocks_per_slice(L4) * sizeof(double));
+  c.take((size_t)L4 * sizeof(double));
+  return c.size();
+}
+
+int lq_pion_correlator(const lq_lattice* lat, int32_t nsrc, const void* props, double* corr,
+                       double* meff, void* ws, size_t ws_bytes, void* stream) {
+  return guard([&] {
+    need(lat && props && corr && ws, "null argument");
+    need(nsrc >= 1, "nsrc must be >= 1");
+    const size_t nb = lq_pion_workspace_bytes(lat);
+    if (ws_bytes < nb) throw Error(LQ_ERR_WORKSPACE, "pion workspace too small: need " + std::to_string(nb));
+    const int L4 = lat->g.L[3];
+    Carver c(ws);
+    double* part = (double*)c.take((size_t)L4 * pion_blocks_per_slice(L4) * sizeof(double));
+    double* dcorr = (double*)c.take((size_t)L4 * sizeof(double));
+    hipStream_t s = S(stream);
+    launch_pion_correlator(lat->g, nsrc, (const double2*)props, part, dcorr, s);
+    check_launch();
+    LQ_HIP(hipMemcpyAsync(corr, dcorr, (size_t)L4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    LQ_HIP(hipStreamSynchronize(s));
+    if (meff) {
+      // periodic cosh effective mass; NaN where no real solution exists
+      for (int t = 0; t < L4; ++t) {
+        const double q = (corr[(t + L4 - 1) % L4] + corr[(t + 1) % L4]) / (2.0 * corr[t]);
+        meff[t] = q >= 1.0 ? std::acosh(q) : std::nan("");
+      }
+    }
+    return LQ_OK;
+  });
+}
+
 // -------------------------------------------------- continuous batching
 struct lq_batch_s {
   Engine e;

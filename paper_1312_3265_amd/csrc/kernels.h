@@ -61,6 +61,12 @@ void launch_plaquette(const Geom& g, const double2* u64, double* part, int nbp, 
                       hipStream_t s);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
+// ---- pion correlator (Wilson point-source propagators, canonical complex128)
+int pion_blocks_per_slice(int L4);
+// part: L4 * pion_blocks_per_slice(L4) doubles; corr: L4 doubles (device)
+void launch_pion_correlator(const Geom& g, int nsrc, const double2* props, double* part,
+                            double* corr, hipStream_t s);
+
 // ---- Lanczos (FP64, one vector of nc planes)
 void launch_lz_dots(const Geom& g, int nc, const double2* V, int nvec, double2* w,
                     const double* alpha_part, int nbp_alpha, double* alpha_out, double* part_h,
