@@ -316,6 +316,26 @@ def evenodd_wilson(lq, fields, src, masses, dims, mc, prec, links, stream, t64w)
     rate1 = 3.0 / sum(t64e.values())
     out["speedup_batched"] = round(out["evenodd"]["solves_per_s"] /
                                    out["unpreconditioned"]["solves_per_s"], 2)
+    # the two even-odd pairs of an iteration alone (HIP events), against their
+    # algorithmic bytes per half site: a pair writes one odd and one even
+    # site per system; links 2 x 4 x 2 directions of 24 B (16-bit 12-real)
+    # or 72 B (FP32 18-real) per pair
+    vec = 12 * {0: 16, 1: 8, 2: 4}[prec] + (4 if prec == lq.Q16 else 0)
+    xv = 12 * (8 if prec == lq.Q16 else {0: 16, 1: 8}[prec])
+    lk = 2 * 8 * (links // 2) * {0: 16, 1: 8, 2: 4}[prec]
+    per = {3: n * (2 * vec + 3 * vec) + lk,                                  # p->w, (w, p)->t
+           4: n * (2 * vec + 2 * vec + 2 * vec + 0.5 * (2 * vec + 2 * xv)) + lk}
+    Vh = fields[0].lattice.volume // 2
+    roof = {}
+    for kern in (3, 4):
+        ms = lq.time_dslash(fields[0], 0, mc["wilson"] + 0.1, precision=prec, links=links, nrhs=n,
+                            reps=20, rhs_per_thread=1, window=0, stream=stream, kernel=kern)
+        roof[kern] = ms
+    def pair(k):
+        gbs = per[k] * Vh / (roof[k] * 1e-3) / 1e9
+        return {"avg_pair_us": round(roof[k] * 1e3, 1), "bytes_per_half_site": per[k],
+                "achieved_GBs": round(gbs, 1), "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4)}
+    out["pairs"] = {"t = M^p + ||t||^2": pair(3), "M^dag t + CG update": pair(4)}
     out["fp64_single_rhs"] = {"solves_per_s_unpreconditioned": round(rate0, 2),
                               "solves_per_s_evenodd": round(rate1, 2),
                               "speedup": round(rate1 / rate0, 2), "iterations_evenodd": it64e}

@@ -224,7 +224,10 @@ int lq_schur_apply(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t
  * stencil of a CG iteration (q = M^dag t fused with r -= alpha q and
  * ||r||^2, and on every other launch with x += alpha' p' + alpha p, the
  * solvers' paired x update; on zeroed solver state) -- the same kernels the
- * solvers launch; `reps` should be even for kernel 2.  rhs_per_thread (1, 2, 4;
+ * solvers launch; `reps` should be even for kernel 2.  kernel = 3 and 4 time
+ * the same two steps of an even-odd preconditioned iteration (Wilson, r = 1,
+ * LQ_FEAT_EO), each a pair of half-lattice launches: t = M^ p with ||t||^2,
+ * and M^dag t fused with the CG update; the average is per pair.  rhs_per_thread (1, 2, 4;
  * FP32/Q16 only) is the number of systems each thread serves, the choice the
  * solvers' autotuner makes per batch; window, the autotuner's other choice,
  * is the block order: w > 0 sweeps windows of w site blocks per XCD over all

@@ -280,7 +280,8 @@ def time_dslash(gauge, formulation, mass, dagger=False, r=1.0, g55=G55_CORNERS, 
                 links=0, nrhs=1, reps=50, rhs_per_thread=1, window=0, stream=None, kernel=None):
     """Average milliseconds per stencil launch (HIP events on the launch stream).
     kernel: 0 = t = M p + ||t||^2, 1 = plain M^dag, 2 = M^dag t with the CG
-    update of r; default 1 if dagger else 0."""
+    update of r; 3, 4 = the even-odd pairs t = M^ p + ||t||^2 and M^dag t with
+    the CG update (per pair); default 1 if dagger else 0."""
     torch = _torch()
     nb = int(lib().lq_time_dslash_workspace_bytes(gauge._h, formulation, precision, nrhs))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")

@@ -297,6 +297,7 @@ size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, in
   c.take((size_t)nrhs * sizeof(SlotState));
   c.take((size_t)nrhs * ncomp_of(formulation) * g->g.Vp * store_bytes(precision == P16 ? P32 : precision));
   c.take(v);
+  c.take(v);   // the odd intermediate of the even-odd pairs
   return c.size();
 }
 
@@ -315,7 +316,9 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     const int nl = links_for(g, precision, links);
     const int nc = ncomp_of(d->formulation);
     const int op = opkind(d->formulation, d->g55_mode);
-    need(kernel >= 0 && kernel <= 2, "kernel selector must be 0, 1 or 2");
+    need(kernel >= 0 && kernel <= 4, "kernel selector must be 0 to 4");
+    const bool eo = kernel >= 3;
+    if (eo) need(d->formulation == LQ_WILSON && d->r == 1.0, "the even-odd pairs are built for Wilson, r = 1");
     const size_t v = (size_t)nrhs * field_bytes(g->g, precision, nc);
     const size_t np = (size_t)nrhs * nbp_of(g->g.V) * sizeof(double);
     Carver c(ws);
@@ -327,14 +330,16 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     SlotState* st = (SlotState*)c.take((size_t)nrhs * sizeof(SlotState));
     void* xlo = c.take((size_t)nrhs * nc * g->g.Vp * store_bytes(precision == P16 ? P32 : precision));
     void* pprev = c.take(v);
+    void* w = c.take(v);
     if (ws_bytes < c.size())
       throw Error(LQ_ERR_WORKSPACE, "timing workspace too small: need " + std::to_string(c.size()));
     const OpArgs oa = make_op(g, d, precision, nl);
     hipStream_t s = S(stream);
     launch_fill_zero(ws, c.size(), s);
+    const Geom vg = eo ? half_geom(g->g) : g->g;   // geometry of the timed fields
     EpiArgs e;
     std::memset(&e, 0, sizeof(e));
-    e.nbp = nbp_of(g->g.V);
+    e.nbp = nbp_of(vg.V);
     e.out = b;
     e.part = part;
     e.rhs_per_thread = rhs_per_thread;
@@ -343,10 +348,14 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     // plain M^dag stencil; 2: the second (q = M^dag t, r -= alpha q, ||r||^2,
     // and on every other launch x += alpha' p' + alpha p, as in the solver's
     // iteration pairs), on zeroed state (alpha = 0: the same loads, stores
-    // and arithmetic)
-    const int epi = kernel == 0 ? EPI_STORE_NORM : kernel == 1 ? EPI_STORE : EPI_CG_UPDATE;
-    if (kernel == 2) {
-      e.stream = stream_cg_vectors(g->g, precision, nc, nrhs);
+    // and arithmetic); 3 and 4: the same two steps of an even-odd
+    // preconditioned iteration, each a pair of half-lattice launches
+    // (t = M^ p with ||t||^2; M^dag t with the CG update), timed per pair
+    const int epi = (kernel == 0 || kernel == 3) ? EPI_STORE_NORM
+                    : kernel == 1                ? EPI_STORE
+                                                 : EPI_CG_UPDATE;
+    if (kernel == 2 || kernel == 4) {
+      e.stream = stream_cg_vectors(vg, precision, nc, nrhs);
       e.r = r;
       e.x = xlo;
       e.p = b;
@@ -355,14 +364,19 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
       e.st = st;
       e.state_mode = 0;
     }
-    launch_stencil(op, precision, nl, kernel != 0, epi, oa, a, e, nrhs, s);   // warm-up
+    const bool dag = kernel == 1 || kernel == 2 || kernel == 4;
+    auto run = [&]() {
+      if (eo) enqueue_schur(g, oa, precision, nl, dag, epi, a, w, e, nrhs, s);
+      else launch_stencil(op, precision, nl, dag, epi, oa, a, e, nrhs, s);
+    };
+    run();   // warm-up
     hipEvent_t t0, t1;
     LQ_HIP(hipEventCreate(&t0));
     LQ_HIP(hipEventCreate(&t1));
     LQ_HIP(hipEventRecord(t0, s));
     for (int k = 0; k < reps; ++k) {
-      e.par = kernel == 2 ? (k & 1) : 0;
-      launch_stencil(op, precision, nl, kernel != 0, epi, oa, a, e, nrhs, s);
+      e.par = (kernel == 2 || kernel == 4) ? (k & 1) : 0;
+      run();
     }
     LQ_HIP(hipEventRecord(t1, s));
     LQ_HIP(hipEventSynchronize(t1));

@@ -142,3 +142,47 @@ def test_eo_refused_outside_wilson_r1():
     with pytest.raises(lq.LQError):
         lq.cg_solve(g, synth.WILSON, 0.5, synth.point_source(dims, synth.WILSON, 0), 1e-8, opts=opts,
                     r=0.7)
+
+
+def test_eo_continuous_batching_alone_vs_in_the_mix():
+    """Requests admitted into free slots while others iterate (even-odd,
+    16-bit) give bitwise the result they give alone."""
+    dims = (8, 8, 8, 8)
+    U, g = _gauge(dims, "near_identity", 2000, eps=0.4359375)
+    opts = lq.solve_opts(precision=lq.Q16, evenodd=1, reliable_interval=48, poll_interval=8)
+    reqs = [(synth.point_source(dims, synth.WILSON, a), m, t)
+            for a, m, t in ((0, -0.3, 1e-8), (5, -0.25, 1e-7), (7, -0.2, 1e-9), (2, -0.28, 1e-8))]
+    alone = [lq.cg_solve(g, synth.WILSON, m, c, t, opts=opts) for c, m, t in reqs]
+    b = lq.Batch(g, synth.WILSON, nslots=2, opts=opts)
+    pending = list(range(len(reqs)))
+    slot_of, results, free = {}, {}, [0, 1]
+    guard = 0
+    while pending or slot_of:
+        while pending and free:
+            k = pending.pop(0)
+            s = free.pop(0)
+            c, m, t = reqs[k]
+            b.load(s, c, m, t)
+            slot_of[s] = k
+        for s, st in enumerate(b.step(16)):
+            if s in slot_of and st in (lq.SLOT_DONE, lq.SLOT_FAILED):
+                results[slot_of.pop(s)] = b.fetch(s)
+                free.append(s)
+        guard += 1
+        assert guard < 10000
+    for k in range(len(reqs)):
+        xm, im = results[k]
+        xa, ia = alone[k]
+        assert im["status"] == lq.OK and im["iterations"] == ia["iterations"]
+        assert torch.equal(xm, xa)
+
+
+def test_eo_pair_timing_modes():
+    dims = (8, 8, 8, 8)
+    U, g = _gauge(dims, "near_identity", 2000, eps=0.4359375)
+    for kern in (3, 4):
+        ms = lq.time_dslash(g, synth.WILSON, -0.3, precision=lq.Q16, links=12, nrhs=5, reps=4,
+                            rhs_per_thread=2, window=-3, kernel=kern)
+        assert 0.0 < ms < 100.0
+    with pytest.raises(lq.LQError):
+        lq.time_dslash(g, synth.STAGGERED_WILSON, -0.3, kernel=3)
