@@ -22,6 +22,7 @@ from oracle import dense, freefield, gauge, lattice, solvers
 from oracle import staggered_wilson as SW
 from oracle import evenodd as EO
 from oracle import spectroscopy as SP
+from oracle import spectrum as SPEC
 from oracle import wilson as W
 
 RNG = np.random.default_rng(12345)
@@ -445,3 +446,29 @@ def test_effective_mass_of_a_cosh_is_its_mass():
     # t = 0 is the wrap-around kink of the periodic cosh: no real solution there
     assert np.abs(meff[1:] - mass).max() < 1e-12 and np.isnan(meff[0])
     assert np.isnan(SP.effective_mass(np.array([1.0, 5.0, 1.0, 5.0]))[1])
+
+
+# ------------------------------------------------------- spectrum of D_SW
+def _multiset(z, nd=8):
+    return sorted(zip(np.round(np.real(z), nd), np.round(np.imag(z), nd)))
+
+
+def test_sw_free_spectrum_closed_form():
+    dims = (4, 4, 4, 4)
+    U = np.zeros(synth.site_shape(dims) + (4, 3, 3), dtype=np.complex128)
+    U[...] = np.eye(3)
+    ev = SPEC.dense_eigenvalues(synth.STAGGERED_WILSON, U, m=0.1)
+    re, im = SPEC.sw_free_real_imag(dims, m=0.1)
+    assert _multiset(ev.real + 1j * np.abs(ev.imag)) == _multiset(re + 1j * im)
+
+
+def test_sw_spectrum_is_closed_under_conjugation():
+    """epsilon-hermiticity (D_SW^dag = epsilon D_SW epsilon) makes the
+    characteristic polynomial real: eigenvalues come in conjugate pairs."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, "haar", 1000)
+    ev = SPEC.dense_eigenvalues(synth.STAGGERED_WILSON, U)
+    assert _multiset(ev, 7) == _multiset(np.conj(ev), 7)
+    near = SPEC.nearest(ev, 0.3, 6)
+    assert np.all(np.diff(np.abs(near - 0.3)) >= 0)
+    assert np.abs(near - 0.3).max() <= np.sort(np.abs(ev - 0.3))[5] + 1e-15
