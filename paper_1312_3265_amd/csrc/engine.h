@@ -16,6 +16,7 @@
 #include "dirac.h"
 #include "kernels.h"
 #include "lq_types.h"
+#include "hessenberg.h"
 #include "stencil.h"
 
 namespace lq {
@@ -207,6 +208,12 @@ void remember_rhs_per_thread(const std::string& key, int k);
 
 // Lanczos with full reorthogonalisation on A = M^dag M.
 size_t lanczos_workspace_bytes(const Geom& g, int formulation, int steps);
+// Eigenvalues of M (the Dirac matrix of d) nearest the real shift sigma by
+// shift-invert Arnoldi; see lq_spectrum.  Returns the number found.
+size_t spectrum_workspace_bytes(const Geom& g, int formulation, int steps);
+int spectrum_run(const lq_gauge_s* g, const lq_dirac* d, double sigma, int steps, double tol,
+                 const void* v0, void* ws, size_t ws_bytes, std::vector<cplx>& eig,
+                 std::vector<double>& resid, hipStream_t s);
 int lanczos_run(const lq_gauge_s* g, const lq_dirac* d, int steps, const void* v0, void* ws,
                 size_t ws_bytes, std::vector<double>& alpha, std::vector<double>& beta,
                 hipStream_t s);
