@@ -629,14 +629,23 @@ def main():
     mixed_iters = {n: {d: float(np.mean(v)) for d, v in dd.items()} for n, dd in mixed_iters.items()}
     mixed_ru = {n: {d: float(np.mean(v)) for d, v in dd.items()} for n, dd in mixed_ru.items()}
 
-    # ------------------------------- even-odd preconditioned Wilson (beside)
-    eo_w, props0 = evenodd_wilson(lq, fields, src, masses, dims, mc, prec, links, stream,
-                                  t64["wilson"])
+    # ------------------ measurements beside the headline (the next rows)
+    def beside(name, fn, *args):
+        # a failure here is reported in the line, in place of that figure
+        try:
+            return fn(*args)
+        except Exception as e:  # noqa: BLE001
+            log(f"{name} failed: {e!r}")
+            return {"error": repr(e)}
+
+    eo_res = beside("even-odd", evenodd_wilson, lq, fields, src, masses, dims, mc, prec, links,
+                    stream, t64["wilson"])
+    eo_w, props0 = eo_res if isinstance(eo_res, tuple) else (eo_res, None)
     log(f"even-odd Wilson: {eo_w}")
-    pion = pion_section(lq, lat, props0, masses[0], stream)
-    spec = spectrum_section(lq, fields[0], dims, stream)
+    pion = (beside("pion", pion_section, lq, lat, props0, masses[0], stream)
+            if props0 is not None else {"error": "no propagators"})
+    spec = beside("spectrum", spectrum_section, lq, fields[0], dims, stream)
     log(f"spectrum: {spec}")
-    log(f"pion: {pion['per_mass'][0]['m_eff']} ... {pion['correlator_GBs_incl_host_sync']} GB/s")
 
     # --------------------------------------------- dominant kernel roofline
     reps = 50
