@@ -286,6 +286,25 @@ __device__ __forceinline__ void st_rec(void* __restrict__ base, int Vp, int i,
   }
 }
 
+// Component q of site i of an FP64 field (one 16-byte plane slab), for code
+// that walks a record component by component.
+template <int CP = 0>
+__device__ __forceinline__ double2 ld_c64(const void* __restrict__ base, int Vp, int i, int q) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc(base), (uint32_t)i * 16u,
+                                                       (uint32_t)q * (uint32_t)Vp * 16u, CP);
+  double2 z;
+  __builtin_memcpy(&z, &v, 16);
+  return z;
+}
+template <int CP = 0>
+__device__ __forceinline__ void st_c64(void* __restrict__ base, int Vp, int i, int q, double2 z) {
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  u4 v;
+  __builtin_memcpy(&v, &z, 16);
+  __builtin_amdgcn_raw_buffer_store_b128(v, rsrc(base), (uint32_t)i * 16u,
+                                         (uint32_t)q * (uint32_t)Vp * 16u, CP);
+}
+
 // Storage words <-> complex values of a policy
 template <class P>
 __device__ __forceinline__ typename P::C dec(const uint32_t* w) {

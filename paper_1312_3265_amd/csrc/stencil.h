@@ -167,7 +167,23 @@ __device__ __forceinline__ double cg_update_site(const EpiArgs& ea, int Vp, int 
     rv[c].x -= a * q[c].x; rv[c].y -= a * q[c].y;
   }
   const double n2 = st_site<Pol, NC, CP>(r, Vp, i, rv);
-  if (ea.par == 1) {   // wavefront-uniform
+  if (ea.par == 1 && Pol::id == 0) {   // wavefront-uniform
+    // FP64: one component at a time, so that the three 48-word records are
+    // never live together (they would spill); the same two multiply-adds
+    double2* x = (double2*)ea.x + (size_t)k * NC * Vp;
+    const double2* pp = (const double2*)ea.pprev + off;
+    const double2* pk = (const double2*)ea.p + off;
+    const double a0 = ea.st[k].alpha[0];
+#pragma unroll 1
+    for (int c = 0; c < NC; ++c) {
+      double2 xv = ld_c64<CP>(x, Vp, i, c);
+      const double2 qv = ld_c64<CP>(pp, Vp, i, c);
+      const double2 pv = ld_c64<CP>(pk, Vp, i, c);
+      xv.x += a0 * qv.x; xv.y += a0 * qv.y;
+      xv.x += (double)a * pv.x; xv.y += (double)a * pv.y;
+      st_c64<CP>(x, Vp, i, c, xv);
+    }
+  } else if (ea.par == 1) {   // wavefront-uniform
     using XP = typename XPol<Pol>::type;
     typename XP::S* x = (typename XP::S*)ea.x + (size_t)k * NC * Vp;
     const R a0 = (R)ea.st[k].alpha[0];
