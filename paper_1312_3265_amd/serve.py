@@ -25,8 +25,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import Batch, Gauge, Lattice, SLOT_DONE, SLOT_FAILED, _torch, solve_opts, \
-    solve_workspace_bytes
+from . import FEAT_CORNERS, FEAT_EO, FEAT_F32, FEAT_Q16, WILSON, Batch, Gauge, Lattice, \
+    SLOT_DONE, SLOT_FAILED, SolveOpts, _torch, solve_opts, solve_workspace_bytes
 
 
 @dataclass
@@ -71,13 +71,17 @@ class SolveServer:
     fields: {dims: canonical gauge field (numpy or torch)}; opts: solver
     options (default FP32 Krylov vectors, 12-real links, FP64 reliable
     updates); mem_budget: bytes of HBM for solver workspaces (all groups);
-    slots: upper bound on slots per group; chunk: iterations per step.
+    slots: upper bound on slots per group; chunk: iterations per step;
+    evenodd: Wilson requests (r = 1) are solved even-odd preconditioned (the
+    gauge fields then carry even-odd link copies); every solution still meets
+    eq. (2)'s residual.
     """
 
     def __init__(self, fields, opts=None, mem_budget=8 << 30, slots=16, chunk=16, r=1.0,
-                 g55=0):
+                 g55=0, evenodd=False):
         self.torch = _torch()
         self.opts = opts or solve_opts(precision=1, links=12, poll_interval=chunk)
+        self.evenodd = bool(evenodd) and r == 1.0
         self.chunk = chunk
         self.r = r
         self.g55 = g55
@@ -89,7 +93,8 @@ class SolveServer:
             dims = tuple(dims)
             lat = Lattice(dims)
             self.lattices[dims] = lat
-            self.gauges[dims] = Gauge(lat, U)
+            feats = FEAT_CORNERS | FEAT_F32 | FEAT_Q16 | (FEAT_EO if self.evenodd else 0)
+            self.gauges[dims] = Gauge(lat, U, feats)
         self.groups = {}
         self.results = []
         self.rejected = []
@@ -99,9 +104,18 @@ class SolveServer:
         self.allocated = 0
 
     # ----------------------------------------------------------- admission
+    def opts_for(self, formulation):
+        """The solver options of a (dims, formulation) group."""
+        if not (self.evenodd and formulation == WILSON):
+            return self.opts
+        o = SolveOpts.from_buffer_copy(self.opts)
+        o.evenodd = 1
+        return o
+
     def per_system_bytes(self, dims, formulation):
-        return solve_workspace_bytes(self.gauges[dims], formulation, self.opts, 2) - \
-            solve_workspace_bytes(self.gauges[dims], formulation, self.opts, 1)
+        o = self.opts_for(formulation)
+        return solve_workspace_bytes(self.gauges[dims], formulation, o, 2) - \
+            solve_workspace_bytes(self.gauges[dims], formulation, o, 1)
 
     def _group(self, dims, formulation):
         key = (dims, formulation)
@@ -111,8 +125,8 @@ class SolveServer:
         share = self.mem_budget // (2 * len(self.gauges))
         per = self.per_system_bytes(dims, formulation)
         nslots = int(min(self.max_slots, max(0, share // max(per, 1))))
-        while nslots > 0 and solve_workspace_bytes(self.gauges[dims], formulation, self.opts,
-                                                   nslots) > share:
+        while nslots > 0 and solve_workspace_bytes(self.gauges[dims], formulation,
+                                                   self.opts_for(formulation), nslots) > share:
             nslots -= 1
         if nslots == 0:
             self.groups[key] = None
@@ -120,7 +134,7 @@ class SolveServer:
         stream = self.torch.cuda.Stream()
         with self.torch.cuda.stream(stream):
             b = Batch(self.gauges[dims], formulation, nslots, r=self.r, g55=self.g55,
-                      opts=self.opts)
+                      opts=self.opts_for(formulation))
         self.allocated += b.nbytes
         g = _Group(key=key, batch=b, stream=stream)
         g.thread = threading.Thread(target=self._worker, args=(g,), daemon=True)

@@ -15,7 +15,9 @@ torch = pytest.importorskip("torch")
 serve = pytest.importorskip("paper_1312_3265_amd.serve")
 
 
-def test_server_poisson_stream_matches_alone_solves():
+@pytest.mark.parametrize("evenodd", [False, True])
+def test_server_poisson_stream_matches_alone_solves(evenodd):
+    """evenodd: Wilson groups solve the even-odd Schur system."""
     dims_choices = [(4, 4, 4, 4), (6, 4, 4, 6)]
     fields = {d: synth.gauge_field(d, "near_identity", 31 + i, 0.436)
               for i, d in enumerate(dims_choices)}
@@ -34,7 +36,8 @@ def test_server_poisson_stream_matches_alone_solves():
                                   d["tol"], arrival=float(t)))
     opts = lq.solve_opts(precision=lq.F32, links=12, poll_interval=8)
     budget = 64 << 20
-    srv = serve.SolveServer(fields, opts=opts, mem_budget=budget, slots=4, chunk=8)
+    srv = serve.SolveServer(fields, opts=opts, mem_budget=budget, slots=4, chunk=8,
+                            evenodd=evenodd)
     results = srv.run(reqs)
     rep = srv.report()
     assert rep["completed"] == len(reqs) and rep["converged"] == len(reqs)
@@ -44,7 +47,8 @@ def test_server_poisson_stream_matches_alone_solves():
     for req in reqs:
         r = by_id[req.id]
         g = srv.gauges[tuple(req.dims)]
-        xa, ia = lq.cg_solve(g, req.formulation, req.mass, req.source, req.tol, opts=opts)
+        xa, ia = lq.cg_solve(g, req.formulation, req.mass, req.source, req.tol,
+                             opts=srv.opts_for(req.formulation))
         assert ia["iterations"] == r.info["iterations"]
         assert torch.equal(xa, r.x)
         rn, _ = solvers.true_residual(req.formulation, fields[tuple(req.dims)], req.source,
