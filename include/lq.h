@@ -327,19 +327,23 @@ int lq_pion_correlator(const lq_lattice* lat, int32_t nsrc, const void* props, d
  * Eigenvalues of the Dirac matrix M of `d` (eq. (2)'s matrix at d->mass;
  * d->mass = 0 gives D itself, as in the low-lying staggered Wilson spectrum
  * of Fig. 1(c), Sec. 3) nearest the real shift sigma, by shift-invert
- * Arnoldi: `steps` Arnoldi steps on (M - sigma)^{-1} from the start vector
- * v0 (device canonical complex128), each application an FP64 CG solve of
- * eq. (2) with mass d->mass - sigma to residual tol, orthogonalised by two
- * classical Gram-Schmidt passes; the eigenvalues mu of the Hessenberg matrix
- * (shifted complex QR on the host) give lambda = sigma + 1/mu.  eig_re/eig_im
- * (host, steps entries) receive *nev values ordered by distance from sigma;
- * resid (host, may be NULL) the Ritz estimates ||(M - sigma)^{-1} u - mu u|| / |mu|
- * (relative; small once converged).  Stops early at an invariant subspace.
- * `ws` is device scratch of lq_spectrum_workspace_bytes.  Synchronises `stream`. */
+ * Krylov-Schur: Arnoldi on (M - sigma)^{-1} from the start vector v0 (device
+ * canonical complex128) to a basis of `steps` vectors, each application an
+ * FP64 CG solve of eq. (2) with mass d->mass - sigma to residual tol,
+ * orthogonalised by two classical Gram-Schmidt passes; then, up to `restarts`
+ * times (0: plain Arnoldi), the projected matrix is brought to Schur form
+ * (host, shifted complex QR), the basis is cut to the steps/2 Ritz vectors
+ * nearest sigma, and Arnoldi extends it again -- stopping once those have
+ * Ritz estimates below 1e3 tol.  The eigenvalues mu of the projected matrix
+ * give lambda = sigma + 1/mu.  eig_re/eig_im (host, steps entries) receive
+ * *nev values ordered by distance from sigma; resid (host, may be NULL) the
+ * Ritz estimates ||(M - sigma)^{-1} u - mu u|| / |mu| (relative).  Stops
+ * early at an invariant subspace.  `ws` is device scratch of
+ * lq_spectrum_workspace_bytes.  Synchronises `stream`. */
 size_t lq_spectrum_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t steps);
-int lq_spectrum(const lq_gauge* g, const lq_dirac* d, double sigma, int32_t steps, double tol,
-                const void* v0, void* ws, size_t ws_bytes, int32_t* nev, double* eig_re,
-                double* eig_im, double* resid, void* stream);
+int lq_spectrum(const lq_gauge* g, const lq_dirac* d, double sigma, int32_t steps,
+                int32_t restarts, double tol, const void* v0, void* ws, size_t ws_bytes,
+                int32_t* nev, double* eig_re, double* eig_im, double* resid, void* stream);
 
 /* ---------------------------------------------------- condition number
  * Lanczos with full reorthogonalisation (classical Gram-Schmidt, twice) on

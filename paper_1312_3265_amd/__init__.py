@@ -106,7 +106,7 @@ def lib():
         "lq_pion_workspace_bytes": ([P], SZ),
         "lq_pion_correlator": ([P, I32, P, P, P, P, SZ, P], I32),
         "lq_spectrum_workspace_bytes": ([P, I32, I32], SZ),
-        "lq_spectrum": ([P, P, D, I32, D, P, P, SZ, P, P, P, P, P], I32),
+        "lq_spectrum": ([P, P, D, I32, I32, D, P, P, SZ, P, P, P, P, P], I32),
         "lq_time_dslash": ([P, P, I32, I32, I32, I32, I32, I32, I32, P, SZ, P, P], I32),
         "lq_time_dslash_workspace_bytes": ([P, I32, I32, I32], SZ),
         "lq_tuned_launch": ([P, P, I32, I32, I32, P, P], I32),
@@ -278,10 +278,11 @@ def pion_correlator(lattice, props, stream=None):
     return corr, meff
 
 
-def spectrum(gauge, formulation, mass, sigma, v0, steps=40, tol=1e-10, r=1.0, g55=G55_CORNERS,
-             stream=None):
+def spectrum(gauge, formulation, mass, sigma, v0, steps=40, tol=1e-10, restarts=0, r=1.0,
+             g55=G55_CORNERS, stream=None):
     """(eigenvalues, Ritz residual estimates) of M at `mass` nearest the real
-    shift sigma by shift-invert Arnoldi (numpy arrays, nearest first)."""
+    shift sigma by shift-invert Krylov-Schur with a basis of `steps` vectors
+    and up to `restarts` restarts (numpy arrays, nearest first)."""
     import numpy as np
     torch = _torch()
     v = _device_tensor(v0, torch.complex128)
@@ -291,7 +292,8 @@ def spectrum(gauge, formulation, mass, sigma, v0, steps=40, tol=1e-10, r=1.0, g5
     re, im, res = np.zeros(steps), np.zeros(steps), np.zeros(steps)
     nev = ctypes.c_int32()
     p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
-    _check(lib().lq_spectrum(gauge._h, ctypes.byref(d), float(sigma), steps, float(tol), _ptr(v),
+    _check(lib().lq_spectrum(gauge._h, ctypes.byref(d), float(sigma), steps, int(restarts),
+                             float(tol), _ptr(v),
                              _ptr(ws), nb, ctypes.byref(nev), p(re), p(im), p(res),
                              _stream(stream)))
     k = nev.value

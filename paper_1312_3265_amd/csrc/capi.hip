@@ -608,21 +608,22 @@ int lq_condition_number(const lq_gauge* g, const lq_dirac* d, int32_t steps, con
 }
 
 size_t lq_spectrum_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t steps) {
-  if (!g || steps < 1 || steps > 500) return 0;
+  if (!g || steps < 2 || steps > 500) return 0;
   if (formulation != LQ_WILSON && formulation != LQ_STAGGERED_WILSON) return 0;
   return spectrum_workspace_bytes(g->g, formulation, steps);
 }
 
-int lq_spectrum(const lq_gauge* g, const lq_dirac* d, double sigma, int32_t steps, double tol,
-                const void* v0, void* ws, size_t ws_bytes, int32_t* nev, double* eig_re,
-                double* eig_im, double* resid, void* stream) {
+int lq_spectrum(const lq_gauge* g, const lq_dirac* d, double sigma, int32_t steps,
+                int32_t restarts, double tol, const void* v0, void* ws, size_t ws_bytes,
+                int32_t* nev, double* eig_re, double* eig_im, double* resid, void* stream) {
   return guard([&] {
     need(g && v0 && ws && nev && eig_re && eig_im, "null argument");
     check_dirac(d);
     need(std::isfinite(sigma), "sigma must be finite");
     std::vector<cplx> eig;
     std::vector<double> res;
-    const int n = spectrum_run(g, d, sigma, steps, tol, v0, ws, ws_bytes, eig, res, S(stream));
+    const int n = spectrum_run(g, d, sigma, steps, restarts, tol, v0, ws, ws_bytes, eig, res,
+                               S(stream));
     for (int k = 0; k < n; ++k) {
       eig_re[k] = eig[k].real();
       eig_im[k] = eig[k].imag();

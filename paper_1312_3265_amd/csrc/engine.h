@@ -211,8 +211,8 @@ size_t lanczos_workspace_bytes(const Geom& g, int formulation, int steps);
 // Eigenvalues of M (the Dirac matrix of d) nearest the real shift sigma by
 // shift-invert Arnoldi; see lq_spectrum.  Returns the number found.
 size_t spectrum_workspace_bytes(const Geom& g, int formulation, int steps);
-int spectrum_run(const lq_gauge_s* g, const lq_dirac* d, double sigma, int steps, double tol,
-                 const void* v0, void* ws, size_t ws_bytes, std::vector<cplx>& eig,
+int spectrum_run(const lq_gauge_s* g, const lq_dirac* d, double sigma, int steps, int restarts,
+                 double tol, const void* v0, void* ws, size_t ws_bytes, std::vector<cplx>& eig,
                  std::vector<double>& resid, hipStream_t s);
 int lanczos_run(const lq_gauge_s* g, const lq_dirac* d, int steps, const void* v0, void* ws,
                 size_t ws_bytes, std::vector<double>& alpha, std::vector<double>& beta,

@@ -744,17 +744,23 @@ int lanczos_run(const lq_gauge_s* gs, const lq_dirac* d, int steps, const void* 
 }
 
 // ============================================================== Arnoldi
-// Shift-invert Arnoldi for the eigenvalues of M nearest sigma: the Krylov
-// space of (M - sigma)^{-1}, each application an FP64 CG solve of eq. (2)
-// with mass m - sigma (the solver engine, one slot), orthogonalised by two
-// classical Gram-Schmidt passes (the Lanczos kernels, complex coefficients);
-// the eigenvalues mu of the Hessenberg matrix give lambda = sigma + 1/mu.
+// Shift-invert Krylov-Schur for the eigenvalues of M nearest sigma: the
+// Krylov space of (M - sigma)^{-1}, each application an FP64 CG solve of
+// eq. (2) with mass m - sigma (the solver engine, one slot), orthogonalised
+// by two classical Gram-Schmidt passes (the Lanczos kernels, complex
+// coefficients).  After `steps` vectors the projected matrix is brought to
+// Schur form, the steps/2 Ritz values of largest modulus (lambda nearest
+// sigma) are moved to its front, and the basis is cut to them plus the last
+// vector, whose coupling becomes one full row of the projected matrix;
+// Arnoldi then extends the basis again.  The eigenvalues mu of the projected
+// matrix give lambda = sigma + 1/mu.
 size_t spectrum_workspace_bytes(const Geom& g, int formulation, int steps) {
   const int nc = ncomp_of(formulation);
   const size_t vec = (size_t)nc * g.Vp * 16;
   const size_t canon = (size_t)g.V * nc * 16;
   Carver c(nullptr);
   c.take(vec * (steps + 1));                                // basis
+  c.take(vec * (steps / 2 + 1));                            // restart: the kept vectors
   c.take(vec);                                              // w
   c.take(canon);                                            // solver input
   c.take(canon);                                            // solver output
@@ -766,28 +772,31 @@ size_t spectrum_workspace_bytes(const Geom& g, int formulation, int steps) {
   return c.size();
 }
 
-int spectrum_run(const lq_gauge_s* gs, const lq_dirac* d, double sigma, int steps, double tol,
-                 const void* v0, void* ws, size_t ws_bytes, std::vector<cplx>& eig,
+int spectrum_run(const lq_gauge_s* gs, const lq_dirac* d, double sigma, int steps, int restarts,
+                 double tol, const void* v0, void* ws, size_t ws_bytes, std::vector<cplx>& eig,
                  std::vector<double>& resid, hipStream_t s) {
   const Geom& g = gs->g;
   const int nc = ncomp_of(d->formulation);
-  if (steps < 1 || steps > 500) throw Error(LQ_ERR_ARG, "steps must be in [1, 500]");
+  if (steps < 2 || steps > 500) throw Error(LQ_ERR_ARG, "steps must be in [2, 500]");
+  if (restarts < 0 || restarts > 1000) throw Error(LQ_ERR_ARG, "restarts must be in [0, 1000]");
   if (!(tol > 0.0 && tol < 1.0)) throw Error(LQ_ERR_ARG, "tol must be in (0, 1)");
   const size_t need = spectrum_workspace_bytes(g, d->formulation, steps);
   if (!ws || ws_bytes < need)
     throw Error(LQ_ERR_WORKSPACE, "spectrum workspace too small: need " + std::to_string(need));
+  const int m = steps, keep = steps / 2;
   const size_t n = (size_t)nc * g.Vp;
   const size_t vec = n * 16;
   const size_t canon = (size_t)g.V * nc * 16;
   Carver c(ws);
-  double2* V = (double2*)c.take(vec * (steps + 1));
+  double2* V = (double2*)c.take(vec * (m + 1));
+  double2* K = (double2*)c.take(vec * (keep + 1));
   double2* w = (double2*)c.take(vec);
   void* cin = c.take(canon);
   void* cout = c.take(canon);
-  double2* h = (double2*)c.take((size_t)(steps + 1) * 16);
-  double* part_h = (double*)c.take((size_t)(steps + 1) * kLzBlocks * 2 * 8);
+  double2* h = (double2*)c.take((size_t)(m + 1) * 16);
+  double* part_h = (double*)c.take((size_t)(m + 1) * kLzBlocks * 2 * 8);
   double* part_n = (double*)c.take((size_t)kLzBlocks * 8);
-  double* bd = (double*)c.take((size_t)(steps + 2) * 8);
+  double* bd = (double*)c.take((size_t)(m + 2) * 8);
   const size_t eb = Engine::workspace_bytes(g, d->formulation, nullptr, 1);
   void* ews = c.take(eb);
   launch_fill_zero(ws, (char*)ews - (char*)ws, s);
@@ -795,71 +804,118 @@ int spectrum_run(const lq_gauge_s* gs, const lq_dirac* d, double sigma, int step
   Engine e;
   e.init(gs, d->formulation, d->g55_mode, d->r, 1, nullptr, ews, eb, s);
 
-  // v_1 = v0 / ||v0||
+  // v_0 = v0 / ||v0||
   launch_field_in(P64, nc, g, v0, 1, w, nbp, 0, 1, s);
   launch_lz_update(g, nc, V, 0, h, w, part_n, kLzBlocks, 1, s);
-  launch_lz_finish(part_n, kLzBlocks, bd + steps, s);
-  launch_lz_normalize(g, nc, w, bd + steps, V, s);
+  launch_lz_finish(part_n, kLzBlocks, bd + m, s);
+  launch_lz_normalize(g, nc, w, bd + m, V, s);
   check_launch();
-  std::vector<cplx> H((size_t)(steps + 1) * steps, cplx(0.0, 0.0));   // (steps+1) x steps
-  std::vector<double2> hh(steps + 1);
-  int m = steps;
-  double beta_last = 0.0;
-  for (int j = 0; j < steps; ++j) {
-    launch_field_out(P64, nc, g, V + (size_t)j * n, cin, 1, nbp, 0, 1, s);
-    check_launch();
-    e.load(0, cin, d->mass - sigma, tol, 100000, s);
-    while (e.running()) e.step(1 << 20, s);
-    lq_solve_info inf;
-    e.fetch(0, cout, &inf, s);
-    if (inf.status != LQ_OK)
-      throw Error(inf.status < 0 ? inf.status : LQ_ERR_BREAKDOWN,
-                  "shift-invert solve " + std::to_string(j) + " did not converge");
-    launch_field_in(P64, nc, g, cout, 1, w, nbp, 0, 1, s);
-    for (int pass = 0; pass < 2; ++pass) {
-      launch_lz_dots(g, nc, V, j + 1, w, nullptr, 0, nullptr, part_h, kLzBlocks, s);
-      launch_lz_reduce(part_h, j + 1, kLzBlocks, h, s);
-      LQ_HIP(hipMemcpyAsync(hh.data(), h, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, s));
-      launch_lz_update(g, nc, V, j + 1, h, w, part_n, kLzBlocks, pass == 1, s);
+  // projected matrix, (m + 1) x m: column j holds the coefficients of
+  // (M - sigma)^{-1} v_j; below the kept block it stays Hessenberg
+  std::vector<cplx> H((size_t)(m + 1) * m, cplx(0.0, 0.0));
+  auto Hat = [&](int r, int col) -> cplx& { return H[(size_t)r * m + col]; };
+  std::vector<double2> hh(m + 1);
+  int j0 = 0, mm = m;
+  double beta = 0.0;
+  std::vector<cplx> T, Q;
+  for (int cycle = 0;; ++cycle) {
+    // extend the basis to mm vectors (mm < m only at an invariant subspace)
+    for (int j = j0; j < m; ++j) {
+      launch_field_out(P64, nc, g, V + (size_t)j * n, cin, 1, nbp, 0, 1, s);
+      check_launch();
+      e.load(0, cin, d->mass - sigma, tol, 100000, s);
+      while (e.running()) e.step(1 << 20, s);
+      lq_solve_info inf;
+      e.fetch(0, cout, &inf, s);
+      if (inf.status != LQ_OK)
+        throw Error(inf.status < 0 ? inf.status : LQ_ERR_BREAKDOWN,
+                    "shift-invert solve " + std::to_string(j) + " did not converge");
+      launch_field_in(P64, nc, g, cout, 1, w, nbp, 0, 1, s);
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_lz_dots(g, nc, V, j + 1, w, nullptr, 0, nullptr, part_h, kLzBlocks, s);
+        launch_lz_reduce(part_h, j + 1, kLzBlocks, h, s);
+        LQ_HIP(hipMemcpyAsync(hh.data(), h, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, s));
+        launch_lz_update(g, nc, V, j + 1, h, w, part_n, kLzBlocks, pass == 1, s);
+        LQ_HIP(hipStreamSynchronize(s));
+        for (int r = 0; r <= j; ++r) Hat(r, j) += cplx(hh[r].x, hh[r].y);
+      }
+      launch_lz_finish(part_n, kLzBlocks, bd + j, s);
+      LQ_HIP(hipMemcpyAsync(&beta, bd + j, 8, hipMemcpyDeviceToHost, s));
       LQ_HIP(hipStreamSynchronize(s));
-      for (int i = 0; i <= j; ++i) H[(size_t)i * steps + j] += cplx(hh[i].x, hh[i].y);
+      check_launch();
+      if (!std::isfinite(beta)) throw Error(LQ_ERR_BREAKDOWN, "Arnoldi produced a non-finite norm");
+      double col = 0.0;
+      for (int r = 0; r <= j; ++r) col = std::fmax(col, std::abs(Hat(r, j)));
+      if (!(beta > 1e-13 * col)) {   // invariant subspace: the basis ends here
+        mm = j + 1;
+        beta = 0.0;
+        break;
+      }
+      Hat(j + 1, j) = beta;
+      launch_lz_normalize(g, nc, w, bd + j, V + (size_t)(j + 1) * n, s);
     }
-    launch_lz_finish(part_n, kLzBlocks, bd + j, s);
-    double beta = 0.0;
-    LQ_HIP(hipMemcpyAsync(&beta, bd + j, 8, hipMemcpyDeviceToHost, s));
-    LQ_HIP(hipStreamSynchronize(s));
+    // Schur form of the projected matrix; Ritz values and estimates
+    T.assign((size_t)mm * mm, cplx(0.0, 0.0));
+    for (int r = 0; r < mm; ++r)
+      for (int col = 0; col < mm; ++col) T[(size_t)r * mm + col] = Hat(r, col);
+    schur_decompose(T, Q, mm);
+    std::vector<std::pair<double, int>> order;   // by |mu| descending
+    for (int r = 0; r < mm; ++r) order.push_back({-std::abs(T[(size_t)r * mm + r]), r});
+    std::sort(order.begin(), order.end());
+    const int want = std::min(keep, mm);
+    bool converged = true;
+    for (int q = 0; q < want; ++q) {
+      const int r = order[q].second;
+      const cplx mu = T[(size_t)r * mm + r];
+      const std::vector<cplx> y = schur_eigenvector(T, Q, mm, r);
+      if (!(beta * std::abs(y[mm - 1]) <= 1e3 * tol * std::abs(mu))) converged = false;
+    }
+    if (mm < m || cycle >= restarts || converged) break;
+    // restart: the wanted Schur vectors first, then cut the basis to them
+    std::vector<char> flag(mm, 0);
+    for (int q = 0; q < keep; ++q) flag[order[q].second] = 1;
+    schur_reorder(T, Q, mm, flag);
+    std::vector<double2> negq(m);
+    for (int q = 0; q < keep; ++q) {
+      // K_q = sum_j Q[j][q] v_j, through w -= sum_j h_j v_j with h = -Q[:, q]
+      for (int r = 0; r < m; ++r) {
+        const cplx z = Q[(size_t)r * m + q];
+        negq[r] = make_double2(-z.real(), -z.imag());
+      }
+      LQ_HIP(hipMemcpyAsync(h, negq.data(), (size_t)m * 16, hipMemcpyHostToDevice, s));
+      launch_fill_zero(K + (size_t)q * n, vec, s);
+      launch_lz_update(g, nc, V, m, h, K + (size_t)q * n, part_n, kLzBlocks, 0, s);
+      LQ_HIP(hipStreamSynchronize(s));   // h is rewritten next round
+    }
+    LQ_HIP(hipMemcpyAsync(V, K, vec * keep, hipMemcpyDeviceToDevice, s));
+    LQ_HIP(hipMemcpyAsync(V + (size_t)keep * n, V + (size_t)m * n, vec, hipMemcpyDeviceToDevice,
+                          s));
     check_launch();
-    if (!std::isfinite(beta)) throw Error(LQ_ERR_BREAKDOWN, "Arnoldi produced a non-finite norm");
-    H[(size_t)(j + 1) * steps + j] = beta;
-    beta_last = beta;
-    double col = 0.0;
-    for (int i = 0; i <= j; ++i) col = std::fmax(col, std::abs(H[(size_t)i * steps + j]));
-    if (!(beta > 1e-13 * col)) {   // invariant subspace: the basis ends here
-      m = j + 1;
-      beta_last = 0.0;
-      break;
-    }
-    if (j + 1 < steps) launch_lz_normalize(g, nc, w, bd + j, V + (size_t)(j + 1) * n, s);
+    // the projected matrix of the kept part: T's leading block, and the
+    // coupling of the carried-over vector as a full row
+    std::vector<cplx> Hn((size_t)(m + 1) * m, cplx(0.0, 0.0));
+    for (int r = 0; r < keep; ++r)
+      for (int col = 0; col < keep; ++col) Hn[(size_t)r * m + col] = T[(size_t)r * m + col];
+    for (int col = 0; col < keep; ++col) Hn[(size_t)keep * m + col] = beta * Q[(size_t)(m - 1) * m + col];
+    H.swap(Hn);
+    j0 = keep;
   }
-  std::vector<cplx> Hm((size_t)m * m);
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) Hm[(size_t)i * m + j] = H[(size_t)i * steps + j];
-  const std::vector<cplx> mu = hessenberg_eigenvalues(Hm, m);
-  std::vector<std::pair<double, int>> order;
+  // every Ritz value of the last projected matrix, nearest sigma first
+  std::vector<std::pair<double, int>> near;
   std::vector<cplx> lam;
   std::vector<double> res;
-  for (const cplx& z : mu) {
-    if (std::abs(z) == 0.0) continue;   // an eigenvalue of M - sigma at infinity: none nearby
-    const std::vector<cplx> y = hessenberg_eigenvector(Hm, m, z);
-    // ||(M - sigma)^{-1} u - mu u|| = beta_m |y_m| for the Ritz vector u
-    res.push_back(beta_last * std::abs(y[m - 1]) / std::abs(z));
-    lam.push_back(sigma + 1.0 / z);
-    order.push_back({std::abs(lam.back() - sigma), (int)lam.size() - 1});
+  for (int r = 0; r < mm; ++r) {
+    const cplx mu = T[(size_t)r * mm + r];
+    if (std::abs(mu) == 0.0) continue;   // an eigenvalue of M - sigma at infinity: none nearby
+    const std::vector<cplx> y = schur_eigenvector(T, Q, mm, r);
+    res.push_back(beta * std::abs(y[mm - 1]) / std::abs(mu));
+    lam.push_back(sigma + 1.0 / mu);
+    near.push_back({std::abs(lam.back() - sigma), (int)lam.size() - 1});
   }
-  std::sort(order.begin(), order.end());
+  std::sort(near.begin(), near.end());
   eig.clear();
   resid.clear();
-  for (const auto& o : order) {
+  for (const auto& o : near) {
     eig.push_back(lam[o.second]);
     resid.push_back(res[o.second]);
   }

@@ -121,3 +121,178 @@ inline std::vector<cplx> hessenberg_eigenvector(const std::vector<cplx>& H, int 
 }
 
 }  // namespace lq
+
+namespace lq {
+
+// Complex Schur decomposition A = Q T Q^H of a general n x n matrix
+// (row-major, in place: A becomes T, upper triangular; Q unitary, row-major):
+// Householder reduction to Hessenberg form, then the shifted QR iteration of
+// hessenberg_eigenvalues with every rotation applied to whole rows and
+// columns and accumulated into Q.
+inline void schur_decompose(std::vector<cplx>& A, std::vector<cplx>& Q, int n) {
+  auto a = [&](int i, int j) -> cplx& { return A[(size_t)i * n + j]; };
+  auto q = [&](int i, int j) -> cplx& { return Q[(size_t)i * n + j]; };
+  Q.assign((size_t)n * n, cplx(0.0, 0.0));
+  for (int i = 0; i < n; ++i) q(i, i) = 1.0;
+  // Householder: column k below the subdiagonal
+  std::vector<cplx> v(n);
+  for (int k = 0; k < n - 2; ++k) {
+    double norm2 = 0.0;
+    for (int i = k + 1; i < n; ++i) norm2 += std::norm(a(i, k));
+    const double alpha = std::sqrt(norm2);
+    if (alpha == 0.0) continue;
+    const cplx x0 = a(k + 1, k);
+    const cplx ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : cplx(1.0, 0.0);
+    for (int i = 0; i < n; ++i) v[i] = 0.0;
+    for (int i = k + 1; i < n; ++i) v[i] = a(i, k);
+    v[k + 1] += ph * alpha;
+    double vn = 0.0;
+    for (int i = k + 1; i < n; ++i) vn += std::norm(v[i]);
+    if (vn == 0.0) continue;
+    // P = I - 2 v v^H / (v^H v); A <- P A P, Q <- Q P
+    for (int j = 0; j < n; ++j) {
+      cplx s = 0.0;
+      for (int i = k + 1; i < n; ++i) s += std::conj(v[i]) * a(i, j);
+      s *= 2.0 / vn;
+      for (int i = k + 1; i < n; ++i) a(i, j) -= v[i] * s;
+    }
+    for (int i = 0; i < n; ++i) {
+      cplx s = 0.0;
+      for (int j = k + 1; j < n; ++j) s += a(i, j) * v[j];
+      s *= 2.0 / vn;
+      for (int j = k + 1; j < n; ++j) a(i, j) -= s * std::conj(v[j]);
+      cplx t = 0.0;
+      for (int j = k + 1; j < n; ++j) t += q(i, j) * v[j];
+      t *= 2.0 / vn;
+      for (int j = k + 1; j < n; ++j) q(i, j) -= t * std::conj(v[j]);
+    }
+    for (int i = k + 2; i < n; ++i) a(i, k) = 0.0;
+  }
+  // shifted QR on the Hessenberg matrix, rotations applied to whole rows and
+  // columns and accumulated into Q
+  const double eps = 1e-15;
+  std::vector<double> cs(n);
+  std::vector<cplx> sn(n);
+  int hi = n - 1, iter = 0, total = 0;
+  while (hi > 0) {
+    int l = hi;
+    while (l > 0 && std::abs(a(l, l - 1)) > eps * (std::abs(a(l, l)) + std::abs(a(l - 1, l - 1))))
+      --l;
+    if (l > 0) a(l, l - 1) = 0.0;
+    if (l == hi) { --hi; iter = 0; continue; }
+    if (++total > 200 * n) throw std::runtime_error("Schur QR did not converge");
+    const cplx aa = a(hi - 1, hi - 1), b = a(hi - 1, hi), c = a(hi, hi - 1), d = a(hi, hi);
+    const cplx half = 0.5 * (aa + d);
+    const cplx disc = std::sqrt(half * half - (aa * d - b * c));
+    const cplx m1 = half + disc, m2 = half - disc;
+    cplx s = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
+    if (++iter % 11 == 0) s = d + std::abs(c);
+    for (int k = l; k <= hi; ++k) a(k, k) -= s;
+    for (int k = l; k < hi; ++k) {
+      const cplx x = a(k, k), y = a(k + 1, k);
+      const double ax = std::abs(x), r = std::hypot(ax, std::abs(y));
+      double cc;
+      cplx ss;
+      if (r == 0.0) { cc = 1.0; ss = 0.0; }
+      else if (ax == 0.0) { cc = 0.0; ss = std::conj(y) / r; }
+      else { cc = ax / r; ss = (x / ax) * std::conj(y) / r; }
+      cs[k] = cc;
+      sn[k] = ss;
+      for (int j = k; j < n; ++j) {
+        const cplx u = a(k, j), w = a(k + 1, j);
+        a(k, j) = cc * u + ss * w;
+        a(k + 1, j) = -std::conj(ss) * u + cc * w;
+      }
+    }
+    for (int k = l; k < hi; ++k) {
+      const double cc = cs[k];
+      const cplx ss = sn[k];
+      const int top = k + 2 < hi ? k + 2 : hi;
+      for (int i = 0; i <= top; ++i) {
+        const cplx u = a(i, k), w = a(i, k + 1);
+        a(i, k) = cc * u + std::conj(ss) * w;
+        a(i, k + 1) = -ss * u + cc * w;
+      }
+      for (int i = 0; i < n; ++i) {
+        const cplx u = q(i, k), w = q(i, k + 1);
+        q(i, k) = cc * u + std::conj(ss) * w;
+        q(i, k + 1) = -ss * u + cc * w;
+      }
+    }
+    for (int k = l; k <= hi; ++k) a(k, k) += s;
+  }
+  for (int i = 1; i < n; ++i)
+    for (int j = 0; j < i; ++j) a(i, j) = 0.0;
+}
+
+// Reorder a complex Schur form T (row-major, with its Q) so that the
+// diagonal entries for which wanted[i] holds come first (their order kept):
+// adjacent entries are exchanged by a rotation that maps the second one's
+// eigenvector onto the first coordinate (Givens swap).
+inline void schur_reorder(std::vector<cplx>& T, std::vector<cplx>& Q, int n,
+                          std::vector<char> wanted) {
+  auto t = [&](int i, int j) -> cplx& { return T[(size_t)i * n + j]; };
+  auto q = [&](int i, int j) -> cplx& { return Q[(size_t)i * n + j]; };
+  int next = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!wanted[i]) continue;
+    for (int j = i; j > next; --j) {
+      // swap diagonal entries j-1 and j
+      const cplx a = t(j - 1, j - 1), b = t(j - 1, j), c = t(j, j);
+      // eigenvector of [[a, b], [0, c]] for c: (b, c - a)
+      cplx x = b, y = c - a;
+      const double r = std::hypot(std::abs(x), std::abs(y));
+      if (r == 0.0) { std::swap(wanted[j - 1], wanted[j]); continue; }
+      x /= r;
+      y /= r;
+      // G = [[x, -conj(y)], [y, conj(x)]] (unitary), T <- G^H T G, Q <- Q G
+      for (int k = 0; k < n; ++k) {   // rows j-1, j: G^H from the left
+        const cplx u = t(j - 1, k), w = t(j, k);
+        t(j - 1, k) = std::conj(x) * u + std::conj(y) * w;
+        t(j, k) = -y * u + x * w;
+      }
+      for (int k = 0; k < n; ++k) {   // columns j-1, j: G from the right
+        const cplx u = t(k, j - 1), w = t(k, j);
+        t(k, j - 1) = u * x + w * y;
+        t(k, j) = -u * std::conj(y) + w * std::conj(x);
+        const cplx qu = q(k, j - 1), qw = q(k, j);
+        q(k, j - 1) = qu * x + qw * y;
+        q(k, j) = -qu * std::conj(y) + qw * std::conj(x);
+      }
+      t(j, j - 1) = 0.0;
+      std::swap(wanted[j - 1], wanted[j]);
+    }
+    ++next;
+  }
+}
+
+// Unit eigenvector of Q T Q^H for the diagonal entry i of the upper
+// triangular T: back substitution in (T - t_ii I) z = 0 with z_i = 1 and
+// z_j = 0 beyond i, then y = Q z.
+inline std::vector<cplx> schur_eigenvector(const std::vector<cplx>& T, const std::vector<cplx>& Q,
+                                           int n, int i) {
+  std::vector<cplx> z(n, cplx(0.0, 0.0));
+  z[i] = 1.0;
+  const cplx lam = T[(size_t)i * n + i];
+  double norm = 0.0;
+  for (const cplx& v : T) norm = std::fmax(norm, std::abs(v));
+  const double tiny = 1e-14 * (norm > 0.0 ? norm : 1.0);
+  for (int r = i - 1; r >= 0; --r) {
+    cplx acc = 0.0;
+    for (int c = r + 1; c <= i; ++c) acc += T[(size_t)r * n + c] * z[c];
+    cplx den = T[(size_t)r * n + r] - lam;
+    if (std::abs(den) < tiny) den = tiny;
+    z[r] = -acc / den;
+  }
+  std::vector<cplx> y(n, cplx(0.0, 0.0));
+  double s = 0.0;
+  for (int r = 0; r < n; ++r) {
+    for (int c = 0; c <= i; ++c) y[r] += Q[(size_t)r * n + c] * z[c];
+    s += std::norm(y[r]);
+  }
+  s = std::sqrt(s);
+  for (cplx& v : y) v /= s;
+  return y;
+}
+
+}  // namespace lq

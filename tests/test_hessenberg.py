@@ -65,3 +65,45 @@ def test_structured_cases(checker):
     S[3, 2] = 0.0
     ev, _ = _run(checker, S)
     assert _match(ev, np.linalg.eigvals(S)) <= 1e-11 * np.abs(ev).max()
+
+
+@pytest.fixture(scope="module")
+def schur():
+    d = tempfile.mkdtemp()
+    exe = os.path.join(d, "schur_check")
+    subprocess.run(["g++", "-O2", "-std=c++17", os.path.join(HERE, "schur_check.cpp"),
+                    "-o", exe], check=True)
+    return exe
+
+
+@pytest.mark.parametrize("n,seed,structured", [(1, 0, False), (5, 1, False), (30, 2, False),
+                                               (40, 3, True)])
+def test_schur_decomposition_and_reordering(schur, n, seed, structured):
+    """A = Q T Q^H with Q unitary and T upper triangular, before and after
+    moving every other diagonal entry to the front; the eigenvalues are numpy's.
+    structured: the Krylov-Schur shape (triangular block, one full row, then
+    Hessenberg)."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    if structured:
+        k = n // 3
+        A = np.triu(A, -1)
+        A[:k, :k] = np.triu(A[:k, :k])
+        A[k, :k] = rng.standard_normal(k) + 1j * rng.standard_normal(k)
+    flags = [i % 2 for i in range(n)]
+    txt = (f"{n}\n" + "\n".join("%.17g %.17g" % (z.real, z.imag) for z in A.ravel())
+           + "\n" + " ".join(map(str, flags)))
+    out = subprocess.run([schur], input=txt, capture_output=True, text=True,
+                         check=True).stdout.strip().splitlines()
+    scale = max(1.0, np.abs(A).max())
+    for line in (out[0], out[n + 1]):
+        e1, e2, e3 = map(float, line.split())
+        assert e1 <= 1e-12 * n * scale and e2 <= 1e-12 * n and e3 == 0.0
+    d0 = np.array([complex(*map(float, l.split())) for l in out[1:n + 1]])
+    d1 = np.array([complex(*map(float, l.split())) for l in out[n + 2:]])
+    assert _match(d0, np.linalg.eigvals(A)) <= 1e-10 * scale
+    # the flagged entries lead, in their original order; the rest follow
+    want = d0[np.array(flags, dtype=bool)]
+    rest = d0[~np.array(flags, dtype=bool)]
+    assert np.abs(d1[:len(want)] - want).max(initial=0.0) <= 1e-10 * scale
+    assert _match(d1[len(want):], rest) <= 1e-10 * scale
