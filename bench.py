@@ -447,8 +447,11 @@ def main():
     ap.add_argument("--reliable-interval", type=int, default=0,
                     help="reliable update at least every this many iterations (0: library default)")
     ap.add_argument("--poll-interval", type=int, default=16)
-    ap.add_argument("--concurrency", type=int, default=2,
+    ap.add_argument("--concurrency", type=int, default=3,
                     help="batches (gauge field x formulation) in flight at once")
+    ap.add_argument("--order", choices=["wilson-first", "interleave"], default="interleave",
+                    help="order in which the batches are taken up (interleave: each Wilson "
+                         "batch followed by the same field's staggered Wilson one)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only time the dominant stencil (the launches a profiler should see)")
@@ -553,9 +556,14 @@ def main():
         import queue
         import threading
         tasks = queue.Queue()
-        for form in (0, 1):            # longer Wilson batches first
+        if a.order == "interleave":    # each Wilson batch beside a staggered Wilson one
             for gi in range(len(fields)):
-                tasks.put((gi, form))
+                tasks.put((gi, 0))
+                tasks.put((gi, 1))
+        else:                          # longer Wilson batches first
+            for form in (0, 1):
+                for gi in range(len(fields)):
+                    tasks.put((gi, form))
         done, errors = [], []
 
         def work(strm, wsc):
