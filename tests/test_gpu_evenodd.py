@@ -186,3 +186,36 @@ def test_eo_pair_timing_modes():
         assert 0.0 < ms < 100.0
     with pytest.raises(lq.LQError):
         lq.time_dslash(g, synth.STAGGERED_WILSON, -0.3, kernel=3)
+
+
+def test_full_size_16x32_schur_and_eo_batch():
+    """The 16^3 x 32 workload field: M^ and M^dag in FP64 against the oracle over
+    the whole field, 16-bit M^ within its roundoff bound, and a 16-bit even-odd
+    batch of the 12 point sources at m_c + 0.1 (the Wilson batch of the
+    benchmark's even-odd comparison, one mass): every full solution meets
+    eq. (2) in the oracle's FP64 recomputation."""
+    from oracle import solvers
+    import json
+    import os
+    wl = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "workloads.json")))
+    dims = tuple(wl["dims"])
+    U, g = _gauge(dims, "near_identity", wl["seed"], eps=wl["eps"])
+    m = wl["m_c"]["wilson"] + 0.1
+    psi = synth.gaussian_field(dims, synth.WILSON, 5)
+    pe = EO.project(psi, EO.EVEN)
+    for dagger in (False, True):
+        out = lq.schur_apply(g, m, psi, dagger=dagger).cpu().numpy()
+        ref = EO.schur_apply(U, pe, m, dagger=dagger)
+        assert _relerr(out, ref) <= 1e-13
+        assert np.abs(EO.project(out, EO.ODD)).max() == 0.0
+    out = lq.schur_apply(g, m, psi, precision=lq.Q16).cpu().numpy()
+    assert _relerr(out, EO.schur_apply(U, pe, m)) <= 1e-4
+    chis = np.stack([synth.point_source(dims, synth.WILSON, a) for a in range(12)])
+    tol = 1e-8
+    x, infos = lq.cg_solve_batch(g, synth.WILSON, [m] * 12, chis, [tol] * 12,
+                                 opts=lq.solve_opts(precision=lq.Q16, evenodd=1))
+    for k in range(12):
+        assert infos[k]["status"] == lq.OK
+        rn, _ = solvers.true_residual(synth.WILSON, U, chis[k], x[k].cpu().numpy(), m)
+        assert rn <= tol
+        assert abs(infos[k]["true_residual"] - rn) <= 1e-3 * tol
