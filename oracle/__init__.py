@@ -19,5 +19,12 @@ Modules:
   condition number (Sec. 3);
 * ``freefield`` -- closed-form free-field spectra (Sec. 3, the 8/sqrt(5) limit);
 * ``dense``    -- dense matrices of the operators on small lattices;
-* ``critical`` -- m_c as the minimiser of the Lanczos lowest eigenvalue.
+* ``critical`` -- m_c as the minimiser of the Lanczos lowest eigenvalue;
+* ``evenodd``  -- even-odd (Schur complement) preconditioned CG for Wilson
+  (footnote to eq. (2), Sec. 3);
+* ``evenodd_sw`` and ``study_sw_evenodd`` -- the same block elimination for
+  staggered Wilson, with inner solves, to measure its cost;
+* ``spectroscopy`` -- the Wilson pion correlator and effective mass (Fig. 1(a));
+* ``spectrum`` -- dense eigenvalues of the Dirac matrix and the free staggered
+  Wilson spectrum (Fig. 1(c)).
 """

@@ -233,3 +233,35 @@ def test_critical_mass_of_the_frozen_workload():
                                   ngolden=6)
         assert abs(mc - w["m_c"][name]) <= 1e-9, (name, mc, w["m_c"][name])
         assert abs(th - w["theta_min_at_m_c"][name]) <= 1e-5 * abs(w["theta_min_at_m_c"][name])
+
+
+def test_full_size_workload_batches_meet_eq2():
+    """Field 0 of the 16^3 x 32 workload in the benchmark's launch
+    configuration: the 36-system Wilson batch (12 point sources x 3 masses) and
+    the 9-system staggered Wilson batch, 16-bit vectors and 12-real links.
+    Every system converges; for one source per mass the oracle recomputes
+    eq. (2)'s residual in FP64 and it meets tol and agrees with the library's."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "workloads.json")) as f:
+        w = json.load(f)
+    dims = tuple(w["dims"])
+    U = synth.gauge_field(dims, "near_identity", w["seed"], w["eps"])
+    g = lq.Gauge(lq.Lattice(dims), U, lq.FEAT_CORNERS | lq.FEAT_Q16)
+    opts = lq.solve_opts(precision=lq.Q16, links=12, poll_interval=16)
+    tol = 1e-8
+    for form, name, nsrc in ((synth.WILSON, "wilson", 12),
+                             (synth.STAGGERED_WILSON, "staggered_wilson", 3)):
+        masses, chis = [], []
+        for d in w["deltas"]:
+            for a in range(nsrc):
+                masses.append(w["m_c"][name] + d)
+                chis.append(synth.point_source(dims, form, a))
+        x, infos = lq.cg_solve_batch(g, form, masses, np.stack(chis), [tol] * len(chis),
+                                     opts=opts)
+        assert all(i["status"] == lq.OK and i["true_residual"] <= tol for i in infos)
+        for j in range(len(w["deltas"])):
+            k = j * nsrc + (j % nsrc)
+            rn, _ = solvers.true_residual(form, U, chis[k], x[k].cpu().numpy(), masses[k])
+            assert rn <= tol, (name, k, rn)
+            assert abs(infos[k]["true_residual"] - rn) <= 1e-3 * tol
