@@ -58,16 +58,16 @@ def bytes_per_site(formulation, precision, links, nrhs, kernel=0):
     """Compulsory HBM bytes per site of one stencil launch over nrhs fields:
     the links (and corners) once, and per RHS: kernel 0 (t = M p + ||t||^2)
     reads p and writes t; kernel 2 (q = M^dag t, r -= alpha q, ||r||^2) reads
-    t and reads and writes r, and on every other launch also reads p_{k-1}
-    and p_k and reads and writes x (FP32 under 16-bit storage) -- per launch
-    on average 4 vectors and one x."""
+    t and reads and writes r, and on every fourth launch also reads the four
+    search directions of the group and reads and writes x (FP32 under 16-bit
+    storage) -- per launch on average 4 vectors and half an x."""
     nc = 12 if formulation == 0 else 3
     per = {0: 16, 1: 8, 2: 4}[precision]
     vec = nc * per + (4 if precision == 2 else 0)            # Q16: per-site float scale
     xvec = nc * (8 if precision == 2 else per)
     link = 4 * (links // 2) * per                            # FP64: 12 = rows 0, 1 read
     corner = 0 if formulation == 0 else 8 * 9 * (4 if precision == 2 else per)
-    per_rhs = 2 * vec if kernel == 0 else 4 * vec + xvec
+    per_rhs = 2 * vec if kernel == 0 else 4 * vec + xvec // 2
     return nrhs * per_rhs + link + corner
 
 
@@ -94,7 +94,7 @@ def stored_traffic(storage, links, cfg):
         with open(PROFILE_JSON) as f:
             p = json.load(f)
     except OSError:
-        return None
+        return None, None
     if (p.get("source_sha256") != stencil_source_hash() or p.get("storage") != storage
             or p.get("links") != links or p.get("rhs_per_thread") != cfg[0]
             or p.get("nrhs") != NRHS_W):
@@ -104,7 +104,7 @@ def stored_traffic(storage, links, cfg):
     return p["fetch_bytes_per_launch"] + p["write_bytes_per_launch"], p.get("window")
 
 
-def roofline(lq, g0, lat, mc, prec, links, storage, cfg, stream, reps=50):
+def roofline(lq, g0, lat, mc, prec, links, storage, cfg, stream, reps=48):
     """Average launch time (HIP events on `stream`) of the batched CG's
     dominant kernel -- the Wilson stencil q = M^dag t fused with the x and r
     updates and ||r||^2, over the 36 systems of one field, in the launch
@@ -127,8 +127,8 @@ def roofline(lq, g0, lat, mc, prec, links, storage, cfg, stream, reps=50):
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
         "traffic_counters_window": traffic_window,
         "kernel": (f"stencil_kernel<WilsonOpR1<{pol}, {links}, true>, CG_UPDATE, K={K}>: "
-                   f"q = M^dag t, r -= alpha q, ||r||^2, x += alpha' p' + alpha p every "
-                   f"other launch; {NRHS_W} systems; average of the pair"),
+                   f"q = M^dag t, r -= alpha q, ||r||^2, x += the four steps of the group every "
+                   f"fourth launch; {NRHS_W} systems; average over the group"),
         "rhs_per_thread": K, "window": win,
         "avg_launch_us": round(ms * 1e3, 2),
         "algorithmic_bytes_per_site": per_site,
@@ -325,7 +325,7 @@ def evenodd_wilson(lq, fields, src, masses, dims, mc, prec, links, stream, t64w)
     xv = 12 * (8 if prec == lq.Q16 else {0: 16, 1: 8}[prec])
     lk = 2 * 8 * (links // 2) * {0: 16, 1: 8, 2: 4}[prec]
     per = {3: n * (2 * vec + 3 * vec) + lk,                                  # p->w, (w, p)->t
-           4: n * (2 * vec + 2 * vec + 2 * vec + 0.5 * (2 * vec + 2 * xv)) + lk}
+           4: n * (2 * vec + 2 * vec + 2 * vec + 0.25 * (4 * vec + 2 * xv)) + lk}
     Vh = fields[0].lattice.volume // 2
     roof = {}
     for kern in (3, 4):

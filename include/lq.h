@@ -125,7 +125,8 @@ typedef struct {
                                  (0 = default 256: the residual triggers do most
                                  of the work; unused for F64)                    */
   int32_t poll_interval;      /* iterations between host convergence polls
-                                 (0 = default 16; rounded up to even)            */
+                                 (0 = default 16; rounded up to a multiple of 4,
+                                 the solution's update groups)                   */
   int32_t use_graph;          /* 1 = replay steady iteration chunks as hipGraphs */
   int32_t max_restarts;       /* reliable updates allowed after the iterated
                                  residual first meets tol (0 = default 50)       */
@@ -222,9 +223,10 @@ int lq_schur_apply(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t
  * events on `stream`.  kernel = 0 times the first stencil of a CG iteration
  * (t = M p fused with ||t||^2), 1 the plain M^dag stencil, 2 the second
  * stencil of a CG iteration (q = M^dag t fused with r -= alpha q and
- * ||r||^2, and on every other launch with x += alpha' p' + alpha p, the
- * solvers' paired x update; on zeroed solver state) -- the same kernels the
- * solvers launch; `reps` should be even for kernel 2.  kernel = 3 and 4 time
+ * ||r||^2, and on every fourth launch (second in FP64) with x advanced by
+ * the steps of the group, the solvers' x update; on zeroed solver state) --
+ * the same kernels the solvers launch; `reps` should be a multiple of 4 for
+ * kernels 2 and 4.  kernel = 3 and 4 time
  * the same two steps of an even-odd preconditioned iteration (Wilson, r = 1,
  * LQ_FEAT_EO), each a pair of half-lattice launches: t = M^ p with ||t||^2,
  * and M^dag t fused with the CG update; the average is per pair.  rhs_per_thread (1, 2, 4;

@@ -298,6 +298,8 @@ size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, in
   c.take((size_t)nrhs * ncomp_of(formulation) * g->g.Vp * store_bytes(precision == P16 ? P32 : precision));
   c.take(v);
   c.take(v);   // the odd intermediate of the even-odd pairs
+  c.take(v);   // two more search directions of the CG update's group of four
+  c.take(v);
   return c.size();
 }
 
@@ -331,6 +333,8 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     void* xlo = c.take((size_t)nrhs * nc * g->g.Vp * store_bytes(precision == P16 ? P32 : precision));
     void* pprev = c.take(v);
     void* w = c.take(v);
+    void* pr1 = c.take(v);
+    void* pr2 = c.take(v);
     if (ws_bytes < c.size())
       throw Error(LQ_ERR_WORKSPACE, "timing workspace too small: need " + std::to_string(c.size()));
     const OpArgs oa = make_op(g, d, precision, nl);
@@ -346,9 +350,9 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     e.window = window;
     // 0: the first matvec of a CG iteration (t = M p with ||t||^2); 1: the
     // plain M^dag stencil; 2: the second (q = M^dag t, r -= alpha q, ||r||^2,
-    // and on every other launch x += alpha' p' + alpha p, as in the solver's
-    // iteration pairs), on zeroed state (alpha = 0: the same loads, stores
-    // and arithmetic); 3 and 4: the same two steps of an even-odd
+    // and on every fourth launch x += the four steps of the group, as in the
+    // solver's iterations), on zeroed state (alpha = 0: the same loads,
+    // stores and arithmetic); 3 and 4: the same two steps of an even-odd
     // preconditioned iteration, each a pair of half-lattice launches
     // (t = M^ p with ||t||^2; M^dag t with the CG update), timed per pair
     const int epi = (kernel == 0 || kernel == 3) ? EPI_STORE_NORM
@@ -359,7 +363,10 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
       e.r = r;
       e.x = xlo;
       e.p = b;
-      e.pprev = pprev;
+      e.pring[0] = pprev;
+      e.pring[1] = precision == P64 ? b : pr1;   // groups of 2 in FP64, else 4
+      e.pring[2] = pr2;
+      e.pring[3] = b;
       e.part_in = part_in;
       e.st = st;
       e.state_mode = 0;
@@ -376,6 +383,11 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     LQ_HIP(hipEventRecord(t0, s));
     for (int k = 0; k < reps; ++k) {
       e.par = (kernel == 2 || kernel == 4) ? (k & 1) : 0;
+      if (kernel == 2 || kernel == 4) {
+        const int G = precision == P64 ? 2 : 4;
+        e.q4 = k % G;
+        e.xstep = e.q4 == G - 1 ? G : 0;
+      }
       run();
     }
     LQ_HIP(hipEventRecord(t1, s));

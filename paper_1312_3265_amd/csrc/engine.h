@@ -149,7 +149,10 @@ struct Engine {
   double *part_f = nullptr, *part_g = nullptr;   // eo: norms behind eq. (2)'s residual
   // device
   double2 *b = nullptr, *xhi = nullptr, *rhi = nullptr, *t64 = nullptr;
-  void *xlo = nullptr, *rlo = nullptr, *p = nullptr, *p1 = nullptr, *t = nullptr;  // p, p1: p_k by parity
+  void *xlo = nullptr, *rlo = nullptr, *t = nullptr;
+  void *p = nullptr, *p1 = nullptr, *p2 = nullptr, *p3 = nullptr;  // the search directions, in turn
+  PRing ring() const { return PRing{{p, p1, p2, p3}}; }
+  int group = 4;   // iterations per x update (2 for FP64: its vectors stay in the last-level cache)
   double *part_t = nullptr, *part_r = nullptr, *part_u = nullptr;
   SlotState* st = nullptr;
   int* mask = nullptr;        // per-slot reliable-update selection

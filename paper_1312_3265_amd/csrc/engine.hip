@@ -195,7 +195,10 @@ void Engine::tune(hipStream_t s) {
   f.state_mode = 0;
   f.part = part_r;
   f.part_in = part_t;
-  f.x = xlo; f.r = rlo; f.p = p; f.pprev = p1;
+  f.x = xlo; f.r = rlo;
+  const PRing rg = ring();
+  for (int j = 0; j < 4; ++j) f.pring[j] = rg.p[j];
+  f.p = p;
   hipEvent_t t0, t1;
   LQ_HIP(hipEventCreate(&t0));
   LQ_HIP(hipEventCreate(&t1));
@@ -213,12 +216,18 @@ void Engine::tune(hipStream_t s) {
       stencil(prec_lo, nl_lo, false, EPI_STORE_NORM, p, e, nslots, s);
       stencil(prec_lo, nl_lo, true, EPI_CG_UPDATE, t, f, nslots, s);
       LQ_HIP(hipEventRecord(t0, s));
-      for (int r = 0; r < 4; ++r) {
-        e.par = f.par = r & 1;   // odd iterations also advance x
-        stencil(prec_lo, nl_lo, false, EPI_STORE_NORM, p, e, nslots, s);
+      for (int r = 0; r < 4; ++r) {   // whole groups: the last iteration also advances x
+        const int q = r % group;
+        e.par = f.par = r & 1;
+        f.q4 = q;
+        f.xstep = q == group - 1 ? group : 0;
+        f.p = rg.p[q];
+        stencil(prec_lo, nl_lo, false, EPI_STORE_NORM, rg.p[q], e, nslots, s);
         stencil(prec_lo, nl_lo, true, EPI_CG_UPDATE, t, f, nslots, s);
       }
       e.par = f.par = 0;
+      f.q4 = f.xstep = 0;
+      f.p = p;
       LQ_HIP(hipEventRecord(t1, s));
       LQ_HIP(hipEventSynchronize(t1));
       check_launch();
@@ -278,7 +287,9 @@ size_t Engine::workspace_bytes(const Geom& g0, int formulation, const lq_solve_o
   }
   if (prec != P64) c.take(vhi);               // t64 (shares t when FP64)
   const size_t vx = (size_t)nslots * nc * g.Vp * store_bytes(prec == P16 ? P32 : prec);
-  c.take(vx); c.take(vlo); c.take(vlo); c.take(vlo); c.take(vlo);   // x_lo, r_lo, p (x2), t
+  c.take(vx); c.take(vlo);                    // x_lo, r_lo
+  const int ndir = prec == P64 ? 2 : 4;       // search directions, one per step of a group
+  for (int k = 0; k < ndir + 1; ++k) c.take(vlo);   // ... and t
   for (int k = 0; k < 3; ++k) c.take((size_t)nslots * nbp * sizeof(double));
   c.take((size_t)nslots * sizeof(SlotState));
   c.take((size_t)nslots * sizeof(int));
@@ -311,8 +322,9 @@ void Engine::init(const lq_gauge_s* g, int form, int g55, double rr, int ns,
   }
   delta = prec_lo == P16 ? 0.1 : (prec_lo == P32 ? 1e-3 : 0.0);
   if (opts && opts->reliable_delta > 0.0 && prec_lo != P64) delta = opts->reliable_delta;
-  poll_every = (poll_every + 1) & ~1;
-  if (poll_every < 2) poll_every = 2;
+  group = prec_lo == P64 ? 2 : 4;
+  poll_every = (poll_every + 3) & ~3;   // whole groups of iterations
+  if (poll_every < 4) poll_every = 4;
   // validate the stencil storage now (throws for a missing feature)
   (void)g->links(prec_lo, nl_lo);
   (void)g->links(P64, 18);
@@ -342,6 +354,8 @@ void Engine::init(const lq_gauge_s* g, int form, int g55, double rr, int ns,
   rlo = c.take(vlo);
   p = c.take(vlo);
   p1 = c.take(vlo);
+  p2 = group == 4 ? c.take(vlo) : nullptr;
+  p3 = group == 4 ? c.take(vlo) : nullptr;
   t = c.take(vlo);
   if (prec_lo == P64) t64 = (double2*)t;
   part_t = (double*)c.take((size_t)ns * nbp * sizeof(double));
@@ -459,7 +473,7 @@ void Engine::load(int slot, const void* chi, double mass, double tol, int maxite
   const double ncomp = (double)nc * g.V;
   launch_ru_finish(st, nullptr, part_u, eo ? part_f : nullptr, eo ? part_g : nullptr, nbp, slot, 1,
                    ncomp, prec_lo != P64, max_cand, 1, 0, s);
-  launch_ru_convert(prec_lo, nc, g, st, nullptr, (const double*)rhi, rlo, p, p1, part_u, nbp, 1, slot,
+  launch_ru_convert(prec_lo, nc, g, st, nullptr, (const double*)rhi, rlo, ring(), part_u, nbp, 1, slot,
                     1, s);
   launch_ru_commit(st, nullptr, part_u, nbp, slot, 1, s);
   check_launch();
@@ -468,12 +482,14 @@ void Engine::load(int slot, const void* chi, double mass, double tol, int maxite
 }
 
 void Engine::enqueue_iterations(int n, hipStream_t s) {
-  // n is even: a chunk starts and ends with p_k in buffer p; x advances on
-  // the odd iterations by both steps of the pair
+  // n is a multiple of four (so of the group size): a chunk starts and ends
+  // with p_k in ring buffer 0; x advances on the last iteration of each
+  // group, by the group's steps
+  const PRing rg = ring();
   for (int it = 0; it < n; ++it) {
-    const int par = it & 1;
-    void* pk = par ? p1 : p;       // p_k
-    void* po = par ? p : p1;       // p_{k-1} on odd iterations; receives p_{k+1}
+    const int par = it & 1, q = it % group;
+    void* pk = rg.p[q];                 // p_k
+    void* pn = rg.p[(q + 1) % group];   // receives p_{k+1}; its old direction is already in x
     EpiArgs e = epi_base();
     e.par = par;
     e.state_mode = 1;
@@ -486,12 +502,15 @@ void Engine::enqueue_iterations(int n, hipStream_t s) {
     f.rhs_per_thread = rhs_per_thread;
     f.window = window;
     f.par = par;
+    f.q4 = q;
+    f.xstep = q == group - 1 ? group : 0;
     f.state_mode = 1;
     f.part = part_r;
     f.part_in = part_t;
-    f.x = xlo; f.r = rlo; f.p = pk; f.pprev = po;
+    f.x = xlo; f.r = rlo; f.p = pk;
+    for (int j = 0; j < 4; ++j) f.pring[j] = rg.p[j];
     stencil(prec_lo, nl_lo, true, EPI_CG_UPDATE, t, f, nslots, s);
-    launch_p_update(prec_lo, nc, vg, st, par, part_r, nbp, pk, po, rlo, 0, nslots, s);
+    launch_p_update(prec_lo, nc, vg, st, par, (q + 1) % group, part_r, nbp, pk, pn, rlo, 0, nslots, s);
   }
 }
 
@@ -499,7 +518,7 @@ void Engine::enqueue_reliable_update(hipStream_t s) {
   const Geom& g = vg;
   const int nl64 = gauge->fp64_links();
   LQ_HIP(hipMemcpyAsync(mask, hmask, sizeof(int) * nslots, hipMemcpyHostToDevice, s));
-  launch_ru_accumulate(prec_lo, nc, g, st, mask, (double*)xhi, xlo, p, nbp, 0, nslots, s);
+  launch_ru_accumulate(prec_lo, nc, g, st, mask, (double*)xhi, xlo, ring(), nbp, 0, nslots, s);
   EpiArgs e = epi_base();
   e.state_mode = 2;
   e.ru_mask = mask;
@@ -528,7 +547,7 @@ void Engine::enqueue_reliable_update(hipStream_t s) {
   }
   launch_ru_finish(st, mask, part_u, eo ? part_f : nullptr, eo ? part_g : nullptr, nbp, 0, nslots,
                    (double)nc * g.V, prec_lo != P64, max_cand, 0, 0, s);
-  launch_ru_convert(prec_lo, nc, g, st, mask, (const double*)rhi, rlo, p, p1, part_u, nbp, 0, 0, nslots,
+  launch_ru_convert(prec_lo, nc, g, st, mask, (const double*)rhi, rlo, ring(), part_u, nbp, 0, 0, nslots,
                     s);
   launch_ru_commit(st, mask, part_u, nbp, 0, nslots, s);
   check_launch();

@@ -45,7 +45,8 @@ constexpr double kGrowth2 = 1e4;   // squared residual growth that forces a reli
 // per-system state step.
 template <class P, int NC>
 __global__ void __launch_bounds__(256)
-p_update_kernel(const Geom g, SlotState* st, int par, const double* __restrict__ part, int nbp,
+p_update_kernel(const Geom g, SlotState* st, int par, int pend_next, const double* __restrict__ part,
+                int nbp,
                 const typename P::S* __restrict__ p, typename P::S* __restrict__ pout,
                 const typename P::S* __restrict__ r, int k0, int nrhs) {
   using C = typename P::C;
@@ -101,9 +102,10 @@ p_update_kernel(const Geom g, SlotState* st, int par, const double* __restrict__
     }
     if (s->iter >= s->maxiter) { s->flags |= 2; stop = 1; }
     s->stop[par ^ 1] = stop;
-    // x is advanced on odd iterations; stopping after an even one leaves
-    // alpha[0] * p (buffer 0) for the reliable update to add
-    if (stop) s->pend = (par == 0);
+    // x is advanced on the last iteration of each group; stopping after
+    // iteration q of a group of G leaves pend_next = (q + 1) % G terms
+    // alpha[j] * p_ring[j] for the reliable update to add
+    if (stop) s->pend = pend_next;
   }
 }
 
@@ -111,8 +113,8 @@ p_update_kernel(const Geom g, SlotState* st, int par, const double* __restrict__
 template <class P, int NC>
 __global__ void __launch_bounds__(256)
 ru_accumulate_kernel(const Geom g, const SlotState* st, const int* mask, double2* __restrict__ xhi,
-                     typename XPol<P>::type::S* __restrict__ xlo,
-                     const typename P::S* __restrict__ p0, int nbp, int k0, int nrhs) {
+                     typename XPol<P>::type::S* __restrict__ xlo, const PRing ring, int nbp,
+                     int k0, int nrhs) {
   using XP = typename XPol<P>::type;
   using C = typename XP::C;
   int sb, kl;
@@ -120,23 +122,33 @@ ru_accumulate_kernel(const Geom g, const SlotState* st, const int* mask, double2
   const int k = k0 + kl;
   if (!ru_selected(st, mask, k)) return;
   const double sc = st[k].scale;
-  const bool pend = st[k].pend != 0;
-  const double a0 = st[k].alpha[0];
+  const int pend = st[k].pend;
   const int i = sb * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
   const size_t off = (size_t)k * NC * g.Vp;
+  const size_t poff = (size_t)k * field_planes<P>(NC) * g.Vp;
   C v[NC], z[NC];
-  typename P::C pv[NC];
+  double2 acc[NC];
   ld_site<XP, NC>(xlo + off, g.Vp, i, v);
-  if (pend) ld_site<P, NC>(p0 + (size_t)k * field_planes<P>(NC) * g.Vp, g.Vp, i, pv);
+#pragma unroll
+  for (int q = 0; q < NC; ++q) acc[q] = make_double2((double)v[q].x, (double)v[q].y);
+  // the steps of an unfinished group, in order
+  for (int j = 0; j < pend; ++j) {
+    typename P::C pv[NC];
+    ld_site<P, NC>((const typename P::S*)ring.p[j] + poff, g.Vp, i, pv);
+    const double aj = st[k].alpha[j];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      acc[q].x += aj * (double)pv[q].x;
+      acc[q].y += aj * (double)pv[q].y;
+    }
+  }
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
     const size_t e = off + (size_t)q * g.Vp + i;
     double2 h = xhi[e];
-    double vx = (double)v[q].x, vy = (double)v[q].y;
-    if (pend) { vx += a0 * (double)pv[q].x; vy += a0 * (double)pv[q].y; }
-    h.x += sc * vx;
-    h.y += sc * vy;
+    h.x += sc * acc[q].x;
+    h.y += sc * acc[q].y;
     xhi[e] = h;
     z[q] = czero<C>();
   }
@@ -204,8 +216,8 @@ template <class P, int NC>
 __global__ void __launch_bounds__(256)
 ru_convert_kernel(const Geom g, const SlotState* st, const int* mask,
                   const double2* __restrict__ rhi, typename P::S* __restrict__ rlo,
-                  typename P::S* __restrict__ p, const typename P::S* __restrict__ p1,
-                  double* __restrict__ part, int nbp, int init, int k0, int nrhs) {
+                  const PRing ring, double* __restrict__ part, int nbp, int init, int k0,
+                  int nrhs) {
   using C = typename P::C;
   using R = typename P::R;
   __shared__ double red[16];
@@ -228,15 +240,16 @@ ru_convert_kernel(const Geom g, const SlotState* st, const int* mask,
       v[q].y = (R)(h.y * inv);
     }
     acc = st_site<P, NC>(rlo + off, g.Vp, i, v);
+    typename P::S* p = (typename P::S*)ring.p[0];
     if (init) {
       C vs[NC];
       ld_site<P, NC>(rlo + off, g.Vp, i, vs);   // p starts as the stored r
       st_site<P, NC>(p + off, g.Vp, i, vs);
     } else {
-      // the current search direction: buffer 1 when the system stopped after
-      // an even iteration, else buffer 0; the next chunk starts in buffer 0
+      // the current search direction: ring buffer pend (where the last p
+      // update wrote it); the next chunk starts in buffer 0
       C pv[NC];
-      ld_site<P, NC>((st[k].pend ? p1 : p) + off, g.Vp, i, pv);
+      ld_site<P, NC>((const typename P::S*)ring.p[st[k].pend] + off, g.Vp, i, pv);
 #pragma unroll
       for (int q = 0; q < NC; ++q) { pv[q].x *= pr; pv[q].y *= pr; }
       st_site<P, NC>(p + off, g.Vp, i, pv);
@@ -298,25 +311,24 @@ load_prepare_kernel(const Geom g, double2* __restrict__ xhi,
     else throw std::runtime_error("unsupported precision/components");               \
   } while (0)
 
-void launch_p_update(int prec, int nc, const Geom& g, SlotState* st, int par, const double* part,
-                     int nbp, const void* p, void* pout, const void* r, int k0, int nrhs,
-                     hipStream_t s) {
+void launch_p_update(int prec, int nc, const Geom& g, SlotState* st, int par, int pend_next,
+                     const double* part, int nbp, const void* p, void* pout, const void* r, int k0,
+                     int nrhs, hipStream_t s) {
   if (nbp * nrhs == 0) return;
   LQ_PREC_NC_SWITCH(prec, nc,
                     hipLaunchKernelGGL((p_update_kernel<PP, NCC>), dim3(nbp * nrhs), dim3(kBlock),
-                                       0, s, g, st, par, part, nbp, (const typename PP::S*)p,
+                                       0, s, g, st, par, pend_next, part, nbp, (const typename PP::S*)p,
                                        (typename PP::S*)pout, (const typename PP::S*)r, k0, nrhs));
 }
 
 void launch_ru_accumulate(int prec, int nc, const Geom& g, const SlotState* st, const int* mask,
-                          double* xhi, void* xlo, const void* p0, int nbp, int k0, int nrhs,
+                          double* xhi, void* xlo, const PRing& ring, int nbp, int k0, int nrhs,
                           hipStream_t s) {
   if (nbp * nrhs == 0) return;
   LQ_PREC_NC_SWITCH(prec, nc,
                     hipLaunchKernelGGL((ru_accumulate_kernel<PP, NCC>), dim3(nbp * nrhs),
                                        dim3(kBlock), 0, s, g, st, mask, (double2*)xhi,
-                                       (typename XPol<PP>::type::S*)xlo,
-                                       (const typename PP::S*)p0, nbp, k0, nrhs));
+                                       (typename XPol<PP>::type::S*)xlo, ring, nbp, k0, nrhs));
 }
 
 void launch_ru_finish(SlotState* st, const int* mask, const double* part, const double* part_f,
@@ -328,14 +340,13 @@ void launch_ru_finish(SlotState* st, const int* mask, const double* part, const 
 }
 
 void launch_ru_convert(int prec, int nc, const Geom& g, const SlotState* st, const int* mask,
-                       const double* rhi, void* rlo, void* p, const void* p1, double* part, int nbp,
+                       const double* rhi, void* rlo, const PRing& ring, double* part, int nbp,
                        int init, int k0, int nrhs, hipStream_t s) {
   if (nbp * nrhs == 0) return;
   LQ_PREC_NC_SWITCH(prec, nc,
                     hipLaunchKernelGGL((ru_convert_kernel<PP, NCC>), dim3(nbp * nrhs),
                                        dim3(kBlock), 0, s, g, st, mask, (const double2*)rhi,
-                                       (typename PP::S*)rlo, (typename PP::S*)p,
-                                       (const typename PP::S*)p1, part, nbp, init, k0, nrhs));
+                                       (typename PP::S*)rlo, ring, part, nbp, init, k0, nrhs));
 }
 
 void launch_ru_commit(SlotState* st, const int* mask, const double* part, int nbp, int k0,

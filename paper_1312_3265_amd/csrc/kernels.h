@@ -11,6 +11,13 @@ namespace lq {
 struct OpArgs;
 struct EpiArgs;
 
+// The search-direction buffers of a CG solve, used in turn: iteration q of a
+// group of G reads p[q] and writes p_{k+1} into p[(q + 1) % G] (G = 4, or 2
+// for FP64; x takes the group's steps on its last iteration).
+struct PRing {
+  void* p[4];
+};
+
 // Threads per block of every site-block kernel; partial-sum arrays hold
 // nbp(V) entries per right-hand side.
 constexpr int kBlock = 256;
@@ -21,19 +28,19 @@ void launch_stencil(int op, int prec, int nl, bool dag, int epi, const OpArgs& o
                     const void* in, const EpiArgs& ea, int nrhs, hipStream_t s);
 
 // ---- CG vector kernels (templated on precision and components)
-void launch_p_update(int prec, int nc, const Geom& g, SlotState* st, int par, const double* part,
-                     int nbp, const void* p, void* pout, const void* r, int k0, int nrhs,
-                     hipStream_t s);
+void launch_p_update(int prec, int nc, const Geom& g, SlotState* st, int par, int pend_next,
+                     const double* part, int nbp, const void* p, void* pout, const void* r, int k0,
+                     int nrhs, hipStream_t s);
 // Reliable-update kernels act on running slots k with mask[k] != 0 (mask may be null).
 void launch_ru_accumulate(int prec, int nc, const Geom& g, const SlotState* st, const int* mask,
-                          double* xhi, void* xlo, const void* p0, int nbp, int k0, int nrhs,
+                          double* xhi, void* xlo, const PRing& ring, int nbp, int k0, int nrhs,
                           hipStream_t s);
 // part_f, part_g: the even-odd norms (null otherwise), see ru_finish_kernel
 void launch_ru_finish(SlotState* st, const int* mask, const double* part, const double* part_f,
                       const double* part_g, int nbp, int k0, int nrhs, double ncomp, int rescale,
                       int max_cand, int init, int par, hipStream_t s);
 void launch_ru_convert(int prec, int nc, const Geom& g, const SlotState* st, const int* mask,
-                       const double* rhi, void* rlo, void* p, const void* p1, double* part, int nbp,
+                       const double* rhi, void* rlo, const PRing& ring, double* part, int nbp,
                        int init, int k0, int nrhs, hipStream_t s);
 void launch_ru_commit(SlotState* st, const int* mask, const double* part, int nbp, int k0,
                       int nrhs, hipStream_t s);

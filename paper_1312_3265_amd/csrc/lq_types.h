@@ -25,7 +25,7 @@ struct SlotState {
   double rho_ru;     // ||r_lo||^2 right after the latest reliable update
   double rho_max;    // largest ||r_lo||^2 since the latest reliable update
   double delta2;     // request a reliable update once rho <= delta2 * rho_max (0: never)
-  double alpha[2];   // alpha of the latest iteration of each parity (x is updated in pairs)
+  double alpha[4];   // alpha of the iterations of the current group of four (x is updated once per group)
   double bfull2;     // even-odd: ||M^dag chi||^2, the b of eq. (2) for the whole lattice
   double full_res2;  // even-odd: ||b - A x||^2 of eq. (2) at the latest reliable update
   int32_t stop[2];   // ring: 1 = frozen until the next reliable update
@@ -38,7 +38,7 @@ struct SlotState {
   int32_t apps;      // applications of A (iterations + reliable updates + setup)
   int32_t ru_iter;   // iteration count at the latest reliable update
   int32_t want_ru;   // frozen because the residual dropped by delta (not converged)
-  int32_t pend;      // frozen after an even iteration: x still lacks alpha[0] * p (buffer 0)
+  int32_t pend;      // terms alpha[j] * p_ring[j], j < pend, that x still lacks (frozen mid-group)
 };
 
 enum SlotStatus { SLOT_EMPTY = 0, SLOT_RUNNING = 1, SLOT_DONE = 2, SLOT_FAILED = 3 };

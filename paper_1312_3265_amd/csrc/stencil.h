@@ -6,12 +6,14 @@
 //   CG_UPDATE   q = op(in) kept in registers; alpha = rho/||t||^2 from the
 //               partials of the previous launch; r -= alpha q; block
 //               partials of ||r||^2                                 (M^dag t)
-//               x is advanced every second iteration, by both steps at once:
-//               x += alpha_{k-1} p_{k-1} + alpha_k p_k on odd iterations
-//               (p is double-buffered), which halves the traffic of x, the
-//               widest vector of a low-precision solve (FP32 under Q16).
-//               The sum is formed in the arithmetic precision, as the two
-//               single steps would be.
+//               x is advanced once per group of G iterations (4 for the
+//               FP32 and 16-bit solves, 2 for FP64), by the G steps at
+//               once: x += sum_j alpha_{k-G+1+j} p_{k-G+1+j} on the group's
+//               last iteration (p rotates through G buffers), which divides
+//               the traffic of x, the widest vector of a low-precision solve
+//               (FP32 under Q16), by G.  The sum is formed in the
+//               arithmetic precision, step after step, as the single steps
+//               would be.
 //   RESID       out = b - op(in), partials of ||out||^2   (FP64 true residual)
 //   LANCZOS     w = op(in) - beta_prev v_prev, partials of Re<v, w>
 // Partial sums are FP64, reduced in a fixed order (wavefront butterfly, then
@@ -44,7 +46,10 @@ struct EpiArgs {
   void* x;                // CG_UPDATE: x_lo
   void* r;                // CG_UPDATE: r_lo
   const void* p;          // CG_UPDATE: p_k
-  const void* pprev;      // CG_UPDATE: p_{k-1} (read on odd iterations)
+  const void* pring[4];   // CG_UPDATE: the ring of search directions of the group
+  int q4;                 // CG_UPDATE: iteration index within its group (alpha[q4] is stored)
+  int xstep;              // CG_UPDATE: 0, or the group size G on the group's last iteration:
+                          // x += sum_{j<G} alpha[j] p_ring[j] (p_ring[G-1] is p)
   const void* b;          // RESID: b (FP64)
   const double* v;        // LANCZOS: v_j
   const double* vprev;    // LANCZOS: v_{j-1}
@@ -144,8 +149,9 @@ template <class Op, int K>
 constexpr int stencil_waves() { return (Op::NC == 12 && K >= 2) ? 3 : Op::kWaves; }
 
 // CG_UPDATE at one site for system k (offset off into the batched fields):
-// r -= alpha q with ||r||^2 returned, and on odd iterations
-// x += alpha_prev p_{k-1} + alpha p_k.  r, p and x are each touched once per
+// r -= alpha q with ||r||^2 returned, and on the last iteration of a group of
+// G x += sum_j alpha_j p_ring[j] (alpha_{G-1} = alpha, p_ring[G-1] = p_k), one
+// direction at a time.  r, p and x are each touched once per
 // launch; CP = kStream marks them non-temporal so that, when the batch's
 // vectors overflow the caches anyway, they do not displace the links and the
 // stencil input from L2.
@@ -167,35 +173,37 @@ __device__ __forceinline__ double cg_update_site(const EpiArgs& ea, int Vp, int 
     rv[c].x -= a * q[c].x; rv[c].y -= a * q[c].y;
   }
   const double n2 = st_site<Pol, NC, CP>(r, Vp, i, rv);
-  if (ea.par == 1 && Pol::id == 0) {   // wavefront-uniform
-    // FP64: one component at a time, so that the three 48-word records are
-    // never live together (they would spill); the same two multiply-adds
+  if (ea.xstep > 0 && Pol::id == 0) {   // wavefront-uniform
+    // FP64: one component at a time, so that the 48-word records are never
+    // live together (they would spill)
     double2* x = (double2*)ea.x + (size_t)k * NC * Vp;
-    const double2* pp = (const double2*)ea.pprev + off;
-    const double2* pk = (const double2*)ea.p + off;
-    const double a0 = ea.st[k].alpha[0];
+    const int G = ea.xstep;
 #pragma unroll 1
     for (int c = 0; c < NC; ++c) {
       double2 xv = ld_c64<CP>(x, Vp, i, c);
-      const double2 qv = ld_c64<CP>(pp, Vp, i, c);
-      const double2 pv = ld_c64<CP>(pk, Vp, i, c);
-      xv.x += a0 * qv.x; xv.y += a0 * qv.y;
-      xv.x += (double)a * pv.x; xv.y += (double)a * pv.y;
+      for (int j = 0; j < G; ++j) {
+        const double aj = j == G - 1 ? (double)a : ea.st[k].alpha[j];
+        const double2 v = ld_c64<CP>((const double2*)ea.pring[j] + off, Vp, i, c);
+        xv.x += aj * v.x; xv.y += aj * v.y;
+      }
       st_c64<CP>(x, Vp, i, c, xv);
     }
-  } else if (ea.par == 1) {   // wavefront-uniform
+  } else if (ea.xstep > 0) {   // wavefront-uniform
     using XP = typename XPol<Pol>::type;
     typename XP::S* x = (typename XP::S*)ea.x + (size_t)k * NC * Vp;
-    const R a0 = (R)ea.st[k].alpha[0];
-    P_C pv[NC], qv[NC];
     typename XP::C xv[NC];
-    ld_site<Pol, NC, CP>((const S*)ea.pprev + off, Vp, i, qv);
-    ld_site<Pol, NC, CP>((const S*)ea.p + off, Vp, i, pv);
     ld_site<XP, NC, CP>(x, Vp, i, xv);
+    // one direction at a time: only x and one record are live
+    const int G = ea.xstep;
+#pragma unroll 1
+    for (int j = 0; j < G; ++j) {
+      const R aj = j == G - 1 ? a : (R)ea.st[k].alpha[j];
+      P_C pv[NC];
+      ld_site<Pol, NC, CP>((const S*)ea.pring[j] + off, Vp, i, pv);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      xv[c].x += a0 * qv[c].x; xv[c].y += a0 * qv[c].y;
-      xv[c].x += a * pv[c].x; xv[c].y += a * pv[c].y;
+      for (int c = 0; c < NC; ++c) {
+        xv[c].x += aj * pv[c].x; xv[c].y += aj * pv[c].y;
+      }
     }
     st_site<XP, NC, CP>(x, Vp, i, xv);
   }
@@ -305,7 +313,7 @@ stencil_kernel(const OpArgs oa, const typename Op::S* __restrict__ in, const Epi
       alpha[kk] = (tt > 0.0 && isfinite(tt) && isfinite(rho)) ? rho / tt : 0.0;
       if (sb == 0 && threadIdx.x == 0) {
         if (!(tt > 0.0 && isfinite(tt))) ea.st[k].flags |= 1;
-        ea.st[k].alpha[ea.par] = alpha[kk];   // read by the next (odd) iteration
+        ea.st[k].alpha[ea.q4] = alpha[kk];   // read on the group's last iteration
       }
     }
   }
