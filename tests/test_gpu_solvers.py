@@ -265,3 +265,38 @@ def test_full_size_workload_batches_meet_eq2():
             rn, _ = solvers.true_residual(form, U, chis[k], x[k].cpu().numpy(), masses[k])
             assert rn <= tol, (name, k, rn)
             assert abs(infos[k]["true_residual"] - rn) <= 1e-3 * tol
+
+
+@pytest.mark.parametrize("formulation", [synth.WILSON, synth.STAGGERED_WILSON])
+def test_grouped_x_update_keeps_every_step(formulation):
+    """FP32 and 16-bit solves advance x once per group of four iterations,
+    FP64 solves once per pair.  A solve cut off after n = 40..43 iterations
+    stops at every position of a group, and its x must still hold all n
+    steps: the FP32 result equals the FP64 iterate after n iterations to FP32
+    roundoff.  With 16-bit storage, reliable updates land mid-group, and a
+    step lost there would cost iterations: the count stays near FP64's."""
+    U, lat, g = _field()
+    chi = synth.point_source(DIMS, formulation, 2)
+    m = MASS[formulation]
+    o32 = lq.solve_opts(precision=lq.F32, links=18)
+    x64 = {}
+    for n in range(39, 44):
+        x64[n], i64 = lq.cg_solve(g, formulation, m, chi, 1e-14, maxiter=n)
+        assert i64["status"] == lq.NOT_CONVERGED and i64["iterations"] == n, i64
+    norm = torch.linalg.vector_norm
+    # a lost step would leave an error the size of one step
+    step = min(norm(x64[n] - x64[n - 1]).item() for n in range(40, 44))
+    for n in range(40, 44):
+        x32, i32 = lq.cg_solve(g, formulation, m, chi, 1e-14, maxiter=n, opts=o32)
+        assert i32["status"] == lq.NOT_CONVERGED and i32["iterations"] == n, i32
+        err = norm(x32 - x64[n]).item()
+        print(f"n={n} |x32 - x64|={err:.3e} smallest step={step:.3e}")
+        assert err <= 0.02 * step, (n, err, step)
+    tol = 1e-8
+    x16, i16 = lq.cg_solve(g, formulation, m, chi, tol, opts=lq.solve_opts(precision=lq.Q16))
+    _, i64 = lq.cg_solve(g, formulation, m, chi, tol)
+    print(f"16-bit {i16['iterations']} iterations, {i16['reliable_updates']} reliable updates; "
+          f"FP64 {i64['iterations']}")
+    assert i16["status"] == lq.OK and i16["reliable_updates"] >= 2
+    assert i16["iterations"] <= 1.1 * i64["iterations"] + 8, (i16, i64["iterations"])
+    assert _res(formulation, U, chi, x16, m) <= tol
