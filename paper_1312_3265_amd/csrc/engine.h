@@ -59,10 +59,11 @@ inline size_t field_bytes(const Geom& g, int prec, int nc) {
   return (size_t)field_planes_host(prec, nc) * g.Vp * store_bytes(prec);
 }
 // Whether the second stencil of a low-precision CG iteration streams its
-// per-system vectors (non-temporal r, p_k, p_{k-1}, x): when those plus t
-// exceed the last-level cache (256 MiB of Infinity Cache on MI355X) none of
-// them survives to the next kernel anyway, and streaming keeps the links and
-// the stencil input in L2; below it they stay cached for the kernels that
+// per-system vectors (non-temporal r, the search directions and x): when an
+// iteration's vectors -- counted as t, r, two directions and x -- exceed the
+// last-level cache (256 MiB of Infinity Cache on MI355X) none of them
+// survives to the next kernel anyway, and streaming keeps the links and the
+// stencil input in L2; below it they stay cached for the kernels that
 // follow.  FP64 kernels always cache.
 constexpr size_t kLastLevelCache = size_t(256) << 20;
 inline int stream_cg_vectors(const Geom& g, int prec, int nc, int nrhs) {
