@@ -475,7 +475,7 @@ def main():
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the workload is a single-GPU batch of "
-              "independent solves (multi-GPU runs are not part of this build)", file=sys.stderr)
+              "independent solves; splitting it across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
