@@ -129,7 +129,11 @@ typedef struct {
                                  the solution's update groups)                   */
   int32_t use_graph;          /* 1 = replay steady iteration chunks as hipGraphs */
   int32_t max_restarts;       /* reliable updates allowed after the iterated
-                                 residual first meets tol (0 = default 50)       */
+                                 residual first meets tol, and in a row without
+                                 halving the true residual (a tol below the
+                                 attainable accuracy then ends LQ_NOT_CONVERGED
+                                 instead of cycling on; so does a true residual
+                                 100x above its best; 0 = default 50)          */
   double reliable_delta;      /* also update once the iterated residual has
                                  dropped by this factor since the last update
                                  (0 = default: 0.1 for Q16, 1e-3 for F32)        */
@@ -281,7 +285,11 @@ int lq_cg_solve_batch(const lq_gauge* g, int32_t formulation, int32_t g55_mode,
  *                    slot's state in states[nslots] (0 empty, 1 running,
  *                    2 converged, 3 failed); synchronises `stream`.
  *   lq_batch_fetch:  copy a finished slot's solution to x (device canonical)
- *                    and its report to info; frees the slot.                  */
+ *                    and its report to info; frees the slot.
+ *   lq_batch_cancel: discard a loaded slot, running or finished, without
+ *                    copying anything out; frees the slot for lq_batch_load.
+ *                    LQ_ERR_STATE if the slot is empty, LQ_ERR_ARG if out of
+ *                    range; synchronises `stream`.                            */
 int lq_batch_create(const lq_gauge* g, int32_t formulation, int32_t g55_mode, double r,
                     int32_t nslots, const lq_solve_opts* opts, void* ws,
                     size_t ws_bytes, lq_batch** out);
@@ -289,6 +297,7 @@ int lq_batch_load(lq_batch* b, int32_t slot, const void* chi, double mass, doubl
                   int32_t maxiter, void* stream);
 int lq_batch_step(lq_batch* b, int32_t iterations, int32_t* states, void* stream);
 int lq_batch_fetch(lq_batch* b, int32_t slot, void* x, lq_solve_info* info, void* stream);
+int lq_batch_cancel(lq_batch* b, int32_t slot, void* stream);
 /* Progress of a slot as of the latest step (host copy, no device work): info
  * gets the slot state (0..3) in `status`, the iteration and update counts,
  * the iterated residual and the FP64 residual of the latest reliable update;

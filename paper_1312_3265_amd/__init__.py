@@ -117,6 +117,7 @@ def lib():
         "lq_batch_load": ([P, I32, P, D, D, I32, P], I32),
         "lq_batch_step": ([P, I32, P, P], I32),
         "lq_batch_fetch": ([P, I32, P, P, P], I32),
+        "lq_batch_cancel": ([P, I32, P], I32),
         "lq_batch_destroy": ([P], None),
         "lq_batch_peek": ([P, I32, P, P], I32),
         "lq_lanczos_workspace_bytes": ([P, I32, I32], SZ),
@@ -456,6 +457,11 @@ class Batch:
         _check(lib().lq_batch_fetch(self._h, slot, _ptr(x), ctypes.byref(info), _stream(stream)))
         self._keep.pop(slot, None)
         return x, info.as_dict()
+
+    def cancel(self, slot, stream=None):
+        """Discard a loaded slot (running or finished) and free it."""
+        _check(lib().lq_batch_cancel(self._h, slot, _stream(stream)))
+        self._keep.pop(slot, None)
 
     def peek(self, slot):
         """Slot progress as of the latest step (no device work)."""

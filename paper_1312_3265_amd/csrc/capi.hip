@@ -552,6 +552,14 @@ int lq_batch_fetch(lq_batch* b, int32_t slot, void* x, lq_solve_info* info, void
   });
 }
 
+int lq_batch_cancel(lq_batch* b, int32_t slot, void* stream) {
+  return guard([&] {
+    need(b != nullptr, "null batch");
+    b->e.cancel(slot, S(stream));
+    return LQ_OK;
+  });
+}
+
 int lq_tuned_launch(const lq_gauge* g, const lq_dirac* d, int32_t precision, int32_t links,
                     int32_t nrhs, int32_t* rhs_per_thread, int32_t* window) {
   return guard([&] {

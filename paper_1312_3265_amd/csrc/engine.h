@@ -175,6 +175,7 @@ struct Engine {
   // advance about `iters` iterations; returns after polling the slot states
   void step(int iters, hipStream_t s);
   void fetch(int slot, void* x, lq_solve_info* info, hipStream_t s);
+  void cancel(int slot, hipStream_t s);   // discard a loaded slot and free it
   int running() const;
 
  private:

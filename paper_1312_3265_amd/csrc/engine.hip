@@ -658,6 +658,19 @@ void Engine::fetch(int slot, void* x, lq_solve_info* info, hipStream_t s) {
   LQ_HIP(hipStreamSynchronize(s));
 }
 
+// Discards slot `slot` (running or finished) without copying anything out.
+// Between steps no kernel of this engine is in flight (step and fetch
+// synchronise), so marking the slot empty on the device takes effect from the
+// next launch on: every kernel skips slots that are not running.
+void Engine::cancel(int slot, hipStream_t s) {
+  if (slot < 0 || slot >= nslots) throw Error(LQ_ERR_ARG, "slot out of range");
+  SlotState& h = hst[slot];
+  if (h.status == SLOT_EMPTY) throw Error(LQ_ERR_STATE, "slot is empty");
+  h.status = SLOT_EMPTY;
+  LQ_HIP(hipMemcpyAsync(&st[slot].status, &h.status, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  LQ_HIP(hipStreamSynchronize(s));
+}
+
 // =============================================================== Lanczos
 static constexpr int kLzBlocks = 256;
 

@@ -199,6 +199,18 @@ __global__ void ru_finish_kernel(SlotState* st, const int* mask, const double* _
     return;
   }
   if (s->flags) { s->status = SLOT_FAILED; return; }
+  // stagnation: a tolerance below the attainable accuracy is never met, and
+  // cycling on from the accuracy floor lets x drift away from it; stop (not
+  // converged) once max_cand updates in a row have not halved the true
+  // residual, or as soon as it has grown 100-fold above its best
+  if (init || rr < 0.25 * s->best2) {
+    s->best2 = rr;
+    s->stall = 0;
+  } else if (++s->stall > max_cand || rr > kGrowth2 * s->best2) {
+    s->flags |= 4;
+    s->status = SLOT_FAILED;
+    return;
+  }
   if (!init && s->stop[par] && !s->want_ru) {
     // the iterated residual met tol but the true residual did not
     s->cand += 1;

@@ -28,6 +28,7 @@ struct SlotState {
   double alpha[4];   // alpha of the iterations of the current group of four (x is updated once per group)
   double bfull2;     // even-odd: ||M^dag chi||^2, the b of eq. (2) for the whole lattice
   double full_res2;  // even-odd: ||b - A x||^2 of eq. (2) at the latest reliable update
+  double best2;      // smallest FP64 true residual^2 so far (stagnation watch)
   int32_t stop[2];   // ring: 1 = frozen until the next reliable update
   int32_t status;    // 0 empty, 1 running, 2 converged, 3 failed
   int32_t iter;      // CG iterations done
@@ -39,6 +40,7 @@ struct SlotState {
   int32_t ru_iter;   // iteration count at the latest reliable update
   int32_t want_ru;   // frozen because the residual dropped by delta (not converged)
   int32_t pend;      // terms alpha[j] * p_ring[j], j < pend, that x still lacks (frozen mid-group)
+  int32_t stall;     // reliable updates since the true residual last halved
 };
 
 enum SlotStatus { SLOT_EMPTY = 0, SLOT_RUNNING = 1, SLOT_DONE = 2, SLOT_FAILED = 3 };

@@ -14,6 +14,11 @@ created, with as many slots as fit into its share of the memory budget; a
 request waits in its group's queue until a slot is free.  A request whose
 group cannot hold even one system is rejected.
 
+Cancellation: ``cancel(request_id)`` (from any thread, or at a request's
+``cancel_at`` time) drops a request that is still queued, and frees the slot
+of one that is running at the next chunk boundary; a request that finished
+first is delivered as usual.
+
 The arithmetic all happens in the library; this module only schedules.
 """
 from __future__ import annotations
@@ -39,6 +44,7 @@ class Request:
     tol: float
     arrival: float = 0.0      # seconds after the server's start
     maxiter: int = 100000
+    cancel_at: float = None   # seconds after the server's start: cancel then
 
 
 @dataclass
@@ -98,6 +104,8 @@ class SolveServer:
         self.groups = {}
         self.results = []
         self.rejected = []
+        self.cancelled = []       # (request id, "queued" or "running", seconds)
+        self._cancel = set()
         self._lock = threading.Lock()
         self._t0 = None
         self._stop = threading.Event()
@@ -157,6 +165,8 @@ class SolveServer:
                     req = g.pending.get_nowait()
                 except queue.Empty:
                     break
+                if self._take_cancel(req.id, "queued"):
+                    continue
                 s = free.pop(0)
                 b.load(s, req.source, req.mass, req.tol, req.maxiter, stream=g.stream)
                 g.slot_req[s] = (req, self._now())
@@ -173,12 +183,53 @@ class SolveServer:
                     with self._lock:
                         self.results.append(Result(req.id, x, info, req.arrival, adm, self._now()))
                     free.append(s)
+                elif s in g.slot_req and self._take_cancel(g.slot_req[s][0].id, "running"):
+                    g.slot_req.pop(s)
+                    b.cancel(s, stream=g.stream)
+                    free.append(s)
+
+    def _take_cancel(self, rid, phase):
+        """True (and recorded) if request rid has been cancelled."""
+        with self._lock:
+            if rid not in self._cancel:
+                return False
+            self._cancel.discard(rid)
+            self.cancelled.append((rid, phase, self._now()))
+            return True
 
     # ----------------------------------------------------------------- API
+    def status(self, request_id):
+        """'running' while the request holds a slot, 'finished' or 'cancelled'
+        once it is out, else None (queued, not yet arrived, or unknown)."""
+        with self._lock:
+            if any(r.id == request_id for r in self.results):
+                return "finished"
+            if any(c[0] == request_id for c in self.cancelled):
+                return "cancelled"
+            for g in list(self.groups.values()):
+                if g is not None and any(req.id == request_id
+                                         for req, _ in list(g.slot_req.values())):
+                    return "running"
+        return None
+
+    def cancel(self, request_id):
+        """Cancel a request: dropped if still queued, its slot freed at the next
+        chunk boundary if running; no effect once it has finished."""
+        with self._lock:
+            if not any(r.id == request_id for r in self.results):
+                self._cancel.add(request_id)
+
     def run(self, requests):
         """Feed requests at their arrival times (seconds from now) and wait
         for all of them.  Returns the results in completion order."""
         self._t0 = time.perf_counter()
+        timers = []
+        for req in requests:
+            if req.cancel_at is not None:
+                t = threading.Timer(req.cancel_at, self.cancel, args=(req.id,))
+                t.daemon = True
+                t.start()
+                timers.append(t)
         for req in sorted(requests, key=lambda r: r.arrival):
             delay = req.arrival - self._now()
             if delay > 0:
@@ -192,6 +243,8 @@ class SolveServer:
         for g in list(self.groups.values()):
             if g is not None:
                 g.thread.join()
+        for t in timers:
+            t.cancel()
         return self.results
 
     def report(self):
@@ -199,6 +252,7 @@ class SolveServer:
         span = max((r.finished for r in self.results), default=0.0)
         ok = sum(1 for r in self.results if r.info["status"] == 0)
         return dict(completed=len(self.results), converged=ok, rejected=len(self.rejected),
+                    cancelled=len(self.cancelled),
                     solves_per_s=len(self.results) / span if span > 0 else 0.0,
                     p50_latency_s=float(np.percentile(lat, 50)),
                     p99_latency_s=float(np.percentile(lat, 99)),

@@ -2,6 +2,8 @@
 formulations; every result must match the same request solved alone
 (bitwise: per-system trajectories do not depend on the batch) and pass the
 oracle's FP64 residual check; admission respects the HBM budget."""
+import time
+
 import numpy as np
 import pytest
 
@@ -106,3 +108,99 @@ def test_server_at_the_workload_lattice_sizes():
                                               r.x.cpu().numpy(), req.mass)
                 assert rn <= req.tol, (req.id, req.dims, rn, req.tol)
     print("offered 20/s:", reports[0], "offered 60/s:", reports[1])
+
+
+def test_batch_cancel_frees_a_running_slot():
+    """A slot cancelled mid-solve is empty from the next step on and can be
+    loaded again; the other slot's trajectory is untouched (bitwise the solve
+    alone); cancelling an empty slot or fetching a cancelled one fails."""
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_field(dims, "near_identity", 7, 0.436)
+    g = lq.Gauge(lq.Lattice(dims), U)
+    form, m, tol = synth.WILSON, -0.25, 1e-9
+    opts = lq.solve_opts(precision=lq.F32, links=12, poll_interval=8)
+    chi0 = synth.point_source(dims, form, 0)
+    chi1 = synth.point_source(dims, form, 5)
+    b = lq.Batch(g, form, 2, opts=opts)
+    b.load(0, chi0, m, tol)
+    b.load(1, chi1, m, tol)
+    states = b.step(16)
+    assert states == [lq.SLOT_RUNNING, lq.SLOT_RUNNING]
+    b.cancel(0)
+    with pytest.raises(lq.LQError) as e:
+        b.fetch(0)
+    assert e.value.code == lq.ERR_STATE
+    with pytest.raises(lq.LQError) as e:
+        b.cancel(0)
+    assert e.value.code == lq.ERR_STATE
+    with pytest.raises(lq.LQError) as e:
+        b.cancel(2)
+    assert e.value.code == lq.ERR_ARG
+    while True:
+        states = b.step(16)
+        assert states[0] == lq.SLOT_EMPTY
+        if states[1] != lq.SLOT_RUNNING:
+            break
+    x1, i1 = b.fetch(1)
+    xa, ia = lq.cg_solve(g, form, m, chi1, tol, opts=opts)
+    assert i1["status"] == lq.OK and ia["iterations"] == i1["iterations"]
+    assert torch.equal(xa, x1)
+    b.load(0, chi0, m, tol)            # the cancelled slot is reused
+    while b.step(16)[0] == lq.SLOT_RUNNING:
+        pass
+    x0, i0 = b.fetch(0)
+    xb, ib = lq.cg_solve(g, form, m, chi0, tol, opts=opts)
+    assert i0["status"] == lq.OK and torch.equal(xb, x0)
+
+
+def test_server_cancels_queued_and_running_requests():
+    """One slot per group.  Request 1 (tol 1e-12 on 16^4 near the critical
+    mass: a long solve) holds the slot; request 2, cancelled before it
+    arrives, is dropped from the queue; request 1 is cancelled once it is seen
+    running, and request 3 then gets the freed slot and converges."""
+    import threading
+    dims = (16, 16, 16, 16)
+    fields = {dims: synth.gauge_field(dims, "near_identity", 9, 0.436)}
+    form = synth.WILSON
+    chi = [synth.point_source(dims, form, a) for a in range(3)]
+    opts = lq.solve_opts(precision=lq.F32, links=12, poll_interval=8)
+    srv = serve.SolveServer(fields, opts=opts, slots=1, chunk=8)
+    reqs = [serve.Request(1, dims, form, -0.44, chi[0], 1e-12, arrival=0.0),
+            serve.Request(2, dims, form, -0.25, chi[1], 1e-8, arrival=0.0),
+            serve.Request(3, dims, form, -0.25, chi[2], 1e-8, arrival=0.0)]
+    srv.cancel(2)
+    out = {}
+    t = threading.Thread(target=lambda: out.setdefault("results", srv.run(reqs)))
+    t.start()
+    while srv.status(1) is None:
+        time.sleep(0.001)
+    assert srv.status(1) == "running"
+    srv.cancel(1)
+    t.join(timeout=120)
+    assert not t.is_alive()
+    results = out["results"]
+    phases = {rid: phase for rid, phase, _ in srv.cancelled}
+    assert phases == {2: "queued", 1: "running"}
+    assert [r.id for r in results] == [3] and results[0].info["status"] == lq.OK
+    assert srv.status(1) == "cancelled" and srv.status(3) == "finished"
+    assert srv.report()["cancelled"] == 2
+    rn, _ = solvers.true_residual(form, fields[dims], chi[2], results[0].x.cpu().numpy(), -0.25)
+    assert rn <= 1e-8
+
+
+def test_unattainable_tolerance_ends_not_converged():
+    """A tolerance far below the attainable accuracy (1e-30) stops once the
+    FP64 true residual has not halved in max_restarts reliable updates in a
+    row, or has grown 100-fold above its best: not converged, with x near the
+    accuracy floor rather than drifting away from it."""
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_field(dims, "near_identity", 9, 0.436)
+    g = lq.Gauge(lq.Lattice(dims), U)
+    chi = synth.point_source(dims, synth.WILSON, 0)
+    opts = lq.solve_opts(precision=lq.F32, links=12, max_restarts=20)
+    x, info = lq.cg_solve(g, synth.WILSON, -0.25, chi, 1e-30, maxiter=1_000_000, opts=opts)
+    assert info["status"] == lq.NOT_CONVERGED, info
+    print(info)
+    assert info["true_residual"] <= 1e-10
+    rn, _ = solvers.true_residual(synth.WILSON, U, chi, x.cpu().numpy(), -0.25)
+    assert rn <= 1e-10
