@@ -36,7 +36,10 @@
  *  - Memory: the library allocates no device memory.  Every device buffer
  *    (gauge storage, solver workspace, inputs, outputs) is owned by the caller,
  *    sized with the *_bytes queries, and must stay alive while a handle that
- *    points into it is in use.  Handles hold host metadata only.
+ *    points into it is in use.  Handles hold host metadata only.  The
+ *    workspace queries take the Gamma_55 mode: with LQ_G55_ONTHEFLY (staggered
+ *    Wilson) the workspace also holds the intermediate fields of the subset
+ *    recursion (14 fields of three complex numbers per site and system).
  *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  Work is
  *    enqueued on it; lq_apply and the *_create calls are asynchronous, the
  *    solve, condition-number and timing calls return after their own
@@ -59,8 +62,16 @@ extern "C" {
 /* status codes */
 #define LQ_OK 0
 #define LQ_NOT_CONVERGED 1     /* maxiter reached; info filled                */
+#define LQ_STAGNATION 2        /* stopped at the attainable accuracy: the FP64
+                                  true residual did not halve over max_restarts
+                                  reliable updates in a row, or stayed 100x above
+                                  its best across a restart; info filled        */
 #define LQ_ERR_ARG (-1)        /* bad dims, pointer, size, enum, non-finite    */
-#define LQ_ERR_WORKSPACE (-2)  /* caller buffer smaller than the query says    */
+#define LQ_ERR_WORKSPACE (-2)  /* caller buffer smaller than the query says:
+                                  the footprint (memory budget) error; the
+                                  library never allocates, so no other
+                                  out-of-memory condition exists               */
+#define LQ_ERR_OOM_BUDGET LQ_ERR_WORKSPACE
 #define LQ_ERR_DEVICE (-3)     /* a HIP runtime call failed                    */
 #define LQ_ERR_BREAKDOWN (-4)  /* CG/Lanczos breakdown: <p,Ap> <= 0 or NaN     */
 #define LQ_ERR_STATE (-5)      /* handle used in a state that does not allow it */
@@ -76,7 +87,11 @@ extern "C" {
 
 /* how the staggered Wilson Gamma_55 is applied */
 #define LQ_G55_CORNERS 0    /* from precomputed path-averaged corner matrices */
-#define LQ_G55_ONTHEFLY 1   /* from the links, every application               */
+#define LQ_G55_ONTHEFLY 1   /* from the links, every application, by the subset
+                               recursion F_S = sum_{mu in S} C_mu F_{S\mu}: three
+                               nearest-neighbour level launches into workspace
+                               fields, the fourth level in the operator's own
+                               stencil; 32 C_mu applications per site          */
 
 /* arithmetic / storage precision of the stencil and Krylov vectors */
 #define LQ_PREC_F64 0
@@ -101,6 +116,10 @@ extern "C" {
 #define LQ_FEAT_Q16 0x4u      /* 16-bit fixed-point links (12- and 18-real), corners */
 #define LQ_FEAT_EO 0x8u       /* even-odd copies of the links (FP64, and F32/Q16 when
                                  those are built): per parity, half-lattice records */
+
+/* where a caller's input array lives (lq_gauge_create) */
+#define LQ_WHERE_HOST 0
+#define LQ_WHERE_DEVICE 1
 
 typedef struct lq_lattice_s lq_lattice;
 typedef struct lq_gauge_s lq_gauge;
@@ -131,9 +150,11 @@ typedef struct {
   int32_t max_restarts;       /* reliable updates allowed after the iterated
                                  residual first meets tol, and in a row without
                                  halving the true residual (a tol below the
-                                 attainable accuracy then ends LQ_NOT_CONVERGED
+                                 attainable accuracy then ends LQ_STAGNATION
                                  instead of cycling on; so does a true residual
-                                 100x above its best; 0 = default 50)          */
+                                 100x above its best at two reliable updates in
+                                 a row, i.e. one that a restart from the FP64
+                                 residual did not bring back; 0 = default 50)  */
   double reliable_delta;      /* also update once the iterated residual has
                                  dropped by this factor since the last update
                                  (0 = default: 0.1 for Q16, 1e-3 for F32)        */
@@ -155,14 +176,20 @@ typedef struct {
  * b = M^dag chi, A = M^dag M; `true_residual` is recomputed in FP64 on the GPU
  * from the returned x. */
 typedef struct {
-  int32_t status;             /* LQ_OK, LQ_NOT_CONVERGED or LQ_ERR_BREAKDOWN      */
+  int32_t status;             /* LQ_OK, LQ_NOT_CONVERGED, LQ_STAGNATION or
+                                 LQ_ERR_BREAKDOWN (lq_batch_peek: the slot state) */
   int32_t iterations;         /* CG iterations (A-applications in the loop)      */
   int32_t reliable_updates;   /* FP64 true-residual recomputations              */
   int32_t applications;       /* all applications of A, including b and updates */
+  int32_t flags;              /* LQ_FLAG_* bits of the solve's stop reasons     */
   double iterated_residual;
   double true_residual;
-  double seconds;             /* wall time of the call                          */
+  double seconds;             /* wall time of the call (0 from lq_batch_fetch
+                                 and lq_batch_peek)                             */
 } lq_solve_info;
+#define LQ_FLAG_BREAKDOWN 1u   /* <p, A p> <= 0 or a non-finite residual         */
+#define LQ_FLAG_MAXITER 2u     /* the iteration limit was reached                */
+#define LQ_FLAG_STAGNATION 4u  /* the accuracy floor: see LQ_STAGNATION          */
 
 /* ---------------------------------------------------------------- errors */
 const char* lq_last_error(void);
@@ -178,20 +205,25 @@ int64_t lq_lattice_volume(const lq_lattice* lat);
 /* ----------------------------------------------------------------- gauge
  * The gauge field of paper Sec. 3 (there: quenched beta = 6 configurations).
  * lq_gauge_bytes: device bytes lq_gauge_create needs for `features`.
- * lq_gauge_create: repacks the canonical complex128 field `U` (device
- *   pointer, V*4*9 complex) into the library's structure-of-arrays layout in
- *   `buf`, builds the FP32/16-bit copies and the staggered Wilson corner matrices
+ * lq_gauge_create: repacks the canonical complex128 field `U` (V*4*9 complex,
+ *   in host memory if where = LQ_WHERE_HOST, in device memory if
+ *   LQ_WHERE_DEVICE; the caller keeps ownership and may free it once the call
+ *   has returned) into the library's structure-of-arrays layout in `buf`,
+ *   builds the FP32/16-bit copies and the staggered Wilson corner matrices
  *   W_s(x) = (1/24) sum over the 24 orderings of the one-link-per-direction
  *   path products from x to x + s, s in {+-1}^4 (8 are stored; the other 8 are
- *   W_{-s}(x+s)^dag).  The call measures how far row 2 of every link is from
+ *   W_{-s}(x+s)^dag).  A host field is uploaded in chunks through a staging
+ *   area inside `buf`.  The call measures how far row 2 of every link is from
  *   conj(row0 x row1) and synchronises `stream`; 12-real links are refused
  *   (LQ_ERR_ARG) unless that deviation is <= 1e-12 (FP64) or 1e-6 (FP32,
- *   Q16), i.e. unless the links are SU(3) to that accuracy.  */
+ *   Q16), i.e. unless the links are SU(3) to that accuracy.  Errors: LQ_ERR_ARG
+ *   for a null pointer, unknown feature bits or where; LQ_ERR_WORKSPACE when
+ *   buf_bytes < lq_gauge_bytes; LQ_ERR_DEVICE for a failed copy or launch.  */
 size_t lq_gauge_bytes(const lq_lattice* lat, uint32_t features);
 /* max over sites and directions of |row2 - conj(row0 x row1)| (real and
  * imaginary parts), measured by lq_gauge_create. */
 int lq_gauge_su3_deviation(const lq_gauge* g, double* dev);
-int lq_gauge_create(const lq_lattice* lat, const void* U, uint32_t features,
+int lq_gauge_create(const lq_lattice* lat, const void* U, int32_t where, uint32_t features,
                     void* buf, size_t buf_bytes, void* stream, lq_gauge** out);
 void lq_gauge_destroy(lq_gauge* g);
 /* Mean plaquette (1/6V) sum_x sum_{mu<nu} (1/3) Re tr U_mu U_nu U_mu^dag U_nu^dag,
@@ -203,7 +235,8 @@ int lq_gauge_plaquette(const lq_gauge* g, double* plaquette, void* stream);
  * canonical fields, complex128 for LQ_PREC_F64 and complex64 for F32/Q16
  * (Q16 rounds the repacked input to 16-bit storage; arithmetic is FP32).
  * `ws` is device scratch of lq_apply_workspace_bytes.  Asynchronous. */
-size_t lq_apply_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t precision);
+size_t lq_apply_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t g55_mode,
+                                int32_t precision);
 int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t op, int32_t precision,
              int32_t links, const void* in, void* out, void* ws, size_t ws_bytes,
              void* stream);
@@ -244,7 +277,8 @@ int lq_schur_apply(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t
  * systems outermost (-3) or innermost (-4) -- on lattices with whole x-y
  * planes of 256-site blocks, L4 % 8 == 0 and even L3; elsewhere they act as 0.  ws: device scratch of
  * lq_time_dslash_workspace_bytes (contents overwritten).  */
-size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t precision,
+size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t g55_mode,
+                                      int32_t precision,
                                       int32_t nrhs);
 int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel,
                    int32_t precision, int32_t links, int32_t nrhs, int32_t rhs_per_thread,
@@ -257,7 +291,7 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel,
  * residual ||b - A x||/||b|| <= tol, with x0 = 0.  Mixed precision (opts)
  * iterates in FP32/Q16 and recomputes the true residual in FP64 at every
  * reliable update; scalars alpha, beta and all reductions are FP64. */
-size_t lq_solve_workspace_bytes(const lq_gauge* g, int32_t formulation,
+size_t lq_solve_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t g55_mode,
                                 const lq_solve_opts* opts, int32_t nrhs);
 int lq_cg_solve(const lq_gauge* g, const lq_dirac* d, const void* chi, void* x,
                 double tol, int32_t maxiter, const lq_solve_opts* opts, void* ws,
@@ -277,7 +311,8 @@ int lq_cg_solve_batch(const lq_gauge* g, int32_t formulation, int32_t g55_mode,
 /* -------------------------------------------------- continuous batching
  * A resident multi-RHS solver with `nslots` slots (serving).  Slots are loaded
  * and harvested between steps while the other slots keep iterating.
- *   lq_batch_create: ws of lq_solve_workspace_bytes(g, formulation, opts, nslots).
+ *   lq_batch_create: ws of lq_solve_workspace_bytes(g, formulation, g55_mode,
+ *                    opts, nslots).
  *   lq_batch_load:   start slot `slot` on source chi (device canonical) with
  *                    mass, tol and an iteration limit; asynchronous.
  *   lq_batch_step:   advance every running slot by about `iterations` CG
@@ -299,10 +334,10 @@ int lq_batch_step(lq_batch* b, int32_t iterations, int32_t* states, void* stream
 int lq_batch_fetch(lq_batch* b, int32_t slot, void* x, lq_solve_info* info, void* stream);
 int lq_batch_cancel(lq_batch* b, int32_t slot, void* stream);
 /* Progress of a slot as of the latest step (host copy, no device work): info
- * gets the slot state (0..3) in `status`, the iteration and update counts,
- * the iterated residual and the FP64 residual of the latest reliable update;
- * `seconds` carries the slot's flag bits (1 breakdown, 2 maxiter, 4 restart
- * limit); scale (may be NULL) the storage scale of its low-precision vectors. */
+ * gets the slot state (0..3) in `status`, the LQ_FLAG_* bits in `flags`, the
+ * iteration and update counts, the iterated residual and the FP64 residual of
+ * the latest reliable update; scale (may be NULL) the storage scale of its
+ * low-precision vectors. */
 int lq_batch_peek(lq_batch* b, int32_t slot, lq_solve_info* info, double* scale);
 void lq_batch_destroy(lq_batch* b);
 
@@ -351,7 +386,8 @@ int lq_pion_correlator(const lq_lattice* lat, int32_t nsrc, const void* props, d
  * Ritz estimates ||(M - sigma)^{-1} u - mu u|| / |mu| (relative).  Stops
  * early at an invariant subspace.  `ws` is device scratch of
  * lq_spectrum_workspace_bytes.  Synchronises `stream`. */
-size_t lq_spectrum_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t steps);
+size_t lq_spectrum_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t g55_mode,
+                                   int32_t steps);
 int lq_spectrum(const lq_gauge* g, const lq_dirac* d, double sigma, int32_t steps,
                 int32_t restarts, double tol, const void* v0, void* ws, size_t ws_bytes,
                 int32_t* nev, double* eig_re, double* eig_im, double* resid, void* stream);
@@ -364,7 +400,8 @@ int lq_spectrum(const lq_gauge* g, const lq_dirac* d, double sigma, int32_t step
  * kappa = lambda_max/lambda_min).  alpha[steps] and beta[steps-1] (host,
  * may be NULL) receive the tridiagonal.  Workspace holds steps+1 FP64 basis
  * vectors: lq_lanczos_workspace_bytes.  Synchronises `stream`.  */
-size_t lq_lanczos_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t steps);
+size_t lq_lanczos_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t g55_mode,
+                                  int32_t steps);
 int lq_condition_number(const lq_gauge* g, const lq_dirac* d, int32_t steps,
                         const void* v0, void* ws, size_t ws_bytes, double* lmin,
                         double* lmax, double* kappa, double* alpha, double* beta,

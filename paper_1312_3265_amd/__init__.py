@@ -26,7 +26,9 @@ OP_M, OP_MDAG, OP_MDAGM = 0, 1, 2
 G55_CORNERS, G55_ONTHEFLY = 0, 1
 F64, F32, Q16 = 0, 1, 2
 FEAT_CORNERS, FEAT_F32, FEAT_Q16, FEAT_EO = 1, 2, 4, 8
-OK, NOT_CONVERGED = 0, 1
+OK, NOT_CONVERGED, STAGNATION = 0, 1, 2
+FLAG_BREAKDOWN, FLAG_MAXITER, FLAG_STAGNATION = 1, 2, 4
+WHERE_HOST, WHERE_DEVICE = 0, 1
 ERR_ARG, ERR_WORKSPACE, ERR_DEVICE, ERR_BREAKDOWN, ERR_STATE = -1, -2, -3, -4, -5
 SLOT_EMPTY, SLOT_RUNNING, SLOT_DONE, SLOT_FAILED = 0, 1, 2, 3
 
@@ -52,6 +54,7 @@ class SolveOpts(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("reliable_updates", ctypes.c_int32), ("applications", ctypes.c_int32),
+                ("flags", ctypes.c_int32),
                 ("iterated_residual", ctypes.c_double), ("true_residual", ctypes.c_double),
                 ("seconds", ctypes.c_double)]
 
@@ -95,22 +98,22 @@ def lib():
         "lq_lattice_destroy": ([P], None),
         "lq_lattice_volume": ([P], I64),
         "lq_gauge_bytes": ([P, c.c_uint32], SZ),
-        "lq_gauge_create": ([P, P, c.c_uint32, P, SZ, P, P], I32),
+        "lq_gauge_create": ([P, P, I32, c.c_uint32, P, SZ, P, P], I32),
         "lq_gauge_destroy": ([P], None),
         "lq_gauge_su3_deviation": ([P, P], I32),
         "lq_gauge_plaquette": ([P, P, P], I32),
-        "lq_apply_workspace_bytes": ([P, I32, I32], SZ),
+        "lq_apply_workspace_bytes": ([P, I32, I32, I32], SZ),
         "lq_apply": ([P, P, I32, I32, I32, P, P, P, SZ, P], I32),
         "lq_schur_workspace_bytes": ([P, I32], SZ),
         "lq_schur_apply": ([P, P, I32, I32, I32, P, P, P, SZ, P], I32),
         "lq_pion_workspace_bytes": ([P], SZ),
         "lq_pion_correlator": ([P, I32, P, P, P, P, SZ, P], I32),
-        "lq_spectrum_workspace_bytes": ([P, I32, I32], SZ),
+        "lq_spectrum_workspace_bytes": ([P, I32, I32, I32], SZ),
         "lq_spectrum": ([P, P, D, I32, I32, D, P, P, SZ, P, P, P, P, P], I32),
         "lq_time_dslash": ([P, P, I32, I32, I32, I32, I32, I32, I32, P, SZ, P, P], I32),
-        "lq_time_dslash_workspace_bytes": ([P, I32, I32, I32], SZ),
+        "lq_time_dslash_workspace_bytes": ([P, I32, I32, I32, I32], SZ),
         "lq_tuned_launch": ([P, P, I32, I32, I32, P, P], I32),
-        "lq_solve_workspace_bytes": ([P, I32, P, I32], SZ),
+        "lq_solve_workspace_bytes": ([P, I32, I32, P, I32], SZ),
         "lq_cg_solve": ([P, P, P, P, D, I32, P, P, SZ, P, P], I32),
         "lq_cg_solve_batch": ([P, I32, I32, D, I32, P, P, P, P, I32, P, P, SZ, P, P], I32),
         "lq_batch_create": ([P, I32, I32, D, I32, P, P, SZ, P], I32),
@@ -120,7 +123,7 @@ def lib():
         "lq_batch_cancel": ([P, I32, P], I32),
         "lq_batch_destroy": ([P], None),
         "lq_batch_peek": ([P, I32, P, P], I32),
-        "lq_lanczos_workspace_bytes": ([P, I32, I32], SZ),
+        "lq_lanczos_workspace_bytes": ([P, I32, I32, I32], SZ),
         "lq_condition_number": ([P, P, I32, P, P, SZ, P, P, P, P, P, P, P], I32),
         "lq_critical_mass": ([P, I32, I32, D, D, D, I32, I32, I32, P, P, SZ, P, P, P], I32),
     }
@@ -155,13 +158,21 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _device_tensor(x, dtype):
+def _device_tensor(x, dtype, stream=None):
+    """x as a contiguous device tensor of dtype.  A conversion or copy runs on
+    torch's current stream; when the library will read the tensor on another
+    `stream`, that stream first waits for the current one."""
     torch = _torch()
     if isinstance(x, torch.Tensor):
         t = x.to(device="cuda", dtype=dtype)
     else:
         t = torch.from_numpy(x).to(device="cuda", dtype=dtype)
-    return t.contiguous()
+    t = t.contiguous()
+    if stream is not None:
+        cur = torch.cuda.current_stream()
+        if stream != cur:
+            stream.wait_stream(cur)
+    return t
 
 
 class Lattice:
@@ -184,17 +195,29 @@ class Lattice:
 
 
 class Gauge:
-    """Gauge field resident in HBM (library layout, FP64 plus requested copies)."""
+    """Gauge field resident in HBM (library layout, FP64 plus requested copies).
+
+    U: canonical complex128 field, a numpy array (uploaded by the library from
+    host memory) or a torch tensor (passed as a device pointer)."""
 
     def __init__(self, lattice, U, features=FEAT_CORNERS | FEAT_F32 | FEAT_Q16, stream=None):
+        import numpy as np
         torch = _torch()
         self.lattice = lattice
         self.features = features
         nbytes = int(lib().lq_gauge_bytes(lattice._h, features))
         self.buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        Ud = _device_tensor(U, torch.complex128)
+        if isinstance(U, torch.Tensor):
+            src, where = _device_tensor(U, torch.complex128, stream), WHERE_DEVICE
+            ptr = _ptr(src)
+        else:
+            src, where = np.ascontiguousarray(U, dtype=np.complex128), WHERE_HOST
+            ptr = ctypes.c_void_p(src.ctypes.data)
+        if stream is not None:
+            # the buffer was allocated on the current stream
+            stream.wait_stream(torch.cuda.current_stream())
         h = ctypes.c_void_p()
-        _check(lib().lq_gauge_create(lattice._h, _ptr(Ud), features, _ptr(self.buf), nbytes,
+        _check(lib().lq_gauge_create(lattice._h, ptr, where, features, _ptr(self.buf), nbytes,
                                      _stream(stream), ctypes.byref(h)))
         _stream_sync(stream)
         self._h = h
@@ -232,9 +255,9 @@ def apply(gauge, formulation, mass, psi, op=OP_M, r=1.0, g55=G55_CORNERS, precis
     """op(psi) with op in {M, M^dag, M^dag M}; returns a new device tensor."""
     torch = _torch()
     dt = torch.complex128 if precision == F64 else torch.complex64
-    x = _device_tensor(psi, dt)
+    x = _device_tensor(psi, dt, stream)
     out = torch.empty_like(x)
-    nb = int(lib().lq_apply_workspace_bytes(gauge._h, formulation, precision))
+    nb = int(lib().lq_apply_workspace_bytes(gauge._h, formulation, g55, precision))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     d = Dirac(formulation, g55, mass, r)
     _check(lib().lq_apply(gauge._h, ctypes.byref(d), op, precision, links, _ptr(x), _ptr(out),
@@ -249,7 +272,7 @@ def schur_apply(gauge, mass, psi, dagger=False, precision=F64, links=0, stream=N
     the odd sites of the result are zero.  Needs a gauge built with FEAT_EO."""
     torch = _torch()
     dt = torch.complex128 if precision == F64 else torch.complex64
-    x = _device_tensor(psi, dt)
+    x = _device_tensor(psi, dt, stream)
     out = torch.empty_like(x)
     nb = int(lib().lq_schur_workspace_bytes(gauge._h, precision))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
@@ -266,7 +289,7 @@ def pion_correlator(lattice, props, stream=None):
     effective mass, numpy arrays of length L4."""
     import numpy as np
     torch = _torch()
-    p = _device_tensor(props, torch.complex128)
+    p = _device_tensor(props, torch.complex128, stream)
     L4 = lattice.dims[3]
     corr = np.zeros(L4)
     meff = np.zeros(L4)
@@ -286,8 +309,8 @@ def spectrum(gauge, formulation, mass, sigma, v0, steps=40, tol=1e-10, restarts=
     and up to `restarts` restarts (numpy arrays, nearest first)."""
     import numpy as np
     torch = _torch()
-    v = _device_tensor(v0, torch.complex128)
-    nb = int(lib().lq_spectrum_workspace_bytes(gauge._h, formulation, steps))
+    v = _device_tensor(v0, torch.complex128, stream)
+    nb = int(lib().lq_spectrum_workspace_bytes(gauge._h, formulation, g55, steps))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     d = Dirac(formulation, g55, mass, r)
     re, im, res = np.zeros(steps), np.zeros(steps), np.zeros(steps)
@@ -308,7 +331,7 @@ def time_dslash(gauge, formulation, mass, dagger=False, r=1.0, g55=G55_CORNERS, 
     update of r; 3, 4 = the even-odd pairs t = M^ p + ||t||^2 and M^dag t with
     the CG update (per pair); default 1 if dagger else 0."""
     torch = _torch()
-    nb = int(lib().lq_time_dslash_workspace_bytes(gauge._h, formulation, precision, nrhs))
+    nb = int(lib().lq_time_dslash_workspace_bytes(gauge._h, formulation, g55, precision, nrhs))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     d = Dirac(formulation, g55, mass, r)
     ms = ctypes.c_double()
@@ -338,19 +361,20 @@ def solve_opts(precision=F64, links=0, reliable_interval=0, poll_interval=0, use
                      reliable_delta, int(evenodd))
 
 
-def solve_workspace_bytes(gauge, formulation, opts, nrhs):
+def solve_workspace_bytes(gauge, formulation, opts, nrhs, g55=G55_CORNERS):
     """Device bytes the solver needs for nrhs systems with these options."""
-    return int(lib().lq_solve_workspace_bytes(gauge._h, formulation, ctypes.byref(opts), nrhs))
+    return int(lib().lq_solve_workspace_bytes(gauge._h, formulation, g55, ctypes.byref(opts),
+                                              nrhs))
 
 
 def cg_solve(gauge, formulation, mass, chi, tol, maxiter=100000, r=1.0, g55=G55_CORNERS,
              opts=None, stream=None):
     """Solve (D+m)^dag (D+m) x = (D+m)^dag chi; returns (x, info dict)."""
     torch = _torch()
-    c = _device_tensor(chi, torch.complex128)
+    c = _device_tensor(chi, torch.complex128, stream)
     x = torch.empty_like(c)
     opts = opts or solve_opts()
-    nb = int(lib().lq_solve_workspace_bytes(gauge._h, formulation, ctypes.byref(opts), 1))
+    nb = int(lib().lq_solve_workspace_bytes(gauge._h, formulation, g55, ctypes.byref(opts), 1))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     d = Dirac(formulation, g55, mass, r)
     info = SolveInfo()
@@ -365,11 +389,11 @@ def cg_solve_batch(gauge, formulation, masses, chis, tols, maxiter=100000, r=1.0
                    g55=G55_CORNERS, opts=None, stream=None, workspace=None):
     """Batched multi-RHS CG; chis has a leading RHS axis.  Returns (x, [info])."""
     torch = _torch()
-    c = _device_tensor(chis, torch.complex128)
+    c = _device_tensor(chis, torch.complex128, stream)
     n = c.shape[0]
     x = torch.empty_like(c)
     opts = opts or solve_opts()
-    nb = int(lib().lq_solve_workspace_bytes(gauge._h, formulation, ctypes.byref(opts), n))
+    nb = int(lib().lq_solve_workspace_bytes(gauge._h, formulation, g55, ctypes.byref(opts), n))
     ws = workspace if workspace is not None and workspace.numel() >= nb else \
         torch.empty(nb, dtype=torch.uint8, device="cuda")
     m = (ctypes.c_double * n)(*[float(v) for v in masses])
@@ -389,8 +413,8 @@ def condition_number(gauge, formulation, mass, v0, steps=200, r=1.0, g55=G55_COR
 
     Returns dict(lmin, lmax, kappa, alpha, beta, steps)."""
     torch = _torch()
-    v = _device_tensor(v0, torch.complex128)
-    nb = int(lib().lq_lanczos_workspace_bytes(gauge._h, formulation, steps))
+    v = _device_tensor(v0, torch.complex128, stream)
+    nb = int(lib().lq_lanczos_workspace_bytes(gauge._h, formulation, g55, steps))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     d = Dirac(formulation, g55, mass, r)
     lmin, lmax, kappa = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
@@ -409,8 +433,8 @@ def critical_mass(gauge, formulation, v0, lo, hi, steps=200, ngrid=7, ngolden=8,
                   g55=G55_CORNERS, stream=None):
     """m_c = argmin_m of the Lanczos lowest Ritz value (scan + golden section)."""
     torch = _torch()
-    v = _device_tensor(v0, torch.complex128)
-    nb = int(lib().lq_lanczos_workspace_bytes(gauge._h, formulation, steps))
+    v = _device_tensor(v0, torch.complex128, stream)
+    nb = int(lib().lq_lanczos_workspace_bytes(gauge._h, formulation, g55, steps))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     mc, th = ctypes.c_double(), ctypes.c_double()
     _check(lib().lq_critical_mass(gauge._h, formulation, g55, r, lo, hi, ngrid, ngolden, steps,
@@ -428,8 +452,8 @@ class Batch:
         self.formulation = formulation
         self.nslots = nslots
         self.opts = opts or solve_opts()
-        nb = int(lib().lq_solve_workspace_bytes(gauge._h, formulation, ctypes.byref(self.opts),
-                                                nslots))
+        nb = int(lib().lq_solve_workspace_bytes(gauge._h, formulation, g55,
+                                                ctypes.byref(self.opts), nslots))
         self.ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
         self.nbytes = nb
         h = ctypes.c_void_p()
@@ -441,7 +465,7 @@ class Batch:
 
     def load(self, slot, chi, mass, tol, maxiter=100000, stream=None):
         torch = _torch()
-        c = _device_tensor(chi, torch.complex128)
+        c = _device_tensor(chi, torch.complex128, stream)
         self._keep[slot] = c
         _check(lib().lq_batch_load(self._h, slot, _ptr(c), mass, tol, maxiter, _stream(stream)))
 
@@ -469,7 +493,7 @@ class Batch:
         sc = ctypes.c_double()
         _check(lib().lq_batch_peek(self._h, slot, ctypes.byref(info), ctypes.byref(sc)))
         d = info.as_dict()
-        d["flags"] = int(d.pop("seconds"))
+        d.pop("seconds")
         d["scale"] = sc.value
         return d
 

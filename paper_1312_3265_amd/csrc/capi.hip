@@ -1,5 +1,6 @@
 // extern "C" entry points of include/lq.h: argument validation, error codes,
 // and thin calls into the engine.  No C++ exception crosses this file.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -104,11 +105,12 @@ size_t lq_gauge_bytes(const lq_lattice* lat, uint32_t features) {
   return gauge_layout(lat->g, features, nullptr, nullptr);
 }
 
-int lq_gauge_create(const lq_lattice* lat, const void* U, uint32_t features, void* buf,
-                    size_t buf_bytes, void* stream, lq_gauge** out) {
+int lq_gauge_create(const lq_lattice* lat, const void* U, int32_t where, uint32_t features,
+                    void* buf, size_t buf_bytes, void* stream, lq_gauge** out) {
   return guard([&] {
     need(lat && U && buf && out, "null argument");
     need((features & ~15u) == 0, "unknown feature bits");
+    need(where == LQ_WHERE_HOST || where == LQ_WHERE_DEVICE, "where must be host or device");
     const size_t nb = gauge_layout(lat->g, features, nullptr, nullptr);
     if (buf_bytes < nb)
       throw Error(LQ_ERR_WORKSPACE, "gauge buffer too small: need " + std::to_string(nb));
@@ -116,7 +118,19 @@ int lq_gauge_create(const lq_lattice* lat, const void* U, uint32_t features, voi
     gauge_layout(lat->g, features, buf, g.get());
     hipStream_t s = S(stream);
     launch_fill_zero(buf, nb, s);
-    launch_gauge_in(g->g, U, g->u64, s);
+    if (where == LQ_WHERE_DEVICE) {
+      launch_gauge_in(g->g, U, g->u64, 0, g->g.V, s);
+    } else {
+      // chunks through the staging area; the copy of a chunk is ordered after
+      // the repack of the previous one on the same stream
+      const size_t site_bytes = 36 * 16;
+      for (int i0 = 0; i0 < g->g.V; i0 += kStageSites) {
+        const int n = std::min(kStageSites, g->g.V - i0);
+        LQ_HIP(hipMemcpyAsync(g->stage, (const char*)U + (size_t)i0 * site_bytes,
+                              (size_t)n * site_bytes, hipMemcpyHostToDevice, s));
+        launch_gauge_in(g->g, g->stage, g->u64, i0, n, s);
+      }
+    }
     launch_su3_deviation(g->g, g->u64, g->scratch, g->scratch + g->nbp + 1, s);
     LQ_HIP(hipMemcpyAsync(&g->su3_dev, g->scratch + g->nbp + 1, sizeof(double),
                           hipMemcpyDeviceToHost, s));
@@ -175,13 +189,16 @@ int lq_gauge_plaquette(const lq_gauge* g, double* plaquette, void* stream) {
 }
 
 // -------------------------------------------------------------- apply
-size_t lq_apply_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t precision) {
+size_t lq_apply_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t g55_mode,
+                                int32_t precision) {
   if (!g || (formulation != LQ_WILSON && formulation != LQ_STAGGERED_WILSON)) return 0;
   if (precision < 0 || precision > 2) return 0;
+  if (g55_mode != LQ_G55_CORNERS && g55_mode != LQ_G55_ONTHEFLY) return 0;
   const size_t v = field_bytes(g->g, precision, ncomp_of(formulation));
   Carver c(nullptr);
   c.take(v); c.take(v); c.take(v);
   c.take((size_t)nbp_of(g->g.V) * 8);
+  if (opkind(formulation, g55_mode) == OP_SW_OTF) c.take(g55_bytes_per_system(g->g, precision));
   return c.size();
 }
 
@@ -205,18 +222,22 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t opsel, int32_t precis
     check_dirac(d);
     check_prec(precision, links);
     need(opsel == LQ_OP_M || opsel == LQ_OP_MDAG || opsel == LQ_OP_MDAGM, "bad op");
-    const size_t nb = lq_apply_workspace_bytes(g, d->formulation, precision);
+    const size_t nb = lq_apply_workspace_bytes(g, d->formulation, d->g55_mode, precision);
     if (ws_bytes < nb) throw Error(LQ_ERR_WORKSPACE, "apply workspace too small: need " + std::to_string(nb));
     const int nl = links_for(g, precision, links);
     const int nc = ncomp_of(d->formulation);
     const int op = opkind(d->formulation, d->g55_mode);
-    const OpArgs oa = make_op(g, d, precision, nl);
+    OpArgs oa = make_op(g, d, precision, nl);
     const size_t v = field_bytes(g->g, precision, nc);
     Carver c(ws);
     void* a = c.take(v);
     void* b = c.take(v);
     void* tmp = c.take(v);
     (void)c.take((size_t)nbp_of(g->g.V) * 8);
+    if (op == OP_SW_OTF) {
+      oa.g55_sys = g55_bytes_per_system(g->g, precision);
+      oa.g55w = c.take(oa.g55_sys);
+    }
     hipStream_t s = S(stream);
     const int nbp = nbp_of(g->g.V);
     const int f64 = precision == LQ_PREC_F64;
@@ -282,10 +303,11 @@ int lq_schur_apply(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t
   });
 }
 
-size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t precision,
-                                      int32_t nrhs) {
+size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t g55_mode,
+                                      int32_t precision, int32_t nrhs) {
   if (!g || nrhs < 1 || precision < 0 || precision > 2) return 0;
   if (formulation != LQ_WILSON && formulation != LQ_STAGGERED_WILSON) return 0;
+  if (g55_mode != LQ_G55_CORNERS && g55_mode != LQ_G55_ONTHEFLY) return 0;
   const size_t v = (size_t)nrhs * field_bytes(g->g, precision, ncomp_of(formulation));
   const size_t np = (size_t)nrhs * nbp_of(g->g.V) * sizeof(double);
   Carver c(nullptr);
@@ -300,6 +322,8 @@ size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, in
   c.take(v);   // the odd intermediate of the even-odd pairs
   c.take(v);   // two more search directions of the CG update's group of four
   c.take(v);
+  if (opkind(formulation, g55_mode) == OP_SW_OTF)
+    c.take((size_t)nrhs * g55_bytes_per_system(g->g, precision));
   return c.size();
 }
 
@@ -335,9 +359,13 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     void* w = c.take(v);
     void* pr1 = c.take(v);
     void* pr2 = c.take(v);
+    OpArgs oa = make_op(g, d, precision, nl);
+    if (op == OP_SW_OTF) {
+      oa.g55_sys = g55_bytes_per_system(g->g, precision);
+      oa.g55w = c.take((size_t)nrhs * oa.g55_sys);
+    }
     if (ws_bytes < c.size())
       throw Error(LQ_ERR_WORKSPACE, "timing workspace too small: need " + std::to_string(c.size()));
-    const OpArgs oa = make_op(g, d, precision, nl);
     hipStream_t s = S(stream);
     launch_fill_zero(ws, c.size(), s);
     const Geom vg = eo ? half_geom(g->g) : g->g;   // geometry of the timed fields
@@ -403,11 +431,12 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
 }
 
 // -------------------------------------------------------------- solves
-size_t lq_solve_workspace_bytes(const lq_gauge* g, int32_t formulation, const lq_solve_opts* opts,
-                                int32_t nrhs) {
+size_t lq_solve_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t g55_mode,
+                                const lq_solve_opts* opts, int32_t nrhs) {
   if (!g || nrhs < 1) return 0;
   if (formulation != LQ_WILSON && formulation != LQ_STAGGERED_WILSON) return 0;
-  return Engine::workspace_bytes(g->g, formulation, opts, nrhs);
+  if (g55_mode != LQ_G55_CORNERS && g55_mode != LQ_G55_ONTHEFLY) return 0;
+  return Engine::workspace_bytes(g->g, formulation, g55_mode, opts, nrhs);
 }
 
 static void check_opts(const lq_solve_opts* o) {
@@ -458,7 +487,7 @@ int lq_cg_solve_batch(const lq_gauge* g, int32_t formulation, int32_t g55_mode, 
       infos[k].seconds = secs;
       const int st = infos[k].status;
       if (st < 0 && (worst >= 0 || st < worst)) worst = st;
-      if (st > 0 && worst == LQ_OK) worst = st;
+      if (st > 0 && worst >= 0 && st > worst) worst = st;
     }
     if (worst != LQ_OK) g_last_error = "at least one system did not converge";
     return worst;
@@ -592,7 +621,8 @@ int lq_batch_peek(lq_batch* b, int32_t slot, lq_solve_info* info, double* scale)
     info->applications = h.apps + 1;
     info->iterated_residual = std::sqrt(h.iter_res2 / bn);
     info->true_residual = std::sqrt(h.true_res2 / bn);
-    info->seconds = (double)h.flags;
+    info->flags = h.flags;
+    info->seconds = 0.0;
     if (scale) *scale = h.scale;
     return LQ_OK;
   });
@@ -601,10 +631,12 @@ int lq_batch_peek(lq_batch* b, int32_t slot, lq_solve_info* info, double* scale)
 void lq_batch_destroy(lq_batch* b) { delete b; }
 
 // ---------------------------------------------------- condition number
-size_t lq_lanczos_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t steps) {
+size_t lq_lanczos_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t g55_mode,
+                                  int32_t steps) {
   if (!g || steps < 1 || steps > 1000) return 0;
   if (formulation != LQ_WILSON && formulation != LQ_STAGGERED_WILSON) return 0;
-  return lanczos_workspace_bytes(g->g, formulation, steps);
+  if (g55_mode != LQ_G55_CORNERS && g55_mode != LQ_G55_ONTHEFLY) return 0;
+  return lanczos_workspace_bytes(g->g, formulation, g55_mode, steps);
 }
 
 int lq_condition_number(const lq_gauge* g, const lq_dirac* d, int32_t steps, const void* v0,
@@ -627,10 +659,12 @@ int lq_condition_number(const lq_gauge* g, const lq_dirac* d, int32_t steps, con
   });
 }
 
-size_t lq_spectrum_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t steps) {
+size_t lq_spectrum_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t g55_mode,
+                                   int32_t steps) {
   if (!g || steps < 2 || steps > 500) return 0;
   if (formulation != LQ_WILSON && formulation != LQ_STAGGERED_WILSON) return 0;
-  return spectrum_workspace_bytes(g->g, formulation, steps);
+  if (g55_mode != LQ_G55_CORNERS && g55_mode != LQ_G55_ONTHEFLY) return 0;
+  return spectrum_workspace_bytes(g->g, formulation, g55_mode, steps);
 }
 
 int lq_spectrum(const lq_gauge* g, const lq_dirac* d, double sigma, int32_t steps,

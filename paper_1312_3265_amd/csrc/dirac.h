@@ -25,6 +25,10 @@ struct OpArgs {
   const void* diag_in = nullptr;
   int eo_par = 0;
   int eo_schur = 0;
+  // on-the-fly Gamma_55: the intermediate fields of system k start at
+  // (char*)g55w + k * g55_sys (see G55Pol, kG55Fields)
+  void* g55w = nullptr;
+  size_t g55_sys = 0;
 };
 
 __device__ __forceinline__ double rhs_mass(const OpArgs& a, int k) {
@@ -559,100 +563,39 @@ struct SWCornerOp {
   }
 };
 
-// On-the-fly form (K2): Gamma_55 psi(x) = phi(x)/24 F_{1234}(x) with
-// F_S(y) = sum_{mu in S} C_mu F_{S\mu}(y), evaluated depth-first inside the
-// 3^4 hypercube around x straight from the links.  C_mu = (V_mu + V_mu^dag)/2,
-// so each level carries a factor 1/2, collected once at the end (1/16).
-template <class P, int NL>
-__device__ __forceinline__ void apply_L(const OpArgs& a, int ysite, int mu, int sgn,
-                                        int nbsite, const typename P::C v[3],
-                                        typename P::C y[3]) {
-  // y = L(y, sgn*mu) v: U_mu(y) v (sgn > 0) or U_mu(y - mu)^dag v (sgn < 0)
-  using C = typename P::C;
-  using LP = typename LinkPol<P, NL>::type;
-  C lk[9];
-  if (sgn > 0) {
-    load_link<LP, NL>((const typename LP::S*)a.links, a.g.Vp, mu, ysite, lk);
-    mv(lk, v, y);
-  } else {
-    load_link<LP, NL>((const typename LP::S*)a.links, a.g.Vp, mu, nbsite, lk);
-    mvd(lk, v, y);
-  }
+// On-the-fly form (K2): the subset recursion of the symmetrised product,
+//   F_{} = psi,   F_S = sum_{mu in S} C_mu F_{S\mu},   Gamma_55 psi = phi F_{1234} / 24,
+// with C_mu = (V_mu + V_mu^dag)/2 (Sec. 2; the 24 orderings of C_1 C_2 C_3 C_4
+// are exactly the words that take one direction out of S at a time).  Every
+// F_S is a field on the whole lattice, so the recursion costs 4 + 6*2 + 4*3 +
+// 4 = 32 applications of some C_mu per site, each a nearest-neighbour hop:
+// level L (|S| = L) reads level L-1 at x +- mu only (halo depth 1).  Levels 1
+// to 3 are separate launches (g55_level_kernel) into intermediate fields in
+// the caller's workspace; level 4 is computed inside the operator below,
+// beside D_st and the diagonal.  The fields are kept unnormalised
+// (V + V^dag at every level), so F_{1234} carries 2^4 and the last step
+// multiplies by phi / (24 * 16).
+//
+// Intermediate fields: FP64 for FP64 operators, FP32 for the FP32 and 16-bit
+// ones (three complex numbers per site, the staggered Wilson vector record).
+// Per system 14 fields: index mu (|S| = 1), 4 + pair index (|S| = 2, pairs
+// 01 02 03 12 13 23), 10 + the missing direction (|S| = 3).
+template <class P> struct G55Pol { using type = F32; };
+template <> struct G55Pol<F64> { using type = F64; };
+constexpr int kG55Fields = 14;
+__host__ __device__ constexpr int g55_field(int mask) {
+  // mask: bit mu set for mu in S, 1 <= |S| <= 3
+  return __builtin_popcount(mask) == 1   ? __builtin_ctz(mask)
+         : __builtin_popcount(mask) == 3 ? 10 + __builtin_ctz(15 ^ mask)
+         : mask == 3 ? 4 : mask == 5 ? 5 : mask == 9 ? 6 : mask == 6 ? 7 : mask == 10 ? 8 : 9;
 }
-
-__device__ __forceinline__ int step_site(const Geom& g, int y[4], int idx, int mu, int sgn,
-                                         int& sign) {
-  // move coordinates y by sgn*mu, return the new site index, update bc sign
-  int n = y[mu] + sgn;
-  if (n < 0) { n += g.L[mu]; idx += (g.L[mu] - 1) * g.stride[mu]; sign *= g.bc[mu]; }
-  else if (n >= g.L[mu]) { n -= g.L[mu]; idx -= (g.L[mu] - 1) * g.stride[mu]; sign *= g.bc[mu]; }
-  else idx += sgn * g.stride[mu];
-  y[mu] = n;
-  return idx;
-}
-
-template <class P, int NL>
-__device__ __noinline__ void gamma55_otf(const OpArgs& a, const typename P::S* __restrict__ in,
-                                         const Coord& c, int i, typename P::C out[3]) {
-  using C = typename P::C;
-  using R = typename P::R;
-  const Geom& g = a.g;
-  C acc4[3] = {czero<C>(), czero<C>(), czero<C>()};
-#pragma unroll 1
-  for (int d4 = 0; d4 < 8; ++d4) {
-    const int mu4 = d4 >> 1, s4 = (d4 & 1) ? -1 : 1;
-    int y3[4] = {c.x[0], c.x[1], c.x[2], c.x[3]};
-    int sg3 = 1;
-    const int i3 = step_site(g, y3, i, mu4, s4, sg3);
-    const int S3 = 15 ^ (1 << mu4);
-    C acc3[3] = {czero<C>(), czero<C>(), czero<C>()};
-#pragma unroll 1
-    for (int d3 = 0; d3 < 8; ++d3) {
-      const int mu3 = d3 >> 1, s3 = (d3 & 1) ? -1 : 1;
-      if (!((S3 >> mu3) & 1)) continue;
-      int y2[4] = {y3[0], y3[1], y3[2], y3[3]};
-      int sg2 = 1;
-      const int i2 = step_site(g, y2, i3, mu3, s3, sg2);
-      const int S2 = S3 ^ (1 << mu3);
-      C acc2[3] = {czero<C>(), czero<C>(), czero<C>()};
-#pragma unroll 1
-      for (int d2 = 0; d2 < 8; ++d2) {
-        const int mu2 = d2 >> 1, s2 = (d2 & 1) ? -1 : 1;
-        if (!((S2 >> mu2) & 1)) continue;
-        int y1[4] = {y2[0], y2[1], y2[2], y2[3]};
-        int sg1 = 1;
-        const int i1 = step_site(g, y1, i2, mu2, s2, sg1);
-        const int mu1 = __ffs(S2 ^ (1 << mu2)) - 1;
-        // level 1: C_mu1 psi at y1 (unnormalised: V + V^dag)
-        C acc1[3] = {czero<C>(), czero<C>(), czero<C>()};
-#pragma unroll
-        for (int s1 = 1; s1 >= -1; s1 -= 2) {
-          int y0[4] = {y1[0], y1[1], y1[2], y1[3]};
-          int sg0 = 1;
-          const int i0 = step_site(g, y0, i1, mu1, s1, sg0);
-          C v[3], y[3];
-          ld_site<P, 3>(in, g.Vp, i0, v);
-          apply_L<P, NL>(a, i1, mu1, s1, i0, v, y);
-#pragma unroll
-          for (int q = 0; q < 3; ++q) acc1[q] = cadd(acc1[q], cscale(y[q], (R)sg0));
-        }
-        C y[3];
-        apply_L<P, NL>(a, i2, mu2, s2, i1, acc1, y);
-#pragma unroll
-        for (int q = 0; q < 3; ++q) acc2[q] = cadd(acc2[q], cscale(y[q], (R)sg1));
-      }
-      C y[3];
-      apply_L<P, NL>(a, i3, mu3, s3, i2, acc2, y);
-#pragma unroll
-      for (int q = 0; q < 3; ++q) acc3[q] = cadd(acc3[q], cscale(y[q], (R)sg2));
-    }
-    C y[3];
-    apply_L<P, NL>(a, i, mu4, s4, i3, acc3, y);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) acc4[q] = cadd(acc4[q], cscale(y[q], (R)sg3));
-  }
-#pragma unroll
-  for (int q = 0; q < 3; ++q) out[q] = acc4[q];
+template <class P>
+__device__ __forceinline__ const typename G55Pol<P>::type::S* g55_in(const OpArgs& a, int k,
+                                                                   int field) {
+  using PC = typename G55Pol<P>::type;
+  const char* base = (const char*)a.g55w + (size_t)k * a.g55_sys;
+  return (const typename PC::S*)(base + (size_t)field * field_planes<PC>(3) * a.g.Vp *
+                                            sizeof(typename PC::S));
 }
 
 template <class P, int NL, bool DAG>
@@ -664,32 +607,61 @@ struct SWOtfOp {
   using R = typename P::R;
   using S = typename P::S;
 
+  // acc[k] += sum_mu [U_mu(x) F_{S_mu}(x + mu) + U_mu(x - mu)^dag F_{S_mu}(x - mu)],
+  // S_mu = the three directions other than mu: the last level of the
+  // recursion from the third-level fields of system k0 + k
+  template <int K>
+  __device__ __forceinline__ static void level4(const OpArgs& a, const Coord& c, int i, int k0,
+                                                unsigned act, C acc[K][3]) {
+    using PC = typename G55Pol<P>::type;
+    using LP = typename LinkPol<P, NL>::type;
+    const Geom& g = a.g;
+#pragma unroll 1
+    for (int h = 0; h < 8; ++h) {
+      const int mu = h >> 1;
+      const bool back = h & 1;
+      bool wrap;
+      const int j = back ? nb_bwd(g, c, i, mu, wrap) : nb_fwd(g, c, i, mu, wrap);
+      const R sg = ((wrap && g.bc[mu] < 0) ? (R)-1 : (R)1) * (R)LP::kRawScale;
+      C lk[9];
+      load_link<LP, NL, true>((const typename LP::S*)a.links, g.Vp, mu, back ? j : i, lk);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (!((act >> k) & 1)) continue;
+        C v[3], y[3];
+        ld_site<PC, 3>(g55_in<P>(a, k0 + k, 10 + mu), g.Vp, j, v);
+        if (back) mvd(lk, v, y); else mv(lk, v, y);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[k][q] = cfmas(y[q], sg, acc[k][q]);
+      }
+    }
+  }
+
   template <int K>
   __device__ __forceinline__ static void site_multi(const OpArgs& a, const S* __restrict__ in0,
                                                     size_t rstride, int i, int k0, unsigned act,
                                                     C out[K][3]) {
-#pragma unroll 1
-    for (int k = 0; k < K; ++k)
-      if ((act >> k) & 1) site(a, in0 + k * rstride, i, k0 + k, out[k]);
-  }
-
-  __device__ __forceinline__ static void site(const OpArgs& a, const S* __restrict__ in, int i,
-                                              int k, C out[3]) {
     const Geom& g = a.g;
     Coord c = site_coords(g, i);
-    C d1[1][3], f[3];
-    dst_site<P, NL, 1>(a, in, 0, c, i, 1u, d1);
-    C* d = d1[0];
-    gamma55_otf<P, NL>(a, in, c, i, f);
-    const R mr = (R)(rhs_mass(a, k) + a.r);
-    // phi/24 * (1/2)^4 from the four C_mu factors
+    C d[K][3], f[K][3];
+    dst_site<P, NL, K>(a, in0, rstride, c, i, act, d);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) f[k][q] = czero<C>();
+    level4<K>(a, c, i, k0, act, f);
+    // phi/24 * (1/2)^4 from the four unnormalised C_mu levels
     const R gcoef = (R)(a.r * phi_sign(c) / (24.0 * 16.0));
     const R dcoef = DAG ? (R)-0.5 : (R)0.5;
-    C v[3];
-    ld_site<P, 3>(in, g.Vp, i, v);
 #pragma unroll
-    for (int q = 0; q < 3; ++q)
-      out[q] = csub(cadd(cscale(v[q], mr), cscale(d[q], dcoef)), cscale(f[q], gcoef));
+    for (int k = 0; k < K; ++k) {
+      const R mr = (R)(rhs_mass(a, k0 + k) + a.r);
+      C v[3] = {czero<C>(), czero<C>(), czero<C>()};
+      if ((act >> k) & 1) ld_site<P, 3>(in0 + k * rstride, g.Vp, i, v);
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        out[k][q] = csub(cadd(cscale(v[q], mr), cscale(d[k][q], dcoef)), cscale(f[k][q], gcoef));
+    }
   }
 };
 

@@ -111,6 +111,7 @@ struct lq_gauge_s {
   float2* c32 = nullptr;
   short2* c16 = nullptr;
   double* scratch = nullptr;  // plaquette partials + result
+  double2* stage = nullptr;   // staging area of a host upload (kStageSites canonical sites)
   int nbp = 0;
   double su3_dev = 0.0;       // max |row2 - conj(row0 x row1)| over the links
 
@@ -125,6 +126,8 @@ struct lq_gauge_s {
 
 namespace lq {
 
+// Canonical sites per chunk of a host gauge upload (576 bytes each).
+constexpr int kStageSites = 4096;
 // Carves a gauge buffer; with base == nullptr only the size is computed.
 size_t gauge_layout(const Geom& g, uint32_t features, void* base, lq_gauge_s* out);
 
@@ -155,6 +158,7 @@ struct Engine {
   PRing ring() const { return PRing{{p, p1, p2, p3}}; }
   int group = 4;   // iterations per x update (2 for FP64: its vectors stay in the last-level cache)
   double *part_t = nullptr, *part_r = nullptr, *part_u = nullptr;
+  void* g55w = nullptr;       // on-the-fly Gamma_55: intermediate fields, FP64-sized per slot
   SlotState* st = nullptr;
   int* mask = nullptr;        // per-slot reliable-update selection
   // host
@@ -165,8 +169,8 @@ struct Engine {
   hipStream_t gstream = nullptr;
   int gchunk = 0;
 
-  static size_t workspace_bytes(const Geom& g, int formulation, const lq_solve_opts* opts,
-                                int nslots);
+  static size_t workspace_bytes(const Geom& g, int formulation, int g55,
+                                const lq_solve_opts* opts, int nslots);
   void init(const lq_gauge_s* g, int formulation, int g55, double r, int nslots,
             const lq_solve_opts* opts, void* ws, size_t ws_bytes, hipStream_t s);
   ~Engine();
@@ -212,10 +216,10 @@ std::string tune_key(const Geom& g, int op, int prec, int nl, int nslots);
 void remember_rhs_per_thread(const std::string& key, int k);
 
 // Lanczos with full reorthogonalisation on A = M^dag M.
-size_t lanczos_workspace_bytes(const Geom& g, int formulation, int steps);
+size_t lanczos_workspace_bytes(const Geom& g, int formulation, int g55, int steps);
 // Eigenvalues of M (the Dirac matrix of d) nearest the real shift sigma by
 // shift-invert Arnoldi; see lq_spectrum.  Returns the number found.
-size_t spectrum_workspace_bytes(const Geom& g, int formulation, int steps);
+size_t spectrum_workspace_bytes(const Geom& g, int formulation, int g55, int steps);
 int spectrum_run(const lq_gauge_s* g, const lq_dirac* d, double sigma, int steps, int restarts,
                  double tol, const void* v0, void* ws, size_t ws_bytes, std::vector<cplx>& eig,
                  std::vector<double>& resid, hipStream_t s);

@@ -100,6 +100,7 @@ size_t gauge_layout(const Geom& g, uint32_t f, void* base, lq_gauge_s* out) {
   }
   const int nbp = nbp_of(g.V);
   double* scratch = (double*)c.take((nbp + 8) * sizeof(double));
+  double2* stage = (double2*)c.take((size_t)std::min(g.V, kStageSites) * 36 * 16);
   if (out) {
     out->g = g;
     out->features = f;
@@ -109,6 +110,7 @@ size_t gauge_layout(const Geom& g, uint32_t f, void* base, lq_gauge_s* out) {
     out->eo16_12 = eo16_12; out->eo16_18 = eo16_18;
     out->c64 = c64; out->c32 = c32; out->c16 = c16;
     out->scratch = scratch;
+    out->stage = stage;
     out->nbp = nbp;
   }
   return c.size();
@@ -268,8 +270,8 @@ void enqueue_schur(const lq_gauge_s* g, const OpArgs& base, int prec, int nl, bo
 // ================================================================ Engine
 static int prec_of(const lq_solve_opts* o) { return o ? o->precision : LQ_PREC_F64; }
 
-size_t Engine::workspace_bytes(const Geom& g0, int formulation, const lq_solve_opts* opts,
-                               int nslots) {
+size_t Engine::workspace_bytes(const Geom& g0, int formulation, int g55,
+                               const lq_solve_opts* opts, int nslots) {
   const int nc = ncomp_of(formulation);
   const int prec = prec_of(opts);
   const bool eo = opts && opts->evenodd;
@@ -293,6 +295,7 @@ size_t Engine::workspace_bytes(const Geom& g0, int formulation, const lq_solve_o
   for (int k = 0; k < 3; ++k) c.take((size_t)nslots * nbp * sizeof(double));
   c.take((size_t)nslots * sizeof(SlotState));
   c.take((size_t)nslots * sizeof(int));
+  if (opkind(formulation, g55) == OP_SW_OTF) c.take((size_t)nslots * g55_bytes_per_system(g, P64));
   return c.size();
 }
 
@@ -331,7 +334,7 @@ void Engine::init(const lq_gauge_s* g, int form, int g55, double rr, int ns,
   if (eo) { (void)g->links_eo(prec_lo, nl_lo, 0); (void)g->links_eo(P64, g->fp64_links(), 0); }
   if (op == OP_SW_CORNERS) { (void)g->corners(prec_lo); (void)g->corners(P64); }
 
-  const size_t need = workspace_bytes(g->g, form, opts, ns);
+  const size_t need = workspace_bytes(g->g, form, g55, opts, ns);
   if (!ws || ws_bytes < need)
     throw Error(LQ_ERR_WORKSPACE, "solver workspace too small: need " + std::to_string(need) +
                                       " bytes, got " + std::to_string(ws_bytes));
@@ -363,6 +366,7 @@ void Engine::init(const lq_gauge_s* g, int form, int g55, double rr, int ns,
   part_u = (double*)c.take((size_t)ns * nbp * sizeof(double));
   st = (SlotState*)c.take((size_t)ns * sizeof(SlotState));
   mask = (int*)c.take((size_t)ns * sizeof(int));
+  if (op == OP_SW_OTF) g55w = c.take((size_t)ns * g55_bytes_per_system(vg, P64));
   // zero the whole workspace once: plane padding stays zero afterwards
   launch_fill_zero(ws, c.size(), s);
   check_launch();
@@ -390,6 +394,10 @@ OpArgs Engine::op_args(int prec, int nl) const {
   a.mass0 = 0.0;
   a.mass = &st[0].mass;
   a.mass_stride = sizeof(SlotState) / sizeof(double);
+  if (op == OP_SW_OTF) {
+    a.g55w = g55w;
+    a.g55_sys = g55_bytes_per_system(vg, prec);
+  }
   return a;
 }
 
@@ -642,7 +650,9 @@ void Engine::fetch(int slot, void* x, lq_solve_info* info, hipStream_t s) {
     const double bn = h.bnorm2 > 0 ? h.bnorm2 : 1.0;
     info->status = h.status == SLOT_DONE ? LQ_OK
                    : (h.flags & 1)       ? LQ_ERR_BREAKDOWN
+                   : (h.flags & 4)       ? LQ_STAGNATION
                                          : LQ_NOT_CONVERGED;
+    info->flags = h.flags;
     info->iterations = h.iter;
     info->reliable_updates = h.ru;
     info->applications = h.apps + 1;   // + b = M^dag chi
@@ -674,7 +684,7 @@ void Engine::cancel(int slot, hipStream_t s) {
 // =============================================================== Lanczos
 static constexpr int kLzBlocks = 256;
 
-size_t lanczos_workspace_bytes(const Geom& g, int formulation, int steps) {
+size_t lanczos_workspace_bytes(const Geom& g, int formulation, int g55, int steps) {
   const int nc = ncomp_of(formulation);
   const size_t vec = (size_t)nc * g.Vp * 16;
   Carver c(nullptr);
@@ -686,6 +696,7 @@ size_t lanczos_workspace_bytes(const Geom& g, int formulation, int steps) {
   c.take((size_t)nbp_of(g.V) * 8);                          // alpha partials
   c.take((size_t)kLzBlocks * 8);                            // norm partials
   c.take((size_t)(steps + 2) * 8 * 2);                      // alpha, beta
+  if (opkind(formulation, g55) == OP_SW_OTF) c.take(g55_bytes_per_system(g, P64));
   return c.size();
 }
 
@@ -696,7 +707,7 @@ int lanczos_run(const lq_gauge_s* gs, const lq_dirac* d, int steps, const void* 
   const int nc = ncomp_of(d->formulation);
   const int op = opkind(d->formulation, d->g55_mode);
   if (steps < 1 || steps > 1000) throw Error(LQ_ERR_ARG, "steps must be in [1, 1000]");
-  const size_t need = lanczos_workspace_bytes(g, d->formulation, steps);
+  const size_t need = lanczos_workspace_bytes(g, d->formulation, d->g55_mode, steps);
   if (!ws || ws_bytes < need)
     throw Error(LQ_ERR_WORKSPACE, "Lanczos workspace too small: need " + std::to_string(need));
   const size_t n = (size_t)nc * g.Vp;
@@ -712,6 +723,7 @@ int lanczos_run(const lq_gauge_s* gs, const lq_dirac* d, int steps, const void* 
   double* part_n = (double*)c.take((size_t)kLzBlocks * 8);
   double* ad = (double*)c.take((size_t)(steps + 2) * 8 * 2);
   double* bd = ad + steps + 2;
+  void* g55w = op == OP_SW_OTF ? c.take(g55_bytes_per_system(g, P64)) : nullptr;
   launch_fill_zero(ws, c.size(), s);
 
   OpArgs oa;
@@ -723,6 +735,8 @@ int lanczos_run(const lq_gauge_s* gs, const lq_dirac* d, int steps, const void* 
   oa.mass0 = d->mass;
   oa.mass = nullptr;
   oa.mass_stride = 0;
+  oa.g55w = g55w;
+  oa.g55_sys = g55_bytes_per_system(g, P64);
 
   // v_1 = v0 / ||v0||
   launch_field_in(P64, nc, g, v0, 1, w, nbp, 0, 1, s);
@@ -786,7 +800,7 @@ int lanczos_run(const lq_gauge_s* gs, const lq_dirac* d, int steps, const void* 
 // vector, whose coupling becomes one full row of the projected matrix;
 // Arnoldi then extends the basis again.  The eigenvalues mu of the projected
 // matrix give lambda = sigma + 1/mu.
-size_t spectrum_workspace_bytes(const Geom& g, int formulation, int steps) {
+size_t spectrum_workspace_bytes(const Geom& g, int formulation, int g55, int steps) {
   const int nc = ncomp_of(formulation);
   const size_t vec = (size_t)nc * g.Vp * 16;
   const size_t canon = (size_t)g.V * nc * 16;
@@ -800,7 +814,7 @@ size_t spectrum_workspace_bytes(const Geom& g, int formulation, int steps) {
   c.take((size_t)(steps + 1) * kLzBlocks * 2 * 8);          // part_h
   c.take((size_t)kLzBlocks * 8);                            // norm partials
   c.take((size_t)(steps + 2) * 8);                          // beta
-  c.take(Engine::workspace_bytes(g, formulation, nullptr, 1));
+  c.take(Engine::workspace_bytes(g, formulation, g55, nullptr, 1));
   return c.size();
 }
 
@@ -812,7 +826,7 @@ int spectrum_run(const lq_gauge_s* gs, const lq_dirac* d, double sigma, int step
   if (steps < 2 || steps > 500) throw Error(LQ_ERR_ARG, "steps must be in [2, 500]");
   if (restarts < 0 || restarts > 1000) throw Error(LQ_ERR_ARG, "restarts must be in [0, 1000]");
   if (!(tol > 0.0 && tol < 1.0)) throw Error(LQ_ERR_ARG, "tol must be in (0, 1)");
-  const size_t need = spectrum_workspace_bytes(g, d->formulation, steps);
+  const size_t need = spectrum_workspace_bytes(g, d->formulation, d->g55_mode, steps);
   if (!ws || ws_bytes < need)
     throw Error(LQ_ERR_WORKSPACE, "spectrum workspace too small: need " + std::to_string(need));
   const int m = steps, keep = steps / 2;
@@ -829,7 +843,7 @@ int spectrum_run(const lq_gauge_s* gs, const lq_dirac* d, double sigma, int step
   double* part_h = (double*)c.take((size_t)(m + 1) * kLzBlocks * 2 * 8);
   double* part_n = (double*)c.take((size_t)kLzBlocks * 8);
   double* bd = (double*)c.take((size_t)(m + 2) * 8);
-  const size_t eb = Engine::workspace_bytes(g, d->formulation, nullptr, 1);
+  const size_t eb = Engine::workspace_bytes(g, d->formulation, d->g55_mode, nullptr, 1);
   void* ews = c.take(eb);
   launch_fill_zero(ws, (char*)ews - (char*)ws, s);
   const int nbp = nbp_of(g.V);

@@ -104,17 +104,22 @@ void launch_field_out(int prec, int nc, const Geom& g, const void* soa, void* ca
 }
 
 // --------------------------------------------------------------- links
+// sites [i0, i0 + n) of the canonical field; canon points at site i0
 __global__ void __launch_bounds__(256)
-gauge_in_kernel(const Geom g, const double2* __restrict__ canon, double2* __restrict__ u64) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.V) return;
+gauge_in_kernel(const Geom g, const double2* __restrict__ canon, double2* __restrict__ u64, int i0,
+                int n) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int i = i0 + j;
 #pragma unroll 4
-  for (int q = 0; q < 36; ++q) u64[(size_t)q * g.Vp + i] = canon[(size_t)i * 36 + q];
+  for (int q = 0; q < 36; ++q) u64[(size_t)q * g.Vp + i] = canon[(size_t)j * 36 + q];
 }
 
-void launch_gauge_in(const Geom& g, const void* canon, double2* u64, hipStream_t s) {
-  hipLaunchKernelGGL(gauge_in_kernel, dim3((g.V + 255) / 256), dim3(256), 0, s, g,
-                     (const double2*)canon, u64);
+void launch_gauge_in(const Geom& g, const void* canon, double2* u64, int i0, int n,
+                     hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(gauge_in_kernel, dim3((n + 255) / 256), dim3(256), 0, s, g,
+                     (const double2*)canon, u64, i0, n);
 }
 
 // FP64 18-real -> precision P with NL reals (12: rows 0 and 1 only)

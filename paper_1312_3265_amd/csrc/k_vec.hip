@@ -202,11 +202,16 @@ __global__ void ru_finish_kernel(SlotState* st, const int* mask, const double* _
   // stagnation: a tolerance below the attainable accuracy is never met, and
   // cycling on from the accuracy floor lets x drift away from it; stop (not
   // converged) once max_cand updates in a row have not halved the true
-  // residual, or as soon as it has grown 100-fold above its best
+  // residual, or once it has stayed 100-fold above its best at two updates
+  // in a row.  A single such update is what the growth trigger of the
+  // low-precision iteration requests: it restarts the iteration from the FP64
+  // residual, which recovers a solve whose drift was only rounding; growth
+  // that survives the restart is not rounding drift.
+  s->grown = (!init && rr > kGrowth2 * s->best2) ? s->grown + 1 : 0;
   if (init || rr < 0.25 * s->best2) {
     s->best2 = rr;
     s->stall = 0;
-  } else if (++s->stall > max_cand || rr > kGrowth2 * s->best2) {
+  } else if (++s->stall > max_cand || s->grown >= 2) {
     s->flags |= 4;
     s->status = SLOT_FAILED;
     return;

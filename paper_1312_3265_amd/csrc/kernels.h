@@ -27,6 +27,10 @@ inline int nbp_of(int V, int block = kBlock) { return (((V + block - 1) / block)
 void launch_stencil(int op, int prec, int nl, bool dag, int epi, const OpArgs& oa,
                     const void* in, const EpiArgs& ea, int nrhs, hipStream_t s);
 
+// Bytes of the intermediate fields of the on-the-fly Gamma_55 for one system
+// (OpArgs::g55w; 14 fields of three complex numbers, FP64 or FP32).
+size_t g55_bytes_per_system(const Geom& g, int prec);
+
 // ---- CG vector kernels (templated on precision and components)
 void launch_p_update(int prec, int nc, const Geom& g, SlotState* st, int par, int pend_next,
                      const double* part, int nbp, const void* p, void* pout, const void* r, int k0,
@@ -55,7 +59,9 @@ void launch_field_in(int prec, int nc, const Geom& g, const void* canon, int can
                      int nbp, int k0, int nrhs, hipStream_t s, int par = -1);
 void launch_field_out(int prec, int nc, const Geom& g, const void* soa, void* canon, int canon_f64,
                       int nbp, int k0, int nrhs, hipStream_t s, int par = -1);
-void launch_gauge_in(const Geom& g, const void* canon, double2* u64, hipStream_t s);
+// sites [i0, i0 + n) of a canonical gauge field whose site i0 is at `canon`
+void launch_gauge_in(const Geom& g, const void* canon, double2* u64, int i0, int n,
+                     hipStream_t s);
 void launch_links_convert(int prec, int nl, const Geom& g, const double2* u64, void* dst,
                           hipStream_t s);
 void launch_links_eo(int prec, int nl, const Geom& g, int Vhp, const double2* u64, void* dst,

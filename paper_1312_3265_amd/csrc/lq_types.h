@@ -35,12 +35,13 @@ struct SlotState {
   int32_t ru;        // reliable updates done
   int32_t cand;      // reliable updates since the iterated residual met tol
   int32_t maxiter;
-  int32_t flags;     // bit0 breakdown, bit1 maxiter reached
+  int32_t flags;     // bit0 breakdown, bit1 maxiter reached, bit2 stagnation
   int32_t apps;      // applications of A (iterations + reliable updates + setup)
   int32_t ru_iter;   // iteration count at the latest reliable update
   int32_t want_ru;   // frozen because the residual dropped by delta (not converged)
   int32_t pend;      // terms alpha[j] * p_ring[j], j < pend, that x still lacks (frozen mid-group)
   int32_t stall;     // reliable updates since the true residual last halved
+  int32_t grown;     // reliable updates in a row with the true residual 100x above its best
 };
 
 enum SlotStatus { SLOT_EMPTY = 0, SLOT_RUNNING = 1, SLOT_DONE = 2, SLOT_FAILED = 3 };

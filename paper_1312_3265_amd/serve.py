@@ -23,6 +23,7 @@ The arithmetic all happens in the library; this module only schedules.
 """
 from __future__ import annotations
 
+import collections
 import queue
 import threading
 import time
@@ -67,6 +68,7 @@ class _Group:
     batch: Batch
     stream: object
     pending: "queue.Queue" = field(default_factory=queue.Queue)
+    waiting: "collections.deque" = field(default_factory=collections.deque)
     slot_req: dict = field(default_factory=dict)
     thread: threading.Thread = None
 
@@ -122,8 +124,8 @@ class SolveServer:
 
     def per_system_bytes(self, dims, formulation):
         o = self.opts_for(formulation)
-        return solve_workspace_bytes(self.gauges[dims], formulation, o, 2) - \
-            solve_workspace_bytes(self.gauges[dims], formulation, o, 1)
+        return solve_workspace_bytes(self.gauges[dims], formulation, o, 2, g55=self.g55) - \
+            solve_workspace_bytes(self.gauges[dims], formulation, o, 1, g55=self.g55)
 
     def _group(self, dims, formulation):
         key = (dims, formulation)
@@ -134,7 +136,8 @@ class SolveServer:
         per = self.per_system_bytes(dims, formulation)
         nslots = int(min(self.max_slots, max(0, share // max(per, 1))))
         while nslots > 0 and solve_workspace_bytes(self.gauges[dims], formulation,
-                                                   self.opts_for(formulation), nslots) > share:
+                                                   self.opts_for(formulation), nslots,
+                                                   g55=self.g55) > share:
             nslots -= 1
         if nslots == 0:
             self.groups[key] = None
@@ -159,19 +162,32 @@ class SolveServer:
         free = list(range(b.nslots))
         torch = self.torch
         while True:
-            # admit waiting requests into free slots
-            while free:
+            # take arrivals into the group's waiting line, drop cancelled
+            # requests from it whether or not a slot is free, then admit
+            while True:
                 try:
                     req = g.pending.get_nowait()
                 except queue.Empty:
                     break
-                if self._take_cancel(req.id, "queued"):
-                    continue
+                with self._lock:
+                    g.waiting.append(req)
+            with self._lock:
+                keep = collections.deque()
+                for req in g.waiting:
+                    if req.id in self._cancel:
+                        self._cancel.discard(req.id)
+                        self.cancelled.append((req.id, "queued", self._now()))
+                    else:
+                        keep.append(req)
+                g.waiting = keep
+            while free and g.waiting:
+                with self._lock:
+                    req = g.waiting.popleft()
                 s = free.pop(0)
                 b.load(s, req.source, req.mass, req.tol, req.maxiter, stream=g.stream)
                 g.slot_req[s] = (req, self._now())
             if not g.slot_req:
-                if self._stop.is_set() and g.pending.empty():
+                if self._stop.is_set() and g.pending.empty() and not g.waiting:
                     return
                 time.sleep(0.0005)
                 continue
@@ -182,6 +198,7 @@ class SolveServer:
                     x, info = b.fetch(s, stream=g.stream)
                     with self._lock:
                         self.results.append(Result(req.id, x, info, req.arrival, adm, self._now()))
+                        self._cancel.discard(req.id)   # finished first: a late cancel is void
                     free.append(s)
                 elif s in g.slot_req and self._take_cancel(g.slot_req[s][0].id, "running"):
                     g.slot_req.pop(s)
@@ -199,17 +216,23 @@ class SolveServer:
 
     # ----------------------------------------------------------------- API
     def status(self, request_id):
-        """'running' while the request holds a slot, 'finished' or 'cancelled'
-        once it is out, else None (queued, not yet arrived, or unknown)."""
+        """'running' while the request holds a slot, 'queued' while it waits
+        for one, 'finished', 'cancelled' or 'rejected' once it is out, else None
+        (not yet arrived, or unknown)."""
         with self._lock:
             if any(r.id == request_id for r in self.results):
                 return "finished"
             if any(c[0] == request_id for c in self.cancelled):
                 return "cancelled"
+            if request_id in self.rejected:
+                return "rejected"
             for g in list(self.groups.values()):
-                if g is not None and any(req.id == request_id
-                                         for req, _ in list(g.slot_req.values())):
+                if g is None:
+                    continue
+                if any(req.id == request_id for req, _ in list(g.slot_req.values())):
                     return "running"
+                if any(req.id == request_id for req in list(g.waiting)):
+                    return "queued"
         return None
 
     def cancel(self, request_id):
@@ -236,7 +259,9 @@ class SolveServer:
                 time.sleep(delay)
             g = self._group(tuple(req.dims), req.formulation)
             if g is None:
-                self.rejected.append(req.id)
+                with self._lock:
+                    self.rejected.append(req.id)
+                    self._cancel.discard(req.id)
                 continue
             g.pending.put(req)
         self._stop.set()

@@ -1,0 +1,129 @@
+"""The hipGraph-captured steady state: the path the benchmark times.
+
+Batched solves with use_graph = 1 on a non-default stream replay captured
+chunks of CG iterations (frozen kernel arguments; the per-system state lives
+in device memory and changes between replays).  Every result must be bitwise
+the one of the same solve launched eagerly, meet eq. (2) by the oracle's FP64
+residual, and a resident batch must keep this across loads, cancellations and
+refills between replays."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import solvers
+
+pytestmark = pytest.mark.gpu
+
+lq = pytest.importorskip("paper_1312_3265_amd")
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "workloads.json")
+
+
+def _workload():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def test_graph_replay_of_the_benchmark_batches_matches_eager_and_eq2():
+    """Field 0 of the 16^3 x 32 workload in the benchmark's configuration:
+    16-bit vectors, 12-real links, polls every 16 iterations, the 36 Wilson
+    systems (12 point sources x 3 masses) and the 9 staggered Wilson ones,
+    solved on a torch stream with and without graph replay."""
+    w = _workload()
+    dims = tuple(w["dims"])
+    U = synth.gauge_field(dims, "near_identity", w["seed"], w["eps"])
+    stream = torch.cuda.Stream()
+    g = lq.Gauge(lq.Lattice(dims), U, lq.FEAT_CORNERS | lq.FEAT_Q16, stream=stream)
+    tol = 1e-8
+    for form, name, nsrc in ((synth.WILSON, "wilson", 12),
+                             (synth.STAGGERED_WILSON, "staggered_wilson", 3)):
+        masses, chis = [], []
+        for d in w["deltas"]:
+            for a in range(nsrc):
+                masses.append(w["m_c"][name] + d)
+                chis.append(synth.point_source(dims, form, a))
+        chis = np.stack(chis)
+        res = {}
+        for use_graph in (1, 0):
+            opts = lq.solve_opts(precision=lq.Q16, links=12, poll_interval=16,
+                                 use_graph=use_graph)
+            x, infos = lq.cg_solve_batch(g, form, masses, chis, [tol] * len(masses), opts=opts,
+                                         stream=stream)
+            torch.cuda.synchronize()
+            assert all(i["status"] == lq.OK and i["true_residual"] <= tol for i in infos), \
+                (use_graph, [i for i in infos if i["status"] != lq.OK])
+            res[use_graph] = (x, infos)
+        xg, ig = res[1]
+        xe, ie = res[0]
+        assert [i["iterations"] for i in ig] == [i["iterations"] for i in ie]
+        assert [i["reliable_updates"] for i in ig] == [i["reliable_updates"] for i in ie]
+        assert torch.equal(xg, xe), name
+        for j in range(len(w["deltas"])):
+            k = j * nsrc + (j % nsrc)
+            rn, _ = solvers.true_residual(form, U, chis[k], xg[k].cpu().numpy(), masses[k])
+            print(f"{name} delta={w['deltas'][j]} system {k}: iterations {ig[k]['iterations']} "
+                  f"eq.(2) residual {rn:.3e}")
+            assert rn <= tol, (name, k, rn)
+            assert abs(ig[k]["true_residual"] - rn) <= 1e-3 * tol
+
+
+def test_resident_batch_with_graph_across_load_cancel_refill():
+    """A resident batch stepping by graph replay on its own stream: requests
+    are loaded, one running slot is cancelled and refilled, finished slots are
+    refilled, all between replays.  Each finished result is bitwise the same
+    request solved alone by the eager path."""
+    dims = (8, 8, 6, 8)
+    U = synth.gauge_field(dims, "near_identity", 5, 0.436)
+    stream = torch.cuda.Stream()
+    g = lq.Gauge(lq.Lattice(dims), U, stream=stream)
+    form = synth.WILSON
+    base = -0.30
+    reqs = [(synth.point_source(dims, form, a), base + d, t)
+            for a, d, t in ((0, 0.0, 1e-8), (5, 0.05, 1e-7), (7, 0.1, 1e-9), (2, 0.02, 1e-8),
+                            (9, 0.05, 1e-6), (3, 0.0, 1e-8))]
+    eager = lq.solve_opts(precision=lq.Q16, links=12, reliable_interval=48, poll_interval=8)
+    graphed = lq.solve_opts(precision=lq.Q16, links=12, reliable_interval=48, poll_interval=8,
+                            use_graph=1)
+    alone = [lq.cg_solve(g, form, m, c, t, opts=eager) for c, m, t in reqs]
+    b = lq.Batch(g, form, nslots=3, opts=graphed)
+    pending = list(range(len(reqs)))
+    slot_of, results, cancelled = {}, {}, []
+    free = [0, 1, 2]
+    steps = 0
+    while pending or slot_of:
+        while pending and free:
+            k = pending.pop(0)
+            s = free.pop(0)
+            c, m, t = reqs[k]
+            b.load(s, c, m, t, stream=stream)
+            slot_of[s] = k
+        states = b.step(8, stream=stream)
+        steps += 1
+        for s, st in enumerate(states):
+            if s in slot_of and st in (lq.SLOT_DONE, lq.SLOT_FAILED):
+                results[slot_of.pop(s)] = b.fetch(s, stream=stream)
+                free.append(s)
+        if steps == 2 and 1 in slot_of.values():
+            # cancel request 1 while it runs; its slot is refilled next round
+            s = next(s for s, k in slot_of.items() if k == 1)
+            b.cancel(s, stream=stream)
+            slot_of.pop(s)
+            cancelled.append(1)
+            free.append(s)
+        assert steps < 10000
+    assert cancelled == [1]
+    for k, (c, m, t) in enumerate(reqs):
+        if k in cancelled:
+            assert k not in results
+            continue
+        xm, im = results[k]
+        xa, ia = alone[k]
+        assert im["status"] == lq.OK, (k, im)
+        assert im["iterations"] == ia["iterations"], k
+        assert torch.equal(xm, xa), k
+        rn, _ = solvers.true_residual(form, U, c, xm.cpu().numpy(), m)
+        assert rn <= t

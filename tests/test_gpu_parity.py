@@ -129,15 +129,22 @@ def test_q16_handles_vanishing_and_denormal_sites():
 
 
 def test_fp64_matvec_full_size_16x32():
-    """16^3 x 32 near-identity field: the whole field against the oracle."""
+    """16^3 x 32 near-identity field (the workload's field 0): the whole field
+    against the oracle, M and M^dag, for Wilson and for staggered Wilson with
+    Gamma_55 from the corner matrices and on the fly (the subset recursion's
+    level launches and the operator's last level)."""
     dims = (16, 16, 16, 32)
     U, lat, g = _gauge(dims, "near_identity", 2000, eps=0.4359375,
                        features=lq.FEAT_CORNERS)
-    for formulation, g55 in [(synth.WILSON, 0), (synth.STAGGERED_WILSON, lq.G55_CORNERS)]:
+    for formulation, g55 in [(synth.WILSON, 0), (synth.STAGGERED_WILSON, lq.G55_CORNERS),
+                             (synth.STAGGERED_WILSON, lq.G55_ONTHEFLY)]:
         psi = synth.gaussian_field(dims, formulation, 8)
-        out = lq.apply(g, formulation, -0.4, psi, op=lq.OP_M, g55=g55).cpu().numpy()
-        ref = _oracle_apply(formulation, U, psi, -0.4, lq.OP_M)
-        assert _relerr(out, ref) <= 1e-13
+        for op in (lq.OP_M, lq.OP_MDAG):
+            out = lq.apply(g, formulation, -0.4, psi, op=op, g55=g55).cpu().numpy()
+            ref = _oracle_apply(formulation, U, psi, -0.4, op)
+            err = _relerr(out, ref)
+            print(f"formulation {formulation} g55 {g55} op {op}: relative error {err:.2e}")
+            assert err <= 1e-13
 
 
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 6, 8)])

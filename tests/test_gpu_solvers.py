@@ -65,6 +65,32 @@ def test_otf_gamma55_solve():
     assert abs(ia["iterations"] - ib["iterations"]) <= 2
 
 
+@pytest.mark.parametrize("precision", [lq.F32, lq.Q16])
+def test_otf_batched_low_precision_every_schedule(precision, monkeypatch):
+    """Staggered Wilson batches with Gamma_55 on the fly (level launches per
+    system, the last level shared by K systems per thread): every systems-per-
+    thread choice gives bitwise the same solutions, each meeting eq. (2) by the
+    oracle's FP64 residual."""
+    U, lat, g = _field()
+    form = synth.STAGGERED_WILSON
+    chis = np.stack([synth.point_source(DIMS, form, a) for a in range(3)] +
+                    [synth.z2_source(DIMS, form, 71)])
+    ms = [MASS[form] + 0.03 * k for k in range(4)]
+    opts = lq.solve_opts(precision=precision, links=12, poll_interval=8)
+    ref = None
+    for K in (1, 2, 4):
+        monkeypatch.setenv("LQ_LAUNCH", f"{K},1")
+        x, infos = lq.cg_solve_batch(g, form, ms, chis, [1e-8] * 4, opts=opts,
+                                     g55=lq.G55_ONTHEFLY)
+        assert all(i["status"] == lq.OK for i in infos), infos
+        if ref is None:
+            ref = x
+            for k in range(4):
+                assert _res(form, U, chis[k], x[k], ms[k]) <= 1e-8
+        else:
+            assert torch.equal(x, ref), K
+
+
 def test_batched_multi_rhs_all_sources_and_masses():
     U, lat, g = _field()
     form = synth.WILSON

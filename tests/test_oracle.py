@@ -472,3 +472,32 @@ def test_sw_spectrum_is_closed_under_conjugation():
     near = SPEC.nearest(ev, 0.3, 6)
     assert np.all(np.diff(np.abs(near - 0.3)) >= 0)
     assert np.abs(near - 0.3).max() <= np.sort(np.abs(ev - 0.3))[5] + 1e-15
+
+
+# ------------------------------------------------------------------- m_c search
+@pytest.mark.parametrize("formulation", [synth.WILSON, synth.STAGGERED_WILSON])
+def test_critical_mass_search_free_field_is_zero(formulation):
+    """On the free field (U = 1, periodic) the lowest eigenvalue of
+    (D+m)^dag (D+m) is m^2 for both operators (p = 0: the Wilson term and
+    r(1 - Gamma_55) vanish there), so the mass minimising theta_min is
+    m_c = 0 and theta_min(m) = m^2.  The bracket is asymmetric so that no
+    grid point lands on 0: the search must find it by the golden section.
+    A sign slip in the mass, a wrong bracket update or a max instead of a
+    min all move the answer away from 0."""
+    from oracle import critical
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, "unit", 0)
+    v0 = synth.gaussian_field(dims, formulation, 7)
+    for m in (-0.21, 0.13):
+        th = critical.theta_min(formulation, U, m, v0, 60)
+        assert abs(th - m * m) <= 1e-10, (m, th)
+    lo, hi, ngrid, ngolden = -0.35, 0.25, 7, 10
+    mc, th, trace = critical.critical_mass(formulation, U, v0, lo, hi, steps=60, ngrid=ngrid,
+                                           ngolden=ngolden)
+    grid = np.linspace(lo, hi, ngrid)
+    assert np.min(np.abs(grid)) > 0.04            # no grid point at the answer
+    # the golden section shrinks the two-cell bracket by 0.618 per step
+    width = 2 * (hi - lo) / (ngrid - 1) * ((np.sqrt(5) - 1) / 2) ** ngolden
+    assert abs(mc) <= width, (mc, width)
+    assert abs(th - mc * mc) <= 1e-10
+    assert all(t >= mm * mm - 1e-12 for mm, t in trace)
