@@ -26,5 +26,8 @@ Modules:
   staggered Wilson, with inner solves, to measure its cost;
 * ``spectroscopy`` -- the Wilson pion correlator and effective mass (Fig. 1(a));
 * ``spectrum`` -- dense eigenvalues of the Dirac matrix and the free staggered
-  Wilson spectrum (Fig. 1(c)).
+  Wilson spectrum (Fig. 1(c));
+* ``overlap``  -- the staggered overlap operator with the staggered Wilson
+  kernel (Secs. 1, 2 and 4): exact from the dense sign function, and the
+  Chebyshev polynomial approximation of the GPU path.
 """

@@ -501,3 +501,92 @@ def test_critical_mass_search_free_field_is_zero(formulation):
     assert abs(mc) <= width, (mc, width)
     assert abs(th - mc * mc) <= 1e-10
     assert all(t >= mm * mm - 1e-12 for mm, t in trace)
+
+
+# ---------------------------------------------------- staggered overlap (oracle)
+from oracle import overlap as OV  # noqa: E402
+
+
+def _ov_field(kind):
+    dims = (4, 4, 4, 4)
+    return dims, synth.gauge_field(dims, kind, 1000 if kind == "haar" else 0)
+
+
+@pytest.mark.parametrize("kind", ["unit", "haar"])
+def test_overlap_dense_ginsparg_wilson_and_epsilon_hermiticity(kind):
+    """D_ov = rho (1 + epsilon sign(epsilon A)), A = D_SW - rho: epsilon-
+    hermitian, V = D_ov / rho - 1 unitary, the Ginsparg-Wilson relation
+    epsilon D + D epsilon = D epsilon D / rho, and every eigenvalue on the
+    circle |lambda - rho| = rho.  A wrong epsilon, a missing sign or a
+    non-hermitian H breaks each of these."""
+    dims, U = _ov_field(kind)
+    rho = 1.0
+    D, A, eps = OV.dense_overlap(U, rho)
+    n = D.shape[0]
+    scale = np.abs(D).max()
+    assert np.abs(eps @ D @ eps - D.conj().T).max() <= 1e-12 * scale
+    V = D / rho - np.eye(n)
+    assert np.abs(V.conj().T @ V - np.eye(n)).max() <= 1e-12
+    gw = eps @ D + D @ eps - D @ eps @ D / rho
+    assert np.abs(gw).max() <= 1e-12 * scale
+    ev = np.linalg.eigvals(D)
+    assert np.abs(np.abs(ev - rho) - rho).max() <= 1e-11
+    # with a mass: (1 - m/(2 rho)) D + m, the circle moves accordingly
+    Dm, _, _ = OV.dense_overlap(U, rho, m=0.1)
+    assert np.abs(Dm - ((1 - 0.1 / (2 * rho)) * D + 0.1 * np.eye(n))).max() <= 1e-13 * scale
+
+
+def test_overlap_sign_is_the_unitary_polar_factor():
+    """epsilon sign(epsilon A) (eigen-decomposition of the hermitian H) equals
+    the unitary factor of A's polar decomposition A = V P computed
+    independently from the SVD: V = W Z^dag for A = W S Z^dag."""
+    dims, U = _ov_field("haar")
+    rho = 1.0
+    D, A, eps = OV.dense_overlap(U, rho)
+    V = D / rho - np.eye(D.shape[0])
+    W, _, Zh = np.linalg.svd(A)
+    assert np.abs(V - W @ Zh).max() <= 1e-11
+
+
+def test_overlap_free_field_closed_form():
+    """At U = 1 the kernel is normal and the overlap eigenvalues are
+    rho (1 + z/|z|) over the closed-form staggered Wilson spectrum z + rho
+    (Re and |Im| compared as multisets)."""
+    dims, U = _ov_field("unit")
+    for rho, m in ((1.0, 0.0), (1.5, 0.2)):
+        D, _, _ = OV.dense_overlap(U, rho, m=m)
+        ev = np.linalg.eigvals(D)
+        got = np.sort_complex(np.round(ev.real + 1j * np.abs(ev.imag), 9))
+        want = np.sort_complex(np.round(OV.free_spectrum(dims, rho, m=m), 9))
+        assert np.abs(got - want).max() <= 1e-8
+
+
+def test_overlap_polynomial_converges_to_dense():
+    """The Chebyshev approximation of (A^dag A)^{-1/2} on [lo, hi] containing
+    the spectrum of A^dag A: the polynomial itself meets its error bound at
+    random points, and D_ov psi from it is within rho * bound * |psi| of the
+    dense exact D_ov psi, with an error that falls as the degree grows.  On
+    the near-identity field of the workload's spread the kernel is well
+    conditioned (kappa(A^dag A) ~ 90 at rho = 1); on Haar-random links A is
+    nearly singular and a polynomial alone converges too slowly."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, "near_identity", 1000, 0.436)
+    rho, m = 1.0, 0.05
+    D, A, _ = OV.dense_overlap(U, rho, m=m)
+    s = np.linalg.svd(A, compute_uv=False)
+    lo, hi = 0.9 * s.min() ** 2, 1.1 * s.max() ** 2
+    psi = synth.gaussian_field(dims, synth.STAGGERED_WILSON, 3)
+    exact = (D @ psi.ravel()).reshape(psi.shape)
+    rng = np.random.default_rng(5)
+    errs = []
+    for deg in (40, 80, 160):
+        c = OV.cheb_coeffs_invsqrt(lo, hi, deg)
+        bound = OV.poly_sign_error(lo, hi, deg)
+        x = rng.uniform(lo, hi, 200)
+        assert np.max(np.abs(np.sqrt(x) * OV.cheb_eval(c, lo, hi, x) - 1)) <= bound * (1 + 1e-9)
+        got = OV.overlap_apply_poly(U, psi, rho, m, lo, hi, deg)
+        err = np.linalg.norm(got - exact) / np.linalg.norm(psi)
+        assert err <= (rho - m / 2) * bound * (1 + 1e-6) + 1e-12, (deg, err, bound)
+        errs.append(err)
+    assert errs[2] < errs[1] < errs[0]
+    assert errs[2] <= 1e-11
