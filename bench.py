@@ -16,12 +16,17 @@ Wilson systems and one for the 9 staggered Wilson systems; stencil and Krylov
 vectors stored in 16-bit fixed point (or FP32), FP32 arithmetic, FP64
 reductions and reliable updates.  `value` is systems solved per second over
 the timed steps.  Alongside (outside the timed region): FP64 single-RHS CG on
-the same mix (the baseline the speed-up is quoted against), the dominant
-kernel's roofline figures from HIP events, the Lanczos condition numbers and
-the oracle timed on the host.
+every system of the same mix, one at a time (the baseline the speed-up is
+quoted against); the dominant kernel's roofline figures from HIP events on
+non-zero data; the FP64 matvecs (Wilson, staggered Wilson from corners and on
+the fly) at 16^3x32 and 32^3x64 against the HBM and FP64 rooflines; the
+Lanczos condition numbers at the three masses; the paper's W/SW cost ratios
+measured (Sec. 3, eqs. (3)-(4)); and the oracle timed on the host's cores
+(before the GPU is touched: its worker processes are spawned).
 
 Profiling modes (each runs only what a profiler should see):
     --roofline-only --rhs-per-thread K --window W   the dominant stencil alone
+    --matvec-only                                   the FP64 matvecs, both sizes
     --copy-calibration                              a 256 MiB device copy x5
     --summarize-profile TRACE FETCH WRITE CFETCH CWRITE
         reads rocprofv3 output of the two modes above and writes the
@@ -54,21 +59,35 @@ def load_workload():
     return w
 
 
-def bytes_per_site(formulation, precision, links, nrhs, kernel=0):
+def bytes_per_site(formulation, precision, links, nrhs, kernel=0, g55=0):
     """Compulsory HBM bytes per site of one stencil launch over nrhs fields:
-    the links (and corners) once, and per RHS: kernel 0 (t = M p + ||t||^2)
-    reads p and writes t; kernel 2 (q = M^dag t, r -= alpha q, ||r||^2) reads
+    the links (and, for the corner form, the corners) once, and per RHS:
+    kernel 0 (t = M p + ||t||^2) and kernel 1 (a plain matvec) read the input
+    and write the output; kernel 2 (q = M^dag t, r -= alpha q, ||r||^2) reads
     t and reads and writes r, and on every fourth launch also reads the four
     search directions of the group and reads and writes x (FP32 under 16-bit
-    storage) -- per launch on average 4 vectors and half an x."""
+    storage) -- per launch on average 4 vectors and half an x.  12-real links
+    are read as their rows 0 and 1 (in FP64 too); g55 = 1 (staggered Wilson
+    on the fly) reads no corners."""
     nc = 12 if formulation == 0 else 3
     per = {0: 16, 1: 8, 2: 4}[precision]
     vec = nc * per + (4 if precision == 2 else 0)            # Q16: per-site float scale
     xvec = nc * (8 if precision == 2 else per)
-    link = 4 * (links // 2) * per                            # FP64: 12 = rows 0, 1 read
-    corner = 0 if formulation == 0 else 8 * 9 * (4 if precision == 2 else per)
-    per_rhs = 2 * vec if kernel == 0 else 4 * vec + xvec // 2
+    link = 4 * (links // 2) * per
+    corner = 0 if (formulation == 0 or g55 == 1) else 8 * 9 * (4 if precision == 2 else per)
+    per_rhs = 2 * vec if kernel in (0, 1) else 4 * vec + xvec // 2
     return nrhs * per_rhs + link + corner
+
+
+# flops per site of one FP64 application of D (a complex 3x3 mat-vec with its
+# accumulation counted as 66 + 12 = 78): Wilson r = 1, 8 spin-projected hops
+# (2 mat-vecs each) plus projection and reconstruction, the paper's 1392
+# (Sec. 3, eq. (4)); staggered Wilson from corners: 8 D_st hops + 16 corners
+# (24 x 78) + the diagonal and combination (30); on the fly: 8 D_st hops +
+# the 32 C applications of the subset recursion (64 mat-vecs) + 30
+FLOPS_PER_SITE = {"wilson": 1392, "staggered_wilson_corners": 24 * 78 + 30,
+                  "staggered_wilson_onthefly": (8 + 64) * 78 + 30}
+FP64_PEAK_TFLOPS = 78.6
 
 
 NRHS_W = 36                      # Wilson systems per field: 12 sources x 3 masses
@@ -87,21 +106,26 @@ def stencil_source_hash():
     return h.hexdigest()
 
 
+def _cfg_key(cfg):
+    return f"K{cfg[0]}_w{cfg[1]}"
+
+
 def stored_traffic(storage, links, cfg):
-    """HBM bytes per launch from the committed counter readings, if they were
-    taken on the current stencil sources with this configuration."""
+    """Bytes per launch beyond L2 (FETCH_SIZE + WRITE_SIZE, calibrated) from the
+    committed counter readings of the dominant stencil, if they were taken on
+    the current stencil sources, with this storage and in this launch
+    configuration (systems per thread, block order); else None."""
     try:
         with open(PROFILE_JSON) as f:
             p = json.load(f)
     except OSError:
-        return None, None
-    if (p.get("source_sha256") != stencil_source_hash() or p.get("storage") != storage
-            or p.get("links") != links or p.get("rhs_per_thread") != cfg[0]
-            or p.get("nrhs") != NRHS_W):
-        return None, None
-    # the block order may differ from the one the autotuner picked on this
-    # GPU; the counters' own is reported beside the figure
-    return p["fetch_bytes_per_launch"] + p["write_bytes_per_launch"], p.get("window")
+        return None
+    if p.get("source_sha256") != stencil_source_hash():
+        return None
+    e = p.get("configs", {}).get(_cfg_key(cfg))
+    if not e or e.get("storage") != storage or e.get("links") != links or e.get("nrhs") != NRHS_W:
+        return None
+    return e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
 
 
 def roofline(lq, g0, lat, mc, prec, links, storage, cfg, stream, reps=48):
@@ -121,11 +145,14 @@ def roofline(lq, g0, lat, mc, prec, links, storage, cfg, stream, reps=48):
     achieved = algo / (ms * 1e-3) / 1e9
     ms0, per0, algo0 = out[0]
     pol = "Q16" if prec == lq.Q16 else "F32"
-    traffic, traffic_window = stored_traffic(storage, links, cfg)
+    traffic = stored_traffic(storage, links, cfg)
     return {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-        "traffic_counters_window": traffic_window,
+        "traffic_scope": ("bytes leaving L2 per launch (FETCH_SIZE + WRITE_SIZE, scaled by a "
+                          "256 MiB device copy), counted in this launch configuration; reads "
+                          "served by the Infinity Cache are included"),
+        "data": "pseudo-random fields, live solver state (alpha = 1)",
         "kernel": (f"stencil_kernel<WilsonOpR1<{pol}, {links}, true>, CG_UPDATE, K={K}>: "
                    f"q = M^dag t, r -= alpha q, ||r||^2, x += the four steps of the group every "
                    f"fourth launch; {NRHS_W} systems; average over the group"),
@@ -173,10 +200,9 @@ def summarize_profile(a, trace, fetch, write, cfetch, cwrite):
     dom = lambda n: "stencil_kernel" in n and ", true>, 2," in n
     f_kib, nf = per_dispatch(fetch, "FETCH_SIZE", dom)
     w_kib, nw = per_dispatch(write, "WRITE_SIZE", dom)
-    out = {
+    entry = {
         "storage": a.precision, "links": a.links, "rhs_per_thread": a.rhs_per_thread,
-        "window": a.window,
-        "nrhs": NRHS_W, "source_sha256": stencil_source_hash(),
+        "window": a.window, "nrhs": NRHS_W,
         "kernel_stats": stats,
         "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib,
         "copy_fetch_kib_per_256MiB": copy_f, "copy_write_kib_per_256MiB": copy_w,
@@ -185,9 +211,20 @@ def summarize_profile(a, trace, fetch, write, cfetch, cwrite):
         "write_bytes_per_launch": int(w_kib * 1024 * wscale),
         "dispatches_counted": [nf, nw],
     }
+    # one entry per launch configuration, all taken on the same sources
+    try:
+        with open(PROFILE_JSON) as fh:
+            doc = json.load(fh)
+    except (OSError, ValueError):
+        doc = {}
+    if doc.get("source_sha256") != stencil_source_hash() or "configs" not in doc:
+        doc = {"source_sha256": stencil_source_hash(), "configs": {}}
+    doc["scope"] = ("bytes leaving L2 (TCC FETCH_SIZE / WRITE_SIZE): HBM traffic plus "
+                    "Infinity Cache hits")
+    doc["configs"][_cfg_key((a.rhs_per_thread, a.window))] = entry
     with open(PROFILE_JSON, "w") as fh:
-        json.dump(out, fh, indent=1)
-    print(json.dumps(out, indent=1))
+        json.dump(doc, fh, indent=1)
+    print(json.dumps(entry, indent=1))
 
 
 SERVING_DIMS = [(8, 8, 8, 16), (16, 16, 16, 32), (24, 24, 24, 48), (32, 32, 32, 64)]
@@ -397,39 +434,241 @@ def pion_section(lq, lat, props, masses, stream):
     return out
 
 
-def cpu_baseline(U, workload, iters_fp64):
-    """The oracle, timed on the host on a bounded sample: a few CG iterations
-    of each formulation at the delta = 0.1 mass, single-threaded BLAS."""
+def matvec_rooflines(lq, U16, dims16, mc, stream, reps=50):
+    """The FP64 single-system matvecs (the plain M^dag stencil, as the FP64
+    solver and every reliable update launch it) at 16^3 x 32 (workload field 0)
+    and 32^3 x 64 (that field repeated twice in every direction; the timing does
+    not depend on the link values), where the working set no longer fits the
+    256 MB Infinity Cache: Wilson, staggered Wilson from corners, and staggered
+    Wilson on the fly (an application = the recursion's three level launches
+    plus the operator's).  Average over `reps` applications (HIP events on the
+    stream), against the algorithmic bytes and flops per site."""
+    import numpy as np
+    import torch
+    out = {}
+    for dims in (dims16, tuple(2 * d for d in dims16)):
+        U = U16 if dims == dims16 else np.tile(U16, (2, 2, 2, 2, 1, 1, 1))
+        lat = lq.Lattice(dims)
+        g = lq.Gauge(lat, U, lq.FEAT_CORNERS, stream=stream)
+        del U
+        V = lat.volume
+        key = "x".join(map(str, dims))
+        out[key] = {}
+        for name, form, g55 in (("wilson", 0, 0), ("staggered_wilson_corners", 1, 0),
+                                ("staggered_wilson_onthefly", 1, 1)):
+            m = mc["wilson" if form == 0 else "staggered_wilson"] + 0.1
+            ms = lq.time_dslash(g, form, m, dagger=True, g55=g55, precision=lq.F64, links=12,
+                                reps=reps, window=-3, stream=stream)
+            by = bytes_per_site(form, 0, 12, 1, kernel=1, g55=g55)
+            by18 = bytes_per_site(form, 0, 18, 1, kernel=1, g55=g55)
+            gbs = by * V / (ms * 1e-3) / 1e9
+            tfl = FLOPS_PER_SITE[name] * V / (ms * 1e-3) / 1e12
+            out[key][name] = {
+                "avg_application_us": round(ms * 1e3, 1),
+                "algorithmic_bytes_per_site": by, "bytes_per_site_18real_links": by18,
+                "achieved_GBs": round(gbs, 1), "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
+                "flops_per_site": FLOPS_PER_SITE[name], "achieved_TFLOPs": round(tfl, 2),
+                "frac_of_fp64_peak": round(tfl / FP64_PEAK_TFLOPS, 4)}
+            log(f"matvec {key} {name}: {ms * 1e3:.1f} us, {gbs:.0f} GB/s, {tfl:.2f} TFLOP/s")
+        del g, lat
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
+
+
+def fp64_single_rhs_mix(lq, fields, src, masses, stream):
+    """Plain FP64 CG (eq. (2), unpreconditioned) on every system of the mix,
+    one system at a time: the baseline the mixed-precision batched rate is
+    compared with.  Returns the rate, the FP64 iteration counts of source 0 on
+    field 0 per delta, and the mean seconds and iterations per solve per
+    formulation and delta over the whole mix."""
+    import numpy as np
+    import torch
+    nsrc = {0: 12, 1: 3}
+    lq.cg_solve(fields[0], 0, masses[0][0], src[0][0], TOL, stream=stream)   # warm
+    torch.cuda.synchronize()
+    secs = {"wilson": {}, "staggered_wilson": {}}
+    its = {"wilson": {}, "staggered_wilson": {}}
+    iters0 = {"wilson": {}, "staggered_wilson": {}}
+    total, n = 0.0, 0
+    for gi, g in enumerate(fields):
+        for form, name in ((0, "wilson"), (1, "staggered_wilson")):
+            for k in range(len(masses[form])):
+                d = str(DELTAS[k // nsrc[form]])
+                ts = time.time()
+                x, inf = lq.cg_solve(g, form, masses[form][k], src[form][k], TOL, stream=stream)
+                el = time.time() - ts
+                if inf["status"] != lq.OK or inf["true_residual"] > TOL:
+                    raise RuntimeError(f"FP64 field {gi} formulation {form} system {k}: {inf}")
+                total += el
+                n += 1
+                secs[name].setdefault(d, []).append(el)
+                its[name].setdefault(d, []).append(inf["iterations"])
+                if gi == 0 and k % nsrc[form] == 0:
+                    iters0[name][d] = inf["iterations"]
+    mean = lambda dd: {d: float(np.mean(v)) for d, v in dd.items()}
+    return dict(rate=n / total, systems=n, seconds=total, iterations_source0_field0=iters0,
+                mean_seconds={k: mean(v) for k, v in secs.items()},
+                mean_iterations={k: mean(v) for k, v in its.items()})
+
+
+def paper_comparison(mv, fp64, kap):
+    """The paper's cost comparison (Sec. 3, eqs. (3)-(4)) with measured
+    numbers: W / SW ratios of the matvec time, the CG iteration count, the
+    cost per iteration and the time per solve (FP64, single system), raw (the
+    same lattice for both) and in eq. (4)'s convention, which multiplies a
+    per-site ratio by 4 because the Wilson matrix is 4 times larger."""
+    out = {"paper_estimates": {
+        "cost_per_iteration_W_over_SW_flops_eq4": 3.2,
+        "cost_per_iteration_W_over_SW_neighbour_count": 2.67,
+        "matvec_speedup_assumed": "2-3", "cg_iteration_ratio": "about 2",
+        "inversion_speedup": "4-6", "kappa_ratio": "about 4",
+        "convention": "eq. (4): 4 x (per-site ratio); the raw figures below compare the "
+                      "two matrices on the same lattice"}}
+    mvr = {}
+    for key, d in mv.items():
+        w = d["wilson"]["avg_application_us"]
+        mvr[key] = {}
+        for form in ("staggered_wilson_corners", "staggered_wilson_onthefly"):
+            raw = w / d[form]["avg_application_us"]
+            mvr[key][form] = {"raw": round(raw, 3), "x4": round(4 * raw, 3)}
+    out["matvec_time_ratio_W_over_SW_fp64"] = mvr
+    it_r, iter_cost, solve = {}, {}, {}
+    for d in map(str, DELTAS):
+        iw, isw = fp64["mean_iterations"]["wilson"][d], fp64["mean_iterations"]["staggered_wilson"][d]
+        tw, tsw = fp64["mean_seconds"]["wilson"][d], fp64["mean_seconds"]["staggered_wilson"][d]
+        it_r[d] = round(iw / isw, 3)
+        c = (tw / iw) / (tsw / isw)
+        iter_cost[d] = {"raw": round(c, 3), "x4": round(4 * c, 3)}
+        solve[d] = {"raw": round(tw / tsw, 3), "x4": round(4 * tw / tsw, 3)}
+    out["cg_iteration_ratio_W_over_SW_fp64"] = it_r
+    out["cost_per_iteration_ratio_W_over_SW_fp64"] = iter_cost
+    out["solve_time_ratio_W_over_SW_fp64"] = solve
+    out["kappa_lanczos200"] = {d: {k: round(v, 1) for k, v in kk.items()} for d, kk in kap.items()}
+    out["kappa_ratio_W_over_SW"] = {d: round(kk["wilson"] / kk["staggered_wilson"], 2)
+                                    for d, kk in kap.items()}
+    return out
+
+
+def _cpu_worker(args):
+    """One host core's share of the all-cores oracle sample (a spawned process,
+    one BLAS thread): the workload field, then n_w CG iterations of Wilson and
+    n_sw of staggered Wilson at delta = 0.1 from point source alpha.  Returns
+    the wall seconds of each, the closing true-residual application included."""
+    alpha, n_w, n_sw = args
     from threadpoolctl import threadpool_limits
 
     import synth
     from oracle import solvers
-
-    dims = tuple(workload["dims"])
+    w = load_workload()
+    dims = tuple(w["dims"])
     out = {}
     with threadpool_limits(limits=1):
-        for form, name in ((0, "wilson"), (1, "staggered_wilson")):
-            m = workload["m_c"][name] + 0.1
-            M, Md, A = solvers.operator(form, U, m)
-            b = Md(synth.point_source(dims, form, 0))
-            n = 3
+        U = synth.gauge_field(dims, "near_identity", w["seed"], w["eps"])
+        for form, name, n in ((0, "wilson", n_w), (1, "staggered_wilson", n_sw)):
+            M, Md, A = solvers.operator(form, U, w["m_c"][name] + 0.1)
+            b = Md(synth.point_source(dims, form, alpha % (12 if form == 0 else 3)))
             t0 = time.time()
-            x, info = solvers.cg(A, b, 1e-30, n)
-            # n iterations plus the closing true-residual application of A
-            out[name] = (time.time() - t0) / (n + 1)
-    # projected solve time on the benchmark mix: GPU FP64 iteration counts x
-    # oracle seconds per iteration
-    tot = 0.0
-    nsys = 0
-    for name, per_sys in (("wilson", 12), ("staggered_wilson", 3)):
+            solvers.cg(A, b, 1e-30, n)
+            out[name] = time.time() - t0
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(workload):
+    """The oracle timed on this host's cores on a bounded sample of the
+    workload (run before the GPU is touched, so that the worker processes can
+    be spawned):
+      * one thread: the FP64 matvec of each formulation at 16^3 x 32, median
+        of 5 (staggered Wilson by the oracle's subset recursion);
+      * all cores (one process per core, one BLAS thread each, at most 16):
+        2 Wilson and 1 staggered Wilson CG iterations per process at
+        delta = 0.1, timed concurrently -> the aggregate seconds per iteration;
+      * projected solves/s on the 360-system mix: the oracle's own FP64
+        iteration counts at 16^3 x 32 (tests/golden/fullsize.json, equal to the
+        GPU's) times that per-iteration cost, labelled as projected.
+    The full oracle solves at delta = 0.1, measured when fullsize.json was
+    written (build host, one thread each), are quoted beside it."""
+    import multiprocessing as mp
+    import statistics
+
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import staggered_wilson, wilson
+
+    w = workload
+    dims = tuple(w["dims"])
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    t_start = time.time()
+    mv = {}
+    with threadpool_limits(limits=1):
+        U = synth.gauge_field(dims, "near_identity", w["seed"], w["eps"])
+        for form, name, fn in ((0, "wilson", wilson.apply), (1, "staggered_wilson",
+                                                            staggered_wilson.apply)):
+            psi = synth.gaussian_field(dims, form, 3)
+            m = w["m_c"][name] + 0.1
+            ts = []
+            for _ in range(5):
+                t0 = time.time()
+                fn(U, psi, m)
+                ts.append(time.time() - t0)
+            mv[name] = statistics.median(ts)
+    del U
+    n_w, n_sw = 2, 1
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_cpu_worker, [(a, n_w, n_sw) for a in range(cores)], chunksize=1)
+    # seconds per iteration of the whole pool: cores iterations run at once
+    per_iter = {}
+    for name, n in (("wilson", n_w), ("staggered_wilson", n_sw)):
+        mean = sum(r[name] for r in res) / len(res)
+        per_iter[name] = mean / (n + 1) / cores      # n iterations + 1 residual application
+    with open(os.path.join(ROOT, "tests", "golden", "fullsize.json")) as f:
+        gold = json.load(f)
+    tot, nsys = 0.0, 0
+    for name, per_field in (("wilson", 12), ("staggered_wilson", 3)):
         for d in DELTAS:
-            tot += 8 * per_sys * iters_fp64[name][str(d)] * out[name]
-            nsys += 8 * per_sys
-    return dict(value=nsys / tot, unit="solves/s", cores=1, kind="oracle",
-                sample=("3 oracle CG iterations per formulation at 16^3x32, delta=0.1, "
-                        "1 BLAS thread; projected to the 360-system mix with the GPU FP64 "
-                        f"iteration counts (s/iter: W {out['wilson']:.2f}, "
-                        f"SW {out['staggered_wilson']:.2f})"))
+            it = gold["cg"][name][str(d)]["iterations"]
+            tot += 8 * per_field * it * per_iter[name]
+            nsys += 8 * per_field
+    return dict(
+        value=round(nsys / tot, 5), unit="solves/s", cores=cores, kind="oracle",
+        cpu_model=cpu_model(), host_cpus=os.cpu_count(),
+        sample=(f"oracle FP64 on this host: 2 Wilson + 1 staggered Wilson CG iterations at "
+                f"16^3x32, delta=0.1, in each of {cores} processes at once (one BLAS thread "
+                f"each); solves/s projected to the 360-system mix with the oracle's FP64 "
+                f"iteration counts from tests/golden/fullsize.json"),
+        projected=True,
+        seconds_per_iteration_all_cores=per_iter,
+        matvec_seconds_1thread_median5={k: round(v, 4) for k, v in mv.items()},
+        # the oracle reads all 18 reals of each link; staggered Wilson by the
+        # subset recursion reads no corners
+        matvec_GBs_1thread={k: round(bytes_per_site(0 if k == "wilson" else 1, 0, 18, 1,
+                                                     kernel=1, g55=1) * gold_volume(w) / v / 1e9, 3)
+                            for k, v in mv.items()},
+        full_solve_seconds_delta0_1_build_host={
+            k: round(gold["cg"][k]["0.1"]["seconds"], 1) for k in ("wilson", "staggered_wilson")},
+        full_solve_note=("measured when tests/golden/fullsize.json was written: one thread per "
+                         "solve, six solves at once on an 8-core Xeon build host, not this box"),
+        wall_seconds=round(time.time() - t_start, 1),
+    )
+
+
+def gold_volume(w):
+    v = 1
+    for d in w["dims"]:
+        v *= d
+    return v
 
 
 def main():
@@ -457,6 +696,9 @@ def main():
                     help="only time the dominant stencil (the launches a profiler should see)")
     ap.add_argument("--rhs-per-thread", type=int, default=1, help="with --roofline-only")
     ap.add_argument("--window", type=int, default=0, help="with --roofline-only")
+    ap.add_argument("--matvec-only", action="store_true",
+                    help="only the FP64 single-system matvecs at 16^3x32 and 32^3x64 (the "
+                         "launches a profiler should see for their roofline entries)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy five times (counter calibration)")
     ap.add_argument("--serving", action="store_true",
@@ -478,6 +720,13 @@ def main():
               "independent solves; splitting it across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
+    w = load_workload()
+    cpu = None
+    if not (a.no_cpu or a.copy_calibration or a.serving or a.roofline_only or a.matvec_only):
+        # before anything touches the GPU: the oracle's worker processes are spawned
+        cpu = cpu_baseline(w)
+        log(f"cpu baseline: {cpu}")
+
     import numpy as np
     import torch
 
@@ -493,7 +742,6 @@ def main():
         print(json.dumps({"copy_calibration_bytes": 256 << 20, "copies": 5}), flush=True)
         return
 
-    w = load_workload()
     if a.serving:
         print(json.dumps({"serving": serving(a, w)}), flush=True)
         return
@@ -512,6 +760,10 @@ def main():
         g0 = lq.Gauge(lat, U, lq.FEAT_CORNERS | lq.FEAT_F32 | lq.FEAT_Q16, stream=stream)
         print(json.dumps({"roofline": roofline(lq, g0, lat, mc, prec, links, a.precision,
                                                (a.rhs_per_thread, a.window), stream)}), flush=True)
+        return
+    if a.matvec_only:
+        U = synth.gauge_field(dims, "near_identity", seeds[0], eps)
+        print(json.dumps({"matvec_fp64": matvec_rooflines(lq, U, dims, mc, stream)}), flush=True)
         return
 
     # ---------------------------------------------------------------- setup
@@ -613,24 +865,12 @@ def main():
     elapsed = time.time() - t0
     value = nsolved / elapsed
 
-    # ------------------------------------------ FP64 single-RHS reference
+    # ------------------------------ FP64 single-RHS reference over the whole mix
     g0 = fields[0]
-    iters64 = {"wilson": {}, "staggered_wilson": {}}
-    t64 = {"wilson": {}, "staggered_wilson": {}}
-    for form, name in ((0, "wilson"), (1, "staggered_wilson")):
-        for d in DELTAS:
-            chi = synth.point_source(dims, form, 0)
-            lq.cg_solve(g0, form, mc[name] + d, chi, TOL, stream=stream)   # warm
-            torch.cuda.synchronize()
-            ts = time.time()
-            x, inf = lq.cg_solve(g0, form, mc[name] + d, chi, TOL, stream=stream)
-            torch.cuda.synchronize()
-            t64[name][str(d)] = time.time() - ts
-            iters64[name][str(d)] = inf["iterations"]
-            assert inf["status"] == lq.OK and inf["true_residual"] <= TOL
-    per_field = sum(t64["wilson"][str(d)] * 12 + t64["staggered_wilson"][str(d)] * 3
-                    for d in DELTAS)
-    fp64_rate = 45.0 / per_field
+    fp64 = fp64_single_rhs_mix(lq, fields, src, masses, stream)
+    fp64_rate = fp64["rate"]
+    iters64 = fp64["iterations_source0_field0"]
+    log(f"fp64 single-RHS: {fp64_rate:.2f} solves/s over {fp64['systems']} systems")
     mixed_iters = {"wilson": {}, "staggered_wilson": {}}
     mixed_ru = {"wilson": {}, "staggered_wilson": {}}
     for gi, form, k, it, ru in rec:
@@ -652,7 +892,7 @@ def main():
             return {"error": repr(e)}
 
     eo_res = beside("even-odd", evenodd_wilson, lq, fields, src, masses, dims, mc, prec, links,
-                    stream, t64["wilson"])
+                    stream, fp64["mean_seconds"]["wilson"])
     eo_w, props0 = eo_res if isinstance(eo_res, tuple) else (eo_res, None)
     log(f"even-odd Wilson: {eo_w}")
     pion = (beside("pion", pion_section, lq, lat, props0, masses[0], stream)
@@ -661,31 +901,21 @@ def main():
     log(f"spectrum: {spec}")
 
     # --------------------------------------------- dominant kernel roofline
-    reps = 50
     cfg = lq.tuned_launch(g0, 0, prec, links, NRHS_W)
     roof = roofline(lq, g0, lat, mc, prec, links, a.precision, cfg or (1, 2), stream)
-    V = lat.volume
-    ms64 = lq.time_dslash(g0, 0, mc["wilson"] + 0.1, precision=lq.F64, links=12, reps=reps,
-                          stream=stream)
-    ms64_sw = lq.time_dslash(g0, 1, mc["staggered_wilson"] + 0.1, precision=lq.F64, links=12,
-                             reps=reps,
-                             stream=stream)
-    gbs64 = bytes_per_site(0, 0, 12, 1) * V / (ms64 * 1e-3) / 1e9
-    gbs64_sw = bytes_per_site(1, 0, 12, 1) * V / (ms64_sw * 1e-3) / 1e9
+    mv = beside("matvec rooflines", matvec_rooflines, lq, U0, dims, mc, stream)
 
-    # ----------------------------------------------- condition numbers (context)
+    # -------------------------------------- condition numbers (paper context)
     kap = {}
-    for form, name in ((0, "wilson"), (1, "staggered_wilson")):
-        v0 = synth.gaussian_field(dims, form, w["v0_seed"])
-        r = lq.condition_number(g0, form, mc[name] + 0.1, v0, steps=200, stream=stream)
-        kap[name] = r["kappa"]
+    for d in DELTAS:
+        kap[str(d)] = {}
+        for form, name in ((0, "wilson"), (1, "staggered_wilson")):
+            v0 = synth.gaussian_field(dims, form, w["v0_seed"])
+            r = lq.condition_number(g0, form, mc[name] + d, v0, steps=200, stream=stream)
+            kap[str(d)][name] = r["kappa"]
+    paper = beside("paper comparison", paper_comparison, mv, fp64, kap) \
+        if "error" not in mv else {"error": "no matvec figures"}
 
-    cpu = None
-    if not a.no_cpu:
-        cpu = cpu_baseline(U0, w, iters64)
-
-    iter_ratio = {d: iters64["wilson"][str(d)] / iters64["staggered_wilson"][str(d)]
-                  for d in DELTAS}
     line = {
         "metric": "CG solves/s + Dslash HBM GB/s vs peak, 16^3x32, mixed-prec batched vs FP64",
         "value": round(value, 3),
@@ -711,22 +941,21 @@ def main():
         "cpu_baseline": cpu,
         "fp64_single_rhs": {
             "solves_per_s_same_mix": round(fp64_rate, 3),
+            "measured_over": f"all {fp64['systems']} systems, one FP64 solve at a time",
             "speedup_mixed_batched_vs_fp64": round(value / fp64_rate, 2),
-            "iterations": iters64,
-            "seconds": {n: {d: round(v, 4) for d, v in dd.items()} for n, dd in t64.items()},
-            "dslash_fp64_gbs": {"wilson": round(gbs64, 1), "staggered_wilson_corners": round(gbs64_sw, 1)},
-            "dslash_fp64_us": {"wilson": round(ms64 * 1e3, 1), "staggered_wilson_corners": round(ms64_sw * 1e3, 1)},
+            "iterations_source0_field0": iters64,
+            "mean_iterations": {n: {d: round(v, 1) for d, v in dd.items()}
+                                for n, dd in fp64["mean_iterations"].items()},
+            "mean_seconds": {n: {d: round(v, 4) for d, v in dd.items()}
+                             for n, dd in fp64["mean_seconds"].items()},
         },
+        "matvec_fp64": mv,
+        "paper_comparison": paper,
         "evenodd_wilson": eo_w,
         "pion_wilson_field0": pion,
         "spectrum_sw_field0": spec,
         "mixed_iterations_field0": mixed_iters,
         "mixed_reliable_updates_field0": mixed_ru,
-        "paper_context": {
-            "cg_iteration_ratio_W_over_SW": {str(d): round(v, 2) for d, v in iter_ratio.items()},
-            "sqrt_kappa_ratio_W_over_SW_delta0.1": round((kap["wilson"] / kap["staggered_wilson"]) ** 0.5, 2),
-            "kappa_lanczos200_delta0.1": {k: round(v, 1) for k, v in kap.items()},
-        },
     }
     print(json.dumps(line), flush=True)
 

@@ -257,11 +257,14 @@ int lq_schur_apply(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t
 
 /* Average device time (ms) of one stencil launch on `nrhs` fields already in
  * the library layout, over `reps` back-to-back launches, measured with HIP
- * events on `stream`.  kernel = 0 times the first stencil of a CG iteration
+ * events on `stream`.  The fields hold deterministic pseudo-random data
+ * (every component uniform in [-1, 1)) and the solver state is live (alpha =
+ * 1, the group's earlier steps non-zero), so the CG update does its full
+ * arithmetic on non-zero values.  kernel = 0 times the first stencil of a CG iteration
  * (t = M p fused with ||t||^2), 1 the plain M^dag stencil, 2 the second
  * stencil of a CG iteration (q = M^dag t fused with r -= alpha q and
  * ||r||^2, and on every fourth launch (second in FP64) with x advanced by
- * the steps of the group, the solvers' x update; on zeroed solver state) --
+ * the steps of the group, the solvers' x update) --
  * the same kernels the solvers launch; `reps` should be a multiple of 4 for
  * kernels 2 and 4.  kernel = 3 and 4 time
  * the same two steps of an even-odd preconditioned iteration (Wilson, r = 1,
@@ -391,6 +394,40 @@ size_t lq_spectrum_workspace_bytes(const lq_gauge* g, int32_t formulation, int32
 int lq_spectrum(const lq_gauge* g, const lq_dirac* d, double sigma, int32_t steps,
                 int32_t restarts, double tol, const void* v0, void* ws, size_t ws_bytes,
                 int32_t* nev, double* eig_re, double* eig_im, double* resid, void* stream);
+
+/* ---------------------------------------------------- staggered overlap
+ * The staggered overlap operator with the 2-flavour staggered Wilson kernel
+ * (the paper presents D_SW as the kernel of a staggered overlap operator,
+ * Secs. 1, 2 and 4; the usual overlap construction with the flavoured
+ * gamma_5 = eps = (-1)^(x1+x2+x3+x4)):
+ *     A = D_SW - rho,   V = eps sign(eps A) = A (A^dag A)^{-1/2},
+ *     D_ov(m) = (rho - m/2) (1 + V) + m,
+ * eps-hermitian, Ginsparg-Wilson (eps D + D eps = D eps D / rho at m = 0).
+ * The library applies V psi ~ A p(A^dag A) psi with p the Chebyshev
+ * interpolant of degree `degree` of x^{-1/2} on [lo, hi]: the result is exact
+ * up to max over [lo, hi] of |x^{1/2} p(x) - 1| per singular direction of A,
+ * provided [lo, hi] contains the spectrum of A^dag A (lq_condition_number at
+ * mass -rho gives its Lanczos estimates; outside the interval the polynomial
+ * is not an approximation).  Cost: degree + 1/2 applications of A^dag A (FP64
+ * stencils of the kernel, Gamma_55 by `g55_mode`).  */
+typedef struct {
+  double rho;        /* kernel mass: A = D_SW - rho; > 0                       */
+  double mass;       /* m of D_ov(m)                                           */
+  double r;          /* Wilson parameter of the kernel                         */
+  double lo, hi;     /* 0 < lo < hi: interval containing spec(A^dag A)          */
+  int32_t degree;    /* 1..4096                                                */
+  int32_t g55_mode;  /* LQ_G55_CORNERS or LQ_G55_ONTHEFLY                       */
+} lq_overlap;
+
+/* out = D_ov(m) in.  in/out: device canonical staggered Wilson fields
+ * (complex128).  ws: device scratch of lq_overlap_workspace_bytes (6 FP64
+ * fields, plus the on-the-fly intermediate fields).  Errors: LQ_ERR_ARG for a
+ * null pointer, a non-finite or out-of-range parameter, a gauge field without
+ * corners for LQ_G55_CORNERS; LQ_ERR_WORKSPACE for a short ws.
+ * Asynchronous. */
+size_t lq_overlap_workspace_bytes(const lq_gauge* g, int32_t g55_mode);
+int lq_overlap_apply(const lq_gauge* g, const lq_overlap* ov, const void* in, void* out,
+                     void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------- condition number
  * Lanczos with full reorthogonalisation (classical Gram-Schmidt, twice) on

@@ -44,6 +44,12 @@ class Dirac(ctypes.Structure):
                 ("mass", ctypes.c_double), ("r", ctypes.c_double)]
 
 
+class Overlap(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_double), ("mass", ctypes.c_double), ("r", ctypes.c_double),
+                ("lo", ctypes.c_double), ("hi", ctypes.c_double), ("degree", ctypes.c_int32),
+                ("g55_mode", ctypes.c_int32)]
+
+
 class SolveOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("links", ctypes.c_int32),
                 ("reliable_interval", ctypes.c_int32), ("poll_interval", ctypes.c_int32),
@@ -124,6 +130,8 @@ def lib():
         "lq_batch_destroy": ([P], None),
         "lq_batch_peek": ([P, I32, P, P], I32),
         "lq_lanczos_workspace_bytes": ([P, I32, I32, I32], SZ),
+        "lq_overlap_workspace_bytes": ([P, I32], SZ),
+        "lq_overlap_apply": ([P, P, P, P, P, SZ, P], I32),
         "lq_condition_number": ([P, P, I32, P, P, SZ, P, P, P, P, P, P, P], I32),
         "lq_critical_mass": ([P, I32, I32, D, D, D, I32, I32, I32, P, P, SZ, P, P, P], I32),
     }
@@ -279,6 +287,22 @@ def schur_apply(gauge, mass, psi, dagger=False, precision=F64, links=0, stream=N
     d = Dirac(WILSON, G55_CORNERS, mass, 1.0)
     _check(lib().lq_schur_apply(gauge._h, ctypes.byref(d), int(dagger), precision, links, _ptr(x),
                                 _ptr(out), _ptr(ws), nb, _stream(stream)))
+    _stream_sync(stream)
+    return out
+
+
+def overlap_apply(gauge, psi, rho, mass, lo, hi, degree, r=1.0, g55=G55_CORNERS, stream=None):
+    """D_ov(m) psi for the staggered overlap operator with kernel A = D_SW - rho
+    (include/lq.h: lq_overlap_apply), (A^dag A)^{-1/2} by the Chebyshev
+    interpolant of the given degree on [lo, hi]; returns a new device tensor."""
+    torch = _torch()
+    x = _device_tensor(psi, torch.complex128, stream)
+    out = torch.empty_like(x)
+    nb = int(lib().lq_overlap_workspace_bytes(gauge._h, g55))
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    ov = Overlap(rho, mass, r, lo, hi, int(degree), g55)
+    _check(lib().lq_overlap_apply(gauge._h, ctypes.byref(ov), _ptr(x), _ptr(out), _ptr(ws), nb,
+                                  _stream(stream)))
     _stream_sync(stream)
     return out
 

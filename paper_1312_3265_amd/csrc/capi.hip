@@ -6,6 +6,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <vector>
 
 #include "engine.h"
 
@@ -369,6 +370,27 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     hipStream_t s = S(stream);
     launch_fill_zero(ws, c.size(), s);
     const Geom vg = eo ? half_geom(g->g) : g->g;   // geometry of the timed fields
+    // non-zero data and a live solver state: every vector field uniform in
+    // [-1, 1) per component, rho = 1 and partials of ||t||^2 summing to 1
+    // (alpha = 1), the group's earlier steps alpha_j = 2^-(j+1)
+    {
+      void* vecs[] = {a, b, r, pprev, pr1, pr2};
+      for (int j = 0; j < 6; ++j) launch_fill_test(precision, nc, vg, vecs[j], nrhs, 101 + j, s);
+      launch_fill_test(precision == P16 ? P32 : precision, nc, vg, xlo, nrhs, 107, s);
+      std::vector<SlotState> hs(nrhs);
+      std::vector<double> hp((size_t)nrhs * nbp_of(vg.V), 1.0 / nbp_of(vg.V));
+      for (auto& q : hs) {
+        std::memset(&q, 0, sizeof(q));
+        q.status = SLOT_RUNNING;
+        q.rho[0] = q.rho[1] = 1.0;
+        q.scale = q.scale_prev = 1.0;
+        q.mass = d->mass;
+        for (int j = 0; j < 4; ++j) q.alpha[j] = std::ldexp(1.0, -(j + 1));
+      }
+      LQ_HIP(hipMemcpyAsync(st, hs.data(), hs.size() * sizeof(SlotState), hipMemcpyHostToDevice, s));
+      LQ_HIP(hipMemcpyAsync(part_in, hp.data(), hp.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      LQ_HIP(hipStreamSynchronize(s));   // the host arrays go out of scope
+    }
     EpiArgs e;
     std::memset(&e, 0, sizeof(e));
     e.nbp = nbp_of(vg.V);
@@ -379,8 +401,8 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     // 0: the first matvec of a CG iteration (t = M p with ||t||^2); 1: the
     // plain M^dag stencil; 2: the second (q = M^dag t, r -= alpha q, ||r||^2,
     // and on every fourth launch x += the four steps of the group, as in the
-    // solver's iterations), on zeroed state (alpha = 0: the same loads,
-    // stores and arithmetic); 3 and 4: the same two steps of an even-odd
+    // solver's iterations), on the live state set up above; 3 and 4: the
+    // same two steps of an even-odd
     // preconditioned iteration, each a pair of half-lattice launches
     // (t = M^ p with ||t||^2; M^dag t with the CG update), timed per pair
     const int epi = (kernel == 0 || kernel == 3) ? EPI_STORE_NORM
@@ -629,6 +651,27 @@ int lq_batch_peek(lq_batch* b, int32_t slot, lq_solve_info* info, double* scale)
 }
 
 void lq_batch_destroy(lq_batch* b) { delete b; }
+
+// ---------------------------------------------------- staggered overlap
+size_t lq_overlap_workspace_bytes(const lq_gauge* g, int32_t g55_mode) {
+  if (!g || (g55_mode != LQ_G55_CORNERS && g55_mode != LQ_G55_ONTHEFLY)) return 0;
+  return overlap_workspace_bytes(g->g, g55_mode);
+}
+
+int lq_overlap_apply(const lq_gauge* g, const lq_overlap* ov, const void* in, void* out,
+                     void* ws, size_t ws_bytes, void* stream) {
+  return guard([&] {
+    need(g && ov && in && out && ws, "null argument");
+    need(std::isfinite(ov->rho) && ov->rho > 0.0, "rho must be finite and > 0");
+    need(std::isfinite(ov->mass) && std::isfinite(ov->r), "mass and r must be finite");
+    need(std::isfinite(ov->lo) && std::isfinite(ov->hi) && ov->lo > 0.0 && ov->hi > ov->lo,
+         "need 0 < lo < hi");
+    need(ov->degree >= 1 && ov->degree <= 4096, "degree must be in [1, 4096]");
+    need(ov->g55_mode == LQ_G55_CORNERS || ov->g55_mode == LQ_G55_ONTHEFLY, "bad g55_mode");
+    overlap_apply(g, ov, in, out, ws, ws_bytes, S(stream));
+    return LQ_OK;
+  });
+}
 
 // ---------------------------------------------------- condition number
 size_t lq_lanczos_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t g55_mode,

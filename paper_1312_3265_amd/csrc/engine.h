@@ -226,6 +226,10 @@ int spectrum_run(const lq_gauge_s* g, const lq_dirac* d, double sigma, int steps
 int lanczos_run(const lq_gauge_s* g, const lq_dirac* d, int steps, const void* v0, void* ws,
                 size_t ws_bytes, std::vector<double>& alpha, std::vector<double>& beta,
                 hipStream_t s);
+// The staggered overlap operator (k_overlap.hip): see lq_overlap_apply.
+size_t overlap_workspace_bytes(const Geom& g, int g55);
+void overlap_apply(const lq_gauge_s* g, const lq_overlap* ov, const void* in, void* out, void* ws,
+                   size_t ws_bytes, hipStream_t s);
 // extreme eigenvalues of the symmetric tridiagonal (alpha, beta) by Sturm bisection
 void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b, double& lo,
                       double& hi);

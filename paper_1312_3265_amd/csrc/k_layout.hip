@@ -444,4 +444,43 @@ void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (uint4*)p, n16);
 }
 
+// Deterministic test data for timing: every component of nrhs vector fields
+// uniform in [-1, 1) from a counter-based hash of (seed, system, site,
+// component) (the 32-bit finaliser of MurmurHash3), stored in the field's
+// precision.
+__device__ __forceinline__ uint32_t mix32(uint32_t h) {
+  h ^= h >> 16; h *= 0x85ebca6bu;
+  h ^= h >> 13; h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+template <class P, int NC>
+__global__ void __launch_bounds__(256)
+fill_test_kernel(const Geom g, typename P::S* __restrict__ f, int nbp, int nrhs, uint32_t seed) {
+  using C = typename P::C;
+  using R = typename P::R;
+  int sb, k;
+  map_block(nbp, nrhs, 1, sb, k);
+  const int i = sb * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  C v[NC];
+  uint32_t h = mix32(seed ^ mix32((uint32_t)k * 0x9e3779b9u ^ mix32((uint32_t)i)));
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    h = mix32(h + 0x632be5abu);
+    const uint32_t h2 = mix32(h ^ 0x5bd1e995u);
+    v[q].x = (R)((int32_t)h * (1.0 / 2147483648.0));
+    v[q].y = (R)((int32_t)h2 * (1.0 / 2147483648.0));
+  }
+  st_site<P, NC>(f + (size_t)k * field_planes<P>(NC) * g.Vp, g.Vp, i, v);
+}
+
+void launch_fill_test(int prec, int nc, const Geom& g, void* soa, int nrhs, uint32_t seed,
+                      hipStream_t s) {
+  const int nbp = nbp_of(g.V);
+  if (nbp * nrhs == 0) return;
+  LQ_PNC(prec, nc, hipLaunchKernelGGL((fill_test_kernel<PP, NCC>), dim3(nbp * nrhs), dim3(256), 0,
+                                      s, g, (typename PP::S*)soa, nbp, nrhs, seed));
+}
+
 }  // namespace lq

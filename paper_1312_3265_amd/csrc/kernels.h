@@ -73,6 +73,10 @@ void launch_su3_deviation(const Geom& g, const double2* u64, double* part, doubl
 void launch_plaquette(const Geom& g, const double2* u64, double* part, int nbp, double* out,
                       hipStream_t s);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+// nrhs vector fields of nc components in precision prec, every component
+// uniform in [-1, 1) from a hash of (seed, system, site, component)
+void launch_fill_test(int prec, int nc, const Geom& g, void* soa, int nrhs, uint32_t seed,
+                      hipStream_t s);
 
 // ---- pion correlator (Wilson point-source propagators, canonical complex128)
 int pion_blocks_per_slice(int L4);
