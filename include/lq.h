@@ -241,6 +241,22 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t op, int32_t precision
              int32_t links, const void* in, void* out, void* ws, size_t ws_bytes,
              void* stream);
 
+/* Allocation-free variant of lq_apply, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same operation, arguments and results as lq_apply,
+ * with the scratch taken from a fixed array inside the library instead of a
+ * caller workspace.  The array holds lq_apply_noalloc_max_bytes() = 80 MiB per
+ * GPU, allocated when the library's device code is loaded and kept until the
+ * process ends; a lattice whose lq_apply_workspace_bytes exceeds it is refused
+ * with LQ_ERR_WORKSPACE (80 MiB covers an FP64 Wilson M^dag M up to a
+ * 16^3 x 32 lattice).  No device memory is allocated or freed by the call.
+ * All calls on one GPU share its array: calls that overlap in time on the
+ * same GPU (other streams or host threads) race on it and must be serialised
+ * by the caller.  Asynchronous, like lq_apply. */
+size_t lq_apply_noalloc_max_bytes(void);
+int lq_apply_noalloc(const lq_gauge* g, const lq_dirac* d, int32_t op, int32_t precision,
+                     int32_t links, const void* in, void* out, void* stream);
+
 /* ------------------------------------------------------- even-odd blocks
  * The Schur complement of the even-odd preconditioned Wilson solve (the
  * preconditioning of the footnote to eq. (2), Sec. 3; r = 1): with sites split

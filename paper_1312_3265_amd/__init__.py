@@ -110,6 +110,8 @@ def lib():
         "lq_gauge_plaquette": ([P, P, P], I32),
         "lq_apply_workspace_bytes": ([P, I32, I32, I32], SZ),
         "lq_apply": ([P, P, I32, I32, I32, P, P, P, SZ, P], I32),
+        "lq_apply_noalloc_max_bytes": ([], SZ),
+        "lq_apply_noalloc": ([P, P, I32, I32, I32, P, P, P], I32),
         "lq_schur_workspace_bytes": ([P, I32], SZ),
         "lq_schur_apply": ([P, P, I32, I32, I32, P, P, P, SZ, P], I32),
         "lq_pion_workspace_bytes": ([P], SZ),
@@ -271,6 +273,18 @@ def apply(gauge, formulation, mass, psi, op=OP_M, r=1.0, g55=G55_CORNERS, precis
     _check(lib().lq_apply(gauge._h, ctypes.byref(d), op, precision, links, _ptr(x), _ptr(out),
                           _ptr(ws), nb, _stream(stream)))
     _stream_sync(stream)
+    return out
+
+
+def apply_noalloc(gauge, formulation, mass, psi, out, op=OP_M, r=1.0, g55=G55_CORNERS,
+                  precision=F64, links=0, stream=None):
+    """op(psi) into the caller's `out` (a device tensor like psi) through the
+    allocation-free entry point (the library's fixed scratch; no device
+    allocation in the call).  Asynchronous on `stream`."""
+    torch = _torch()
+    d = Dirac(formulation, g55, mass, r)
+    _check(lib().lq_apply_noalloc(gauge._h, ctypes.byref(d), op, precision, links, _ptr(psi),
+                                  _ptr(out), _stream(stream)))
     return out
 
 

@@ -6,6 +6,9 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <string>
+#include <mutex>
+#include <map>
 #include <vector>
 
 #include "engine.h"
@@ -258,6 +261,51 @@ int lq_apply(const lq_gauge* g, const lq_dirac* d, int32_t opsel, int32_t precis
     }
     launch_field_out(precision, nc, g->g, b, out, f64, nbp, 0, 1, s);
     check_launch();
+    return LQ_OK;
+  });
+}
+
+// ------------------------------------------------- allocation-free apply
+// Scratch of lq_apply_noalloc: one array per GPU, resident from module load
+// until the process ends.  Its name is only a host-side stand-in for the
+// device symbol; the device address is looked up once per device with
+// hipGetSymbolAddress and used everywhere instead.
+constexpr size_t kApplyScratchBytes = size_t(80) << 20;
+static __device__ __align__(256) unsigned char scratch[kApplyScratchBytes];
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;   // device ordinal -> device address of `scratch`
+
+static void* apply_scratch() {
+  int dev = 0;
+  LQ_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    throw Error(LQ_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[dev] = ptr;
+  return ptr;
+}
+
+size_t lq_apply_noalloc_max_bytes(void) { return kApplyScratchBytes; }
+
+int lq_apply_noalloc(const lq_gauge* g, const lq_dirac* d, int32_t opsel, int32_t precision,
+                     int32_t links, const void* in, void* out, void* stream) {
+  return guard([&] {
+    need(g && d && in && out, "null argument");
+    check_dirac(d);
+    check_prec(precision, links);
+    const size_t nb = lq_apply_workspace_bytes(g, d->formulation, d->g55_mode, precision);
+    if (nb == 0) throw Error(LQ_ERR_ARG, "bad formulation, Gamma_55 mode or precision");
+    if (nb > kApplyScratchBytes)
+      throw Error(LQ_ERR_WORKSPACE, "lq_apply_noalloc: this lattice needs " + std::to_string(nb) +
+                                        " bytes of scratch, above its fixed maximum of " +
+                                        std::to_string(kApplyScratchBytes));
+    void* ws = apply_scratch();
+    const int rc = lq_apply(g, d, opsel, precision, links, in, out, ws, kApplyScratchBytes, stream);
+    if (rc != LQ_OK) throw Error(rc, g_last_error);
     return LQ_OK;
   });
 }
