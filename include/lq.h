@@ -287,7 +287,9 @@ int lq_schur_apply(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t
  * LQ_FEAT_EO), each a pair of half-lattice launches: t = M^ p with ||t||^2,
  * and M^dag t fused with the CG update; the average is per pair.  rhs_per_thread (1, 2, 4;
  * FP32/Q16 only) is the number of systems each thread serves, the choice the
- * solvers' autotuner makes per batch; window, the autotuner's other choice,
+ * solvers' autotuner makes per batch; 8 selects the lanes stencil (kernels 0-2,
+ * Wilson, r = 1, 18-real links: four systems across the lanes of each site,
+ * the link products on the matrix cores, results bitwise those of 1); window, the autotuner's other choice,
  * is the block order: w > 0 sweeps windows of w site blocks per XCD over all
  * systems before moving on, 0 gives each XCD one contiguous site range, -1
  * gives each XCD a contiguous eighth of the system-major (system, site)
@@ -363,7 +365,11 @@ void lq_batch_destroy(lq_batch* b);
 /* Batched solvers tune their launch configuration once per (GPU, lattice,
  * operator, storage, batch size) and cache it in the file LQ_TUNE_CACHE
  * (default $HOME/.cache/lq_tune.txt).  The environment variable LQ_LAUNCH =
- * "K,window" (K in {1, 2, 4}, window >= -4) forces a configuration instead.
+ * "K,window" (K in {1, 2, 4, 8}, window >= -4) forces a configuration instead.
+ *
+ * LQ_LAUNCH = "8,window" runs the unpreconditioned r = 1 Wilson stencils of
+ * FP32/16-bit batches with 18-real links as the lanes stencil (see
+ * lq_time_dslash); the autotuner does not choose it.
  *
  * The launch configuration the solvers' autotuner chose for batches of
  * `nrhs` systems of this operator and storage on this lattice (in this

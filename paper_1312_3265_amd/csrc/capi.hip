@@ -384,8 +384,8 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     check_dirac(d);
     check_prec(precision, links);
     need(nrhs >= 1 && reps >= 1, "nrhs and reps must be >= 1");
-    need(rhs_per_thread == 1 || rhs_per_thread == 2 || rhs_per_thread == 4,
-         "rhs_per_thread must be 1, 2 or 4");
+    need(rhs_per_thread == 1 || rhs_per_thread == 2 || rhs_per_thread == 4 || rhs_per_thread == 8,
+         "rhs_per_thread must be 1, 2, 4 or 8");
     need(rhs_per_thread == 1 || precision != LQ_PREC_F64, "FP64 stencils take one system per thread");
     need(window >= -4, "window must be >= -4");
     const int nl = links_for(g, precision, links);
@@ -394,6 +394,10 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     need(kernel >= 0 && kernel <= 4, "kernel selector must be 0 to 4");
     const bool eo = kernel >= 3;
     if (eo) need(d->formulation == LQ_WILSON && d->r == 1.0, "the even-odd pairs are built for Wilson, r = 1");
+    if (rhs_per_thread == 8)
+      need(d->formulation == LQ_WILSON && d->r == 1.0 && nl == 18 && !eo,
+           "rhs_per_thread 8 (the lanes stencil) is built for Wilson, r = 1, 18-real links, "
+           "unpreconditioned");
     const size_t v = (size_t)nrhs * field_bytes(g->g, precision, nc);
     const size_t np = (size_t)nrhs * nbp_of(g->g.V) * sizeof(double);
     Carver c(ws);
@@ -673,8 +677,8 @@ int lq_tuned_launch(const lq_gauge* g, const lq_dirac* d, int32_t precision, int
     const int v = tuned_rhs_per_thread(
         tune_key(g->g, opkind(d->formulation, d->g55_mode), precision, nl, nrhs));
     if (v == 0) throw Error(LQ_ERR_STATE, "no batch of this shape has been tuned");
-    *rhs_per_thread = v & 7;
-    *window = (v >> 3) - 3;
+    *rhs_per_thread = v & 15;
+    *window = (v >> 4) - 3;
     return LQ_OK;
   });
 }

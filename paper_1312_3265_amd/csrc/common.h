@@ -242,30 +242,33 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base) {
 // blocks re-read (links shared by the systems of a batch, stencil neighbours).
 constexpr int kStream = 2;
 
+// lo: a per-lane byte offset added to the lane's address, so that lanes may
+// address different fields of a batch (a fixed stride apart) through one
+// wavefront-uniform base
 template <int BYTES, int CP = 0>
 __device__ __forceinline__ void ld_rec(const void* __restrict__ base, int Vp, int i,
-                                       uint32_t w[Rec<BYTES>::W]) {
+                                       uint32_t w[Rec<BYTES>::W], uint32_t lo = 0) {
   using R = Rec<BYTES>;
   const __amdgpu_buffer_rsrc_t rs = rsrc(base);
   const uint32_t vp = (uint32_t)Vp, ui = (uint32_t)i;
 #pragma unroll
   for (int j = 0; j < R::A; ++j) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, ui * 16u, (uint32_t)j * vp * 16u, CP);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, lo + ui * 16u, (uint32_t)j * vp * 16u, CP);
     w[4 * j] = v[0]; w[4 * j + 1] = v[1]; w[4 * j + 2] = v[2]; w[4 * j + 3] = v[3];
   }
   if constexpr (R::B) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, ui * 8u, (uint32_t)R::A * vp * 16u, CP);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, lo + ui * 8u, (uint32_t)R::A * vp * 16u, CP);
     w[4 * R::A] = v[0]; w[4 * R::A + 1] = v[1];
   }
   if constexpr (R::C) {
     w[R::W - 1] = __builtin_amdgcn_raw_buffer_load_b32(
-        rs, ui * 4u, (uint32_t)R::A * vp * 16u + (uint32_t)R::B * vp * 8u, CP);
+        rs, lo + ui * 4u, (uint32_t)R::A * vp * 16u + (uint32_t)R::B * vp * 8u, CP);
   }
 }
 
 template <int BYTES, int CP = 0>
 __device__ __forceinline__ void st_rec(void* __restrict__ base, int Vp, int i,
-                                       const uint32_t w[Rec<BYTES>::W]) {
+                                       const uint32_t w[Rec<BYTES>::W], uint32_t lo = 0) {
   using R = Rec<BYTES>;
   const __amdgpu_buffer_rsrc_t rs = rsrc(base);
   const uint32_t vp = (uint32_t)Vp, ui = (uint32_t)i;
@@ -274,14 +277,14 @@ __device__ __forceinline__ void st_rec(void* __restrict__ base, int Vp, int i,
 #pragma unroll
   for (int j = 0; j < R::A; ++j) {
     u4 v = {w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]};
-    __builtin_amdgcn_raw_buffer_store_b128(v, rs, ui * 16u, (uint32_t)j * vp * 16u, CP);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, lo + ui * 16u, (uint32_t)j * vp * 16u, CP);
   }
   if constexpr (R::B) {
     u2 v = {w[4 * R::A], w[4 * R::A + 1]};
-    __builtin_amdgcn_raw_buffer_store_b64(v, rs, ui * 8u, (uint32_t)R::A * vp * 16u, CP);
+    __builtin_amdgcn_raw_buffer_store_b64(v, rs, lo + ui * 8u, (uint32_t)R::A * vp * 16u, CP);
   }
   if constexpr (R::C) {
-    __builtin_amdgcn_raw_buffer_store_b32(w[R::W - 1], rs, ui * 4u,
+    __builtin_amdgcn_raw_buffer_store_b32(w[R::W - 1], rs, lo + ui * 4u,
                                           (uint32_t)R::A * vp * 16u + (uint32_t)R::B * vp * 8u, CP);
   }
 }
@@ -334,10 +337,10 @@ template <class P> __host__ __device__ constexpr int vec_rec_bytes(int nc) {
 // All NC components of site i of a vector field f.
 template <class P, int NC, int CP = 0>
 __device__ __forceinline__ void ld_site(const typename P::S* __restrict__ f, int Vp, int i,
-                                        typename P::C v[NC]) {
+                                        typename P::C v[NC], uint32_t lo = 0) {
   constexpr int BY = vec_rec_bytes<P>(NC);
   uint32_t w[BY / 4];
-  ld_rec<BY, CP>(f, Vp, i, w);
+  ld_rec<BY, CP>(f, Vp, i, w, lo);
   if constexpr (P::kSiteScale) {
     const float s = __uint_as_float(w[NC]) * (1.0f / kQ16);
 #pragma unroll
@@ -357,11 +360,12 @@ __device__ __forceinline__ void ld_site(const typename P::S* __restrict__ f, int
 // that a caller can apply it after a linear step on fewer numbers.
 template <class P, int NC>
 __device__ __forceinline__ void ld_site_raw(const typename P::S* __restrict__ f, int Vp, int i,
-                                            typename P::C v[NC], typename P::R& scale) {
+                                            typename P::C v[NC], typename P::R& scale,
+                                            uint32_t lo = 0) {
   if constexpr (P::kSiteScale) {
     constexpr int BY = vec_rec_bytes<P>(NC);
     uint32_t w[BY / 4];
-    ld_rec<BY>(f, Vp, i, w);
+    ld_rec<BY>(f, Vp, i, w, lo);
     scale = __uint_as_float(w[NC]) * (1.0f / kQ16);
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
@@ -370,14 +374,14 @@ __device__ __forceinline__ void ld_site_raw(const typename P::S* __restrict__ f,
     }
   } else {
     scale = (typename P::R)1;
-    ld_site<P, NC>(f, Vp, i, v);
+    ld_site<P, NC>(f, Vp, i, v, lo);
   }
 }
 
 // Store site i; returns ||stored value||^2 (the rounded value actually kept).
 template <class P, int NC, int CP = 0>
 __device__ __forceinline__ double st_site(typename P::S* __restrict__ f, int Vp, int i,
-                                          const typename P::C v[NC]) {
+                                          const typename P::C v[NC], uint32_t lo = 0) {
   constexpr int BY = vec_rec_bytes<P>(NC);
   uint32_t w[BY / 4];
   double n2 = 0.0;
@@ -409,7 +413,7 @@ __device__ __forceinline__ double st_site(typename P::S* __restrict__ f, int Vp,
       n2 += cnorm2(v[q]);
     }
   }
-  st_rec<BY, CP>(f, Vp, i, w);
+  st_rec<BY, CP>(f, Vp, i, w, lo);
   return n2;
 }
 

@@ -130,10 +130,10 @@ struct WilsonOp {
   // conversions instead of 24.  sc = the site's scale.
   template <int MU, int TT>
   __device__ __forceinline__ static void project_q16(const S* __restrict__ f, int Vp, int j,
-                                                     C h[2][3], R& sc) {
+                                                     C h[2][3], R& sc, uint32_t lo = 0) {
     constexpr int BY = vec_rec_bytes<P>(12);
     uint32_t w[BY / 4];
-    ld_rec<BY>(f, Vp, j, w);
+    ld_rec<BY>(f, Vp, j, w, lo);
     sc = __uint_as_float(w[12]) * (1.0f / kQ16);
     const auto i16x2 = [](uint32_t v) { return make_int2((int)(short)(v & 0xffffu), (int)v >> 16); };
 #pragma unroll
@@ -157,6 +157,11 @@ struct WilsonOp {
     C uh[2][3];
     if (BACK) { mvd(lk, h[0], uh[0]); mvd(lk, h[1], uh[1]); }
     else { mv(lk, h[0], uh[0]); mv(lk, h[1], uh[1]); }
+    accumulate_uh<MU, TT>(uh, f, acc);
+  }
+  // acc += f [uh; TT B^dag uh] for the link product uh = L h already formed
+  template <int MU, int TT>
+  __device__ __forceinline__ static void accumulate_uh(const C uh[2][3], R f, C acc[12]) {
     const R ft = TT > 0 ? f : -f;
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {

@@ -211,7 +211,7 @@ struct Engine {
 void enqueue_schur(const lq_gauge_s* g, const OpArgs& base, int prec, int nl, bool dag, int epi,
                    const void* in, void* w, const EpiArgs& e, int nrhs, hipStream_t s);
 
-int tuned_rhs_per_thread(const std::string& key);   // 0: not tuned; else K + 8 * (window + 3)
+int tuned_rhs_per_thread(const std::string& key);   // 0: not tuned; else K + 16 * (window + 3)
 std::string tune_key(const Geom& g, int op, int prec, int nl, int nslots);
 void remember_rhs_per_thread(const std::string& key, int k);
 

@@ -157,7 +157,7 @@ std::string tune_key(const Geom& g, int op, int prec, int nl, int nslots) {
   LQ_HIP(hipGetDevice(&dev));
   LQ_HIP(hipGetDeviceProperties(&prop, dev));
   std::ostringstream key;
-  key << "v10:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
+  key << "v11:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
       << ":op" << op << ":p" << prec << ":l" << nl << ":n" << nslots;
   std::string k = key.str();
   for (auto& ch : k) if (ch == ' ') ch = '_';
@@ -174,19 +174,26 @@ void Engine::tune(hipStream_t s) {
   if (prec_lo == P64 || nslots < 2) return;
   // LQ_LAUNCH="K,window" forces the launch configuration (testing every
   // block order against the tuned one); it is not remembered
+  // K = 8: the lanes stencil (four systems across the lanes of a site, link
+  // products on the matrix cores): unpreconditioned r = 1 Wilson, 18-real
+  // links, on request only (LQ_LAUNCH)
+  const bool lanes_ok = op == OP_WILSON && r == 1.0 && nl_lo == 18;
   if (const char* f = std::getenv("LQ_LAUNCH")) {
     int kk = 1, w = 0;
-    if (std::sscanf(f, "%d,%d", &kk, &w) == 2 && (kk == 1 || kk == 2 || kk == 4) && w >= -4) {
-      rhs_per_thread = kk;
+    if (std::sscanf(f, "%d,%d", &kk, &w) == 2 && (kk == 1 || kk == 2 || kk == 4 || kk == 8) &&
+        w >= -4) {
+      // the lanes stencil applies to r = 1 Wilson with 18-real links only;
+      // elsewhere K = 8 runs the one-system kernels
+      rhs_per_thread = (kk == 8 && !lanes_ok) ? 1 : kk;
       window = w;
       return;
     }
-    throw Error(LQ_ERR_ARG, std::string("LQ_LAUNCH must be \"K,window\" with K in {1,2,4} and "
+    throw Error(LQ_ERR_ARG, std::string("LQ_LAUNCH must be \"K,window\" with K in {1,2,4,8} and "
                                         "window >= -4, got ") + f);
   }
   const std::string k = tune_key(gauge->g, op, prec_lo, nl_lo, nslots);
-  const int cached = tuned_rhs_per_thread(k);   // encoded as K + 8 * (window + 3)
-  if (cached) { rhs_per_thread = cached & 7; window = (cached >> 3) - 3; return; }
+  const int cached = tuned_rhs_per_thread(k);   // encoded as K + 16 * (window + 3)
+  if (cached) { rhs_per_thread = cached & 15; window = (cached >> 4) - 3; return; }
   EpiArgs e = epi_base();
   e.st = nullptr;
   e.out = t;
@@ -206,8 +213,10 @@ void Engine::tune(hipStream_t s) {
   LQ_HIP(hipEventCreate(&t1));
   float best = 1e30f;
   int bestk = 1, bestw = 0;
+  // the lanes stencil (8) is not a candidate: exact, but slower than one
+  // system per thread (it is selected explicitly with LQ_LAUNCH)
   for (int kk : {1, 2, 4}) {
-    if (kk > nslots) break;
+    if (kk > nslots) continue;
     // the system-major orders (-1, -2) are left out: every XCD then needs all
     // the links, which alone on the GPU the last-level cache hides, but with
     // other batches in flight they are fetched again per system (16^3x32, 36
@@ -242,7 +251,7 @@ void Engine::tune(hipStream_t s) {
   (void)hipEventDestroy(t1);
   rhs_per_thread = bestk;
   window = bestw;
-  remember_rhs_per_thread(k, bestk + 8 * (bestw + 3));
+  remember_rhs_per_thread(k, bestk + 16 * (bestw + 3));
 }
 
 // ======================================================== even-odd blocks

@@ -155,24 +155,30 @@ constexpr int stencil_waves() { return (Op::NC == 12 && K >= 2) ? 3 : Op::kWaves
 // launch; CP = kStream marks them non-temporal so that, when the batch's
 // vectors overflow the caches anyway, they do not displace the links and the
 // stencil input from L2.
+// kb >= 0 (the lanes stencil): the fields are addressed from the uniform base
+// of system kb (off = kb's offset) plus per-lane byte offsets lo_v (vectors of
+// policy Pol) and lo_x (x), system k being kb + its lane's share; FP32/16-bit
+// only.
 template <class Op, int CP>
 __device__ __forceinline__ double cg_update_site(const EpiArgs& ea, int Vp, int k, size_t off,
                                                  int i, double alpha,
-                                                 const typename Op::C q[Op::NC]) {
+                                                 const typename Op::C q[Op::NC], int kb = -1,
+                                                 uint32_t lo_v = 0, uint32_t lo_x = 0) {
   using P_C = typename Op::C;
   using R = typename Op::R;
   using S = typename Op::S;
   using Pol = typename Op::Pol;
   constexpr int NC = Op::NC;
+  const int kx = kb >= 0 ? kb : k;
   S* r = (S*)ea.r + off;
   const R a = (R)alpha;
   P_C rv[NC];
-  ld_site<Pol, NC, CP>(r, Vp, i, rv);
+  ld_site<Pol, NC, CP>(r, Vp, i, rv, lo_v);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     rv[c].x -= a * q[c].x; rv[c].y -= a * q[c].y;
   }
-  const double n2 = st_site<Pol, NC, CP>(r, Vp, i, rv);
+  const double n2 = st_site<Pol, NC, CP>(r, Vp, i, rv, lo_v);
   if (ea.xstep > 0 && Pol::id == 0) {   // wavefront-uniform
     // FP64: one component at a time, so that the 48-word records are never
     // live together (they would spill)
@@ -190,22 +196,22 @@ __device__ __forceinline__ double cg_update_site(const EpiArgs& ea, int Vp, int 
     }
   } else if (ea.xstep > 0) {   // wavefront-uniform
     using XP = typename XPol<Pol>::type;
-    typename XP::S* x = (typename XP::S*)ea.x + (size_t)k * NC * Vp;
+    typename XP::S* x = (typename XP::S*)ea.x + (size_t)kx * NC * Vp;
     typename XP::C xv[NC];
-    ld_site<XP, NC, CP>(x, Vp, i, xv);
+    ld_site<XP, NC, CP>(x, Vp, i, xv, lo_x);
     // one direction at a time: only x and one record are live
     const int G = ea.xstep;
 #pragma unroll 1
     for (int j = 0; j < G; ++j) {
       const R aj = j == G - 1 ? a : (R)ea.st[k].alpha[j];
       P_C pv[NC];
-      ld_site<Pol, NC, CP>((const S*)ea.pring[j] + off, Vp, i, pv);
+      ld_site<Pol, NC, CP>((const S*)ea.pring[j] + off, Vp, i, pv, lo_v);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         xv[c].x += aj * pv[c].x; xv[c].y += aj * pv[c].y;
       }
     }
-    st_site<XP, NC, CP>(x, Vp, i, xv);
+    st_site<XP, NC, CP>(x, Vp, i, xv, lo_x);
   }
   return n2;
 }

@@ -219,6 +219,40 @@ def test_every_launch_schedule_gives_the_same_solution(formulation, precision, d
                 assert torch.equal(x, ref[0]), (K, w)
 
 
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (16, 16, 4, 8), (6, 4, 6, 8)])
+@pytest.mark.parametrize("precision", [lq.F32, lq.Q16])
+def test_lanes_stencil_is_bitwise_the_one_system_stencil(precision, dims, monkeypatch):
+    """The Wilson stencils with four systems across the lanes of each site and
+    the link products on the matrix cores (systems-per-thread code 8, 18-real
+    links) reproduce the one-system-per-thread kernels bit for bit: the same
+    FMA sequence for every link product (one MFMA step rounds like one FMA),
+    the block partial sums in the same order.  5 systems leave a partial group
+    of four; 6x4x6x8 has a ragged last site block."""
+    U, lat, g = _field(dims, 9)
+    form = synth.WILSON
+    chis = np.stack([synth.point_source(dims, form, a) for a in range(3)] +
+                    [synth.z2_source(dims, form, 70 + s) for s in range(2)])
+    ms = [MASS[form] + 0.02 * k for k in range(5)]
+    opts = lq.solve_opts(precision=precision, links=18, poll_interval=8)
+    ref = None
+    for K, w in ((1, 1), (8, 1), (8, 0), (8, -3), (8, -4), (8, 2)):
+        monkeypatch.setenv("LQ_LAUNCH", f"{K},{w}")
+        x, infos = lq.cg_solve_batch(g, form, ms, chis, [1e-8] * 5, opts=opts)
+        assert all(i["status"] == lq.OK for i in infos), (K, w, infos)
+        its = [i["iterations"] for i in infos]
+        if ref is None:
+            ref = (x, its)
+            for k in range(5):
+                assert _res(form, U, chis[k], x[k], ms[k]) <= 1e-8
+        else:
+            assert its == ref[1], (K, w, its, ref[1])
+            assert torch.equal(x, ref[0]), (K, w)
+    # a single system through the lanes stencil (three idle lanes per site)
+    monkeypatch.setenv("LQ_LAUNCH", "8,1")
+    x1, i1 = lq.cg_solve_batch(g, form, ms[:1], chis[:1], [1e-8], opts=opts)
+    assert i1[0]["iterations"] == ref[1][0] and torch.equal(x1[0], ref[0][0])
+
+
 def test_tuned_launch_and_stencil_timing():
     """The autotuner's choice is reported for the batch shape it tuned, and the
     three stencil timing modes run the solver's kernels."""
@@ -326,3 +360,38 @@ def test_grouped_x_update_keeps_every_step(formulation):
     assert i16["status"] == lq.OK and i16["reliable_updates"] >= 2
     assert i16["iterations"] <= 1.1 * i64["iterations"] + 8, (i16, i64["iterations"])
     assert _res(formulation, U, chi, x16, m) <= tol
+
+
+def test_full_size_fp64_iterations_and_kappa_match_oracle_golden():
+    """The 16^3 x 32 workload field 0 (Sec. 3's lattice): plain FP64 CG on
+    eq. (2) from the point source alpha = 0 at m_c + {0.02, 0.05, 0.1} takes the
+    oracle's iteration counts (tests/golden/fullsize.json, written by the
+    oracle alone) to within 2%, and the 200-step Lanczos estimates of
+    theta_min, theta_max and kappa of (D+m)^dag (D+m) from the same start
+    vector agree with the oracle's."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    with open(os.path.join(here, "workloads.json")) as f:
+        w = json.load(f)
+    with open(os.path.join(here, "fullsize.json")) as f:
+        gold = json.load(f)
+    dims = tuple(w["dims"])
+    U = synth.gauge_field(dims, "near_identity", w["seed"], w["eps"])
+    g = lq.Gauge(lq.Lattice(dims), U)
+    for form, name in ((synth.WILSON, "wilson"), (synth.STAGGERED_WILSON, "staggered_wilson")):
+        chi = synth.point_source(dims, form, 0)
+        v0 = synth.gaussian_field(dims, form, gold["v0_seed"])
+        for d in w["deltas"]:
+            m = w["m_c"][name] + d
+            x, info = lq.cg_solve(g, form, m, chi, gold["tol"])
+            it_o = gold["cg"][name][str(d)]["iterations"]
+            print(f"{name} delta={d}: iterations {info['iterations']} (oracle {it_o})")
+            assert info["status"] == lq.OK and info["true_residual"] <= gold["tol"]
+            assert abs(info["iterations"] - it_o) <= max(2, 0.02 * it_o)
+            k = lq.condition_number(g, form, m, v0, steps=gold["lanczos_steps"])
+            lo = gold["lanczos"][name][str(d)]
+            print(f"  kappa {k['kappa']:.6g} (oracle {lo['kappa']:.6g})")
+            assert abs(k["lmax"] - lo["theta_max"]) <= 1e-9 * lo["theta_max"]
+            assert abs(k["lmin"] - lo["theta_min"]) <= 1e-6 * lo["theta_min"]
+            assert abs(k["kappa"] - lo["kappa"]) <= 1e-6 * lo["kappa"]
