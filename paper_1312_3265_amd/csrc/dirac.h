@@ -107,6 +107,8 @@ struct WilsonOp {
 
   template <int K>
   static constexpr bool kHopPairs() { return P::id != 0 && K == 1; }
+  template <int K>
+  static constexpr bool kStraight() { return P::id != 0 && K >= 2; }
 
   // r = 1 hop along +-MU with the gamma structure fixed at compile time:
   // h = sgn * scale * (psi_up + TT B psi_lo) (TT = -s forward, +s backward),
@@ -241,11 +243,31 @@ struct WilsonOp {
     }
     if constexpr (!GENERAL_R) {
       // Each hop's code has its gamma structure and coordinates built in.
-      // The loop stays rolled (its index made opaque to the compiler, which
-      // would otherwise unroll it and hoist every hop's loads into spills);
-      // an iteration covers one hop, or both hops of a direction where the
-      // registers allow (single-system FP32/Q16).
-      if constexpr (kHopPairs<K>()) {
+      // Several FP32/16-bit systems per thread: the eight hops in a straight
+      // line, a scheduling barrier between them so that no hop's loads are
+      // hoisted into an earlier one (a rolled loop would shuffle the K
+      // accumulators through its back edge, a register move per value per
+      // hop).  Otherwise the loop stays rolled (its index made opaque to the
+      // compiler, which would unroll it and hoist every hop's loads into
+      // spills); an iteration covers one hop, or both hops of a direction
+      // where the registers allow (single-system FP32/Q16).
+      if constexpr (kStraight<K>()) {
+        hop_r1<0, false, K>(a, in0, rstride, c, i, act, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        hop_r1<0, true, K>(a, in0, rstride, c, i, act, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        hop_r1<1, false, K>(a, in0, rstride, c, i, act, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        hop_r1<1, true, K>(a, in0, rstride, c, i, act, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        hop_r1<2, false, K>(a, in0, rstride, c, i, act, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        hop_r1<2, true, K>(a, in0, rstride, c, i, act, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        hop_r1<3, false, K>(a, in0, rstride, c, i, act, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        hop_r1<3, true, K>(a, in0, rstride, c, i, act, acc);
+      } else if constexpr (kHopPairs<K>()) {
 #pragma unroll 1
         for (int m0 = 0; m0 < 4; ++m0) {
           int mu = m0;
@@ -398,7 +420,23 @@ struct WilsonEOOp {
 #pragma unroll
       for (int q = 0; q < 12; ++q) acc[k][q] = diag ? cscale(v[q], coef) : czero<C>();
     }
-    if constexpr (W::template kHopPairs<K>()) {
+    if constexpr (W::template kStraight<K>()) {
+      hop_eo<0, false, K>(a, in0, rstride, c, i, h, act, fm, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      hop_eo<0, true, K>(a, in0, rstride, c, i, h, act, fm, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      hop_eo<1, false, K>(a, in0, rstride, c, i, h, act, fm, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      hop_eo<1, true, K>(a, in0, rstride, c, i, h, act, fm, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      hop_eo<2, false, K>(a, in0, rstride, c, i, h, act, fm, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      hop_eo<2, true, K>(a, in0, rstride, c, i, h, act, fm, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      hop_eo<3, false, K>(a, in0, rstride, c, i, h, act, fm, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      hop_eo<3, true, K>(a, in0, rstride, c, i, h, act, fm, acc);
+    } else if constexpr (W::template kHopPairs<K>()) {
 #pragma unroll 1
       for (int m0 = 0; m0 < 4; ++m0) {
         int mu = m0;
