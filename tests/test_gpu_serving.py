@@ -71,8 +71,8 @@ def test_server_at_the_workload_lattice_sizes():
     """Poisson stream over 8^3x16, 16^3x32 and 24^3x48 resident fields (both
     formulations, point and Z2 sources, tolerances 1e-10..1e-6), 16-bit
     storage, at two offered loads; every result meets its tolerance by the
-    oracle's FP64 residual.  (32^3x64 serves the same way; it is left out here
-    only to keep the oracle's residual checks short.)"""
+    oracle's FP64 residual.  32^3x64 is served in
+    test_server_at_32x64_lends_memory_between_sizes."""
     dims_choices = [(8, 8, 8, 16), (16, 16, 16, 32), (24, 24, 24, 48)]
     eps = 0.4359375
     fields = {d: synth.gauge_field(d, "near_identity", 2000 + i, eps)
@@ -108,6 +108,63 @@ def test_server_at_the_workload_lattice_sizes():
                                               r.x.cpu().numpy(), req.mass)
                 assert rn <= req.tol, (req.id, req.dims, rn, req.tol)
     print("offered 20/s:", reports[0], "offered 60/s:", reports[1])
+
+
+@pytest.mark.timeout(900)
+def test_server_at_32x64_lends_memory_between_sizes():
+    """32^3x64 (the 16^3x32 workload field repeated twice in every direction)
+    beside 16^3x32, both formulations, 16-bit storage, Z2 and point sources.
+    The budget holds the 16^3x32 Wilson burst's four-slot pool or one
+    32^3x64 Wilson system, not both: the 32^3x64 Wilson requests that arrive
+    while the 16^3x32 systems run wait until that pool has drained and
+    closed, then take its memory (the smaller staggered Wilson systems start
+    in what is left).  Every
+    result meets its tolerance by eq. (2)'s residual recomputed with the
+    library's FP64 operator (pinned to the oracle at full size); one Wilson
+    32^3x64 result is also checked by the oracle."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "workloads.json")) as f:
+        w = json.load(f)
+    d16 = tuple(w["dims"])
+    d32 = tuple(2 * d for d in d16)
+    U16 = synth.gauge_field(d16, "near_identity", w["seed"], w["eps"])
+    U32 = np.tile(U16, (2, 2, 2, 2, 1, 1, 1))
+    fields = {d16: U16, d32: U32}
+    mc = {synth.WILSON: w["m_c"]["wilson"], synth.STAGGERED_WILSON: w["m_c"]["staggered_wilson"]}
+    opts = lq.solve_opts(precision=lq.Q16, links=12, poll_interval=16)
+    srv = serve.SolveServer(fields, opts=opts, slots=4, chunk=16, min_pool=4)
+    W, S = synth.WILSON, synth.STAGGERED_WILSON
+    p16, p32 = srv.pool_bytes(d16, W, 4), srv.pool_bytes(d32, W, 1)
+    budget = p32 + p16 // 2
+    srv.set_budget(budget)
+    assert p16 <= budget < p16 + p32 and srv.pool_bytes(d32, S, 1) <= budget - p16
+    reqs = []
+    for i in range(4):
+        reqs.append(serve.Request(i, d16, W, mc[W] + 0.05, synth.point_source(d16, W, 3 * i),
+                                  1e-8, arrival=0.0))
+    for i, (f, tol) in enumerate(((W, 1e-8), (S, 1e-6), (W, 1e-6), (S, 1e-8))):
+        chi = synth.z2_source(d32, f, 50 + i) if i % 2 else synth.point_source(d32, f, 0)
+        reqs.append(serve.Request(10 + i, d32, f, mc[f] + 0.1, chi, tol, arrival=0.02))
+    results = srv.run(reqs)
+    rep = srv.report()
+    print(rep)
+    assert rep["completed"] == len(reqs) and rep["converged"] == len(reqs)
+    assert rep["workspace_bytes"] <= budget and rep["pools_lent"] >= 1
+    by = {r.id: r for r in results}
+    last16 = max(by[i].finished for i in range(4))
+    assert min(by[i].admitted for i in (10, 12)) >= last16
+    for req in reqs:
+        r = by[req.id]
+        g = srv.gauges[tuple(req.dims)]
+        chi = torch.as_tensor(req.source).cuda()
+        b = lq.apply(g, req.formulation, req.mass, chi, op=lq.OP_MDAG)
+        ax = lq.apply(g, req.formulation, req.mass, r.x, op=lq.OP_MDAGM)
+        rn = float(torch.linalg.vector_norm(b - ax) / torch.linalg.vector_norm(b))
+        assert rn <= req.tol, (req.id, req.dims, rn, req.tol)
+    r10 = by[10]
+    rn, _ = solvers.true_residual(W, U32, reqs[4].source, r10.x.cpu().numpy(), reqs[4].mass)
+    assert rn <= reqs[4].tol
 
 
 def test_batch_cancel_frees_a_running_slot():
@@ -165,6 +222,7 @@ def test_server_cancels_queued_and_running_requests():
     chi = [synth.point_source(dims, form, a) for a in range(3)]
     opts = lq.solve_opts(precision=lq.F32, links=12, poll_interval=8)
     srv = serve.SolveServer(fields, opts=opts, slots=1, chunk=8)
+    srv.set_budget(srv.pool_bytes(dims, form, 1))    # room for one system only
     reqs = [serve.Request(1, dims, form, -0.44, chi[0], 1e-12, arrival=0.0),
             serve.Request(2, dims, form, -0.25, chi[1], 1e-8, arrival=0.0),
             serve.Request(3, dims, form, -0.25, chi[2], 1e-8, arrival=0.0)]
@@ -172,9 +230,10 @@ def test_server_cancels_queued_and_running_requests():
     out = {}
     t = threading.Thread(target=lambda: out.setdefault("results", srv.run(reqs)))
     t.start()
-    while srv.status(1) is None:
+    deadline = time.time() + 60
+    while srv.status(1) != "running" and time.time() < deadline:
         time.sleep(0.001)
-    assert srv.status(1) == "running"
+    assert srv.status(1) == "running" and srv.status(3) == "queued"
     srv.cancel(1)
     t.join(timeout=120)
     assert not t.is_alive()
@@ -183,7 +242,7 @@ def test_server_cancels_queued_and_running_requests():
     assert phases == {2: "queued", 1: "running"}
     assert [r.id for r in results] == [3] and results[0].info["status"] == lq.OK
     assert srv.status(1) == "cancelled" and srv.status(3) == "finished"
-    assert srv.report()["cancelled"] == 2
+    assert srv.report()["cancelled"] == 2 and srv.report()["pools_opened"] == 1
     rn, _ = solvers.true_residual(form, fields[dims], chi[2], results[0].x.cpu().numpy(), -0.25)
     assert rn <= 1e-8
 
