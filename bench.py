@@ -851,6 +851,14 @@ def main():
             n += len(infos)
         return n
 
+    # every batch shape is tuned alone, before the concurrent workers start:
+    # the autotuner times kernels on its own stream, and other batches
+    # running meanwhile would decide its choice
+    for form in (0, 1):
+        lq.cg_solve_batch(fields[0], form, masses[form], src[form], [TOL] * len(masses[form]),
+                          opts=opts, stream=workers[0][0], workspace=workers[0][1][form])
+    torch.cuda.synchronize()
+    log(f"tuned launch (K, window): wilson {lq.tuned_launch(fields[0], 0, prec, links, NRHS_W)}")
     for i in range(a.warmup):
         one_step()
         log(f"warmup step {i} done")

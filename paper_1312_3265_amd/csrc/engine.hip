@@ -9,6 +9,8 @@
 #include <mutex>
 #include <cstdio>
 #include <sstream>
+#include <utility>
+#include <vector>
 
 #include "engine.h"
 
@@ -157,7 +159,7 @@ std::string tune_key(const Geom& g, int op, int prec, int nl, int nslots) {
   LQ_HIP(hipGetDevice(&dev));
   LQ_HIP(hipGetDeviceProperties(&prop, dev));
   std::ostringstream key;
-  key << "v11:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
+  key << "v12:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
       << ":op" << op << ":p" << prec << ":l" << nl << ":n" << nslots;
   std::string k = key.str();
   for (auto& ch : k) if (ch == ' ') ch = '_';
@@ -211,19 +213,25 @@ void Engine::tune(hipStream_t s) {
   hipEvent_t t0, t1;
   LQ_HIP(hipEventCreate(&t0));
   LQ_HIP(hipEventCreate(&t1));
-  float best = 1e30f;
-  int bestk = 1, bestw = 0;
   // the lanes stencil (8) is not a candidate: exact, but slower than one
-  // system per thread (it is selected explicitly with LQ_LAUNCH)
-  for (int kk : {1, 2, 4}) {
-    if (kk > nslots) continue;
-    // the system-major orders (-1, -2) are left out: every XCD then needs all
-    // the links, which alone on the GPU the last-level cache hides, but with
-    // other batches in flight they are fetched again per system (16^3x32, 36
-    // Wilson systems, two batches in flight: 84 solves/s with -2, 100 with -3)
-    for (int w : {1, 2, 4, 0, -3, -4}) {
-      e.rhs_per_thread = f.rhs_per_thread = kk;
-      e.window = f.window = w;
+  // system per thread (it is selected explicitly with LQ_LAUNCH).
+  // The system-major orders (-1, -2) are left out: every XCD then needs all
+  // the links, which alone on the GPU the last-level cache hides, but with
+  // other batches in flight they are fetched again per system (16^3x32, 36
+  // Wilson systems, two batches in flight: 84 solves/s with -2, 100 with -3).
+  // Every candidate is timed twice, in two passes of opposite order, and
+  // keeps its faster time, so that work of other streams running meanwhile
+  // (a caller's concurrent batches) is less likely to decide the choice.
+  std::vector<std::pair<int, int>> cand;
+  for (int kk : {1, 2, 4})
+    if (kk <= nslots)
+      for (int w : {1, 2, 4, 0, -3, -4}) cand.push_back({kk, w});
+  std::vector<float> tbest(cand.size(), 1e30f);
+  for (int pass = 0; pass < 2; ++pass) {
+    for (size_t ci = 0; ci < cand.size(); ++ci) {
+      const size_t c = pass == 0 ? ci : cand.size() - 1 - ci;
+      e.rhs_per_thread = f.rhs_per_thread = cand[c].first;
+      e.window = f.window = cand[c].second;
       stencil(prec_lo, nl_lo, false, EPI_STORE_NORM, p, e, nslots, s);
       stencil(prec_lo, nl_lo, true, EPI_CG_UPDATE, t, f, nslots, s);
       LQ_HIP(hipEventRecord(t0, s));
@@ -244,11 +252,15 @@ void Engine::tune(hipStream_t s) {
       check_launch();
       float ms = 0.0f;
       LQ_HIP(hipEventElapsedTime(&ms, t0, t1));
-      if (ms < best) { best = ms; bestk = kk; bestw = w; }
+      tbest[c] = std::min(tbest[c], ms);
     }
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
+  int bestk = 1, bestw = 0;
+  float best = 1e30f;
+  for (size_t c = 0; c < cand.size(); ++c)
+    if (tbest[c] < best) { best = tbest[c]; bestk = cand[c].first; bestw = cand[c].second; }
   rhs_per_thread = bestk;
   window = bestw;
   remember_rhs_per_thread(k, bestk + 16 * (bestw + 3));
