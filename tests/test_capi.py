@@ -33,6 +33,11 @@ def test_lattice_validation_without_gpu():
     good = (ctypes.c_int32 * 4)(4, 6, 8, 4)
     badbc = (ctypes.c_int32 * 4)(1, 1, 2, 1)
     assert L.lq_lattice_create(good, badbc, ctypes.byref(h)) == lq.ERR_ARG
+    huge = (ctypes.c_int32 * 4)(1024, 1024, 16, 16)       # 2^28 sites: above the limit
+    assert L.lq_lattice_create(huge, None, ctypes.byref(h)) == lq.ERR_ARG
+    assert b"2^28" in L.lq_last_error()
+    small = (ctypes.c_int32 * 4)(4, 2, 4, 4)              # extents below 4
+    assert L.lq_lattice_create(small, None, ctypes.byref(h)) == lq.ERR_ARG
     assert L.lq_lattice_create(good, None, ctypes.byref(h)) == lq.OK
     assert L.lq_lattice_volume(h) == 4 * 6 * 8 * 4
     # gauge storage query: 36 FP64 planes of padded length plus scratch

@@ -77,3 +77,42 @@ def test_q16_wilson_long_reliable_interval_converges(interval):
     assert info["status"] == lq.OK, info
     rn, _ = solvers.true_residual(synth.WILSON, U, chi, x.cpu().numpy(), m)
     assert rn <= 1e-8, rn
+
+
+@pytest.mark.parametrize("precision", [lq.F64, lq.F32, lq.Q16])
+@pytest.mark.parametrize("formulation", [synth.WILSON, synth.STAGGERED_WILSON])
+def test_zero_source_is_solved_by_zero_and_leaves_the_batch_alone(formulation, precision):
+    """chi = 0 gives b = M^dag chi = 0, whose solution is x = 0: the system is
+    done at load (no iteration), x is exactly zero, and in a batch beside
+    non-zero sources the other systems are bitwise what they are alone.
+    Also even-odd (Wilson): the same."""
+    dims = (6, 4, 6, 8)
+    U = synth.gauge_field(dims, "near_identity", 17, 0.436)
+    g = lq.Gauge(lq.Lattice(dims), U, lq.FEAT_CORNERS | lq.FEAT_F32 | lq.FEAT_Q16 | lq.FEAT_EO)
+    m = -0.2 if formulation == synth.WILSON else -0.3
+    zero = np.zeros(synth.field_shape(dims, formulation), dtype=np.complex128)
+    chi = synth.z2_source(dims, formulation, 5)
+    variants = [lq.solve_opts(precision=precision, links=12, poll_interval=8)]
+    if formulation == synth.WILSON:
+        variants.append(lq.solve_opts(precision=precision, links=12, poll_interval=8, evenodd=1))
+    for opts in variants:
+        x0, i0 = lq.cg_solve(g, formulation, m, zero, 1e-8, opts=opts)
+        assert i0["status"] == lq.OK and i0["iterations"] == 0, i0
+        assert not torch.any(x0 != 0)
+        xs, infos = lq.cg_solve_batch(g, formulation, [m, m, m], np.stack([chi, zero, chi]),
+                                      [1e-8, 1e-8, 1e-9], opts=opts)
+        assert [i["status"] for i in infos] == [lq.OK] * 3 and infos[1]["iterations"] == 0
+        assert not torch.any(xs[1] != 0)
+        xa, ia = lq.cg_solve(g, formulation, m, chi, 1e-8, opts=opts)
+        assert ia["iterations"] == infos[0]["iterations"] and torch.equal(xa, xs[0])
+        rn, _ = solvers.true_residual(formulation, U, chi, xs[2].cpu().numpy(), m)
+        assert rn <= 1e-9
+
+
+def test_empty_batch_is_refused():
+    dims = (4, 4, 4, 4)
+    g = lq.Gauge(lq.Lattice(dims), synth.gauge_field(dims, "haar", 3))
+    chis = np.zeros((0,) + synth.field_shape(dims, synth.WILSON), dtype=np.complex128)
+    with pytest.raises(lq.LQError) as e:
+        lq.cg_solve_batch(g, synth.WILSON, [], chis, [])
+    assert e.value.code == lq.ERR_ARG
