@@ -664,6 +664,48 @@ def cpu_baseline(workload):
     )
 
 
+def oracle_error(lq, g0, dims, mc, stream):
+    """Per storage precision, the single-system solve of field 0's point
+    source alpha = 0 at each mass against the oracle's FP64 solution x*, from
+    its fingerprint in tests/golden/fullsize_solutions.json (written by the
+    oracle alone): iterations, and the error on the 64 sampled sites and on
+    the four seeded projections, each relative to ||x*||.  Two solutions that
+    both meet eq. (2) at tol differ by at most 2 tol kappa ||x*|| (about)."""
+    import numpy as np
+    import torch
+
+    import synth
+    with open(os.path.join(ROOT, "tests", "golden", "fullsize_solutions.json")) as f:
+        sols = json.load(f)
+    V = int(np.prod(dims))
+    out = {}
+    for form, name in ((0, "wilson"), (1, "staggered_wilson")):
+        chi = synth.point_source(dims, form, 0)
+        vs = [torch.from_numpy(synth.gaussian_field(dims, form, s)).to("cuda")
+              for s in sols["proj_seeds"]]
+        out[name] = {}
+        for d in DELTAS:
+            ref = sols["solutions"][name][str(d)]
+            nrm = float(np.sqrt(ref["norm2"]))
+            sites = torch.as_tensor(ref["sites"], device="cuda")
+            samp = torch.complex(torch.tensor(ref["samples_re"], dtype=torch.float64),
+                                 torch.tensor(ref["samples_im"], dtype=torch.float64)).to("cuda")
+            row = {"oracle_iterations": ref["iterations"]}
+            for prec, pname in ((lq.F64, "f64"), (lq.F32, "f32"), (lq.Q16, "q16")):
+                opts = lq.solve_opts(precision=prec, links=12)
+                x, info = lq.cg_solve(g0, form, mc[name] + d, chi, TOL, opts=opts, stream=stream)
+                torch.cuda.synchronize()
+                e_s = float(torch.linalg.vector_norm(x.reshape(V, -1)[sites] - samp)) / nrm
+                e_p = max(abs(complex(torch.vdot(v.reshape(-1), x.reshape(-1))) -
+                              complex(pr, pi)) / (float(torch.linalg.vector_norm(v)) * nrm)
+                          for v, pr, pi in zip(vs, ref["proj_re"], ref["proj_im"]))
+                row[pname] = {"iterations": info["iterations"],
+                              "true_residual": info["true_residual"],
+                              "err_sampled": float(f"{e_s:.3e}"), "err_projections": float(f"{e_p:.3e}")}
+            out[name][str(d)] = row
+    return out
+
+
 def gold_volume(w):
     v = 1
     for d in w["dims"]:
@@ -682,6 +724,8 @@ def main():
     ap.add_argument("--links", type=int, default=12, choices=[12, 18],
                     help="link storage of the batched stencil (16-bit with q16): 18 = 18-real, "
                          "12 = 12-real in the vector storage")
+    ap.add_argument("--links-sw", type=int, default=0, choices=[0, 12, 18],
+                    help="link storage of the staggered Wilson batches (0: as --links)")
     ap.add_argument("--fields", type=int, default=8)
     ap.add_argument("--reliable-interval", type=int, default=0,
                     help="reliable update at least every this many iterations (0: library default)")
@@ -790,6 +834,10 @@ def main():
         masses[form] = ms
     opts = lq.solve_opts(precision=prec, links=links, poll_interval=a.poll_interval, use_graph=1,
                          reliable_interval=a.reliable_interval)
+    links_sw = a.links_sw or links
+    opts_f = {0: opts, 1: lq.solve_opts(precision=prec, links=links_sw,
+                                        poll_interval=a.poll_interval, use_graph=1,
+                                        reliable_interval=a.reliable_interval)}
     # `concurrency` batches in flight, each on its own stream with its own
     # workspace: a batch's instruction-bound stencil then shares the device
     # with another batch's bandwidth-bound kernels
@@ -798,7 +846,7 @@ def main():
         wsc = {}
         for form in (0, 1):
             n = len(masses[form])
-            wsc[form] = torch.empty(lq.solve_workspace_bytes(fields[0], form, opts, n),
+            wsc[form] = torch.empty(lq.solve_workspace_bytes(fields[0], form, opts_f[form], n),
                                     dtype=torch.uint8, device="cuda")
         workers.append((stream if c == 0 else torch.cuda.Stream(), wsc))
     torch.cuda.synchronize()
@@ -826,7 +874,7 @@ def main():
                     return
                 try:
                     x, infos = lq.cg_solve_batch(fields[gi], form, masses[form], src[form],
-                                                 [TOL] * len(masses[form]), opts=opts,
+                                                 [TOL] * len(masses[form]), opts=opts_f[form],
                                                  stream=strm, workspace=wsc[form])
                     for k, inf in enumerate(infos):
                         if inf["status"] != lq.OK or inf["true_residual"] > TOL:
@@ -856,7 +904,7 @@ def main():
     # running meanwhile would decide its choice
     for form in (0, 1):
         lq.cg_solve_batch(fields[0], form, masses[form], src[form], [TOL] * len(masses[form]),
-                          opts=opts, stream=workers[0][0], workspace=workers[0][1][form])
+                          opts=opts_f[form], stream=workers[0][0], workspace=workers[0][1][form])
     torch.cuda.synchronize()
     log(f"tuned launch (K, window): wilson {lq.tuned_launch(fields[0], 0, prec, links, NRHS_W)}")
     for i in range(a.warmup):
@@ -907,6 +955,8 @@ def main():
             if props0 is not None else {"error": "no propagators"})
     spec = beside("spectrum", spectrum_section, lq, fields[0], dims, stream)
     log(f"spectrum: {spec}")
+    oerr = beside("error vs oracle", oracle_error, lq, fields[0], dims, mc, stream)
+    log(f"error vs oracle: {oerr}")
 
     # --------------------------------------------- dominant kernel roofline
     cfg = lq.tuned_launch(g0, 0, prec, links, NRHS_W)
@@ -942,7 +992,8 @@ def main():
                          "W 12 + SW 3 point sources x 3 masses m_c+{0.02,0.05,0.1}, "
                          "tol 1e-8, batched CG with FP64 reliable updates"),
             "systems_per_step": nsolved // a.steps,
-            "storage": a.precision, "links": links, "batches_in_flight": a.concurrency,
+            "storage": a.precision, "links": links, "links_staggered_wilson": links_sw,
+            "batches_in_flight": a.concurrency,
             "reliable_interval": a.reliable_interval or "default", "poll_interval": a.poll_interval,
         },
         "roofline": roof,
@@ -962,6 +1013,7 @@ def main():
         "evenodd_wilson": eo_w,
         "pion_wilson_field0": pion,
         "spectrum_sw_field0": spec,
+        "solution_error_vs_oracle_field0": oerr,
         "mixed_iterations_field0": mixed_iters,
         "mixed_reliable_updates_field0": mixed_ru,
     }

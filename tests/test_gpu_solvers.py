@@ -395,3 +395,64 @@ def test_full_size_fp64_iterations_and_kappa_match_oracle_golden():
             assert abs(k["lmax"] - lo["theta_max"]) <= 1e-9 * lo["theta_max"]
             assert abs(k["lmin"] - lo["theta_min"]) <= 1e-6 * lo["theta_min"]
             assert abs(k["kappa"] - lo["kappa"]) <= 1e-6 * lo["kappa"]
+
+
+def _solution_errors(x, ref, form, dims):
+    """(sampled error, projection error) of x against the oracle fingerprint ref,
+    both relative to ||x*||: the components at ref's sites, and the projections
+    on ref's seeded Gaussian fields."""
+    V = int(np.prod(dims))
+    xs = x.reshape(V, -1)
+    sites = torch.as_tensor(ref["sites"], device=x.device)
+    samp = torch.complex(torch.tensor(ref["samples_re"], dtype=torch.float64),
+                         torch.tensor(ref["samples_im"], dtype=torch.float64)).to(x.device)
+    nrm = float(np.sqrt(ref["norm2"]))
+    e_samp = float(torch.linalg.vector_norm(xs[sites] - samp)) / nrm
+    e_proj = 0.0
+    for s, pr, pi in zip(ref["proj_seeds"], ref["proj_re"], ref["proj_im"]):
+        v = torch.from_numpy(synth.gaussian_field(dims, form, s)).to(x.device)
+        d = complex(torch.vdot(v.reshape(-1), x.reshape(-1))) - complex(pr, pi)
+        e_proj = max(e_proj, abs(d) / (float(torch.linalg.vector_norm(v)) * nrm))
+    return e_samp, e_proj
+
+
+@pytest.mark.timeout(600)
+def test_full_size_solutions_match_the_oracle_in_every_precision():
+    """16^3 x 32 workload field 0, point source alpha = 0, both formulations at
+    m_c + {0.02, 0.05, 0.1}: FP64, FP32 and 16-bit solves of eq. (2) at tol 1e-8
+    against the oracle's own FP64 solution x* (its fingerprint in
+    tests/golden/fullsize_solutions.json, written by the oracle alone).  Two
+    solutions that both meet eq. (2) at tol differ by at most
+    2 tol kappa (1 + tol kappa) ||x*|| (kappa of A = (D+m)^dag (D+m), the
+    oracle's 200-step Lanczos value); the error on the 64 sampled sites and on
+    the four seeded projections, each relative to ||x*||, must stay within it.
+    The errors are printed per precision."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    with open(os.path.join(here, "workloads.json")) as f:
+        w = json.load(f)
+    with open(os.path.join(here, "fullsize.json")) as f:
+        gold = json.load(f)
+    with open(os.path.join(here, "fullsize_solutions.json")) as f:
+        sols = json.load(f)
+    dims = tuple(w["dims"])
+    U = synth.gauge_field(dims, "near_identity", w["seed"], w["eps"])
+    g = lq.Gauge(lq.Lattice(dims), U, lq.FEAT_CORNERS | lq.FEAT_F32 | lq.FEAT_Q16)
+    tol = sols["tol"]
+    for form, name in ((synth.WILSON, "wilson"), (synth.STAGGERED_WILSON, "staggered_wilson")):
+        chi = synth.point_source(dims, form, 0)
+        for d in w["deltas"]:
+            m = w["m_c"][name] + d
+            ref = dict(sols["solutions"][name][str(d)], proj_seeds=sols["proj_seeds"])
+            kappa = gold["lanczos"][name][str(d)]["kappa"]
+            bound = 2 * tol * kappa * (1 + tol * kappa)
+            for prec in (lq.F64, lq.F32, lq.Q16):
+                opts = lq.solve_opts(precision=prec, links=12)
+                x, info = lq.cg_solve(g, form, m, chi, tol, opts=opts)
+                assert info["status"] == lq.OK and info["true_residual"] <= tol
+                es, ep = _solution_errors(x, ref, form, dims)
+                print(f"{name} delta={d} precision={prec}: iterations {info['iterations']} "
+                      f"(oracle {ref['iterations']}), error vs oracle: sampled {es:.2e}, "
+                      f"projections {ep:.2e} (bound {bound:.1e})")
+                assert es <= bound and ep <= bound, (name, d, prec, es, ep, bound)
