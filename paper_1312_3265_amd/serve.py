@@ -20,7 +20,9 @@ in the order of their longest-waiting request.  A group that cannot open even
 a one-slot pool waits; meanwhile the pools of the other groups that have no
 request waiting take no new request, close once their running systems have
 finished, and return their bytes to the budget, so a lattice size without
-traffic lends its memory to a busy one.  A request is rejected only if a
+traffic lends its memory to a busy one.  Running pools are never preempted:
+a group whose queue never empties keeps its pools, and a starved group waits
+until the other groups' queues drain.  A request is rejected only if a
 one-slot pool of its group exceeds the whole budget, or its lattice is not
 resident.
 
