@@ -259,8 +259,8 @@ def serving(a, w):
         reqs = [serve.Request(d["id"], d["dims"], d["formulation"], mc[d["formulation"]] + d["delta"],
                               src, d["tol"], arrival=float(t), maxiter=20000)
                 for d, src, t in zip(descs, sources, arrivals)]
-        srv = serve.SolveServer(fields, opts=opts, mem_budget=96 << 30, slots=8, chunk=16,
-                                evenodd=a.serving_evenodd)
+        srv = serve.SolveServer(fields, opts=opts, mem_budget=96 << 30, slots=a.serving_slots,
+                                chunk=16, evenodd=a.serving_evenodd, min_pool=a.serving_min_pool)
         results = srv.run(reqs)
         rep = srv.report()
         rep.pop("groups", None)
@@ -277,7 +277,8 @@ def serving(a, w):
     cap = run([0.0] * len(descs))
     log(f"serving: capacity {cap['solves_per_s']:.2f} solves/s")
     out = {"requests": len(descs), "dims": [list(d) for d in SERVING_DIMS], "storage": "q16",
-           "wilson_evenodd": bool(a.serving_evenodd), "capacity": cap}
+           "wilson_evenodd": bool(a.serving_evenodd), "slots_per_pool": a.serving_slots,
+           "min_pool": a.serving_min_pool, "capacity": cap}
     for frac in (0.5, 0.9):
         rate = frac * cap["solves_per_s"]
         out[f"offered_{int(frac * 100)}pct"] = dict(
@@ -749,6 +750,9 @@ def main():
                     help="only the continuous-batching measurement: Poisson arrivals over four "
                          "lattice sizes at 50%% and 90%% of the measured capacity")
     ap.add_argument("--serving-requests", type=int, default=64)
+    ap.add_argument("--serving-slots", type=int, default=8, help="with --serving: slots per pool")
+    ap.add_argument("--serving-min-pool", type=int, default=1,
+                    help="with --serving: slots a new pool asks for at least")
     ap.add_argument("--serving-evenodd", type=int, default=1, choices=[0, 1],
                     help="with --serving: Wilson requests solved even-odd preconditioned")
     ap.add_argument("--summarize-profile", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "CFETCH", "CWRITE"),

@@ -135,7 +135,7 @@ class SolveServer:
     """
 
     def __init__(self, fields, opts=None, mem_budget=8 << 30, slots=16, chunk=16, r=1.0,
-                 g55=0, evenodd=False, min_pool=4):
+                 g55=0, evenodd=False, min_pool=1):
         self.torch = _torch()
         self.opts = opts or solve_opts(precision=1, links=12, poll_interval=chunk)
         self.evenodd = bool(evenodd) and r == 1.0
