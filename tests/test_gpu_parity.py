@@ -147,6 +147,37 @@ def test_fp64_matvec_full_size_16x32():
             assert err <= 1e-13
 
 
+@pytest.mark.timeout(900)
+def test_matvecs_at_32x64_match_oracle():
+    """32^3 x 64, the largest lattice of the serving workload (the 16^3 x 32
+    field repeated twice in every direction): M^dag on a Gaussian field,
+    against the oracle over the whole field, in the storages and link forms the
+    solvers use -- FP64 (rows 0 and 1 of the links read) within 1e-13, FP32
+    and 16-bit within the bounds of test_low_precision_matvec_within_roundoff;
+    staggered Wilson with Gamma_55 from corners and on the fly."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "workloads.json")) as f:
+        w = json.load(f)
+    d16 = tuple(w["dims"])
+    dims = tuple(2 * d for d in d16)
+    U = np.tile(synth.gauge_field(d16, "near_identity", w["seed"], w["eps"]), (2, 2, 2, 2, 1, 1, 1))
+    g = lq.Gauge(lq.Lattice(dims), U, lq.FEAT_CORNERS | lq.FEAT_F32 | lq.FEAT_Q16)
+    for formulation, g55s in ((synth.WILSON, (0,)),
+                              (synth.STAGGERED_WILSON, (lq.G55_CORNERS, lq.G55_ONTHEFLY))):
+        psi = synth.gaussian_field(dims, formulation, 8)
+        ref = _oracle_apply(formulation, U, psi, -0.4, lq.OP_MDAG)
+        for g55 in g55s:
+            for prec, links, bound in ((lq.F64, 12, 1e-13), (lq.F32, 12, 4e-6),
+                                       (lq.Q16, 12, 1e-4)):
+                out = lq.apply(g, formulation, -0.4, psi, op=lq.OP_MDAG, g55=g55,
+                               precision=prec, links=links).cpu().numpy()
+                err = _relerr(out, ref)
+                print(f"32^3x64 formulation {formulation} g55 {g55} precision {prec}: "
+                      f"relative error {err:.2e}")
+                assert err <= bound, (formulation, g55, prec, err)
+
+
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 6, 8)])
 @pytest.mark.parametrize("formulation,g55", [(synth.WILSON, 0),
                                              (synth.STAGGERED_WILSON, lq.G55_CORNERS),
