@@ -1,9 +1,57 @@
 // Stencil kernel instantiations for WilsonOp.
+#include <cstdlib>
+
 #include "stencil_dispatch.h"
+#include "stencil_tsweep.h"
 
 namespace lq {
 void launch_stencil_wilson_lanes(int prec, int nl, bool dag, int epi, const OpArgs& oa,
                                  const void* in, const EpiArgs& ea, int nrhs, hipStream_t s);
+
+template <int NL, bool DAG, int EPI>
+static void launch_tsweep(const OpArgs& oa, const void* in, const EpiArgs& ea, int nrhs, int T,
+                          hipStream_t s) {
+  const Geom& g = oa.g;
+  const int per = ((g.L[0] * g.L[1]) >> 8) * g.L[2] * (g.L[3] / T);
+  hipLaunchKernelGGL((wilson_tsweep_kernel<NL, DAG, EPI>), dim3(per * nrhs), dim3(256), 0, s, oa,
+                     (const double2*)in, ea, T, nrhs);
+}
+
+// FP64, r = 1, one system per thread, on lattices tsweep_slices accepts:
+// the t-sweeping stencil (stencil_tsweep.h); false where it does not apply.
+// LQ_TSWEEP=0 turns it off (the plain stencil_kernel runs instead).
+template <int NL>
+static bool try_tsweep(bool dag, int epi, const OpArgs& oa, const void* in, const EpiArgs& ea,
+                       int nrhs, hipStream_t s) {
+  const char* e = std::getenv("LQ_TSWEEP");
+  if (e && e[0] == '0') return false;
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      n = 256;
+    ncu = n > 0 ? n : 256;
+  }
+  const int T = tsweep_slices(oa.g, ncu);
+  if (T == 0 || nrhs < 1) return false;
+  if (!dag) {
+    switch (epi) {
+      case EPI_STORE: launch_tsweep<NL, false, EPI_STORE>(oa, in, ea, nrhs, T, s); return true;
+      case EPI_STORE_NORM: launch_tsweep<NL, false, EPI_STORE_NORM>(oa, in, ea, nrhs, T, s); return true;
+      case EPI_RESID: launch_tsweep<NL, false, EPI_RESID>(oa, in, ea, nrhs, T, s); return true;
+      default: return false;
+    }
+  }
+  switch (epi) {
+    case EPI_STORE: launch_tsweep<NL, true, EPI_STORE>(oa, in, ea, nrhs, T, s); return true;
+    case EPI_STORE_NORM: launch_tsweep<NL, true, EPI_STORE_NORM>(oa, in, ea, nrhs, T, s); return true;
+    case EPI_CG_UPDATE: launch_tsweep<NL, true, EPI_CG_UPDATE>(oa, in, ea, nrhs, T, s); return true;
+    case EPI_RESID: launch_tsweep<NL, true, EPI_RESID>(oa, in, ea, nrhs, T, s); return true;
+    case EPI_LANCZOS: launch_tsweep<NL, true, EPI_LANCZOS>(oa, in, ea, nrhs, T, s); return true;
+    default: return false;
+  }
+}
 
 void launch_stencil_wilson(int prec, int nl, bool dag, int epi, const OpArgs& oa, const void* in,
           const EpiArgs& ea, int nrhs, hipStream_t s) {
@@ -11,6 +59,11 @@ void launch_stencil_wilson(int prec, int nl, bool dag, int epi, const OpArgs& oa
   // products on the matrix cores (k_stencil_wlanes.hip)
   if (ea.rhs_per_thread == 8)
     return launch_stencil_wilson_lanes(prec, nl, dag, epi, oa, in, ea, nrhs, s);
+  if (oa.r == 1.0 && prec == P64 && ea.rhs_per_thread <= 1) {
+    if (nl == 12 ? try_tsweep<12>(dag, epi, oa, in, ea, nrhs, s)
+                 : try_tsweep<18>(dag, epi, oa, in, ea, nrhs, s))
+      return;
+  }
   if (oa.r == 1.0) return dispatch_prec<WilsonOpR1>(prec, nl, dag, epi, oa, in, ea, nrhs, s);
   if (prec != P64)
     throw std::runtime_error("Wilson stencil with r != 1 is built for FP64 only");
