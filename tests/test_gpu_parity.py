@@ -242,3 +242,35 @@ def test_lanczos_4x4_matches_oracle(formulation):
     np.testing.assert_allclose(res["beta"][:30], b[:30], rtol=1e-9)
     assert abs(res["lmin"] - lo) <= 1e-8 * hi
     assert abs(res["lmax"] - hi) <= 1e-10 * hi
+
+
+def test_fp64_wilson_t_sweep_agrees_with_the_plain_stencil(monkeypatch):
+    """16^3 x 32, where the FP64 Wilson stencils sweep t (two slices per block):
+    M, M^dag and M^dag M equal the plain one-site-per-thread stencil
+    (LQ_TSWEEP=0) to rounding, a plain FP64 CG solve takes the same iterations
+    either way, and with the sweep a batch of three systems gives bitwise the
+    solutions of the three solves alone (the kernel choice depends on the
+    lattice, not on the batch)."""
+    dims = (16, 16, 16, 32)
+    U, lat, g = _gauge(dims, "near_identity", 2000, eps=0.4359375, features=lq.FEAT_CORNERS)
+    psi = synth.gaussian_field(dims, synth.WILSON, 12)
+    m = -0.37
+    out = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("LQ_TSWEEP", flag)
+        out[flag] = [lq.apply(g, synth.WILSON, m, psi, op=op) for op in
+                     (lq.OP_M, lq.OP_MDAG, lq.OP_MDAGM)]
+    for a, b in zip(out["1"], out["0"]):
+        assert (a - b).abs().max().item() <= 1e-14 * b.abs().max().item()
+    chis = np.stack([synth.point_source(dims, synth.WILSON, a) for a in (0, 4, 9)])
+    its = {}
+    for flag in ("0", "1"):
+        monkeypatch.setenv("LQ_TSWEEP", flag)
+        x, info = lq.cg_solve(g, synth.WILSON, m, chis[0], 1e-8)
+        assert info["status"] == lq.OK
+        its[flag] = info["iterations"]
+    assert abs(its["1"] - its["0"]) <= 1, its
+    xb, ib = lq.cg_solve_batch(g, synth.WILSON, [m, m + 0.01, m], chis, [1e-8, 1e-8, 1e-9])
+    for k, (mk, tk) in enumerate(((m, 1e-8), (m + 0.01, 1e-8), (m, 1e-9))):
+        xa, ia = lq.cg_solve(g, synth.WILSON, mk, chis[k], tk)
+        assert ia["iterations"] == ib[k]["iterations"] and torch.equal(xa, xb[k]), k
