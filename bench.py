@@ -94,7 +94,7 @@ NRHS_W = 36                      # Wilson systems per field: 12 sources x 3 mass
 PROFILE_JSON = os.path.join(ROOT, "profiles", "stencil_wilson_batched_16x32_traffic.json")
 # sources whose change invalidates the stored counter readings of the stencil
 STENCIL_SOURCES = ["csrc/common.h", "csrc/dirac.h", "csrc/stencil.h", "csrc/stencil_dispatch.h",
-                   "csrc/k_stencil_wilson.hip", "build.py"]
+                   "csrc/stencil_tsweep.h", "csrc/k_stencil_wilson.hip", "build.py"]
 
 
 def stencil_source_hash():

@@ -387,7 +387,7 @@ int lq_time_dslash(const lq_gauge* g, const lq_dirac* d, int32_t kernel, int32_t
     need(rhs_per_thread == 1 || rhs_per_thread == 2 || rhs_per_thread == 4 || rhs_per_thread == 8,
          "rhs_per_thread must be 1, 2, 4 or 8");
     need(rhs_per_thread == 1 || precision != LQ_PREC_F64, "FP64 stencils take one system per thread");
-    need(window >= -4, "window must be >= -4");
+    need(window >= -4 || (window <= -11 && window >= -16), "window must be >= -4 or a t-sweep order -11 ... -16");
     const int nl = links_for(g, precision, links);
     const int nc = ncomp_of(d->formulation);
     const int op = opkind(d->formulation, d->g55_mode);

@@ -358,14 +358,11 @@ __device__ __forceinline__ void ld_site(const typename P::S* __restrict__ f, int
 // Site i without applying the Q16 site scale: v = stored integers (as float)
 // and `scale` = the factor that turns them into values (1 for F32 and F64), so
 // that a caller can apply it after a linear step on fewer numbers.
+// dec_site_raw: the same from the record's storage words.
 template <class P, int NC>
-__device__ __forceinline__ void ld_site_raw(const typename P::S* __restrict__ f, int Vp, int i,
-                                            typename P::C v[NC], typename P::R& scale,
-                                            uint32_t lo = 0) {
+__device__ __forceinline__ void dec_site_raw(const uint32_t* w, typename P::C v[NC],
+                                             typename P::R& scale) {
   if constexpr (P::kSiteScale) {
-    constexpr int BY = vec_rec_bytes<P>(NC);
-    uint32_t w[BY / 4];
-    ld_rec<BY>(f, Vp, i, w, lo);
     scale = __uint_as_float(w[NC]) * (1.0f / kQ16);
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
@@ -373,9 +370,20 @@ __device__ __forceinline__ void ld_site_raw(const typename P::S* __restrict__ f,
       v[q] = make_float2((float)z.x, (float)z.y);
     }
   } else {
+    constexpr int WPC = sizeof(typename P::S) / 4;
     scale = (typename P::R)1;
-    ld_site<P, NC>(f, Vp, i, v, lo);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) v[q] = dec<P>(w + q * WPC);
   }
+}
+template <class P, int NC>
+__device__ __forceinline__ void ld_site_raw(const typename P::S* __restrict__ f, int Vp, int i,
+                                            typename P::C v[NC], typename P::R& scale,
+                                            uint32_t lo = 0) {
+  constexpr int BY = vec_rec_bytes<P>(NC);
+  uint32_t w[BY / 4];
+  ld_rec<BY>(f, Vp, i, w, lo);
+  dec_site_raw<P, NC>(w, v, scale);
 }
 
 // Store site i; returns ||stored value||^2 (the rounded value actually kept).

@@ -68,6 +68,7 @@ template <class P, int NL, bool DAG, bool GENERAL_R = false>
 struct WilsonOp {
   using Pol = P;
   static constexpr int NC = 12;
+  static constexpr bool kDag = DAG;
   static constexpr int kWaves = P::id == 0 ? 3 : 4;
   using C = typename P::C;
   using R = typename P::R;
@@ -129,13 +130,10 @@ struct WilsonOp {
   // project<MU, TT> of the 16-bit site j, on the stored integers: sums and
   // differences of two int16 are exact in int32 and convert exactly to FP32,
   // so h is bitwise what projecting the converted components gives, from 12
-  // conversions instead of 24.  sc = the site's scale.
+  // conversions instead of 24.  sc = the site's scale.  project_q16_words:
+  // the same from the record's storage words.
   template <int MU, int TT>
-  __device__ __forceinline__ static void project_q16(const S* __restrict__ f, int Vp, int j,
-                                                     C h[2][3], R& sc, uint32_t lo = 0) {
-    constexpr int BY = vec_rec_bytes<P>(12);
-    uint32_t w[BY / 4];
-    ld_rec<BY>(f, Vp, j, w, lo);
+  __device__ __forceinline__ static void project_q16_words(const uint32_t* w, C h[2][3], R& sc) {
     sc = __uint_as_float(w[12]) * (1.0f / kQ16);
     const auto i16x2 = [](uint32_t v) { return make_int2((int)(short)(v & 0xffffu), (int)v >> 16); };
 #pragma unroll
@@ -147,6 +145,26 @@ struct WilsonOp {
       const int2 h1 = TT > 0 ? cadd(u1, b1) : csub(u1, b1);
       h[0][cc] = make_float2((float)h0.x, (float)h0.y);
       h[1][cc] = make_float2((float)h1.x, (float)h1.y);
+    }
+  }
+  template <int MU, int TT>
+  __device__ __forceinline__ static void project_q16(const S* __restrict__ f, int Vp, int j,
+                                                     C h[2][3], R& sc, uint32_t lo = 0) {
+    constexpr int BY = vec_rec_bytes<P>(12);
+    uint32_t w[BY / 4];
+    ld_rec<BY>(f, Vp, j, w, lo);
+    project_q16_words<MU, TT>(w, h, sc);
+  }
+  // project<MU, TT> of a site from its storage words, as hop_r1 forms it
+  // (the raw integers for 16-bit storage, sc = the site's scale)
+  template <int MU, int TT>
+  __device__ __forceinline__ static void project_words(const uint32_t* w, C h[2][3], R& sc) {
+    if constexpr (P::kSiteScale) {
+      project_q16_words<MU, TT>(w, h, sc);
+    } else {
+      C psi[12];
+      dec_site_raw<P, 12>(w, psi, sc);
+      project<MU, TT>(psi, h);
     }
   }
 

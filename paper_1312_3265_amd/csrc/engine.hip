@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "engine.h"
+#include "stencil_tsweep.h"
 
 const void* lq_gauge_s::links(int prec, int nl) const {
   using namespace lq;
@@ -159,7 +160,7 @@ std::string tune_key(const Geom& g, int op, int prec, int nl, int nslots) {
   LQ_HIP(hipGetDevice(&dev));
   LQ_HIP(hipGetDeviceProperties(&prop, dev));
   std::ostringstream key;
-  key << "v12:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
+  key << "v13:" << prop.gcnArchName << ":" << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3]
       << ":op" << op << ":p" << prec << ":l" << nl << ":n" << nslots;
   std::string k = key.str();
   for (auto& ch : k) if (ch == ' ') ch = '_';
@@ -183,7 +184,7 @@ void Engine::tune(hipStream_t s) {
   if (const char* f = std::getenv("LQ_LAUNCH")) {
     int kk = 1, w = 0;
     if (std::sscanf(f, "%d,%d", &kk, &w) == 2 && (kk == 1 || kk == 2 || kk == 4 || kk == 8) &&
-        w >= -4) {
+        (w >= -4 || (kk == 1 && w <= -11 && w >= -16))) {
       // the lanes stencil applies to r = 1 Wilson with 18-real links only;
       // elsewhere K = 8 runs the one-system kernels
       rhs_per_thread = (kk == 8 && !lanes_ok) ? 1 : kk;
@@ -191,7 +192,8 @@ void Engine::tune(hipStream_t s) {
       return;
     }
     throw Error(LQ_ERR_ARG, std::string("LQ_LAUNCH must be \"K,window\" with K in {1,2,4,8} and "
-                                        "window >= -4, got ") + f);
+                                        "window >= -4 (or, for K = 1, a t-sweep order -11 ... -16), "
+                                        "got ") + f);
   }
   const std::string k = tune_key(gauge->g, op, prec_lo, nl_lo, nslots);
   const int cached = tuned_rhs_per_thread(k);   // encoded as K + 16 * (window + 3)
@@ -226,6 +228,14 @@ void Engine::tune(hipStream_t s) {
   for (int kk : {1, 2, 4})
     if (kk <= nslots)
       for (int w : {1, 2, 4, 0, -3, -4}) cand.push_back({kk, w});
+  // the t-sweeping Wilson stencils (16-bit, one system per thread; bitwise
+  // the same results as the orders above)
+  if (op == OP_WILSON && r == 1.0 && prec_lo == P16)
+    for (int w = -11; w >= -16; --w) {
+      int T = 0;
+      bool xy = false;
+      if (tsweep_lo_code(w, T, xy) && tsweep_lo_ok(gauge->g, T, xy)) cand.push_back({1, w});
+    }
   std::vector<float> tbest(cand.size(), 1e30f);
   for (int pass = 0; pass < 2; ++pass) {
     for (size_t ci = 0; ci < cand.size(); ++ci) {

@@ -210,5 +210,243 @@ wilson_tsweep_kernel(const OpArgs oa, const double2* __restrict__ in, const EpiA
   }
 }
 
-}  // namespace lq
+// ------------------------------------------------ FP32 / 16-bit, batched
+// The batched FP32/16-bit Wilson CG stencils (r = 1, one system per thread)
+// sweeping t in the same way.  A block owns the slab (p, z) of one system for
+// t in [t0, t0 + T); the storage words of psi at the step's slice sit in LDS,
+// so the diagonal needs no fetch, and the -t hop of t + 1 is formed at step t
+// from psi(t) and the link U_t(t) of the +t hop (kept in registers: twelve
+// FP32 values).  With XY (x-y planes of exactly 256 sites, i.e. the slab is
+// the whole plane) the x and y neighbours are read from the LDS words as well,
+// and only the z and +t neighbours are fetched.
+//
+// Every step does what stencil_kernel does for that site in the same order
+// and with the same operations (diagonal, x+, x-, y+, y-, z+, z-, t+, t-; the
+// -t link product is the same mvd of the same decoded link and projection,
+// only formed one step earlier), so the result is bitwise stencil_kernel's:
+// the choice between them (an autotuner candidate) never changes a solve.
+//
+// Blocks: XCD x owns the t-slices [x L4/8, (x+1) L4/8) (T divides L4/8) and
+// takes the systems one after the other, as block order -3 does, so the links
+// of its slices stay in its L2 across the systems.
+// Block-order codes (EpiArgs::window) of this kernel: -11, -12, -13 sweep
+// T = 2, 4, 8 slices with the x and y neighbours from LDS, -14, -15, -16 the
+// same with them fetched.
+__host__ __device__ inline bool tsweep_lo_code(int window, int& T, bool& xy) {
+  if (window > -11 || window < -16) return false;
+  const int c = -window - 10;
+  T = 2 << ((c - 1) % 3);
+  xy = c <= 3;
+  return true;
+}
+__host__ inline bool tsweep_lo_ok(const Geom& g, int T, bool xy) {
+  const int plane = g.L[0] * g.L[1];
+  if (T < 1 || (plane & 255) || nbp_of(g.V) * 256 != g.V || g.L[3] % (8 * T)) return false;
+  return !xy || plane == 256;
+}
 
+// One r = 1 hop along +-MU whose neighbour lies in the slab: as
+// WilsonOp::hop_r1, with the neighbour's storage words read from LDS (rc =
+// the slab's words, base = the slab's first site).
+template <class W, class LP, int NL, int NW, int MU, bool BACK>
+__device__ __forceinline__ void tsweep_hop_lds(const Geom& g, const typename LP::S* links,
+                                               const uint32_t (*rc)[256], int base,
+                                               const Coord& c, int i, typename W::C acc[12]) {
+  constexpr int s = W::kDag ? -1 : 1;
+  constexpr int TT = BACK ? s : -s;
+  bool wrap;
+  const int j = BACK ? nb_bwd(g, c, i, MU, wrap) : nb_fwd(g, c, i, MU, wrap);
+  const bool flip = wrap && g.bc[MU] < 0;
+  typename W::C lk[9];
+  load_link<LP, NL, true>(links, g.Vp, MU, BACK ? j : i, lk);
+  uint32_t w[NW];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) w[q] = rc[q][j - base];
+  typename W::C h[2][3];
+  typename W::R sc;
+  W::template project_words<MU, TT>(w, h, sc);
+  W::template accumulate<MU, TT, BACK>(lk, h, W::template hop_factor<LP>(sc, flip), acc);
+}
+
+template <class P, int NL, bool DAG, int EPI, int CP, bool XY>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(WilsonOpR1<P, NL, DAG>::kWaves, 8)))
+wilson_tsweep_lo_kernel(const OpArgs oa, const typename P::S* __restrict__ in, const EpiArgs ea,
+                        int T, int nrhs) {
+  using Op = WilsonOpR1<P, NL, DAG>;
+  using W = WilsonOp<P, NL, DAG, false>;
+  using LP = typename LinkPol<P, NL>::type;
+  using C = typename P::C;
+  using R = typename P::R;
+  constexpr int NW = vec_rec_bytes<P>(12) / 4;
+  constexpr int sgn = DAG ? -1 : 1;
+  constexpr int TTF = -sgn, TTB = sgn;   // hop along +t, along -t
+  __shared__ double red[16];
+  __shared__ uint32_t rec[2][NW][256];   // psi's storage words at the step's slice / the next
+  const Geom& g = oa.g;
+  const int plane = g.L[0] * g.L[1];
+  const int P_ = plane >> 8, TX = (g.L[3] >> 3) / T;
+  const int per = P_ * g.L[2] * TX;      // blocks of one system on one XCD
+  const int b = blockIdx.x, xcd = b & 7, kk = b >> 3;
+  const int kr = kk / per;
+  int rem = kk - kr * per;
+  const int p = rem % P_;
+  rem /= P_;
+  const int z = rem % g.L[2];
+  const int tc = xcd * TX + rem / g.L[2];
+  const int k = ea.k0 + kr;
+  if (ea.st && !slot_active(ea.st, k, ea.state_mode, ea.par, ea.ru_mask)) return;   // uniform
+  const int Vp = g.Vp;
+  const size_t rstride = (size_t)field_planes<P>(12) * Vp;
+  const typename P::S* f = in + (size_t)k * rstride;
+  const typename LP::S* links = (const typename LP::S*)oa.links;
+  const int tid = threadIdx.x;
+  const int t0 = tc * T;
+
+  double alpha[1] = {0.0};
+  if constexpr (EPI == EPI_CG_UPDATE) {
+    const double tt = sum_partials(ea.part_in + (size_t)k * ea.nbp, ea.nbp, red);
+    const double rho = ea.st[k].rho[ea.par];
+    alpha[0] = (tt > 0.0 && isfinite(tt) && isfinite(rho)) ? rho / tt : 0.0;
+    if (p == 0 && z == 0 && tc == 0 && tid == 0) {   // the block holding site block 0
+      if (!(tt > 0.0 && isfinite(tt))) ea.st[k].flags |= 1;
+      ea.st[k].alpha[ea.q4] = alpha[0];
+    }
+  }
+  const R diag = (R)(rhs_mass(oa, k) + 4.0 * oa.r);
+
+  // prologue: psi(t0)'s words into LDS; the -t hop of t0 from psi(t0 - 1), U_t(t0 - 1)
+  int i = p * 256 + tid + plane * (z + g.L[2] * t0);
+  Coord c = site_coords(g, i);
+  {
+    uint32_t w[NW];
+    ld_rec<NW * 4>(f, Vp, i, w);
+#pragma unroll
+    for (int q = 0; q < NW; ++q) rec[0][q][tid] = w[q];
+  }
+  C ub[2][3];
+  R fb;
+  {
+    bool wrap;
+    const int j = nb_bwd(g, c, i, 3, wrap);
+    C lk[9];
+    load_link<LP, NL, true>(links, Vp, 3, j, lk);
+    uint32_t w[NW];
+    ld_rec<NW * 4>(f, Vp, j, w);
+    C h[2][3];
+    R sc;
+    W::template project_words<3, TTB>(w, h, sc);
+    mvd(lk, h[0], ub[0]);
+    mvd(lk, h[1], ub[1]);
+    fb = W::template hop_factor<LP>(sc, wrap && g.bc[3] < 0);
+  }
+  if constexpr (XY) __syncthreads();   // the step reads its neighbours' words
+
+#pragma unroll 1
+  for (int st = 0; st < T; ++st) {
+    const int cur = st & 1;
+    if (st > 0) {
+      i += plane * g.L[2];
+      c.x[3] += 1;
+    }
+    const int sb = i >> 8;
+    C acc[1][12];
+    {
+      uint32_t w[NW];
+#pragma unroll
+      for (int q = 0; q < NW; ++q) w[q] = rec[cur][q][tid];
+      C v[12];
+      R sc;
+      dec_site_raw<P, 12>(w, v, sc);
+      const R coef = (R)-2 * diag * sc;
+#pragma unroll
+      for (int q = 0; q < 12; ++q) acc[0][q] = cscale(v[q], coef);
+    }
+    if constexpr (XY) {
+      // x and y hops with the neighbour's words from LDS (same slab, same slice)
+      const uint32_t(*rc)[256] = rec[cur];
+      const int base = i - tid;
+#pragma unroll 1
+      for (int h0 = 0; h0 < 4; ++h0) {
+        int hh = h0;
+        asm volatile("" : "+s"(hh));
+        switch (hh) {
+          case 0: tsweep_hop_lds<W, LP, NL, NW, 0, false>(g, links, rc, base, c, i, acc[0]); break;
+          case 1: tsweep_hop_lds<W, LP, NL, NW, 0, true>(g, links, rc, base, c, i, acc[0]); break;
+          case 2: tsweep_hop_lds<W, LP, NL, NW, 1, false>(g, links, rc, base, c, i, acc[0]); break;
+          default: tsweep_hop_lds<W, LP, NL, NW, 1, true>(g, links, rc, base, c, i, acc[0]); break;
+        }
+      }
+#pragma unroll 1
+      for (int h0 = 0; h0 < 2; ++h0) {
+        int hh = h0;
+        asm volatile("" : "+s"(hh));
+        if (hh == 0) W::template hop_r1<2, false, 1>(oa, f, rstride, c, i, 1u, acc);
+        else W::template hop_r1<2, true, 1>(oa, f, rstride, c, i, 1u, acc);
+      }
+    } else {
+#pragma unroll 1
+      for (int h0 = 0; h0 < 6; ++h0) {
+        int hh = h0;
+        asm volatile("" : "+s"(hh));
+        switch (hh) {
+          case 0: W::template hop_r1<0, false, 1>(oa, f, rstride, c, i, 1u, acc); break;
+          case 1: W::template hop_r1<0, true, 1>(oa, f, rstride, c, i, 1u, acc); break;
+          case 2: W::template hop_r1<1, false, 1>(oa, f, rstride, c, i, 1u, acc); break;
+          case 3: W::template hop_r1<1, true, 1>(oa, f, rstride, c, i, 1u, acc); break;
+          case 4: W::template hop_r1<2, false, 1>(oa, f, rstride, c, i, 1u, acc); break;
+          default: W::template hop_r1<2, true, 1>(oa, f, rstride, c, i, 1u, acc); break;
+        }
+      }
+    }
+    // +t hop; psi(t + 1)'s words become the next step's, and U_t(t)^dag P psi(t)
+    // the next step's -t hop
+    C un[2][3];
+    R fn = (R)0;
+    {
+      bool wrap;
+      const int j = nb_fwd(g, c, i, 3, wrap);
+      C lk[9];
+      load_link<LP, NL, true>(links, Vp, 3, i, lk);
+      {
+        uint32_t w[NW];
+        ld_rec<NW * 4>(f, Vp, j, w);
+        if (st + 1 < T) {
+#pragma unroll
+          for (int q = 0; q < NW; ++q) rec[cur ^ 1][q][tid] = w[q];
+        }
+        C h[2][3];
+        R sc;
+        W::template project_words<3, TTF>(w, h, sc);
+        W::template accumulate<3, TTF, false>(lk, h, W::template hop_factor<LP>(sc, wrap && g.bc[3] < 0),
+                                              acc[0]);
+      }
+      if (st + 1 < T) {
+        uint32_t w[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) w[q] = rec[cur][q][tid];
+        C h[2][3];
+        R sc;
+        W::template project_words<3, TTB>(w, h, sc);
+        mvd(lk, h[0], un[0]);
+        mvd(lk, h[1], un[1]);
+        fn = W::template hop_factor<LP>(sc, false);   // t + 1 < L4 inside a chunk
+      }
+    }
+    // -t hop (formed at the previous step, or in the prologue)
+    W::template accumulate_uh<3, TTB>(ub, fb, acc[0]);
+    if (st + 1 < T) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) ub[q / 3][q % 3] = un[q / 3][q % 3];
+      fb = fn;
+    }
+    C o[1][12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) o[0][q] = cscale(acc[0][q], (R)-0.5);
+    site_epilogue<Op, EPI, 1, CP>(oa, ea, k, 1u, i, true, sb, o, alpha, red);
+    // the epilogue's block sum orders this step's reads of rec[cur] before
+    // the next step's writes to it, and this step's writes before its reads
+  }
+}
+
+}  // namespace lq
