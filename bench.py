@@ -191,13 +191,16 @@ def summarize_profile(a, trace, fetch, write, cfetch, cwrite):
                 ids.add(r["Dispatch_Id"])
         return tot / len(ids), len(ids)
 
-    stats = [r for r in rows(trace, "*kernel_stats.csv") if "stencil_kernel" in r["Name"]]
+    stencil = lambda n: "stencil_kernel" in n or "tsweep_lo_kernel" in n
+    stats = [r for r in rows(trace, "*kernel_stats.csv") if stencil(r["Name"])]
     copy_f, _ = per_dispatch(cfetch, "FETCH_SIZE", lambda n: "copyBuffer" in n)
     copy_w, _ = per_dispatch(cwrite, "WRITE_SIZE", lambda n: "copyBuffer" in n)
     fs, wsz = 256 << 20, 256 << 20
     fscale = fs / (copy_f * 1024.0)
     wscale = wsz / (copy_w * 1024.0)
-    dom = lambda n: "stencil_kernel" in n and ", true>, 2," in n
+    # the CG-update stencil: M^dag with epilogue 2 (one-site or t-sweeping kernel)
+    dom = lambda n: (("stencil_kernel" in n and ", true>, 2," in n) or
+                     ("tsweep_lo_kernel" in n and ", true, 2," in n))
     f_kib, nf = per_dispatch(fetch, "FETCH_SIZE", dom)
     w_kib, nw = per_dispatch(write, "WRITE_SIZE", dom)
     entry = {
