@@ -22,7 +22,8 @@ non-zero data; the FP64 matvecs (Wilson, staggered Wilson from corners and on
 the fly) at 16^3x32 and 32^3x64 against the HBM and FP64 rooflines; the
 Lanczos condition numbers at the three masses; the paper's W/SW cost ratios
 measured (Sec. 3, eqs. (3)-(4)); and the oracle timed on the host's cores
-(before the GPU is touched: its worker processes are spawned).
+(before the GPU is touched: its worker processes are spawned).  Last, the
+serving loop (`--serving` alone runs just that; `--no-serving` skips it).
 
 Profiling modes (each runs only what a profiler should see):
     --roofline-only --rhs-per-thread K --window W   the dominant stencil alone
@@ -740,6 +741,8 @@ def main():
                     help="order in which the batches are taken up (interleave: each Wilson "
                          "batch followed by the same field's staggered Wilson one)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving section at the end of the default run")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only time the dominant stencil (the launches a profiler should see)")
     ap.add_argument("--rhs-per-thread", type=int, default=1, help="with --roofline-only")
@@ -980,6 +983,13 @@ def main():
             kap[str(d)][name] = r["kappa"]
     paper = beside("paper comparison", paper_comparison, mv, fp64, kap) \
         if "error" not in mv else {"error": "no matvec figures"}
+    # the serving loop of the continuous-batching row, after everything else
+    # (its pools and fields are its own)
+    serv = None
+    if not a.no_serving:
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        serv = beside("serving", serving, a, w)
 
     line = {
         "metric": "CG solves/s + Dslash HBM GB/s vs peak, 16^3x32, mixed-prec batched vs FP64",
@@ -1017,6 +1027,7 @@ def main():
         },
         "matvec_fp64": mv,
         "paper_comparison": paper,
+        "serving": serv,
         "evenodd_wilson": eo_w,
         "pion_wilson_field0": pion,
         "spectrum_sw_field0": spec,
