@@ -930,6 +930,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.time() - t0
     value = nsolved / elapsed
+    log(f"timed: {value:.2f} solves/s ({nsolved} solves in {elapsed:.2f} s)")
 
     # ------------------------------ FP64 single-RHS reference over the whole mix
     g0 = fields[0]
