@@ -53,13 +53,30 @@ static bool try_tsweep(bool dag, int epi, const OpArgs& oa, const void* in, cons
   }
 }
 
+// Launches the 16-bit t-sweep; false (nothing launched) where fewer than four
+// of its blocks fit on a compute unit.  Wrong results were seen in such
+// launches: with FP32 storage (three blocks per CU), and with the 16-bit
+// kernel's LDS padded to 49 or 60 KB (three or two blocks), in the systems
+// whose blocks have indices past the first 256; padded to 33 or 38 KB (four
+// blocks) it stayed bitwise exact.  The cause was not found.
 template <class P, int NL, bool DAG, int EPI, int CPL, bool XY>
-static void launch_tsweep_lo(const OpArgs& oa, const void* in, const EpiArgs& ea, int nrhs, int T,
+static bool launch_tsweep_lo(const OpArgs& oa, const void* in, const EpiArgs& ea, int nrhs, int T,
                              hipStream_t s) {
+  static int fits = -1;   // blocks of this kernel per CU
+  if (fits < 0) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(&wilson_tsweep_lo_kernel<P, NL, DAG, EPI, CPL, XY>),
+            256, 0) != hipSuccess)
+      n = 0;
+    fits = n;
+  }
+  if (fits < 4) return false;
   const Geom& g = oa.g;
   const int per = ((g.L[0] * g.L[1]) >> 8) * g.L[2] * ((g.L[3] >> 3) / T);
   hipLaunchKernelGGL((wilson_tsweep_lo_kernel<P, NL, DAG, EPI, CPL, XY>), dim3(8 * per * nrhs),
                      dim3(256), 0, s, oa, (const typename P::S*)in, ea, T, nrhs);
+  return true;
 }
 
 // 16-bit, r = 1, one system per thread, a t-sweep block order
@@ -72,20 +89,15 @@ static bool try_tsweep_lo(bool dag, int epi, const OpArgs& oa, const void* in, c
   int T = 0;
   bool xy = false;
   if (nrhs < 1 || !tsweep_lo_code(ea.window, T, xy) || !tsweep_lo_ok(oa.g, T, xy)) return false;
-  if (!dag && epi == EPI_STORE_NORM) {
-    if (xy) launch_tsweep_lo<P, NL, false, EPI_STORE_NORM, 0, true>(oa, in, ea, nrhs, T, s);
-    else launch_tsweep_lo<P, NL, false, EPI_STORE_NORM, 0, false>(oa, in, ea, nrhs, T, s);
-    return true;
-  }
+  if (!dag && epi == EPI_STORE_NORM)
+    return xy ? launch_tsweep_lo<P, NL, false, EPI_STORE_NORM, 0, true>(oa, in, ea, nrhs, T, s)
+              : launch_tsweep_lo<P, NL, false, EPI_STORE_NORM, 0, false>(oa, in, ea, nrhs, T, s);
   if (dag && epi == EPI_CG_UPDATE) {
-    if (ea.stream) {
-      if (xy) launch_tsweep_lo<P, NL, true, EPI_CG_UPDATE, kStream, true>(oa, in, ea, nrhs, T, s);
-      else launch_tsweep_lo<P, NL, true, EPI_CG_UPDATE, kStream, false>(oa, in, ea, nrhs, T, s);
-    } else {
-      if (xy) launch_tsweep_lo<P, NL, true, EPI_CG_UPDATE, 0, true>(oa, in, ea, nrhs, T, s);
-      else launch_tsweep_lo<P, NL, true, EPI_CG_UPDATE, 0, false>(oa, in, ea, nrhs, T, s);
-    }
-    return true;
+    if (ea.stream)
+      return xy ? launch_tsweep_lo<P, NL, true, EPI_CG_UPDATE, kStream, true>(oa, in, ea, nrhs, T, s)
+                : launch_tsweep_lo<P, NL, true, EPI_CG_UPDATE, kStream, false>(oa, in, ea, nrhs, T, s);
+    return xy ? launch_tsweep_lo<P, NL, true, EPI_CG_UPDATE, 0, true>(oa, in, ea, nrhs, T, s)
+              : launch_tsweep_lo<P, NL, true, EPI_CG_UPDATE, 0, false>(oa, in, ea, nrhs, T, s);
   }
   return false;
 }
@@ -101,9 +113,8 @@ void launch_stencil_wilson(int prec, int nl, bool dag, int epi, const OpArgs& oa
                  : try_tsweep<18>(dag, epi, oa, in, ea, nrhs, s))
       return;
   }
-  // 16-bit storage only: with FP32 storage the same kernel gave wrong results
-  // in some systems of a batch (those whose blocks ran beside others on a
-  // CU); the cause was not found, so FP32 keeps stencil_kernel
+  // 16-bit storage only: with FP32 storage the kernel fits three blocks per
+  // CU and gave wrong results (launch_tsweep_lo), so FP32 keeps stencil_kernel
   if (oa.r == 1.0 && prec == P16 && ea.rhs_per_thread <= 1 && ea.window <= -11) {
     if (nl == 12 ? try_tsweep_lo<Q16, 12>(dag, epi, oa, in, ea, nrhs, s)
                  : try_tsweep_lo<Q16, 18>(dag, epi, oa, in, ea, nrhs, s))
