@@ -296,7 +296,14 @@ int lq_schur_apply(const lq_gauge* g, const lq_dirac* d, int32_t dagger, int32_t
  * order, -2 the same with every other system swept backwards; -3 and -4 tile
  * each XCD's eighth of the t range in chunks of two z-planes with t inner,
  * systems outermost (-3) or innermost (-4) -- on lattices with whole x-y
- * planes of 256-site blocks, L4 % 8 == 0 and even L3; elsewhere they act as 0.  ws: device scratch of
+ * planes of 256-site blocks, L4 % 8 == 0 and even L3; elsewhere they act as 0.
+ * -11, -12, -13 (16-bit Wilson, r = 1, one system per thread, kernels 0-2):
+ * each block sweeps one system's 256-site slab through T = 2, 4, 8 t-slices,
+ * the diagonal and the x-y neighbours from LDS (x-y planes of exactly 256
+ * sites); -14, -15, -16 the same with the x-y neighbours fetched; results
+ * bitwise those of the other orders; where the sweep does not apply (other
+ * storage, L4 not a multiple of 8T, other plane sizes, or fewer than four
+ * blocks per CU) they act as 0.  ws: device scratch of
  * lq_time_dslash_workspace_bytes (contents overwritten).  */
 size_t lq_time_dslash_workspace_bytes(const lq_gauge* g, int32_t formulation, int32_t g55_mode,
                                       int32_t precision,
@@ -365,7 +372,8 @@ void lq_batch_destroy(lq_batch* b);
 /* Batched solvers tune their launch configuration once per (GPU, lattice,
  * operator, storage, batch size) and cache it in the file LQ_TUNE_CACHE
  * (default $HOME/.cache/lq_tune.txt).  The environment variable LQ_LAUNCH =
- * "K,window" (K in {1, 2, 4, 8}, window >= -4) forces a configuration instead.
+ * "K,window" (K in {1, 2, 4, 8}, window >= -4, or K = 1 and a t-sweep order
+ * -11 ... -16) forces a configuration instead.
  *
  * LQ_LAUNCH = "8,window" runs the unpreconditioned r = 1 Wilson stencils of
  * FP32/16-bit batches with 18-real links as the lanes stencil (see
