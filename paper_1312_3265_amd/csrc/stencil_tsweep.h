@@ -281,6 +281,9 @@ wilson_tsweep_lo_kernel(const OpArgs oa, const typename P::S* __restrict__ in, c
   constexpr int NW = vec_rec_bytes<P>(12) / 4;
   constexpr int sgn = DAG ? -1 : 1;
   constexpr int TTF = -sgn, TTB = sgn;   // hop along +t, along -t
+  // the epilogue's block sum is what orders each step's LDS writes before
+  // the next step's reads
+  static_assert(EPI == EPI_STORE_NORM || EPI == EPI_CG_UPDATE, "epilogues with a block sum only");
   __shared__ double red[16];
   __shared__ uint32_t rec[2][NW][256];   // psi's storage words at the step's slice / the next
   const Geom& g = oa.g;
