@@ -215,8 +215,9 @@ wilson_tsweep_kernel(const OpArgs oa, const double2* __restrict__ in, const EpiA
 // sweeping t in the same way.  A block owns the slab (p, z) of one system for
 // t in [t0, t0 + T); the storage words of psi at the step's slice sit in LDS,
 // so the diagonal needs no fetch, and the -t hop of t + 1 is formed at step t
-// from psi(t) and the link U_t(t) of the +t hop (kept in registers: twelve
-// FP32 values).  With XY (x-y planes of exactly 256 sites, i.e. the slab is
+// from psi(t) and the link U_t(t) of the +t hop (kept in LDS: carried in
+// registers through the step loop it cost a register move per value and
+// hop).  With XY (x-y planes of exactly 256 sites, i.e. the slab is
 // the whole plane) the x and y neighbours are read from the LDS words as well,
 // and only the z and +t neighbours are fetched.
 //
@@ -286,6 +287,7 @@ wilson_tsweep_lo_kernel(const OpArgs oa, const typename P::S* __restrict__ in, c
   static_assert(EPI == EPI_STORE_NORM || EPI == EPI_CG_UPDATE, "epilogues with a block sum only");
   __shared__ double red[16];
   __shared__ uint32_t rec[2][NW][256];   // psi's storage words at the step's slice / the next
+  __shared__ C ubs[6][256];              // the step's -t link product (registers would shuffle)
   const Geom& g = oa.g;
   const int plane = g.L[0] * g.L[1];
   const int P_ = plane >> 8, TX = (g.L[3] >> 3) / T;
@@ -327,7 +329,6 @@ wilson_tsweep_lo_kernel(const OpArgs oa, const typename P::S* __restrict__ in, c
 #pragma unroll
     for (int q = 0; q < NW; ++q) rec[0][q][tid] = w[q];
   }
-  C ub[2][3];
   R fb;
   {
     bool wrap;
@@ -336,11 +337,13 @@ wilson_tsweep_lo_kernel(const OpArgs oa, const typename P::S* __restrict__ in, c
     load_link<LP, NL, true>(links, Vp, 3, j, lk);
     uint32_t w[NW];
     ld_rec<NW * 4>(f, Vp, j, w);
-    C h[2][3];
+    C h[2][3], ub[2][3];
     R sc;
     W::template project_words<3, TTB>(w, h, sc);
     mvd(lk, h[0], ub[0]);
     mvd(lk, h[1], ub[1]);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) ubs[q][tid] = ub[q / 3][q % 3];
     fb = W::template hop_factor<LP>(sc, wrap && g.bc[3] < 0);
   }
   if constexpr (XY) __syncthreads();   // the step reads its neighbours' words
@@ -365,47 +368,45 @@ wilson_tsweep_lo_kernel(const OpArgs oa, const typename P::S* __restrict__ in, c
 #pragma unroll
       for (int q = 0; q < 12; ++q) acc[0][q] = cscale(v[q], coef);
     }
-    if constexpr (XY) {
-      // x and y hops with the neighbour's words from LDS (same slab, same slice)
+    // x, y and z hops, both hops of a direction per iteration (the loop kept
+    // rolled: unrolled, every hop's loads are hoisted and spill)
+    {
       const uint32_t(*rc)[256] = rec[cur];
       const int base = i - tid;
 #pragma unroll 1
-      for (int h0 = 0; h0 < 4; ++h0) {
-        int hh = h0;
-        asm volatile("" : "+s"(hh));
-        switch (hh) {
-          case 0: tsweep_hop_lds<W, LP, NL, NW, 0, false>(g, links, rc, base, c, i, acc[0]); break;
-          case 1: tsweep_hop_lds<W, LP, NL, NW, 0, true>(g, links, rc, base, c, i, acc[0]); break;
-          case 2: tsweep_hop_lds<W, LP, NL, NW, 1, false>(g, links, rc, base, c, i, acc[0]); break;
-          default: tsweep_hop_lds<W, LP, NL, NW, 1, true>(g, links, rc, base, c, i, acc[0]); break;
-        }
-      }
-#pragma unroll 1
-      for (int h0 = 0; h0 < 2; ++h0) {
-        int hh = h0;
-        asm volatile("" : "+s"(hh));
-        if (hh == 0) W::template hop_r1<2, false, 1>(oa, f, rstride, c, i, 1u, acc);
-        else W::template hop_r1<2, true, 1>(oa, f, rstride, c, i, 1u, acc);
-      }
-    } else {
-#pragma unroll 1
-      for (int h0 = 0; h0 < 6; ++h0) {
-        int hh = h0;
-        asm volatile("" : "+s"(hh));
-        switch (hh) {
-          case 0: W::template hop_r1<0, false, 1>(oa, f, rstride, c, i, 1u, acc); break;
-          case 1: W::template hop_r1<0, true, 1>(oa, f, rstride, c, i, 1u, acc); break;
-          case 2: W::template hop_r1<1, false, 1>(oa, f, rstride, c, i, 1u, acc); break;
-          case 3: W::template hop_r1<1, true, 1>(oa, f, rstride, c, i, 1u, acc); break;
-          case 4: W::template hop_r1<2, false, 1>(oa, f, rstride, c, i, 1u, acc); break;
-          default: W::template hop_r1<2, true, 1>(oa, f, rstride, c, i, 1u, acc); break;
+      for (int m0 = 0; m0 < 3; ++m0) {
+        int mu = m0;
+        asm volatile("" : "+s"(mu));
+        switch (mu) {
+          case 0:
+            if constexpr (XY) {
+              tsweep_hop_lds<W, LP, NL, NW, 0, false>(g, links, rc, base, c, i, acc[0]);
+              tsweep_hop_lds<W, LP, NL, NW, 0, true>(g, links, rc, base, c, i, acc[0]);
+            } else {
+              W::template hop_r1<0, false, 1>(oa, f, rstride, c, i, 1u, acc);
+              W::template hop_r1<0, true, 1>(oa, f, rstride, c, i, 1u, acc);
+            }
+            break;
+          case 1:
+            if constexpr (XY) {
+              tsweep_hop_lds<W, LP, NL, NW, 1, false>(g, links, rc, base, c, i, acc[0]);
+              tsweep_hop_lds<W, LP, NL, NW, 1, true>(g, links, rc, base, c, i, acc[0]);
+            } else {
+              W::template hop_r1<1, false, 1>(oa, f, rstride, c, i, 1u, acc);
+              W::template hop_r1<1, true, 1>(oa, f, rstride, c, i, 1u, acc);
+            }
+            break;
+          default:
+            W::template hop_r1<2, false, 1>(oa, f, rstride, c, i, 1u, acc);
+            W::template hop_r1<2, true, 1>(oa, f, rstride, c, i, 1u, acc);
+            break;
         }
       }
     }
-    // +t hop; psi(t + 1)'s words become the next step's, and U_t(t)^dag P psi(t)
-    // the next step's -t hop
-    C un[2][3];
-    R fn = (R)0;
+    // +t hop, then the -t hop (formed at the previous step, or in the
+    // prologue); psi(t + 1)'s words become the next step's, and
+    // U_t(t)^dag P psi(t) the next step's -t hop (the order of the one-site
+    // stencil's accumulation: t+ before t-)
     {
       bool wrap;
       const int j = nb_fwd(g, c, i, 3, wrap);
@@ -424,24 +425,25 @@ wilson_tsweep_lo_kernel(const OpArgs oa, const typename P::S* __restrict__ in, c
         W::template accumulate<3, TTF, false>(lk, h, W::template hop_factor<LP>(sc, wrap && g.bc[3] < 0),
                                               acc[0]);
       }
+      {
+        C ub[2][3];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) ub[q / 3][q % 3] = ubs[q][tid];
+        W::template accumulate_uh<3, TTB>(ub, fb, acc[0]);
+      }
       if (st + 1 < T) {
         uint32_t w[NW];
 #pragma unroll
         for (int q = 0; q < NW; ++q) w[q] = rec[cur][q][tid];
-        C h[2][3];
+        C h[2][3], un[2][3];
         R sc;
         W::template project_words<3, TTB>(w, h, sc);
         mvd(lk, h[0], un[0]);
         mvd(lk, h[1], un[1]);
-        fn = W::template hop_factor<LP>(sc, false);   // t + 1 < L4 inside a chunk
-      }
-    }
-    // -t hop (formed at the previous step, or in the prologue)
-    W::template accumulate_uh<3, TTB>(ub, fb, acc[0]);
-    if (st + 1 < T) {
 #pragma unroll
-      for (int q = 0; q < 6; ++q) ub[q / 3][q % 3] = un[q / 3][q % 3];
-      fb = fn;
+        for (int q = 0; q < 6; ++q) ubs[q][tid] = un[q / 3][q % 3];
+        fb = W::template hop_factor<LP>(sc, false);   // t + 1 < L4 inside a chunk
+      }
     }
     C o[1][12];
 #pragma unroll
