@@ -210,9 +210,11 @@ wilson_tsweep_kernel(const OpArgs oa, const double2* __restrict__ in, const EpiA
   }
 }
 
-// ------------------------------------------------ FP32 / 16-bit, batched
-// The batched FP32/16-bit Wilson CG stencils (r = 1, one system per thread)
-// sweeping t in the same way.  A block owns the slab (p, z) of one system for
+// ------------------------------------------------------- 16-bit, batched
+// The batched 16-bit Wilson CG stencils (r = 1, one system per thread)
+// sweeping t in the same way.  The kernel is written for any storage policy,
+// but runs only where four of its blocks fit on a CU (launch_tsweep_lo), which
+// rules out FP32 storage (130 VGPRs, 60 KB of LDS).  A block owns the slab (p, z) of one system for
 // t in [t0, t0 + T); the storage words of psi at the step's slice sit in LDS,
 // so the diagonal needs no fetch, and the -t hop of t + 1 is formed at step t
 // from psi(t) and the link U_t(t) of the +t hop (kept in LDS: carried in
