@@ -25,14 +25,13 @@ static bool try_tsweep(bool dag, int epi, const OpArgs& oa, const void* in, cons
                        int nrhs, hipStream_t s) {
   const char* e = std::getenv("LQ_TSWEEP");
   if (e && e[0] == '0') return false;
-  static int ncu = 0;
-  if (ncu == 0) {
+  static const int ncu = [] {   // initialised once, thread-safe
     int dev = 0, n = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       n = 256;
-    ncu = n > 0 ? n : 256;
-  }
+    return n > 0 ? n : 256;
+  }();
   const int T = tsweep_slices(oa.g, ncu);
   if (T == 0 || nrhs < 1) return false;
   if (!dag) {
@@ -62,15 +61,16 @@ static bool try_tsweep(bool dag, int epi, const OpArgs& oa, const void* in, cons
 template <class P, int NL, bool DAG, int EPI, int CPL, bool XY>
 static bool launch_tsweep_lo(const OpArgs& oa, const void* in, const EpiArgs& ea, int nrhs, int T,
                              hipStream_t s) {
-  static int fits = -1;   // blocks of this kernel per CU
-  if (fits < 0) {
+  // blocks of this kernel per CU (a function-local static: initialised once,
+  // also when several host threads launch at the same time)
+  static const int fits = [] {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &n, reinterpret_cast<const void*>(&wilson_tsweep_lo_kernel<P, NL, DAG, EPI, CPL, XY>),
             256, 0) != hipSuccess)
       n = 0;
-    fits = n;
-  }
+    return n;
+  }();
   if (fits < 4) return false;
   const Geom& g = oa.g;
   const int per = ((g.L[0] * g.L[1]) >> 8) * g.L[2] * ((g.L[3] >> 3) / T);
