@@ -147,6 +147,16 @@ def roofline(lq, g0, lat, mc, prec, links, storage, cfg, stream, reps=48):
     ms0, per0, algo0 = out[0]
     pol = "Q16" if prec == lq.Q16 else "F32"
     traffic = stored_traffic(storage, links, cfg)
+    if -16 <= win <= -11 and prec == lq.Q16:
+        # the t-sweeping kernel of block orders -11 ... -16
+        c = -win - 10
+        how = (f"t-sweep, T = {2 << ((c - 1) % 3)} slices per block, x-y neighbours "
+               f"{'from LDS' if c <= 3 else 'fetched'}")
+        name, name0 = (f"wilson_tsweep_lo_kernel<{pol}, {links}, true, CG_UPDATE> ({how})",
+                       f"wilson_tsweep_lo_kernel<{pol}, {links}, false, STORE_NORM> ({how})")
+    else:
+        name, name0 = (f"stencil_kernel<WilsonOpR1<{pol}, {links}, true>, CG_UPDATE, K={K}>",
+                       f"stencil_kernel<WilsonOpR1<{pol}, {links}, false>, STORE_NORM>")
     return {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -154,7 +164,7 @@ def roofline(lq, g0, lat, mc, prec, links, storage, cfg, stream, reps=48):
                           "256 MiB device copy), counted in this launch configuration; reads "
                           "served by the Infinity Cache are included"),
         "data": "pseudo-random fields, live solver state (alpha = 1)",
-        "kernel": (f"stencil_kernel<WilsonOpR1<{pol}, {links}, true>, CG_UPDATE, K={K}>: "
+        "kernel": (f"{name}: "
                    f"q = M^dag t, r -= alpha q, ||r||^2, x += the four steps of the group every "
                    f"fourth launch; {NRHS_W} systems; average over the group"),
         "rhs_per_thread": K, "window": win,
@@ -162,7 +172,7 @@ def roofline(lq, g0, lat, mc, prec, links, storage, cfg, stream, reps=48):
         "algorithmic_bytes_per_site": per_site,
         "algorithmic_bytes_per_launch": int(algo),
         "other_stencil": {
-            "kernel": f"stencil_kernel<WilsonOpR1<{pol}, {links}, false>, STORE_NORM>: t = M p, ||t||^2",
+            "kernel": f"{name0}: t = M p, ||t||^2",
             "avg_launch_us": round(ms0 * 1e3, 2),
             "algorithmic_bytes_per_site": per0,
             "achieved_GBs": round(algo0 / (ms0 * 1e-3) / 1e9, 1),
