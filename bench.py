@@ -745,6 +745,9 @@ def main():
     ap.add_argument("--reliable-interval", type=int, default=0,
                     help="reliable update at least every this many iterations (0: library default)")
     ap.add_argument("--poll-interval", type=int, default=16)
+    ap.add_argument("--reliable-delta", type=float, default=0.0,
+                    help="reliable update once the iterated residual has dropped by this factor "
+                         "(0: library default)")
     ap.add_argument("--concurrency", type=int, default=3,
                     help="batches (gauge field x formulation) in flight at once")
     ap.add_argument("--order", choices=["wilson-first", "interleave"], default="interleave",
@@ -853,11 +856,12 @@ def main():
         src[form] = torch.from_numpy(np.stack(chis)).to("cuda")
         masses[form] = ms
     opts = lq.solve_opts(precision=prec, links=links, poll_interval=a.poll_interval, use_graph=1,
-                         reliable_interval=a.reliable_interval)
+                         reliable_interval=a.reliable_interval, reliable_delta=a.reliable_delta)
     links_sw = a.links_sw or links
     opts_f = {0: opts, 1: lq.solve_opts(precision=prec, links=links_sw,
                                         poll_interval=a.poll_interval, use_graph=1,
-                                        reliable_interval=a.reliable_interval)}
+                                        reliable_interval=a.reliable_interval,
+                                        reliable_delta=a.reliable_delta)}
     # `concurrency` batches in flight, each on its own stream with its own
     # workspace: a batch's instruction-bound stencil then shares the device
     # with another batch's bandwidth-bound kernels
@@ -1023,6 +1027,7 @@ def main():
             "storage": a.precision, "links": links, "links_staggered_wilson": links_sw,
             "batches_in_flight": a.concurrency,
             "reliable_interval": a.reliable_interval or "default", "poll_interval": a.poll_interval,
+            "reliable_delta": a.reliable_delta or "default",
         },
         "roofline": roof,
         "cpu_baseline": cpu,
