@@ -71,6 +71,39 @@ def test_graph_replay_of_the_benchmark_batches_matches_eager_and_eq2():
             assert abs(ig[k]["true_residual"] - rn) <= 1e-3 * tol
 
 
+def test_benchmark_wilson_batch_in_every_block_order_family_is_bitwise_equal(monkeypatch):
+    """The benchmark's 36 Wilson systems of field 0 (16-bit, 12-real links,
+    graph replay on a torch stream) with the t-sweep of block order -12 (what
+    the autotuner picks there), its variant -15 (x-y neighbours fetched) and
+    the one-site stencil in orders -3 and 0: the same iterations, reliable
+    updates and solutions bit for bit."""
+    w = _workload()
+    dims = tuple(w["dims"])
+    U = synth.gauge_field(dims, "near_identity", w["seed"], w["eps"])
+    stream = torch.cuda.Stream()
+    g = lq.Gauge(lq.Lattice(dims), U, lq.FEAT_Q16, stream=stream)
+    masses, chis = [], []
+    for d in w["deltas"]:
+        for a in range(12):
+            masses.append(w["m_c"]["wilson"] + d)
+            chis.append(synth.point_source(dims, synth.WILSON, a))
+    chis = np.stack(chis)
+    opts = lq.solve_opts(precision=lq.Q16, links=12, poll_interval=16, use_graph=1)
+    ref = None
+    for win in (-12, -15, -3, 0):
+        monkeypatch.setenv("LQ_LAUNCH", f"1,{win}")
+        x, infos = lq.cg_solve_batch(g, synth.WILSON, masses, chis, [1e-8] * len(masses),
+                                     opts=opts, stream=stream)
+        torch.cuda.synchronize()
+        assert all(i["status"] == lq.OK and i["true_residual"] <= 1e-8 for i in infos), win
+        key = ([i["iterations"] for i in infos], [i["reliable_updates"] for i in infos])
+        if ref is None:
+            ref = (x, key)
+        else:
+            assert key == ref[1], win
+            assert torch.equal(x, ref[0]), win
+
+
 def test_resident_batch_with_graph_across_load_cancel_refill():
     """A resident batch stepping by graph replay on its own stream: requests
     are loaded, one running slot is cancelled and refilled, finished slots are
